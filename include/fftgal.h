@@ -1,0 +1,214 @@
+/*
+ * fftgal -- guaranteed bounds on the homogenized conductivity of a periodic
+ * medium by the Fourier-Galerkin method with exact integration (the "Ga"
+ * scheme of J. Vondrejc, arXiv:1412.2033), on one AMD MI355X (gfx950).
+ *
+ * Problem (Sec. 1.1, eq. intro_HP; Def. homog_problem): for a Y-periodic,
+ * symmetric, uniformly elliptic A(x) on the unit cell Y = (-1/2, 1/2)^d,
+ * d in {2, 3}, find A_H.  The Ga scheme (Def. Ga, eq. Ga) minimises the exact
+ * energy over trigonometric fields of odd order N (eq. N_odd): the primal
+ * minimum over E_N gives A_{H,N}, the dual minimum of the A^{-1} energy over
+ * J_N gives B_{H,N}, and Prop. struct_bounds gives
+ *
+ *      B_{H,N}^{-1}  <=  A_H  <=  A_{H,N}        (Loewner order),
+ *
+ * guaranteed because the energies are evaluated exactly by the double-grid
+ * quadrature of Lemma integ_eval_VM on M >= 2N-1 points per axis.  Each
+ * minimiser is found by conjugate gradients (Remark CG) on the linear systems
+ * of Cor. Ga_linsys (eq. Ga_linsys_orig), whose matrix-vector product is
+ * Algorithm 2 (material multiply, FFT, projection, inverse FFT).
+ *
+ * Conventions.  Axis 1 is the slowest in every array; frequencies and grid
+ * points follow eqs. index_set and grid_points; the M-grid point with index j
+ * is x = j/M (mod 1).  M is the smallest odd 3,5,7-smooth integer >= 2N-1
+ * (Lemma integ_eval_VM allows any M >= 2N-1; the bounds do not depend on it).
+ *
+ * Memory.  The library never allocates device memory: the caller passes one
+ * device workspace of fftgal_workspace_bytes() bytes and a HIP stream (as a
+ * void*; NULL is the default stream) to fftgal_plan().  All device work of a
+ * plan is ordered on that stream.  Host arrays passed in are copied before the
+ * call returns.  The plan object itself is host memory owned by the library
+ * and released by fftgal_destroy().  One plan must not be used from two
+ * threads at once; distinct plans are independent (no global mutable state).
+ *
+ * Errors.  Every entry point returns an fftgal_status code and never aborts;
+ * fftgal_last_error() gives a message for the last failing call on a plan
+ * (or for a failing fftgal_plan() when called with NULL).
+ */
+#ifndef FFTGAL_H
+#define FFTGAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fftgal_status {
+    FFTGAL_OK = 0,
+    FFTGAL_EINVAL = -1,     /* invalid argument (message says which)            */
+    FFTGAL_ENOMEM = -2,     /* workspace smaller than fftgal_workspace_bytes()   */
+    FFTGAL_EDEVICE = -3,    /* a HIP call failed                                */
+    FFTGAL_ENOTCONV = -4,   /* CG stopped at maxit; the field is still admissible,
+                               so fftgal_bounds() still returns guaranteed bounds */
+    FFTGAL_ESTATE = -5,     /* call out of order (e.g. bounds before solves)     */
+    FFTGAL_EBREAKDOWN = -6  /* CG breakdown: (p, Kp) <= 0 or not finite (a
+                               non-SPD or non-finite material)                   */
+};
+
+enum fftgal_precision {
+    FFTGAL_FP64 = 0,      /* every step in FP64                                  */
+    FFTGAL_FP32_ITER = 1  /* CG iterations (FFTs, projection, material multiply,
+                             vector updates) in FP32 with inner products
+                             accumulated in FP64; the final re-projection and the
+                             bound quadrature in FP64                            */
+};
+
+enum fftgal_material_kind {
+    FFTGAL_INCLUSIONS = 0, /* eq. inclcomp: matrix phase plus inclusions          */
+    FFTGAL_VOXELS = 1      /* eq. gridcomp: piecewise-constant voxel image        */
+};
+
+enum fftgal_shape {
+    FFTGAL_RECT = 0, /* box |x_a - c_a| < h_a / 2 (eq. def_cube)                 */
+    FFTGAL_CIRC = 1  /* disc |x - c| < r, d = 2 only (eq. char_func_Four)         */
+};
+
+/*
+ * Material description (host memory; copied by fftgal_set_material).
+ *
+ * FFTGAL_INCLUSIONS (eq. inclcomp, eq. inclcomp_formula): A0 is the matrix
+ *   phase (d x d, row-major, SPD).  Inclusion i has shape[i], centre
+ *   center[i*d .. i*d+d-1] in the cell, size[i*d ..] = side lengths h
+ *   (0 < h_a <= 1) for RECT or size[i*d] = radius r (0 < r <= 1/2) for CIRC,
+ *   and ABSOLUTE conductivity A_in[i*d*d ..] (SPD; not the increment
+ *   A_i = A_in - A0 of eq. inclcomp, because the dual needs A_in^{-1}).
+ *   Inclusions must not overlap (periodic minimum image); the dual material
+ *   is then A^{-1} = A0^{-1} + sum_i f_i [A_in^{-1} - A0^{-1}].  Supported:
+ *   all A_in equal (two-phase, any SPD matrices), or A0 and every A_in
+ *   isotropic (multiples of I).
+ * FFTGAL_VOXELS (eq. gridcomp with psi = rect_{1/P}, Lemma grid_compos,
+ *   Remark eval_with_FFT): image holds P[0]*...*P[d-1] positive scalar
+ *   conductivities, row-major, voxel p centred at x = p/P; the dual uses
+ *   1/image.  Each P[a] must be an odd 3,5,7-smooth integer.  If
+ *   image_device is non-zero, image is a device pointer that is read
+ *   (stream-ordered, on the plan's stream) during fftgal_set_material only and
+ *   validated on the device; otherwise it is host memory.
+ */
+typedef struct fftgal_material {
+    int32_t kind;
+    double A0[9];
+    int32_t n_incl;
+    const int32_t *shape;
+    const double *center;
+    const double *size;
+    const double *A_in;
+    int32_t P[3];
+    const double *image;
+    int32_t image_device;
+} fftgal_material;
+
+/* Outcome of one CG solve (Remark CG). */
+typedef struct fftgal_info {
+    int32_t iters;      /* CG iterations taken                                  */
+    int32_t converged;  /* 1 if the stopping test was met within maxit          */
+    double rel_res;     /* ||r_k|| / ||r_0|| at exit (0 if r_0 = 0)             */
+    double res0;        /* ||r_0|| in the (.,.)_{R^{d x M}} norm                */
+} fftgal_info;
+
+/*
+ * Bytes of device workspace a plan of dimension d (2 or 3), orders N[0..d-1]
+ * (odd, >= 1) and precision needs; 0 if the arguments are invalid.  Used for
+ * admission by HBM footprint.  If voxel images with resolution P other than
+ * the plan's M will be set, pass the largest P through fftgal_workspace_bytes_p.
+ */
+size_t fftgal_workspace_bytes(int d, const int32_t *N, int precision);
+size_t fftgal_workspace_bytes_p(int d, const int32_t *N, int precision, const int32_t *P);
+
+/*
+ * Create a plan on `dev_workspace` (device pointer, 256-byte aligned, at least
+ * fftgal_workspace_bytes() bytes; owned by the caller and used until
+ * fftgal_destroy) and `hip_stream` (hipStream_t or NULL).  Writes FFT twiddle
+ * tables into the workspace (stream-ordered).  Returns EINVAL for d not in
+ * {2,3}, even or non-positive N, unknown precision, or a misaligned workspace;
+ * ENOMEM if bytes is too small.
+ */
+int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision,
+                void *dev_workspace, size_t bytes, void *hip_stream);
+
+/*
+ * Build the double-grid material fields A_M and B_M (eq. MBA_GA; Lemma
+ * integ_eval_VM) on the device from closed-form Fourier coefficients
+ * (Remark anal_Fourier) or from the voxel image (Lemma grid_compos), for both
+ * the primal (A) and the dual (A^{-1}) problem.  Invalidates earlier solves.
+ * EINVAL on any violation listed above.
+ */
+int fftgal_set_material(struct fftgal_plan *plan, const fftgal_material *m);
+
+/*
+ * Solve the primal cell problem G A_M e = -G A_M E (eq. Ga_linsys_orig) by CG
+ * from e_0 = 0 for E = e_alpha (alpha in 0..d-1) or for all d unit fields
+ * (alpha = -1).  Stops when ||r_k|| <= rtol ||r_0||, or when ||r_k|| <=
+ * 1e-14 ||A_M E|| (FP64) / 1e-7 ||A_M E|| (FP32_ITER) -- a right-hand side at
+ * rounding level of the load is treated as zero -- or at maxit.  `info` (may be
+ * NULL; an array of d entries when alpha = -1) receives the outcome.  Returns
+ * OK, ENOTCONV, EBREAKDOWN, ESTATE (no material) or EINVAL.
+ */
+int fftgal_solve_primal(struct fftgal_plan *plan, int alpha, double rtol, int maxit,
+                        fftgal_info *info);
+
+/* The dual problem G^J B_M j = -G^J B_M J with J = e_alpha, as above. */
+int fftgal_solve_dual(struct fftgal_plan *plan, int alpha, double rtol, int maxit,
+                      fftgal_info *info);
+
+/*
+ * Guaranteed bounds from the d primal and d dual fields (Prop. struct_bounds):
+ * upper = A_{H,N} and lower = B_{H,N}^{-1}, each d x d row-major on the host,
+ * and gap = tr(upper - lower)/2 (eq. error).  The energy Gram matrices
+ * (A_M (E_a + e_a), E_b + e_b)_{R^{d x M}} are evaluated in FP64 on the device
+ * from fields that lie in E_N (J_N) by construction, then symmetrised; B is
+ * inverted on the host.  Any pointer may be NULL.  ESTATE unless all 2d
+ * solves exist.
+ */
+int fftgal_bounds(struct fftgal_plan *plan, double *upper, double *lower, double *gap);
+
+/* Release the plan (host memory only; the workspace stays the caller's). */
+int fftgal_destroy(struct fftgal_plan *plan);
+
+/* Message for the last error on `plan` (or of the last failed fftgal_plan()
+ * call on this thread when plan is NULL).  Never NULL. */
+const char *fftgal_last_error(const struct fftgal_plan *plan);
+
+/* The grid size M the plan uses along axis a (0 if invalid). */
+int fftgal_grid_size(const struct fftgal_plan *plan, int axis);
+
+/*
+ * Kernel timing (tracing).  While enabled, every kernel launch of the plan is
+ * bracketed by a pair of HIP events on the plan's stream, tagged with one of
+ * the classes below.  fftgal_read_timing() waits for the stream, writes the
+ * summed milliseconds and the launch counts per class (arrays of
+ * FFTGAL_K_COUNT entries; either may be NULL) since the previous read, and
+ * resets them.  Enabling adds two event records per launch.
+ */
+enum fftgal_kernel_class {
+    FFTGAL_K_EXPAND = 0,      /* CG state -> d components, inverse DFT along axis 1 */
+    FFTGAL_K_PENCIL_INV = 1,  /* inverse DFT along axis 2 (d = 3)                   */
+    FFTGAL_K_ROW = 2,         /* C2R along axis d, material multiply, R2C           */
+    FFTGAL_K_PENCIL_FWD = 3,  /* forward DFT along axis 2 (d = 3)                   */
+    FFTGAL_K_PROJECT = 4,     /* forward DFT along axis 1, projection, (p, Kp)      */
+    FFTGAL_K_CG_UPDATE = 5,   /* x += alpha p, r -= alpha q, (r, r)                 */
+    FFTGAL_K_CG_SCALAR = 6,   /* alpha / beta / stopping test, vector clears        */
+    FFTGAL_K_RHS = 7,         /* right-hand side -G A_M E                           */
+    FFTGAL_K_BOUNDS = 8,      /* FP64 fields and energy Gram quadrature             */
+    FFTGAL_K_SETUP = 9,       /* material fields A_M, B_M                           */
+    FFTGAL_K_COUNT = 10
+};
+int fftgal_set_timing(struct fftgal_plan *plan, int enable);
+int fftgal_read_timing(struct fftgal_plan *plan, double *ms, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTGAL_H */

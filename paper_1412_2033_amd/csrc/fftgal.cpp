@@ -1,0 +1,1227 @@
+// Host side of the fftgal C ABI: plan and workspace layout, input validation,
+// material setup, the device-resident CG driver and the bounds.
+#include "../../include/fftgal.h"
+#include "fftgal_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace fftgal;
+
+namespace {
+
+thread_local std::string g_plan_error = "no error";
+
+constexpr int kMaxHist = 20000;      // CG history entries kept per solve
+constexpr int kUpdateBlocks = 1024;  // fixed grid of the CG update kernel
+constexpr double kFloor64 = 1e-14;   // residual floor relative to ||A_M E|| (FP64)
+constexpr double kFloor32 = 1e-7;    // (FP32 iterations)
+
+int smooth_odd(int m) {
+    for (int n = std::max(1, m);; ++n) {
+        if (n % 2 == 0) continue;
+        int x = n;
+        for (int p : {3, 5, 7})
+            while (x % p == 0) x /= p;
+        if (x == 1) return n;
+    }
+}
+
+bool is_smooth_odd(int n) { return n >= 1 && smooth_odd(n) == n; }
+
+std::vector<int> factor(int n) {
+    std::vector<int> f;
+    for (int p : {7, 5, 3})
+        while (n % p == 0) {
+            f.push_back(p);
+            n /= p;
+        }
+    return f;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Sizes that fix the workspace layout.
+struct Dims {
+    int d = 0;
+    int N[3] = {1, 1, 1};
+    int M[3] = {1, 1, 1};
+    int L[3] = {1, 1, 1};   // 2N - 1: the support Z_{2N-1} of the material series
+    int P[3] = {1, 1, 1};   // largest voxel resolution to provision for
+    int Nh = 1;             // (N_d + 1) / 2 stored entries along the last axis
+    int Lh = 1;             // N_d: stored entries of Z_{2N_d - 1} along the last axis
+    long Ns = 0;            // state entries per component
+    long Mtot = 0;          // |M|
+    int nc_max = 1;
+};
+
+bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o) {
+    if (d != 2 && d != 3 || N == nullptr) return false;
+    o->d = d;
+    for (int a = 0; a < d; ++a) {
+        if (N[a] < 1 || N[a] % 2 == 0 || N[a] > 100000) return false;
+        o->N[a] = N[a];
+        o->L[a] = 2 * N[a] - 1;
+        o->M[a] = smooth_odd(2 * N[a] - 1);
+        o->P[a] = P ? std::max<int>(P[a], o->M[a]) : o->M[a];
+        if (P && !is_smooth_odd(P[a])) return false;
+    }
+    o->Nh = (o->N[d - 1] + 1) / 2;
+    o->Lh = o->N[d - 1];
+    o->Ns = (d == 3 ? (long)o->N[0] * o->N[1] : (long)o->N[0]) * o->Nh;
+    o->Mtot = 1;
+    for (int a = 0; a < d; ++a) o->Mtot *= o->M[a];
+    o->nc_max = std::max(1, d - 1);
+    return true;
+}
+
+struct Layout {
+    size_t tw64, tw32, twP64, twP32, T1, T2, r, p, q, xsol, xsol64, gA64, gB64, gA32, gB32, part_a, part_b,
+        part_c, gram, status, hist, total;
+    size_t tw_len, twP_len;  // complex entries per table region
+    size_t part_len;         // doubles per partial region
+};
+
+int pencil_B(int n, int lacc, bool fp64, int Bmax) {
+    const size_t es = fp64 ? 16 : 8;
+    int B = Bmax;
+    while (B > 1 && es * ((size_t)2 * n * B + (size_t)lacc * B) > 80 * 1024) B /= 2;
+    return B;
+}
+
+int row_RP(int n, int nz, bool fp64) {
+    const size_t es = fp64 ? 16 : 8;
+    int RP = 8;
+    while (RP > 1 && es * (size_t)(nz + 1) * RP * n > 80 * 1024) RP /= 2;
+    return RP;
+}
+
+Layout make_layout(const Dims &D, int precision) {
+    Layout L{};
+    const int d = D.d;
+    const size_t c16 = 16;
+    const long d2 = (long)d * d;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    // twiddle tables: one per axis length M_a (<= sum of lengths entries)
+    L.tw_len = 0;
+    for (int a = 0; a < d; ++a) L.tw_len += D.M[a];
+    L.twP_len = 0;
+    for (int a = 0; a < d; ++a) L.twP_len += D.P[a];
+    L.tw64 = take(L.tw_len * c16);
+    L.tw32 = take(L.tw_len * 8);
+    L.twP64 = take(L.twP_len * c16);
+    L.twP32 = take(L.twP_len * 8);
+    // transform intermediates (also the material setup scratch)
+    size_t t1, t2;
+    if (d == 3) {
+        t1 = (size_t)d2 * D.M[0] * D.N[1] * D.Nh;
+        t2 = (size_t)d2 * D.M[0] * D.M[1] * D.Nh;
+        const size_t Lh = D.Lh;
+        const size_t s_u = std::max({(size_t)D.L[0] * D.L[1] * Lh, (size_t)D.M[0] * D.M[1] * Lh,
+                                     (size_t)D.P[0] * D.L[1] * Lh, (size_t)D.P[0] * D.P[1] * D.P[2] / 2 + 1});
+        const size_t s_w = std::max({(size_t)D.M[0] * D.L[1] * Lh, (size_t)D.P[0] * D.P[1] * Lh,
+                                     (size_t)D.L[0] * D.L[1] * Lh, (size_t)D.M[0] * D.M[1] * Lh});
+        t2 = std::max(t2, s_u);
+        t1 = std::max(t1, s_w + 4096);
+    } else {
+        t1 = (size_t)d2 * D.M[0] * D.Nh;
+        t2 = 0;
+        const size_t Lh = D.Lh;
+        const size_t s_u = std::max({(size_t)D.L[0] * Lh, (size_t)D.P[0] * D.P[1] / 2 + 1});
+        const size_t s_w = std::max({(size_t)D.P[0] * Lh, (size_t)D.M[0] * Lh});
+        t2 = s_u;
+        t1 = std::max(t1, s_w + 4096);
+    }
+    L.T1 = take(t1 * c16);
+    L.T2 = take(t2 * c16);
+    const size_t vec = (size_t)D.nc_max * D.Ns * c16;
+    L.r = take(vec);
+    L.p = take(vec);
+    L.q = take(vec);
+    L.xsol = take((size_t)2 * d * vec);  // [kind][alpha][nc][Ns]
+    L.xsol64 = take(precision == FFTGAL_FP32_ITER ? (size_t)d * vec : 0);
+    L.gA64 = take((size_t)D.Mtot * 8);
+    L.gB64 = take((size_t)D.Mtot * 8);
+    L.gA32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.Mtot * 4 : 0);
+    L.gB32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.Mtot * 4 : 0);
+    // partial sums: the largest work-group count of any reducing launch
+    long nwg = kUpdateBlocks;
+    for (int fp = 0; fp < 2; ++fp) {
+        const bool f64 = fp == 1;
+        const int nbz = (d == 3) ? D.N[1] * D.Nh : D.Nh;
+        const int B = pencil_B(D.M[0], D.nc_max * D.N[0], f64, f64 ? 8 : 16);
+        nwg = std::max<long>(nwg, (nbz + B - 1) / B);
+        const long nrows = (d == 3) ? (long)D.M[0] * D.M[1] : D.M[0];
+        const int RP = row_RP(D.M[d - 1], d, f64);
+        nwg = std::max<long>(nwg, ((nrows + 1) / 2 + RP - 1) / RP);
+        const int RPg = row_RP(D.M[d - 1], (int)d2, true);
+        nwg = std::max<long>(nwg, (((nrows + 1) / 2 + RPg - 1) / RPg) * d2);
+    }
+    L.part_len = (size_t)nwg + 64;
+    L.part_a = take(L.part_len * 8);
+    L.part_b = take(L.part_len * 8);
+    L.part_c = take(L.part_len * 8);
+    L.gram = take(64 * 8);
+    L.status = take(6 * sizeof(CgStatus));
+    L.hist = take((size_t)6 * 2 * (kMaxHist + 1) * 8);
+    L.total = align256(off);
+    return L;
+}
+
+void build_fft(int n, size_t tw_base_entry, std::vector<double> &tab, FftDesc *f) {
+    std::vector<int> rad = factor(n);
+    f->n = n;
+    f->nst = (int)rad.size();
+    int p = 1;
+    size_t pos = tw_base_entry;
+    for (int s = 0; s < f->nst; ++s) {
+        const int r = rad[s];
+        f->radix[s] = r;
+        f->twoff[s] = (int)pos;
+        for (int q = 1; q < r; ++q)
+            for (int k = 0; k < p; ++k) {
+                const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)(q * k) /
+                                        (long double)(p * r);
+                tab.push_back((double)cosl(ang));
+                tab.push_back((double)sinl(ang));
+            }
+        pos += (size_t)(r - 1) * p;
+        p *= r;
+    }
+}
+
+}  // namespace
+
+struct fftgal_plan {
+    Dims D;
+    Layout Lo;
+    int precision = FFTGAL_FP64;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    FftDesc fM[3];  // transform along axis a on the M-grid
+    FftDesc fP[3];  // transform along axis a of a voxel image
+    int Pcur[3] = {0, 0, 0};
+    bool have_mat = false;
+    bool separate_gB = false;
+    double A0[9], DA[9], B0[9], DB[9];
+    bool solved[2][3] = {{false, false, false}, {false, false, false}};
+    fftgal_info last_info[2][3];
+    bool hist_on = false;  // per-iteration (rr, alpha) history; only when maxit <= kMaxHist
+    int cur_alpha = 0;
+    // kernel timing (fftgal_set_timing)
+    bool timing = false;
+    struct Ev {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> evs;
+    std::vector<hipEvent_t> pool;
+    double t_ms[FFTGAL_K_COUNT] = {0};
+    int32_t t_cnt[FFTGAL_K_COUNT] = {0};
+    std::string err = "no error";
+
+    template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
+    bool fp64_iter() const { return precision == FFTGAL_FP64; }
+    int nc(int kind) const { return kind == KIND_E ? 1 : std::max(1, D.d - 1); }
+    size_t vec_bytes() const { return (size_t)D.nc_max * D.Ns * 16; }
+    void *xsol(int kind, int alpha) { return ws + Lo.xsol + ((size_t)kind * D.d + alpha) * vec_bytes(); }
+    CgStatus *status(int kind, int alpha) { return at<CgStatus>(Lo.status) + kind * 3 + alpha; }
+    double *hist(int kind, int alpha) {
+        return at<double>(Lo.hist) + (size_t)(kind * 3 + alpha) * 2 * (kMaxHist + 1);
+    }
+};
+
+typedef struct fftgal_plan Plan;  // the C function of the same name hides the tag in C++
+
+namespace {
+
+hipEvent_t pool_event(Plan *pl) {
+    if (!pl->pool.empty()) {
+        hipEvent_t e = pl->pool.back();
+        pl->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets the launches issued during its lifetime with two events of class
+// `cls` when the plan's timing is on.
+struct Timed {
+    Plan *pl;
+    int cls;
+    hipEvent_t a = nullptr;
+    Timed(Plan *p, int c) : pl(p), cls(c) {
+        if (pl->timing) {
+            a = pool_event(pl);
+            if (a) (void)hipEventRecord(a, pl->stream);
+        }
+    }
+    ~Timed() {
+        if (pl->timing && a) {
+            hipEvent_t b = pool_event(pl);
+            if (b) {
+                (void)hipEventRecord(b, pl->stream);
+                pl->evs.push_back({cls, a, b});
+            } else {
+                pl->pool.push_back(a);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+namespace {
+
+int fail(Plan *pl, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (pl)
+        pl->err = buf;
+    else
+        g_plan_error = buf;
+    return code;
+}
+
+#define HIPCHECK(pl, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(pl, FFTGAL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---- pass builders -------------------------------------------------------
+
+PencilArgs base_pencil(Plan *pl, const FftDesc &f, bool fp64, bool tabP = false) {
+    PencilArgs a{};
+    a.f = f;
+    a.tw = pl->ws + (fp64 ? (tabP ? pl->Lo.twP64 : pl->Lo.tw64) : (tabP ? pl->Lo.twP32 : pl->Lo.tw32));
+    a.d = pl->D.d;
+    a.Nh = pl->D.Nh;
+    a.Nmid = pl->D.d == 3 ? pl->D.N[1] : 0;
+    a.scale = 1.0;
+    a.nsol = 1;
+    return a;
+}
+
+int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int Bmax, int cls) {
+    int lacc = 0;
+    if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
+    if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
+    a.B = pencil_B(a.f.n, lacc, fp64, Bmax);
+    if (pencil_lds_bytes(a, fp64) > 160 * 1024)
+        return fail(pl, FFTGAL_EINVAL, "transform length %d too large for one work-group", a.f.n);
+    Timed t(pl, cls);
+    HIPCHECK(pl, launch_pencil(a, nouter, fp64, pl->stream));
+    return FFTGAL_OK;
+}
+
+int run_row(Plan *pl, RowArgs &r, bool fp64, int cls) {
+    int nz = r.ncomp;
+    if (r.mode == ROW_RHS) nz = r.d;
+    if (r.mode == ROW_C2R || r.mode == ROW_R2C) nz = 1;
+    r.RP = row_RP(r.f.n, nz, fp64);
+    if (row_lds_bytes(r, fp64) > 160 * 1024)
+        return fail(pl, FFTGAL_EINVAL, "row length %d with %d components too large for one work-group", r.f.n, nz);
+    Timed t(pl, cls);
+    HIPCHECK(pl, launch_row(r, fp64, pl->stream));
+    return FFTGAL_OK;
+}
+
+// The inverse half of the operator: CG state (n_c components per solution)
+// -> d spatial components per solution on the M-grid, stored as half-spectrum
+// rows along the last axis (T1 in 2D, T2 in 3D).
+int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss, int nsol,
+                   bool update_p, const CgStatus *st, void **rows_out, int cls_expand, int cls_inv) {
+    const Dims &D = pl->D;
+    const int d = D.d;
+    const int ncomp_total = nsol * d;
+    PencilArgs a = base_pencil(pl, pl->fM[0], fp64);
+    a.pro = PRO_EXPAND;
+    a.epi = EPI_PLAIN;
+    a.kind = kind;
+    a.nc = pl->nc(kind);
+    a.ncomp = d;
+    a.nsol = nsol;
+    a.sgn = +1;
+    a.L_in = D.N[0];
+    a.L_out = D.M[0];
+    a.st_cs = D.Ns;
+    a.st_ss = st_ss;
+    a.update_p = update_p ? 1 : 0;
+    a.status = st;
+    if (update_p) {
+        a.st_r = pl->ws + pl->Lo.r;
+        a.st_p = pl->ws + pl->Lo.p;
+    } else {
+        a.st_x = state;
+    }
+    a.out = pl->ws + pl->Lo.T1;
+    if (d == 3) {
+        a.nb = D.N[1] * D.Nh;
+        a.in_ls = (long)D.N[1] * D.Nh;
+        a.out_ls = (long)D.N[1] * D.Nh;
+        a.out_cs = (long)D.M[0] * D.N[1] * D.Nh;
+    } else {
+        a.nb = D.Nh;
+        a.in_ls = D.Nh;
+        a.out_ls = D.Nh;
+        a.out_cs = (long)D.M[0] * D.Nh;
+    }
+    int rc = run_pencil(pl, a, 1, fp64, fp64 ? 8 : 16, cls_expand);
+    if (rc) return rc;
+    if (d == 2) {
+        *rows_out = pl->ws + pl->Lo.T1;
+        return FFTGAL_OK;
+    }
+    PencilArgs b = base_pencil(pl, pl->fM[1], fp64);
+    b.pro = PRO_PLAIN;
+    b.epi = EPI_PLAIN;
+    b.ncomp = ncomp_total;
+    b.sgn = +1;
+    b.L_in = D.N[1];
+    b.L_out = D.M[1];
+    b.status = st;
+    b.in = pl->ws + pl->Lo.T1;
+    b.out = pl->ws + pl->Lo.T2;
+    b.nb = D.Nh;
+    b.in_cs = (long)D.M[0] * D.N[1] * D.Nh;
+    b.in_os = (long)D.N[1] * D.Nh;
+    b.in_ls = D.Nh;
+    b.out_cs = (long)D.M[0] * D.M[1] * D.Nh;
+    b.out_os = (long)D.M[1] * D.Nh;
+    b.out_ls = D.Nh;
+    rc = run_pencil(pl, b, D.M[0], fp64, fp64 ? 8 : 16, cls_inv);
+    if (rc) return rc;
+    *rows_out = pl->ws + pl->Lo.T2;
+    return FFTGAL_OK;
+}
+
+// The forward half: half-spectrum rows -> projected CG vector q (scaled),
+// plus partial sums of (dot, q) (or (q, q) when dot == nullptr).
+int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const void *dot, double scale,
+                   const CgStatus *st, double *partial, int *nparts, int cls_fwd, int cls_proj) {
+    const Dims &D = pl->D;
+    const int d = D.d;
+    void *src = rows;
+    if (d == 3) {
+        PencilArgs b = base_pencil(pl, pl->fM[1], fp64);
+        b.pro = PRO_PLAIN;
+        b.epi = EPI_PLAIN;
+        b.ncomp = d;
+        b.sgn = -1;
+        b.L_in = D.M[1];
+        b.L_out = D.N[1];
+        b.status = st;
+        b.in = rows;
+        b.out = pl->ws + pl->Lo.T1;
+        b.nb = D.Nh;
+        b.in_cs = (long)D.M[0] * D.M[1] * D.Nh;
+        b.in_os = (long)D.M[1] * D.Nh;
+        b.in_ls = D.Nh;
+        b.out_cs = (long)D.M[0] * D.N[1] * D.Nh;
+        b.out_os = (long)D.N[1] * D.Nh;
+        b.out_ls = D.Nh;
+        int rc = run_pencil(pl, b, D.M[0], fp64, fp64 ? 8 : 16, cls_fwd);
+        if (rc) return rc;
+        src = pl->ws + pl->Lo.T1;
+    }
+    PencilArgs a = base_pencil(pl, pl->fM[0], fp64);
+    a.pro = PRO_PLAIN;
+    a.epi = EPI_PROJECT;
+    a.kind = kind;
+    a.nc = pl->nc(kind);
+    a.ncomp = d;
+    a.sgn = -1;
+    a.scale = scale;
+    a.L_in = D.M[0];
+    a.L_out = D.N[0];
+    a.status = st;
+    a.in = src;
+    a.out = q;
+    a.st_dot = dot;
+    a.partial = partial;
+    if (d == 3) {
+        a.nb = D.N[1] * D.Nh;
+        a.in_cs = (long)D.M[0] * D.N[1] * D.Nh;
+        a.in_ls = (long)D.N[1] * D.Nh;
+        a.out_ls = (long)D.N[1] * D.Nh;
+    } else {
+        a.nb = D.Nh;
+        a.in_cs = (long)D.M[0] * D.Nh;
+        a.in_ls = D.Nh;
+        a.out_ls = D.Nh;
+    }
+    a.out_cs = D.Ns;
+    int rc = run_pencil(pl, a, 1, fp64, fp64 ? 8 : 16, cls_proj);
+    if (rc) return rc;
+    *nparts = pencil_grid_x(a);
+    return FFTGAL_OK;
+}
+
+RowArgs base_row(Plan *pl, bool fp64, int mode, void *rows, int kind) {
+    const Dims &D = pl->D;
+    RowArgs r{};
+    r.data = rows;
+    r.nrows = (D.d == 3) ? D.M[0] * D.M[1] : D.M[0];
+    r.Nh_row = D.Nh;
+    r.cs = (long)r.nrows * D.Nh;
+    r.f = pl->fM[D.d - 1];
+    r.tw = pl->ws + (fp64 ? pl->Lo.tw64 : pl->Lo.tw32);
+    r.d = D.d;
+    r.ncomp = D.d;
+    r.mode = mode;
+    r.scale = 1.0;
+    const bool gsep = pl->separate_gB && kind == KIND_J;
+    if (fp64)
+        r.g = pl->ws + (gsep ? pl->Lo.gB64 : pl->Lo.gA64);
+    else
+        r.g = pl->ws + (gsep ? pl->Lo.gB32 : pl->Lo.gA32);
+    const double *c0 = kind == KIND_E ? pl->A0 : pl->B0;
+    const double *c1 = kind == KIND_E ? pl->DA : pl->DB;
+    for (int i = 0; i < 9; ++i) {
+        r.A0[i] = c0[i];
+        r.D[i] = c1[i];
+    }
+    return r;
+}
+
+// ---- material setup --------------------------------------------------------
+
+// Inverse transforms of a Fourier half-grid on Z_{2N-1} (stored wrapped,
+// layout [n1][n2][n3 >= 0]) into a real field on the M-grid (eq. MBA_GA).
+int series_to_field(Plan *pl, void *coef, double *field) {
+    const Dims &D = pl->D;
+    const int d = D.d;
+    void *U = pl->ws + pl->Lo.T2;
+    void *W = pl->ws + pl->Lo.T1;
+    void *cur = coef;
+    PencilArgs a = base_pencil(pl, pl->fM[0], true);
+    a.pro = PRO_PLAIN;
+    a.epi = EPI_PLAIN;
+    a.ncomp = 1;
+    a.sgn = +1;
+    a.L_in = D.L[0];
+    a.L_out = D.M[0];
+    a.in = cur;
+    void *dst1 = (cur == U) ? W : U;
+    a.out = dst1;
+    if (d == 3) {
+        a.nb = D.L[1] * D.Lh;
+        a.in_ls = a.out_ls = (long)D.L[1] * D.Lh;
+    } else {
+        a.nb = D.Lh;
+        a.in_ls = a.out_ls = D.Lh;
+    }
+    int rc = run_pencil(pl, a, 1, true, 8, FFTGAL_K_SETUP);
+    if (rc) return rc;
+    cur = dst1;
+    if (d == 3) {
+        PencilArgs b = base_pencil(pl, pl->fM[1], true);
+        b.pro = PRO_PLAIN;
+        b.epi = EPI_PLAIN;
+        b.ncomp = 1;
+        b.sgn = +1;
+        b.L_in = D.L[1];
+        b.L_out = D.M[1];
+        b.in = cur;
+        void *dst2 = (cur == U) ? W : U;
+        b.out = dst2;
+        b.nb = D.Lh;
+        b.in_os = (long)D.L[1] * D.Lh;
+        b.in_ls = D.Lh;
+        b.out_os = (long)D.M[1] * D.Lh;
+        b.out_ls = D.Lh;
+        rc = run_pencil(pl, b, D.M[0], true, 8, FFTGAL_K_SETUP);
+        if (rc) return rc;
+        cur = dst2;
+    }
+    RowArgs r{};
+    r.data = cur;
+    r.nrows = (d == 3) ? D.M[0] * D.M[1] : D.M[0];
+    r.Nh_row = D.Lh;
+    r.cs = 0;
+    r.f = pl->fM[d - 1];
+    r.tw = pl->ws + pl->Lo.tw64;
+    r.ncomp = 1;
+    r.d = d;
+    r.mode = ROW_C2R;
+    r.real_out = field;
+    r.real_stride = D.M[d - 1];
+    r.scale = 1.0;
+    return run_row(pl, r, true, FFTGAL_K_SETUP);
+}
+
+// Voxel image (host, P^d doubles, row-major) -> truncated/extended Fourier
+// half-grid on Z_{2N-1} times the sinc window of psi = rect_{1/P}
+// (Lemma grid_compos, Remark eval_with_FFT), left in the returned buffer.
+int voxel_series(Plan *pl, const double *img_dev, int imgmap, double vmax, void **coef_out) {
+    const Dims &D = pl->D;
+    const int d = D.d;
+    const int *P = pl->Pcur;
+    void *U = pl->ws + pl->Lo.T2;
+    void *W = pl->ws + pl->Lo.T1;
+    long Ptot = 1;
+    for (int a = 0; a < d; ++a) Ptot *= P[a];
+    // rows along the last axis: R2C, keep n_d in [0, N_d)
+    RowArgs r{};
+    r.data = W;
+    r.nrows = (int)(Ptot / P[d - 1]);
+    r.Nh_row = D.Lh;
+    r.cs = 0;
+    r.f = pl->fP[d - 1];
+    r.tw = pl->ws + pl->Lo.twP64;
+    r.ncomp = 1;
+    r.d = d;
+    r.mode = ROW_R2C;
+    r.real_in = img_dev;
+    r.real_stride = P[d - 1];
+    r.imgmap = imgmap;
+    r.vmax = vmax;
+    r.scale = 1.0;
+    int rc = run_row(pl, r, true, FFTGAL_K_SETUP);
+    if (rc) return rc;
+    void *cur = W;
+    if (d == 3) {
+        PencilArgs b = base_pencil(pl, pl->fP[1], true, true);
+        b.pro = PRO_PLAIN;
+        b.epi = EPI_PLAIN;
+        b.ncomp = 1;
+        b.sgn = -1;
+        b.L_in = P[1];
+        b.L_out = D.L[1];
+        b.in = W;
+        b.out = U;
+        b.nb = D.Lh;
+        b.in_os = (long)P[1] * D.Lh;
+        b.in_ls = D.Lh;
+        b.out_os = (long)D.L[1] * D.Lh;
+        b.out_ls = D.Lh;
+        rc = run_pencil(pl, b, P[0], true, 8, FFTGAL_K_SETUP);
+        if (rc) return rc;
+        cur = U;
+    }
+    PencilArgs a = base_pencil(pl, pl->fP[0], true, true);
+    a.pro = PRO_PLAIN;
+    a.epi = EPI_WINDOW;
+    a.ncomp = 1;
+    a.sgn = -1;
+    a.L_in = P[0];
+    a.L_out = D.L[0];
+    a.in = cur;
+    void *dst = (cur == U) ? W : U;
+    a.out = dst;
+    a.Nh = D.Lh;
+    a.Nmid = (d == 3) ? D.L[1] : 0;
+    a.Pw[0] = P[0];
+    a.Pw[1] = P[1];
+    a.Pw[2] = d == 3 ? P[2] : 1;
+    a.winscale = 1.0 / (double)Ptot;
+    if (d == 3) {
+        a.nb = D.L[1] * D.Lh;
+        a.in_ls = a.out_ls = (long)D.L[1] * D.Lh;
+    } else {
+        a.nb = D.Lh;
+        a.in_ls = a.out_ls = D.Lh;
+    }
+    rc = run_pencil(pl, a, 1, true, 8, FFTGAL_K_SETUP);
+    if (rc) return rc;
+    *coef_out = dst;
+    return FFTGAL_OK;
+}
+
+bool chol_spd(const double *A, int d) {
+    double L[9] = {0};
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * d + j];
+            for (int k = 0; k < j; ++k) s -= L[i * d + k] * L[j * d + k];
+            if (i == j) {
+                if (!(s > 0.0) || !std::isfinite(s)) return false;
+                L[i * d + i] = std::sqrt(s);
+            } else {
+                L[i * d + j] = s / L[j * d + j];
+            }
+        }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            if (std::fabs(A[i * d + j] - A[j * d + i]) > 1e-12 * (std::fabs(A[i * d + j]) + std::fabs(A[j * d + i])))
+                return false;
+    return true;
+}
+
+bool inv_small(const double *A, int d, double *out) {
+    long double m[3][6];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < 2 * d; ++j) m[i][j] = j < d ? A[i * d + j] : (j - d == i ? 1.0L : 0.0L);
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < d; ++i)
+            if (fabsl(m[i][c]) > fabsl(m[piv][c])) piv = i;
+        if (m[piv][c] == 0.0L) return false;
+        if (piv != c)
+            for (int j = 0; j < 2 * d; ++j) std::swap(m[c][j], m[piv][j]);
+        const long double inv = 1.0L / m[c][c];
+        for (int j = 0; j < 2 * d; ++j) m[c][j] *= inv;
+        for (int i = 0; i < d; ++i)
+            if (i != c) {
+                const long double f = m[i][c];
+                for (int j = 0; j < 2 * d; ++j) m[i][j] -= f * m[c][j];
+            }
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) out[i * d + j] = (double)m[i][d + j];
+    return true;
+}
+
+bool is_iso(const double *A, int d, double *a) {
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            if (i != j && A[i * d + j] != 0.0) return false;
+    for (int i = 1; i < d; ++i)
+        if (A[i * d + i] != A[0]) return false;
+    *a = A[0];
+    return true;
+}
+
+double min_image(double x) { return x - std::nearbyint(x); }
+
+bool overlap(int d, int s1, const double *c1, const double *h1, int s2, const double *c2, const double *h2) {
+    double dc[3];
+    for (int a = 0; a < d; ++a) dc[a] = std::fabs(min_image(c1[a] - c2[a]));
+    if (s1 == FFTGAL_RECT && s2 == FFTGAL_RECT) {
+        for (int a = 0; a < d; ++a)
+            if (dc[a] >= 0.5 * (h1[a] + h2[a])) return false;
+        return true;
+    }
+    if (s1 == FFTGAL_CIRC && s2 == FFTGAL_CIRC) {
+        double s = 0;
+        for (int a = 0; a < d; ++a) s += dc[a] * dc[a];
+        return std::sqrt(s) < h1[0] + h2[0];
+    }
+    const double *hb = s1 == FFTGAL_RECT ? h1 : h2;
+    const double r = s1 == FFTGAL_CIRC ? h1[0] : h2[0];
+    double s = 0;
+    for (int a = 0; a < d; ++a) {
+        const double e = std::max(0.0, dc[a] - 0.5 * hb[a]);
+        s += e * e;
+    }
+    return std::sqrt(s) < r;
+}
+
+// ---- CG driver ---------------------------------------------------------------
+
+int enqueue_iteration(Plan *pl, int kind, CgStatus *st, void *x, bool fp64) {
+    const Dims &D = pl->D;
+    void *rows = nullptr;
+    int rc = inverse_passes(pl, fp64, kind, nullptr, 0, 1, true, st, &rows, FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV);
+    if (rc) return rc;
+    RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind);
+    r.status = st;
+    rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
+    if (rc) return rc;
+    int npq = 0;
+    rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.q, pl->ws + pl->Lo.p, 1.0 / (double)D.Mtot, st,
+                        pl->at<double>(pl->Lo.part_a), &npq, FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT);
+    if (rc) return rc;
+    {
+        Timed t(pl, FFTGAL_K_CG_SCALAR);
+        HIPCHECK(pl, launch_cg_alpha(st, pl->at<double>(pl->Lo.part_a), npq, pl->stream));
+    }
+    const int nc = pl->nc(kind);
+    {
+        Timed t(pl, FFTGAL_K_CG_UPDATE);
+        HIPCHECK(pl, launch_cg_update(x, pl->ws + pl->Lo.r, pl->ws + pl->Lo.p, pl->ws + pl->Lo.q, D.Ns, nc, D.Ns,
+                                      D.Nh, st, pl->at<double>(pl->Lo.part_c), kUpdateBlocks, fp64, pl->stream));
+    }
+    double *hist = pl->hist_on ? pl->hist(kind, pl->cur_alpha) : nullptr;
+    Timed t(pl, FFTGAL_K_CG_SCALAR);
+    HIPCHECK(pl, launch_cg_check(st, pl->at<double>(pl->Lo.part_c), kUpdateBlocks, hist, pl->stream));
+    return FFTGAL_OK;
+}
+
+int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info *info) {
+    const Dims &D = pl->D;
+    const bool fp64 = pl->fp64_iter();
+    CgStatus *st = pl->status(kind, alpha);
+    void *x = pl->xsol(kind, alpha);
+    pl->hist_on = maxit <= kMaxHist;
+    pl->cur_alpha = alpha;
+    const size_t es = fp64 ? 16 : 8;
+    const size_t vbytes = (size_t)pl->nc(kind) * D.Ns * es;
+    // right-hand side r_0 = -P^* F_M (A_M E) and ||A_M E||^2
+    void *rows = pl->ws + (D.d == 3 ? pl->Lo.T2 : pl->Lo.T1);
+    RowArgs r = base_row(pl, fp64, ROW_RHS, rows, kind);
+    for (int a = 0; a < 3; ++a) r.E[a] = (a == alpha) ? 1.0 : 0.0;
+    r.partial = pl->at<double>(pl->Lo.part_b);
+    int rc = run_row(pl, r, fp64, FFTGAL_K_RHS);
+    if (rc) return rc;
+    const int nload = row_grid(r);
+    int nrr = 0;
+    rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.r, nullptr, -1.0 / (double)D.Mtot, nullptr,
+                        pl->at<double>(pl->Lo.part_a), &nrr, FFTGAL_K_RHS, FFTGAL_K_RHS);
+    if (rc) return rc;
+    {
+        // The load sums |A_M E|^2 over grid points; (., .)_{R^{d x M}} divides by |M|.
+        Timed t(pl, FFTGAL_K_CG_SCALAR);
+        HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload,
+                                    rtol, (fp64 ? kFloor64 : kFloor32) / std::sqrt((double)D.Mtot), maxit,
+                                    pl->hist(kind, alpha), pl->stream));
+        HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
+        HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
+    }
+    // Iterations are enqueued in chunks without host synchronisation; after a
+    // chunk the host reads the status and sizes the next chunk from the
+    // observed per-iteration residual reduction, so that few no-op launches
+    // (kernels return at once when `done` is set) follow convergence.
+    CgStatus h{};
+    int chunk = 8;
+    int enq = 0;
+    int it_prev = 0;
+    double rr_prev = 0.0;
+    for (;;) {
+        const int todo = std::min(chunk, std::max(0, maxit - enq));
+        for (int i = 0; i < todo; ++i) {
+            rc = enqueue_iteration(pl, kind, st, x, fp64);
+            if (rc) return rc;
+        }
+        enq += todo;
+        HIPCHECK(pl, hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, pl->stream));
+        HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+        if (h.done || enq >= maxit) break;
+        const double target = std::max(h.tol2 * h.rr0, h.floor2);
+        int next = 2 * chunk;
+        if (it_prev > 0 && h.iter > it_prev && h.rr < rr_prev && h.rr > 0.0 && target > 0.0) {
+            const double rate = std::log(h.rr / rr_prev) / (h.iter - it_prev);  // < 0
+            const double remain = std::log(target / h.rr) / rate;
+            next = (int)std::ceil(1.1 * remain) + 1;
+        }
+        chunk = std::max(2, std::min(next, 64));
+        it_prev = h.iter;
+        rr_prev = h.rr;
+    }
+    fftgal_info inf{};
+    inf.iters = h.iter;
+    inf.converged = h.converged;
+    inf.res0 = std::sqrt(std::max(0.0, h.rr0));
+    inf.rel_res = h.rr0 > 0 ? std::sqrt(std::max(0.0, h.rr) / h.rr0) : 0.0;
+    pl->last_info[kind][alpha] = inf;
+    if (info) *info = inf;
+    pl->solved[kind][alpha] = true;
+    if (h.breakdown) return fail(pl, FFTGAL_EBREAKDOWN, "CG breakdown (non-SPD or non-finite material)");
+    if (!h.converged) return fail(pl, FFTGAL_ENOTCONV, "CG did not converge in %d iterations", maxit);
+    return FFTGAL_OK;
+}
+
+int solve_entry(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info *info) {
+    if (!pl) return FFTGAL_EINVAL;
+    if (!pl->have_mat) return fail(pl, FFTGAL_ESTATE, "no material set");
+    if (alpha < -1 || alpha >= pl->D.d) return fail(pl, FFTGAL_EINVAL, "alpha %d out of range", alpha);
+    if (!(rtol >= 0.0) || maxit < 0) return fail(pl, FFTGAL_EINVAL, "rtol must be >= 0 and maxit >= 0");
+    int worst = FFTGAL_OK;
+    const int a0 = alpha < 0 ? 0 : alpha;
+    const int a1 = alpha < 0 ? pl->D.d : alpha + 1;
+    for (int a = a0; a < a1; ++a) {
+        const int rc = run_solve(pl, kind, a, rtol, maxit, info ? info + (a - a0) : nullptr);
+        if (rc == FFTGAL_EDEVICE || rc == FFTGAL_EINVAL) return rc;
+        if (rc != FFTGAL_OK && worst == FFTGAL_OK) worst = rc;
+    }
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fftgal_workspace_bytes_p(int d, const int32_t *N, int precision, const int32_t *P) {
+    Dims D;
+    if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
+    if (!make_dims(d, N, P, &D)) return 0;
+    return make_layout(D, precision).total;
+}
+
+size_t fftgal_workspace_bytes(int d, const int32_t *N, int precision) {
+    return fftgal_workspace_bytes_p(d, N, precision, nullptr);
+}
+
+int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace, size_t bytes,
+                void *hip_stream) {
+    if (out == nullptr) return fail(nullptr, FFTGAL_EINVAL, "out is NULL");
+    *out = nullptr;
+    Dims D;
+    if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
+        return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
+    if (!make_dims(d, N, nullptr, &D))
+        return fail(nullptr, FFTGAL_EINVAL, "d must be 2 or 3 and every N odd and >= 1");
+    if (dev_workspace == nullptr || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))
+        return fail(nullptr, FFTGAL_EINVAL, "workspace must be a 256-byte aligned device pointer");
+    Layout Lo = make_layout(D, precision);
+    if (bytes < Lo.total)
+        return fail(nullptr, FFTGAL_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, Lo.total);
+    // a larger workspace provisions voxel images up to the largest P that fits
+    auto *pl = new Plan();
+    pl->D = D;
+    pl->Lo = Lo;
+    pl->precision = precision;
+    pl->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    pl->ws = reinterpret_cast<char *>(dev_workspace);
+    pl->ws_bytes = bytes;
+    std::vector<double> tab;
+    size_t entry = 0;
+    for (int a = 0; a < d; ++a) {
+        build_fft(D.M[a], entry, tab, &pl->fM[a]);
+        entry = tab.size() / 2;
+    }
+    std::vector<float> tab32(tab.begin(), tab.end());
+    hipError_t e = hipMemcpyAsync(pl->ws + Lo.tw64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl->ws + Lo.tw32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) {
+        delete pl;
+        return fail(nullptr, FFTGAL_EDEVICE, "twiddle upload failed: %s", hipGetErrorString(e));
+    }
+    *out = pl;
+    return FFTGAL_OK;
+}
+
+int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
+    if (!pl) return FFTGAL_EINVAL;
+    if (!m) return fail(pl, FFTGAL_EINVAL, "material is NULL");
+    const Dims &D = pl->D;
+    const int d = D.d;
+    pl->have_mat = false;
+    for (auto &row : pl->solved)
+        for (bool &s : row) s = false;
+    double *gA = pl->at<double>(pl->Lo.gA64);
+    double *gB = pl->at<double>(pl->Lo.gB64);
+    int rc = FFTGAL_OK;
+    if (m->kind == FFTGAL_INCLUSIONS) {
+        if (!chol_spd(m->A0, d)) return fail(pl, FFTGAL_EINVAL, "A0 is not symmetric positive definite");
+        const int n = m->n_incl;
+        if (n < 0 || n > 100000) return fail(pl, FFTGAL_EINVAL, "n_incl out of range");
+        if (n > 0 && (!m->shape || !m->center || !m->size || !m->A_in))
+            return fail(pl, FFTGAL_EINVAL, "inclusion arrays must not be NULL");
+        std::vector<InclDev> inc(n);
+        for (int i = 0; i < n; ++i) {
+            const int s = m->shape[i];
+            if (s != FFTGAL_RECT && s != FFTGAL_CIRC) return fail(pl, FFTGAL_EINVAL, "inclusion %d: bad shape", i);
+            if (s == FFTGAL_CIRC && d != 2) return fail(pl, FFTGAL_EINVAL, "inclusion %d: CIRC needs d = 2", i);
+            inc[i].shape = s;
+            for (int a = 0; a < 3; ++a) {
+                inc[i].c[a] = a < d ? m->center[i * d + a] : 0.0;
+                inc[i].h[a] = a < d ? m->size[i * d + a] : 0.0;
+            }
+            for (int a = 0; a < d; ++a)
+                if (!std::isfinite(inc[i].c[a])) return fail(pl, FFTGAL_EINVAL, "inclusion %d: bad centre", i);
+            if (s == FFTGAL_RECT) {
+                for (int a = 0; a < d; ++a)
+                    if (!(inc[i].h[a] > 0.0 && inc[i].h[a] <= 1.0))
+                        return fail(pl, FFTGAL_EINVAL, "inclusion %d: side must be in (0, 1]", i);
+            } else if (!(inc[i].h[0] > 0.0 && inc[i].h[0] <= 0.5)) {
+                return fail(pl, FFTGAL_EINVAL, "inclusion %d: radius must be in (0, 1/2]", i);
+            }
+            if (!chol_spd(m->A_in + (size_t)i * d * d, d))
+                return fail(pl, FFTGAL_EINVAL, "inclusion %d: A_in is not symmetric positive definite", i);
+        }
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (overlap(d, inc[i].shape, inc[i].c, inc[i].h, inc[j].shape, inc[j].c, inc[j].h))
+                    return fail(pl, FFTGAL_EINVAL, "inclusions %d and %d overlap", i, j);
+        bool same = true;
+        for (int i = 1; i < n && same; ++i)
+            for (int k = 0; k < d * d; ++k)
+                if (m->A_in[(size_t)i * d * d + k] != m->A_in[k]) same = false;
+        double A0inv[9];
+        inv_small(m->A0, d, A0inv);
+        double wA0 = 0.0, wB0 = 0.0;
+        std::vector<double> wA(n), wB(n);
+        if (same) {
+            pl->separate_gB = false;
+            std::memset(pl->DA, 0, sizeof pl->DA);
+            std::memset(pl->DB, 0, sizeof pl->DB);
+            for (int k = 0; k < d * d; ++k) {
+                pl->A0[k] = m->A0[k];
+                pl->B0[k] = A0inv[k];
+            }
+            if (n > 0) {
+                double Ainv[9];
+                inv_small(m->A_in, d, Ainv);
+                for (int k = 0; k < d * d; ++k) {
+                    pl->DA[k] = m->A_in[k] - m->A0[k];
+                    pl->DB[k] = Ainv[k] - A0inv[k];
+                }
+            }
+            for (int i = 0; i < n; ++i) wA[i] = wB[i] = 1.0;
+        } else {
+            double a0;
+            if (!is_iso(m->A0, d, &a0))
+                return fail(pl, FFTGAL_EINVAL, "different inclusion phases need isotropic A0 and A_in");
+            pl->separate_gB = true;
+            wA0 = a0;
+            wB0 = 1.0 / a0;
+            for (int i = 0; i < n; ++i) {
+                double ai;
+                if (!is_iso(m->A_in + (size_t)i * d * d, d, &ai))
+                    return fail(pl, FFTGAL_EINVAL, "different inclusion phases need isotropic A0 and A_in");
+                wA[i] = ai - a0;
+                wB[i] = 1.0 / ai - 1.0 / a0;
+            }
+            for (int k = 0; k < 9; ++k) pl->A0[k] = pl->B0[k] = pl->DA[k] = pl->DB[k] = 0.0;
+            for (int a = 0; a < d; ++a) pl->DA[a * d + a] = pl->DB[a * d + a] = 1.0;
+        }
+        // device inclusion table lives at the end of the W scratch region
+        void *U = pl->ws + pl->Lo.T2;
+        const size_t inc_bytes = (size_t)std::max(n, 1) * sizeof(InclDev);
+        const size_t t1_bytes = pl->Lo.T2 - pl->Lo.T1;
+        if (inc_bytes + 4096 > t1_bytes / 2) return fail(pl, FFTGAL_EINVAL, "too many inclusions for this plan");
+        InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1 + (t1_bytes - inc_bytes - 256) / 256 * 256);
+        for (int pass = 0; pass < (pl->separate_gB ? 2 : 1); ++pass) {
+            for (int i = 0; i < n; ++i) inc[i].w = pass == 0 ? wA[i] : wB[i];
+            HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
+                                        pl->stream));
+            {
+                Timed t(pl, FFTGAL_K_SETUP);
+                HIPCHECK(pl, launch_incl_coeff(U, d, D.L[0], D.L[1], D.Lh, inc_dev, n, pass == 0 ? wA0 : wB0,
+                                               pl->stream));
+            }
+            rc = series_to_field(pl, U, pass == 0 ? gA : gB);
+            if (rc) return rc;
+            HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // host table reused
+        }
+    } else if (m->kind == FFTGAL_VOXELS) {
+        long Ptot = 1;
+        for (int a = 0; a < d; ++a) {
+            if (!is_smooth_odd(m->P[a]))
+                return fail(pl, FFTGAL_EINVAL, "voxel resolution P[%d] = %d is not an odd 3,5,7-smooth integer", a,
+                            m->P[a]);
+            Ptot *= m->P[a];
+        }
+        if (!m->image) return fail(pl, FFTGAL_EINVAL, "image is NULL");
+        // the image and its R2C rows must fit the scratch regions of this plan
+        const size_t ubytes = pl->Lo.r - pl->Lo.T2;
+        const size_t wbytes = pl->Lo.T2 - pl->Lo.T1;
+        size_t need_u = (size_t)Ptot * 8, need_w = (size_t)(Ptot / m->P[d - 1]) * D.Lh * 16;
+        if (d == 3) {
+            need_u = std::max(need_u, (size_t)m->P[0] * D.L[1] * D.Lh * 16);
+            need_w = std::max(need_w, (size_t)D.L[0] * D.L[1] * D.Lh * 16);
+        }
+        if (need_u > ubytes || need_w > wbytes)
+            return fail(pl, FFTGAL_ENOMEM, "voxel image too large for this workspace (use fftgal_workspace_bytes_p)");
+        // twiddles for the image axes
+        std::vector<double> tab;
+        size_t entry = 0;
+        FftDesc fP[3];
+        for (int a = 0; a < d; ++a) {
+            build_fft(m->P[a], entry, tab, &fP[a]);
+            entry = tab.size() / 2;
+        }
+        if (entry > pl->Lo.twP_len) return fail(pl, FFTGAL_ENOMEM, "voxel resolution exceeds the plan's provision");
+        for (int a = 0; a < d; ++a) {
+            pl->Pcur[a] = m->P[a];
+            pl->fP[a] = fP[a];
+        }
+        std::vector<float> tab32(tab.begin(), tab.end());
+        HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->Lo.twP64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice,
+                                    pl->stream));
+        HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->Lo.twP32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice,
+                                    pl->stream));
+        // the image is read from the caller's device buffer, or from a staging
+        // copy at the start of the U scratch region (re-uploaded per pass,
+        // since the transforms overwrite U)
+        double *staging = pl->at<double>(pl->Lo.T2);
+        const double *img = m->image_device ? m->image : staging;
+        auto upload = [&]() -> int {
+            if (!m->image_device)
+                HIPCHECK(pl, hipMemcpyAsync(staging, m->image, (size_t)Ptot * 8, hipMemcpyHostToDevice, pl->stream));
+            return FFTGAL_OK;
+        };
+        if ((rc = upload())) return rc;
+        double stats[4];
+        {
+            Timed t(pl, FFTGAL_K_SETUP);
+            HIPCHECK(pl, launch_image_stats(img, Ptot, pl->at<double>(pl->Lo.part_a), pl->at<double>(pl->Lo.gram),
+                                            pl->stream));
+        }
+        HIPCHECK(pl, hipMemcpyAsync(stats, pl->at<double>(pl->Lo.gram), sizeof stats, hipMemcpyDeviceToHost,
+                                    pl->stream));
+        HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+        if (stats[2] != 0.0)
+            return fail(pl, FFTGAL_EINVAL, "%.0f voxels are not positive finite conductivities", stats[2]);
+        const double vmin = stats[0], vmax = stats[1];
+        const bool two = stats[3] == 0.0;
+        std::memset(pl->DA, 0, sizeof pl->DA);
+        std::memset(pl->DB, 0, sizeof pl->DB);
+        std::memset(pl->A0, 0, sizeof pl->A0);
+        std::memset(pl->B0, 0, sizeof pl->B0);
+        pl->separate_gB = !two;
+        if (two) {
+            for (int a = 0; a < d; ++a) {
+                pl->A0[a * d + a] = vmin;
+                pl->DA[a * d + a] = vmax - vmin;
+                pl->B0[a * d + a] = 1.0 / vmin;
+                pl->DB[a * d + a] = 1.0 / vmax - 1.0 / vmin;
+            }
+        } else {
+            for (int a = 0; a < d; ++a) pl->DA[a * d + a] = pl->DB[a * d + a] = 1.0;
+        }
+        const int npass = two ? 1 : 2;
+        for (int pass = 0; pass < npass; ++pass) {
+            if (pass > 0 && (rc = upload())) return rc;
+            const int map = two ? (vmax == vmin ? 3 : 1) : (pass == 0 ? 0 : 2);
+            void *coef = nullptr;
+            rc = voxel_series(pl, img, map, vmax, &coef);
+            if (rc) return rc;
+            rc = series_to_field(pl, coef, pass == 0 ? gA : gB);
+            if (rc) return rc;
+        }
+    } else {
+        return fail(pl, FFTGAL_EINVAL, "unknown material kind %d", m->kind);
+    }
+    if (!pl->fp64_iter()) {
+        Timed t(pl, FFTGAL_K_SETUP);
+        HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gA32), gA, D.Mtot, pl->stream));
+        if (pl->separate_gB)
+            HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gB32), gB, D.Mtot, pl->stream));
+    }
+    HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+    pl->have_mat = true;
+    return FFTGAL_OK;
+}
+
+int fftgal_solve_primal(struct fftgal_plan *pl, int alpha, double rtol, int maxit, fftgal_info *info) {
+    return solve_entry(pl, KIND_E, alpha, rtol, maxit, info);
+}
+
+int fftgal_solve_dual(struct fftgal_plan *pl, int alpha, double rtol, int maxit, fftgal_info *info) {
+    return solve_entry(pl, KIND_J, alpha, rtol, maxit, info);
+}
+
+int fftgal_bounds(struct fftgal_plan *pl, double *upper, double *lower, double *gap) {
+    if (!pl) return FFTGAL_EINVAL;
+    const Dims &D = pl->D;
+    const int d = D.d;
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < d; ++a)
+            if (!pl->solved[k][a]) return fail(pl, FFTGAL_ESTATE, "bounds need all %d primal and dual solves", d);
+    double gram[2][9];
+    for (int kind = 0; kind < 2; ++kind) {
+        const int nc = pl->nc(kind);
+        const void *xs = pl->xsol(kind, 0);
+        long st_ss = (long)D.nc_max * D.Ns;
+        if (!pl->fp64_iter()) {
+            // FP64 copies of the FP32 iterates (component-wise exact)
+            double *x64 = pl->at<double>(pl->Lo.xsol64);
+            Timed t(pl, FFTGAL_K_BOUNDS);
+            for (int a = 0; a < d; ++a)
+                HIPCHECK(pl, launch_convert_f2d(x64 + (size_t)a * D.nc_max * D.Ns * 2,
+                                                reinterpret_cast<const float *>(pl->xsol(kind, a)),
+                                                (size_t)nc * D.Ns * 2, pl->stream));
+            xs = x64;
+        } else {
+            st_ss = (long)(pl->vec_bytes() / 16);
+        }
+        void *rows = nullptr;
+        int rc = inverse_passes(pl, true, kind, xs, st_ss, d, false, nullptr, &rows, FFTGAL_K_BOUNDS,
+                                FFTGAL_K_BOUNDS);
+        if (rc) return rc;
+        RowArgs r = base_row(pl, true, ROW_GRAM, rows, kind);
+        r.ncomp = d * d;
+        r.partial = pl->at<double>(pl->Lo.part_b);
+        rc = run_row(pl, r, true, FFTGAL_K_BOUNDS);
+        if (rc) return rc;
+        Timed t(pl, FFTGAL_K_BOUNDS);
+        HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->Lo.part_b), row_grid(r),
+                                         d * d, pl->stream));
+        HIPCHECK(pl, hipMemcpyAsync(gram[kind], pl->at<double>(pl->Lo.gram), d * d * 8, hipMemcpyDeviceToHost,
+                                    pl->stream));
+        HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+        for (int i = 0; i < d * d; ++i) gram[kind][i] /= (double)D.Mtot;
+    }
+    double up[9], bh[9], lo[9];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            up[i * d + j] = 0.5 * (gram[0][i * d + j] + gram[0][j * d + i]);
+            bh[i * d + j] = 0.5 * (gram[1][i * d + j] + gram[1][j * d + i]);
+        }
+    if (!inv_small(bh, d, lo)) return fail(pl, FFTGAL_EBREAKDOWN, "dual Gram matrix is singular");
+    for (int i = 0; i < d; ++i)
+        for (int j = i + 1; j < d; ++j) lo[i * d + j] = lo[j * d + i] = 0.5 * (lo[i * d + j] + lo[j * d + i]);
+    if (upper) std::memcpy(upper, up, sizeof(double) * d * d);
+    if (lower) std::memcpy(lower, lo, sizeof(double) * d * d);
+    if (gap) {
+        double g = 0;
+        for (int i = 0; i < d; ++i) g += up[i * d + i] - lo[i * d + i];
+        *gap = 0.5 * g;
+    }
+    return FFTGAL_OK;
+}
+
+int fftgal_set_timing(struct fftgal_plan *pl, int enable) {
+    if (!pl) return FFTGAL_EINVAL;
+    pl->timing = enable != 0;
+    return FFTGAL_OK;
+}
+
+int fftgal_read_timing(struct fftgal_plan *pl, double *ms, int32_t *count) {
+    if (!pl) return FFTGAL_EINVAL;
+    HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+    for (const auto &e : pl->evs) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e.a, e.b) == hipSuccess) {
+            pl->t_ms[e.cls] += t;
+            pl->t_cnt[e.cls] += 1;
+        }
+        pl->pool.push_back(e.a);
+        pl->pool.push_back(e.b);
+    }
+    pl->evs.clear();
+    for (int c = 0; c < FFTGAL_K_COUNT; ++c) {
+        if (ms) ms[c] = pl->t_ms[c];
+        if (count) count[c] = pl->t_cnt[c];
+        pl->t_ms[c] = 0.0;
+        pl->t_cnt[c] = 0;
+    }
+    return FFTGAL_OK;
+}
+
+int fftgal_destroy(struct fftgal_plan *pl) {
+    if (!pl) return FFTGAL_OK;
+    if (!pl->evs.empty()) (void)hipStreamSynchronize(pl->stream);
+    for (const auto &e : pl->evs) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (hipEvent_t e : pl->pool) (void)hipEventDestroy(e);
+    delete pl;
+    return FFTGAL_OK;
+}
+
+const char *fftgal_last_error(const struct fftgal_plan *pl) {
+    return pl ? pl->err.c_str() : g_plan_error.c_str();
+}
+
+int fftgal_grid_size(const struct fftgal_plan *pl, int axis) {
+    if (!pl || axis < 0 || axis >= pl->D.d) return 0;
+    return pl->D.M[axis];
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Internal declarations shared by the host library (fftgal.cpp) and the HIP
+// kernels (fftgal_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fftgal {
+
+constexpr int kThreads = 256;   // work-group size of every kernel
+constexpr int kMaxStages = 16;  // radix-3/5/7 stages per FFT length
+
+// Mixed-radix factorisation of one FFT length and where its twiddles live.
+// Stage s has radix radix[s] and twiddles w(q, k) = exp(-2 pi i q k / (p r)),
+// q = 1..r-1, k = 0..p-1 (p = product of the earlier radices), stored at
+// twoff[s] + (q - 1) * p + k in the plan's twiddle tables.
+struct FftDesc {
+    int n;
+    int nst;
+    int radix[kMaxStages];
+    int twoff[kMaxStages];
+};
+
+// Device-resident state of one CG solve (Remark CG), advanced by the scalar
+// kernels; every kernel of an iteration returns at once when `done` is set.
+struct CgStatus {
+    double rr;       // (r_k, r_k)
+    double rr0;      // (r_0, r_0)
+    double pq;       // (p_k, K p_k)
+    double alpha;    // rr / pq
+    double beta;     // rr_{k+1} / rr_k (0 before the first step)
+    double tol2;     // rtol^2
+    double floor2;   // (floor * ||A_M E||)^2
+    double load2;    // ||A_M E||^2
+    int32_t iter;
+    int32_t maxit;
+    int32_t done;
+    int32_t converged;
+    int32_t breakdown;
+    int32_t pad;
+};
+
+enum Prologue { PRO_PLAIN = 0, PRO_EXPAND = 1 };
+enum Epilogue { EPI_PLAIN = 0, EPI_PROJECT = 1, EPI_WINDOW = 2 };
+enum RowMode { ROW_OPER = 0, ROW_RHS = 1, ROW_GRAM = 2, ROW_C2R = 3, ROW_R2C = 4 };
+enum SolveKind { KIND_E = 0, KIND_J = 1 };
+
+// A batched 1D DFT along one strided axis ("pencils"), with optional
+// prologue/epilogue.  Element (component c, outer o, position l, batch b) of
+// an operand lives at base + c*cs + o*os + l*ls + b (complex units).  Stored
+// position l of a length-L operand holds frequency wrap_L(l) (or grid point l
+// when L equals the transform length n), placed in the transform at
+// wrap_L(l) mod n.
+struct PencilArgs {
+    const void *in;
+    void *out;
+    long in_cs, out_cs, in_os, out_os, in_ls, out_ls;
+    int L_in, L_out;
+    int nb;       // batch extent (contiguous)
+    int B;        // pencils per work-group
+    int ncomp;    // transformed components (per solution)
+    int sgn;      // +1: inverse DFT (omega^{+mk}); -1: forward
+    double scale; // applied to every output value
+    FftDesc f;
+    const void *tw;
+    int pro, epi;
+    // frequency decoding for EXPAND / PROJECT / WINDOW
+    int d, kind, nc, Nmid, Nh;
+    // EXPAND: state vectors (component stride st_cs, solution stride st_ss)
+    const void *st_r;
+    void *st_p;
+    const void *st_x;
+    long st_cs, st_ss;
+    int nsol;
+    int update_p;
+    const CgStatus *status;
+    // PROJECT
+    void *st_q;
+    const void *st_dot;
+    double *partial;
+    // WINDOW: sinc window of a P-voxel image, times 1/|P|
+    int Pw[3];
+    double winscale;
+};
+
+// Batched real transforms along the last (contiguous, half-spectrum) axis,
+// two rows packed per complex transform, with the material multiply fused.
+struct RowArgs {
+    void *data;       // complex rows: comp stride cs, row stride Nh_row
+    long cs;
+    int nrows;
+    int Nh_row;
+    int n;
+    FftDesc f;
+    const void *tw;
+    int ncomp;
+    int d;
+    int mode;
+    int RP;           // row pairs per work-group
+    const void *g;    // material field g (M^d, precision of the kernel)
+    double A0[9];     // A(x) = A0 + g(x) D
+    double D[9];
+    double E[3];      // load for ROW_RHS
+    void *real_out;   // ROW_C2R output rows (length n)
+    const void *real_in;  // ROW_R2C input rows (length n)
+    long real_stride;
+    int imgmap;       // ROW_R2C: voxel value mapping (see map_voxel)
+    double vmax;
+    double scale;
+    double *partial;  // RHS: |A_M E|^2 sums; GRAM: d*d sums per work-group
+    const CgStatus *status;
+};
+
+struct InclDev {
+    int shape;
+    double c[3];
+    double h[3];
+    double w;  // weight of this inclusion's indicator
+};
+
+// ---- launchers (fftgal_kernels.hip) ----
+size_t pencil_lds_bytes(const PencilArgs &a, bool fp64);
+size_t row_lds_bytes(const RowArgs &a, bool fp64);
+hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s);
+hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s);
+int row_grid(const RowArgs &a);
+int pencil_grid_x(const PencilArgs &a);
+
+hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part,
+                          int n_load, double tol, double floor_rel, int maxit, double *hist,
+                          hipStream_t s);
+hipError_t launch_cg_alpha(CgStatus *st, const double *pq_part, int n, hipStream_t s);
+hipError_t launch_cg_check(CgStatus *st, const double *rr_part, int n, double *hist, hipStream_t s);
+hipError_t launch_cg_update(void *x, void *r, const void *p, const void *q, long n_per_comp, int nc,
+                            long cs, int Nh, const CgStatus *st, double *partial, int nblocks,
+                            bool fp64, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_convert_f2d(double *dst, const float *src, size_t n, hipStream_t s);
+hipError_t launch_convert_d2f(float *dst, const double *src, size_t n, hipStream_t s);
+hipError_t launch_sum_partials(double *out, const double *part, int nparts, int nvals,
+                               hipStream_t s);
+hipError_t launch_image_stats(const double *img, long n, double *part, double *out, hipStream_t s);
+hipError_t launch_incl_coeff(void *out, int d, int L1, int L2, int Lh, const InclDev *incl, int n_incl,
+                             double w0, hipStream_t s);
+
+}  // namespace fftgal

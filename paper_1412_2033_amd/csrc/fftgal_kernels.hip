@@ -1,0 +1,1010 @@
+// HIP kernels for gfx950: the double-grid Ga operator (Algorithm 2) as
+// fused FFT passes, conjugate-gradient vector kernels, FP64 energy quadrature,
+// and the material setup (eq. MBA_GA, eq. inclcomp_formula, Lemma grid_compos).
+//
+// Transforms are mixed-radix (3, 5, 7) self-sorting Stockham DFTs staged in
+// LDS; every grid size is odd (M >= 2N-1 odd and 3,5,7-smooth), so no radix 2
+// and no Nyquist frequency ever occurs.
+#include "fftgal_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+namespace fftgal {
+namespace {
+
+template <typename T> struct VecOf;
+template <> struct VecOf<float> { using type = float2; };
+template <> struct VecOf<double> { using type = double2; };
+
+template <typename T> using Vt = typename VecOf<T>::type;
+
+template <typename T>
+__device__ __forceinline__ Vt<T> mk(T a, T b) {
+    Vt<T> v;
+    v.x = a;
+    v.y = b;
+    return v;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) {
+    a.x += b.x;
+    a.y += b.y;
+    return a;
+}
+template <typename V> __device__ __forceinline__ V csub(V a, V b) {
+    a.x -= b.x;
+    a.y -= b.y;
+    return a;
+}
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+// cos(2 pi j / R) and sin(2 pi j / R), 0 <= j <= (R - 1) / 2.
+template <int R> __device__ constexpr double ccos(int j);
+template <int R> __device__ constexpr double csin(int j);
+template <> __device__ constexpr double ccos<3>(int j) { return j == 0 ? 1.0 : -0.5; }
+template <> __device__ constexpr double csin<3>(int j) {
+    return j == 0 ? 0.0 : 0.86602540378443864676372317075294;
+}
+template <> __device__ constexpr double ccos<5>(int j) {
+    return j == 0 ? 1.0 : j == 1 ? 0.30901699437494742410229341718282 : -0.80901699437494742410229341718282;
+}
+template <> __device__ constexpr double csin<5>(int j) {
+    return j == 0 ? 0.0 : j == 1 ? 0.95105651629515357211643933337938 : 0.58778525229247312916870595463907;
+}
+template <> __device__ constexpr double ccos<7>(int j) {
+    return j == 0 ? 1.0
+         : j == 1 ? 0.62348980185873353052500488400424
+         : j == 2 ? -0.22252093395631440428890256449680
+                  : -0.90096886790241912623610231950745;
+}
+template <> __device__ constexpr double csin<7>(int j) {
+    return j == 0 ? 0.0
+         : j == 1 ? 0.78183148246802980870844452667406
+         : j == 2 ? 0.97492791218182360701813168299393
+                  : 0.43388373911755812047576833284836;
+}
+
+// In-register DFT of odd length R: U[m] = sum_q u[q] exp(sg 2 pi i q m / R),
+// computed from the symmetric and antisymmetric pair sums u[q] +- u[R-q].
+template <typename T, int R>
+__device__ __forceinline__ void dft(Vt<T> *u, T sg) {
+    constexpr int H = (R - 1) / 2;
+    Vt<T> sp[H], sm[H];
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+        sp[q - 1] = cadd(u[q], u[R - q]);
+        sm[q - 1] = csub(u[q], u[R - q]);
+    }
+    const Vt<T> u0 = u[0];
+    Vt<T> tot = u0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) tot = cadd(tot, sp[q]);
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+        Vt<T> a = u0;
+        Vt<T> b = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int q = 1; q <= H; ++q) {
+            const int j = (q * m) % R;
+            const T cv = T(j <= H ? ccos<R>(j) : ccos<R>(R - j));
+            const T sv = T(j <= H ? csin<R>(j) : -csin<R>(R - j));
+            a.x += cv * sp[q - 1].x;
+            a.y += cv * sp[q - 1].y;
+            b.x += sv * sm[q - 1].x;
+            b.y += sv * sm[q - 1].y;
+        }
+        b.x *= sg;
+        b.y *= sg;
+        u[m] = mk<T>(a.x - b.y, a.y + b.x);
+        u[R - m] = mk<T>(a.x + b.y, a.y - b.x);
+    }
+    u[0] = tot;
+}
+
+// One Stockham stage of radix R over nb independent transforms of length n.
+// Butterfly i (k = i mod p) reads positions i + q n/R, applies the twiddles
+// exp(sg 2 pi i q k / (p R)), a length-R DFT, and writes positions
+// (i - k) R + k + q p.  ROWL: element (pos, b) at b*n + pos, else pos*nb + b.
+template <typename T, int R, bool ROWL>
+__device__ __forceinline__ void stage(const Vt<T> *X, Vt<T> *Y, int n, int p, int nb,
+                                      const Vt<T> *__restrict__ tw, T sg) {
+    const int Tq = n / R;
+    const int total = Tq * nb;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int i, b;
+        if (ROWL) {
+            b = idx / Tq;
+            i = idx - b * Tq;
+        } else {
+            i = idx / nb;
+            b = idx - i * nb;
+        }
+        const int k = i % p;
+        Vt<T> u[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int pos = i + q * Tq;
+            u[q] = ROWL ? X[b * n + pos] : X[pos * nb + b];
+        }
+        if (p > 1) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                Vt<T> w = tw[(q - 1) * p + k];
+                w.y *= -sg;  // table holds exp(-2 pi i q k / (p R))
+                u[q] = cmul(u[q], w);
+            }
+        }
+        dft<T, R>(u, sg);
+        const int j = (i - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int pos = j + q * p;
+            if (ROWL)
+                Y[b * n + pos] = u[q];
+            else
+                Y[pos * nb + b] = u[q];
+        }
+    }
+}
+
+// Full transform in LDS, ping-ponging between A and Bf; returns the buffer
+// holding the result.  Must be called by every thread of the work-group.
+template <typename T, bool ROWL>
+__device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
+    Vt<T> *X = A;
+    Vt<T> *Y = Bf;
+    int p = 1;
+    for (int s = 0; s < f.nst; ++s) {
+        const int r = f.radix[s];
+        const Vt<T> *t = tw + f.twoff[s];
+        if (r == 3)
+            stage<T, 3, ROWL>(X, Y, f.n, p, nb, t, sg);
+        else if (r == 5)
+            stage<T, 5, ROWL>(X, Y, f.n, p, nb, t, sg);
+        else
+            stage<T, 7, ROWL>(X, Y, f.n, p, nb, t, sg);
+        __syncthreads();
+        Vt<T> *tmp = X;
+        X = Y;
+        Y = tmp;
+        p *= r;
+    }
+    return X;
+}
+
+// Deterministic work-group sum (fixed shuffle tree, then waves in order);
+// the result is valid in thread 0.
+__device__ double block_sum(double v) {
+    __shared__ double red[kThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ int wrapi(int i, int L) { return i < (L + 1) / 2 ? i : i - L; }
+__device__ __forceinline__ int posmod(int k, int n) {
+    int r = k % n;
+    return r < 0 ? r + n : r;
+}
+
+// Orthonormal basis t_a(k) (a < nc) of the admissible directions at frequency k:
+// primal (E_N): k/|k|; dual (J_N), d = 2: R k/|k| with R the rotation by +90
+// degrees; d = 3: t1 = k x e_j / |k x e_j| with j the axis of smallest |k_j|
+// (lowest index on ties) and t2 = s(k) k/|k| x t1 with s(k) the sign of the
+// first non-zero k_j.  Every t_a is odd in k, so a field i sum_a t_a(k) c_a(k)
+// is real exactly when each c_a is Hermitian.  Returns 0 at k = 0.
+template <typename T>
+__device__ __forceinline__ int basis(int d, int kind, int k1, int k2, int k3, T t[2][3]) {
+    const T a = T(k1), b = T(k2), c = T(d == 3 ? k3 : 0);
+    const T nn = a * a + b * b + c * c;
+    if (nn == T(0)) return 0;
+    const T inv = T(1) / sqrt(nn);
+    const T h1 = a * inv, h2 = b * inv, h3 = c * inv;
+    if (kind == KIND_E) {
+        t[0][0] = h1;
+        t[0][1] = h2;
+        t[0][2] = h3;
+        return 1;
+    }
+    if (d == 2) {
+        t[0][0] = -h2;
+        t[0][1] = h1;
+        t[0][2] = T(0);
+        return 1;
+    }
+    const int ab1 = k1 < 0 ? -k1 : k1, ab2 = k2 < 0 ? -k2 : k2, ab3 = k3 < 0 ? -k3 : k3;
+    T u1, u2, u3;
+    if (ab1 <= ab2 && ab1 <= ab3) {  // k x e_1
+        u1 = T(0);
+        u2 = c;
+        u3 = -b;
+    } else if (ab2 <= ab3) {  // k x e_2
+        u1 = -c;
+        u2 = T(0);
+        u3 = a;
+    } else {  // k x e_3
+        u1 = b;
+        u2 = -a;
+        u3 = T(0);
+    }
+    const T un = T(1) / sqrt(u1 * u1 + u2 * u2 + u3 * u3);
+    u1 *= un;
+    u2 *= un;
+    u3 *= un;
+    const T s = (k1 != 0) ? (k1 > 0 ? T(1) : T(-1)) : (k2 != 0) ? (k2 > 0 ? T(1) : T(-1)) : (k3 > 0 ? T(1) : T(-1));
+    t[0][0] = u1;
+    t[0][1] = u2;
+    t[0][2] = u3;
+    t[1][0] = s * (h2 * u3 - h3 * u2);
+    t[1][1] = s * (h3 * u1 - h1 * u3);
+    t[1][2] = s * (h1 * u2 - h2 * u1);
+    return 2;
+}
+
+__device__ __forceinline__ double sinc_pi(double x) {
+    return x == 0.0 ? 1.0 : sinpi(x) / (M_PI * x);
+}
+
+// ---------------------------------------------------------------------------
+// Pencil pass: batched DFT along a strided axis.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
+    using V = Vt<T>;
+    if (a.status != nullptr && a.status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    const int n = a.f.n;
+    const int B = a.B;
+    V *bufA = reinterpret_cast<V *>(smem_raw);
+    V *bufB = bufA + (size_t)n * B;
+    V *acc = bufB + (size_t)n * B;
+    const int b0 = blockIdx.x * B;
+    const int o = blockIdx.y;
+    const int nbw = min(B, a.nb - b0);
+    const V *tw = reinterpret_cast<const V *>(a.tw);
+    const T sg = T(a.sgn);
+    const T scale = T(a.scale);
+    const V *in = reinterpret_cast<const V *>(a.in);
+    V *out = reinterpret_cast<V *>(a.out);
+    const V zero = mk<T>(T(0), T(0));
+
+    auto freq = [&](int l, int L, int b, int *k1, int *k2, int *k3) {
+        *k1 = wrapi(l, L);
+        if (a.d == 3) {
+            *k2 = wrapi(b / a.Nh, a.Nmid);
+            *k3 = b % a.Nh;
+        } else {
+            *k2 = b % a.Nh;
+            *k3 = 0;
+        }
+    };
+
+    if (a.pro == PRO_EXPAND) {
+        // c_a -> e_alpha = i sum_a t_a(k)_alpha c_a on Z_N, zero-padded to n.
+        const V *sr = reinterpret_cast<const V *>(a.st_r);
+        V *sp = reinterpret_cast<V *>(a.st_p);
+        const V *sx = reinterpret_cast<const V *>(a.st_x);
+        const T beta = (a.update_p && a.status) ? T(a.status->beta) : T(0);
+        for (int s = 0; s < a.nsol; ++s) {
+            for (int idx = threadIdx.x; idx < a.nc * a.L_in * B; idx += blockDim.x) {
+                const int bb = idx % B;
+                const int l = (idx / B) % a.L_in;
+                const int c = idx / (B * a.L_in);
+                V v = zero;
+                if (bb < nbw) {
+                    const long off = s * a.st_ss + c * a.st_cs + (long)l * a.in_ls + b0 + bb;
+                    if (a.update_p) {
+                        const V r = sr[off];
+                        const V pv = sp[off];
+                        v = mk<T>(r.x + beta * pv.x, r.y + beta * pv.y);
+                        sp[off] = v;
+                    } else {
+                        v = sx[off];
+                    }
+                }
+                acc[(c * a.L_in + l) * B + bb] = v;
+            }
+            __syncthreads();
+            for (int al = 0; al < a.ncomp; ++al) {
+                for (int idx = threadIdx.x; idx < n * B; idx += blockDim.x) bufA[idx] = zero;
+                __syncthreads();
+                for (int idx = threadIdx.x; idx < a.L_in * B; idx += blockDim.x) {
+                    const int bb = idx % B;
+                    const int l = idx / B;
+                    if (bb >= nbw) continue;
+                    int k1, k2, k3;
+                    freq(l, a.L_in, b0 + bb, &k1, &k2, &k3);
+                    T t[2][3];
+                    const int nt = basis<T>(a.d, a.kind, k1, k2, k3, t);
+                    T ex = T(0), ey = T(0);
+                    for (int c = 0; c < nt; ++c) {
+                        const V cv = acc[(c * a.L_in + l) * B + bb];
+                        ex -= t[c][al] * cv.y;  // i * t * c
+                        ey += t[c][al] * cv.x;
+                    }
+                    bufA[posmod(k1, n) * B + bb] = mk<T>(ex, ey);
+                }
+                __syncthreads();
+                V *res = fft_lds<T, false>(bufA, bufB, a.f, B, tw, sg);
+                const long cbase = (long)(s * a.ncomp + al) * a.out_cs + (long)o * a.out_os + b0;
+                for (int idx = threadIdx.x; idx < a.L_out * B; idx += blockDim.x) {
+                    const int bb = idx % B;
+                    const int l = idx / B;
+                    if (bb >= nbw) continue;
+                    const int pos = posmod(wrapi(l, a.L_out), n);
+                    V v = res[pos * B + bb];
+                    v.x *= scale;
+                    v.y *= scale;
+                    out[cbase + (long)l * a.out_ls + bb] = v;
+                }
+                __syncthreads();
+            }
+        }
+        return;
+    }
+
+    // PRO_PLAIN
+    if (a.epi == EPI_PROJECT) {
+        for (int idx = threadIdx.x; idx < a.nc * a.L_out * B; idx += blockDim.x) acc[idx] = zero;
+    }
+    double part = 0.0;
+    for (int al = 0; al < a.ncomp; ++al) {
+        if (a.L_in < n) {
+            for (int idx = threadIdx.x; idx < n * B; idx += blockDim.x) bufA[idx] = zero;
+            __syncthreads();
+        }
+        const long ibase = (long)al * a.in_cs + (long)o * a.in_os + b0;
+        for (int idx = threadIdx.x; idx < a.L_in * B; idx += blockDim.x) {
+            const int bb = idx % B;
+            const int l = idx / B;
+            V v = zero;
+            if (bb < nbw) v = in[ibase + (long)l * a.in_ls + bb];
+            bufA[posmod(wrapi(l, a.L_in), n) * B + bb] = v;
+        }
+        __syncthreads();
+        V *res = fft_lds<T, false>(bufA, bufB, a.f, B, tw, sg);
+        if (a.epi == EPI_PROJECT) {
+            // q_a += -i t_a(k)_alpha yhat_alpha(k) on Z_N
+            for (int idx = threadIdx.x; idx < a.L_out * B; idx += blockDim.x) {
+                const int bb = idx % B;
+                const int l = idx / B;
+                if (bb >= nbw) continue;
+                int k1, k2, k3;
+                freq(l, a.L_out, b0 + bb, &k1, &k2, &k3);
+                T t[2][3];
+                const int nt = basis<T>(a.d, a.kind, k1, k2, k3, t);
+                const V y = res[posmod(k1, n) * B + bb];
+                for (int c = 0; c < nt; ++c) {
+                    V &q = acc[(c * a.L_out + l) * B + bb];
+                    const T tt = t[c][al] * scale;
+                    q.x += tt * y.y;
+                    q.y -= tt * y.x;
+                }
+            }
+        } else {
+            const long obase = (long)al * a.out_cs + (long)o * a.out_os + b0;
+            for (int idx = threadIdx.x; idx < a.L_out * B; idx += blockDim.x) {
+                const int bb = idx % B;
+                const int l = idx / B;
+                if (bb >= nbw) continue;
+                const int kk = wrapi(l, a.L_out);
+                V v = res[posmod(kk, n) * B + bb];
+                T sc = scale;
+                if (a.epi == EPI_WINDOW) {
+                    int k1, k2, k3;
+                    freq(l, a.L_out, b0 + bb, &k1, &k2, &k3);
+                    double w = a.winscale * sinc_pi((double)k1 / a.Pw[0]) * sinc_pi((double)k2 / a.Pw[1]);
+                    if (a.d == 3) w *= sinc_pi((double)k3 / a.Pw[2]);
+                    sc = T(w * a.scale);
+                }
+                v.x *= sc;
+                v.y *= sc;
+                out[obase + (long)l * a.out_ls + bb] = v;
+            }
+        }
+        __syncthreads();
+    }
+    if (a.epi == EPI_PROJECT) {
+        V *q = out;
+        const V *dv = reinterpret_cast<const V *>(a.st_dot);
+        for (int idx = threadIdx.x; idx < a.nc * a.L_out * B; idx += blockDim.x) {
+            const int bb = idx % B;
+            const int l = (idx / B) % a.L_out;
+            const int c = idx / (B * a.L_out);
+            if (bb >= nbw) continue;
+            const V v = acc[idx];
+            const long off = (long)c * a.out_cs + (long)l * a.out_ls + b0 + bb;
+            q[off] = v;
+            const int klast = (b0 + bb) % a.Nh;
+            const double w = klast == 0 ? 1.0 : 2.0;
+            if (dv != nullptr) {
+                const V pv = dv[off];
+                part += w * ((double)pv.x * (double)v.x + (double)pv.y * (double)v.y);
+            } else {
+                part += w * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
+            }
+        }
+        const double s = block_sum(part);
+        if (threadIdx.x == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// Voxel value as seen by the material series: the conductivity itself (0), the
+// indicator of the high phase of a two-phase image (1), the inverse
+// conductivity (2), or zero (3, a one-phase image).
+template <typename T>
+__device__ __forceinline__ T map_voxel(T v, int mode, double vmax) {
+    if (mode == 1) return v == T(vmax) ? T(1) : T(0);
+    if (mode == 2) return T(1) / v;
+    if (mode == 3) return T(0);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Row pass: real transforms along the last axis, two rows per complex DFT.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
+    using V = Vt<T>;
+    if (a.status != nullptr && a.status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    const int n = a.f.n;
+    const int RP = a.RP;
+    const int nh = a.Nh_row;
+    V *S = reinterpret_cast<V *>(smem_raw);
+    V *Z = S + (size_t)RP * n;  // Z[c] = Z + c * RP * n
+    const V *tw = reinterpret_cast<const V *>(a.tw);
+    V *data = reinterpret_cast<V *>(a.data);
+    const T *g = reinterpret_cast<const T *>(a.g);
+    const int pair0 = blockIdx.x * RP;
+    const int npairs_total = (a.nrows + 1) / 2;
+    const int nvp = min(RP, npairs_total - pair0);
+    const V zero = mk<T>(T(0), T(0));
+    const int d = a.d;
+    const int nzc = (a.mode == ROW_RHS || a.mode == ROW_R2C) ? (a.mode == ROW_RHS ? d : 1) : a.ncomp;
+
+    auto zbuf = [&](int c) { return Z + (size_t)c * RP * n; };
+    auto fft_into = [&](int c, T sg) {
+        V *res = fft_lds<T, true>(zbuf(c), S, a.f, RP, tw, sg);
+        if (res != zbuf(c)) {
+            for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) zbuf(c)[idx] = res[idx];
+            __syncthreads();
+        }
+    };
+
+    // ---- spatial values ----
+    if (a.mode == ROW_OPER || a.mode == ROW_GRAM || a.mode == ROW_C2R) {
+        for (int c = 0; c < a.ncomp; ++c) {
+            V *zc = zbuf(c);
+            for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) zc[idx] = zero;
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < RP * nh; idx += blockDim.x) {
+                const int j = idx / nh;
+                const int kx = idx - j * nh;
+                if (j >= nvp) continue;
+                const int r1 = 2 * (pair0 + j);
+                const int r2 = r1 + 1;
+                const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
+                const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+                if (kx == 0) {
+                    zc[j * n] = mk<T>(u1.x, u2.x);
+                } else {
+                    zc[j * n + kx] = mk<T>(u1.x - u2.y, u1.y + u2.x);
+                    zc[j * n + n - kx] = mk<T>(u1.x + u2.y, u2.x - u1.y);
+                }
+            }
+            __syncthreads();
+            fft_into(c, T(1));
+        }
+    } else if (a.mode == ROW_R2C) {
+        const T *rin = reinterpret_cast<const T *>(a.real_in);
+        V *zc = zbuf(0);
+        for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) {
+            const int j = idx / n;
+            const int x = idx - j * n;
+            V v = zero;
+            if (j < nvp) {
+                const int r1 = 2 * (pair0 + j);
+                const int r2 = r1 + 1;
+                v.x = map_voxel<T>(rin[(long)r1 * a.real_stride + x], a.imgmap, a.vmax);
+                v.y = (r2 < a.nrows) ? map_voxel<T>(rin[(long)r2 * a.real_stride + x], a.imgmap, a.vmax) : T(0);
+            }
+            zc[idx] = v;
+        }
+        __syncthreads();
+    }
+
+    // ---- pointwise work ----
+    if (a.mode == ROW_OPER || a.mode == ROW_RHS) {
+        T A0[9], D[9], E[3];
+        for (int i = 0; i < d * d; ++i) {
+            A0[i] = T(a.A0[i]);
+            D[i] = T(a.D[i]);
+        }
+        for (int i = 0; i < 3; ++i) E[i] = T(a.E[i]);
+        double load = 0.0;
+        for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) {
+            const int j = idx / n;
+            const int x = idx - j * n;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            const bool v2 = r2 < a.nrows;
+            const T g1 = g[(long)r1 * n + x];
+            const T g2 = v2 ? g[(long)r2 * n + x] : T(0);
+            T e1[3], e2[3];
+            for (int b = 0; b < d; ++b) {
+                if (a.mode == ROW_OPER) {
+                    const V zv = zbuf(b)[idx];
+                    e1[b] = zv.x;
+                    e2[b] = zv.y;
+                } else {
+                    e1[b] = E[b];
+                    e2[b] = v2 ? E[b] : T(0);
+                }
+            }
+            for (int al = 0; al < d; ++al) {
+                T y1 = T(0), y2 = T(0);
+                for (int b = 0; b < d; ++b) {
+                    y1 += (A0[al * d + b] + g1 * D[al * d + b]) * e1[b];
+                    y2 += (A0[al * d + b] + g2 * D[al * d + b]) * e2[b];
+                }
+                zbuf(al)[idx] = mk<T>(y1, y2);
+                load += (double)y1 * y1 + (double)y2 * y2;
+            }
+        }
+        __syncthreads();
+        if (a.mode == ROW_RHS) {
+            const double s = block_sum(load);
+            if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+        }
+    } else if (a.mode == ROW_GRAM) {
+        // (A_M (E_s + e_s), E_t + e_t) summed over the rows' grid points
+        T A0[9], D[9];
+        for (int i = 0; i < d * d; ++i) {
+            A0[i] = T(a.A0[i]);
+            D[i] = T(a.D[i]);
+        }
+        double gs[9];
+        for (int i = 0; i < 9; ++i) gs[i] = 0.0;
+        for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) {
+            const int j = idx / n;
+            const int x = idx - j * n;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            for (int half = 0; half < 2; ++half) {
+                const int r = half ? r2 : r1;
+                if (r >= a.nrows) continue;
+                const T gg = g[(long)r * n + x];
+                T f[3][3];
+                for (int s = 0; s < d; ++s)
+                    for (int b = 0; b < d; ++b) {
+                        const V zv = zbuf(s * d + b)[idx];
+                        f[s][b] = (half ? zv.y : zv.x) + (s == b ? T(1) : T(0));
+                    }
+                for (int t = 0; t < d; ++t) {
+                    T af[3];
+                    for (int al = 0; al < d; ++al) {
+                        T y = T(0);
+                        for (int b = 0; b < d; ++b) y += (A0[al * d + b] + gg * D[al * d + b]) * f[t][b];
+                        af[al] = y;
+                    }
+                    for (int s = 0; s < d; ++s) {
+                        T dot = T(0);
+                        for (int al = 0; al < d; ++al) dot += f[s][al] * af[al];
+                        gs[s * d + t] += dot;
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < d * d; ++i) {
+            const double s = block_sum(gs[i]);
+            if (threadIdx.x == 0) a.partial[(long)blockIdx.x * d * d + i] = s;
+        }
+        return;
+    } else if (a.mode == ROW_C2R) {
+        T *rout = reinterpret_cast<T *>(a.real_out);
+        const T scale = T(a.scale);
+        for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) {
+            const int j = idx / n;
+            const int x = idx - j * n;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            const V zv = zbuf(0)[idx];
+            rout[(long)r1 * a.real_stride + x] = zv.x * scale;
+            if (r2 < a.nrows) rout[(long)r2 * a.real_stride + x] = zv.y * scale;
+        }
+        return;
+    }
+
+    // ---- forward transforms and Hermitian split ----
+    const T half = T(a.scale) * T(0.5);
+    for (int c = 0; c < nzc; ++c) {
+        fft_into(c, T(-1));
+        const V *zc = zbuf(c);
+        for (int idx = threadIdx.x; idx < RP * nh; idx += blockDim.x) {
+            const int j = idx / nh;
+            const int kx = idx - j * nh;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            const V w = zc[j * n + posmod(kx, n)];
+            const V wm = zc[j * n + posmod(-kx, n)];
+            data[(long)c * a.cs + (long)r1 * nh + kx] = mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half);
+            if (r2 < a.nrows)
+                data[(long)c * a.cs + (long)r2 * nh + kx] = mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CG scalar and vector kernels (Remark CG; Saad Alg. 6.18).
+// ---------------------------------------------------------------------------
+__device__ double sum_fixed(const double *part, int n) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    return block_sum(v);
+}
+
+__global__ __launch_bounds__(kThreads) void cg_init_kernel(CgStatus *st, const double *rr_part, int n_rr,
+                                                           const double *load_part, int n_load, double tol,
+                                                           double floor_rel, int maxit, double *hist) {
+    const double rr = sum_fixed(rr_part, n_rr);
+    const double load = sum_fixed(load_part, n_load);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        st->rr0 = rr;
+        st->pq = 0.0;
+        st->alpha = 0.0;
+        st->beta = 0.0;
+        st->tol2 = tol * tol;
+        st->load2 = load;
+        st->floor2 = floor_rel * floor_rel * load;
+        st->iter = 0;
+        st->maxit = maxit;
+        st->breakdown = !isfinite(rr) || !isfinite(load);
+        st->converged = (rr == 0.0 || rr <= st->floor2) && !st->breakdown;
+        st->done = st->converged || st->breakdown || maxit <= 0;
+        if (hist != nullptr) {
+            hist[0] = rr;
+            hist[1] = 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void cg_alpha_kernel(CgStatus *st, const double *pq_part, int n) {
+    if (st->done) return;
+    const double pq = sum_fixed(pq_part, n);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            st->breakdown = 1;
+            st->done = 1;
+        } else {
+            st->alpha = st->rr / pq;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void cg_check_kernel(CgStatus *st, const double *rr_part, int n,
+                                                            double *hist) {
+    if (st->done) return;
+    const double rr = sum_fixed(rr_part, n);
+    if (threadIdx.x == 0) {
+        const int it = st->iter + 1;
+        st->iter = it;
+        if (hist != nullptr) {
+            hist[2 * it] = rr;
+            hist[2 * it + 1] = st->alpha;
+        }
+        if (!isfinite(rr)) {
+            st->breakdown = 1;
+            st->done = 1;
+            return;
+        }
+        st->beta = rr / st->rr;
+        st->rr = rr;
+        if (rr <= st->tol2 * st->rr0 || rr <= st->floor2) {
+            st->converged = 1;
+            st->done = 1;
+        } else if (it >= st->maxit) {
+            st->done = 1;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cg_update_kernel(Vt<T> *x, Vt<T> *r, const Vt<T> *p, const Vt<T> *q,
+                                                             long n_per_comp, int nc, long cs, int Nh,
+                                                             const CgStatus *st, double *partial) {
+    if (st->done) return;
+    const T alpha = T(st->alpha);
+    double part = 0.0;
+    const long total = n_per_comp * nc;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const long c = idx / n_per_comp;
+        const long i = idx - c * n_per_comp;
+        const long off = c * cs + i;
+        Vt<T> xv = x[off], rv = r[off];
+        const Vt<T> pv = p[off], qv = q[off];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        rv.x -= alpha * qv.x;
+        rv.y -= alpha * qv.y;
+        x[off] = xv;
+        r[off] = rv;
+        const double w = (i % Nh) == 0 ? 1.0 : 2.0;
+        part += w * ((double)rv.x * rv.x + (double)rv.y * rv.y);
+    }
+    const double s = block_sum(part);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void fill_zero_kernel(unsigned int *p, size_t nwords) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void f2d_kernel(double *dst, const float *src, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+__global__ void d2f_kernel(float *dst, const double *src, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+// out[v] = sum_i part[i * nvals + v] in a fixed order (one work-group).
+__global__ __launch_bounds__(kThreads) void sum_partials_kernel(double *out, const double *part, int nparts,
+                                                                int nvals) {
+    for (int v = 0; v < nvals; ++v) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[(long)i * nvals + v];
+        s = block_sum(s);
+        if (threadIdx.x == 0) out[v] = s;
+    }
+}
+
+// Fourier coefficients on the half grid of Z_{L} (L = 2N-1): entry
+// (n_1, [n_2,] n_3 >= 0) = w0 [n = 0] + sum_i w_i exp(-2 pi i n.c_i) fhat_i(n),
+// with fhat of the box prod_a h_a sinc(h_a n_a) or of the disc
+// r J_1(2 pi r |n|)/|n| (pi r^2 at n = 0)  (eq. char_func_Four, eq. inclcomp_formula).
+__global__ __launch_bounds__(kThreads) void incl_coeff_kernel(double2 *out, int d, int L1, int L2, int Lh,
+                                                              const InclDev *incl, int n_incl, double w0) {
+    const long total = (d == 3 ? (long)L1 * L2 * Lh : (long)L1 * Lh);
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        int n1, n2, n3;
+        if (d == 3) {
+            n3 = (int)(idx % Lh);
+            n2 = wrapi((int)((idx / Lh) % L2), L2);
+            n1 = wrapi((int)(idx / ((long)Lh * L2)), L1);
+        } else {
+            n3 = 0;
+            n2 = (int)(idx % Lh);
+            n1 = wrapi((int)(idx / Lh), L1);
+        }
+        double re = (n1 == 0 && n2 == 0 && n3 == 0) ? w0 : 0.0, im = 0.0;
+        for (int i = 0; i < n_incl; ++i) {
+            const InclDev &q = incl[i];
+            double f;
+            if (q.shape == 0) {
+                f = q.h[0] * sinc_pi(q.h[0] * n1) * q.h[1] * sinc_pi(q.h[1] * n2);
+                if (d == 3) f *= q.h[2] * sinc_pi(q.h[2] * n3);
+            } else {
+                const double kn = sqrt((double)n1 * n1 + (double)n2 * n2);
+                const double r = q.h[0];
+                f = kn == 0.0 ? M_PI * r * r : r * j1(2.0 * M_PI * r * kn) / kn;
+            }
+            const double arg = -2.0 * ((double)n1 * q.c[0] + (double)n2 * q.c[1] + (d == 3 ? (double)n3 * q.c[2] : 0.0));
+            double sv, cv;
+            sincospi(arg, &sv, &cv);
+            re += q.w * f * cv;
+            im += q.w * f * sv;
+        }
+        out[idx] = make_double2(re, im);
+    }
+}
+
+// Device-side validation of a voxel image: per work-group min, max and the
+// number of entries that are not positive finite (part[3 b + 0..2]).
+__global__ __launch_bounds__(kThreads) void image_stats_kernel(const double *img, long n, double *part) {
+    double mn = INFINITY, mx = -INFINITY, bad = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = img[i];
+        if (!(v > 0.0) || !isfinite(v)) {
+            bad += 1.0;
+        } else {
+            mn = fmin(mn, v);
+            mx = fmax(mx, v);
+        }
+    }
+    __shared__ double smn[kThreads], smx[kThreads], sbd[kThreads];
+    smn[threadIdx.x] = mn;
+    smx[threadIdx.x] = mx;
+    sbd[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + w]);
+            smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + w]);
+            sbd[threadIdx.x] += sbd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = smn[0];
+        part[3 * blockIdx.x + 1] = smx[0];
+        part[3 * blockIdx.x + 2] = sbd[0];
+    }
+}
+
+// out[0..3] = min, max, #invalid, #entries equal to neither min nor max.
+__global__ __launch_bounds__(kThreads) void image_stats_reduce(const double *part, int nb, double *out) {
+    if (threadIdx.x == 0) {
+        double mn = INFINITY, mx = -INFINITY, bad = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            mn = fmin(mn, part[3 * b]);
+            mx = fmax(mx, part[3 * b + 1]);
+            bad += part[3 * b + 2];
+        }
+        out[0] = mn;
+        out[1] = mx;
+        out[2] = bad;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void image_other_kernel(const double *img, long n, const double *mm,
+                                                               double *part) {
+    const double mn = mm[0], mx = mm[1];
+    double cnt = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = img[i];
+        if (v != mn && v != mx) cnt += 1.0;
+    }
+    const double s = block_sum(cnt);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
+    const size_t es = fp64 ? 16 : 8;
+    int lacc = 0;
+    if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
+    if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
+    return es * ((size_t)2 * a.f.n * a.B + (size_t)lacc * a.B);
+}
+
+size_t row_lds_bytes(const RowArgs &a, bool fp64) {
+    const size_t es = fp64 ? 16 : 8;
+    int nz = a.ncomp;
+    if (a.mode == ROW_RHS) nz = a.d;
+    if (a.mode == ROW_R2C || a.mode == ROW_C2R) nz = 1;
+    return es * (size_t)(nz + 1) * a.RP * a.f.n;
+}
+
+int pencil_grid_x(const PencilArgs &a) { return (a.nb + a.B - 1) / a.B; }
+int row_grid(const RowArgs &a) { return ((a.nrows + 1) / 2 + a.RP - 1) / a.RP; }
+
+hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s) {
+    dim3 grid(pencil_grid_x(a), nouter);
+    const size_t lds = pencil_lds_bytes(a, fp64);
+    if (fp64) {
+        hipLaunchKernelGGL(pencil_kernel<double>, grid, dim3(kThreads), lds, s, a);
+    } else {
+        hipLaunchKernelGGL(pencil_kernel<float>, grid, dim3(kThreads), lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s) {
+    const size_t lds = row_lds_bytes(a, fp64);
+    if (fp64) {
+        hipLaunchKernelGGL(row_kernel<double>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);
+    } else {
+        hipLaunchKernelGGL(row_kernel<float>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part, int n_load,
+                          double tol, double floor_rel, int maxit, double *hist, hipStream_t s) {
+    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kThreads), 0, s, st, rr_part, n_rr, load_part, n_load, tol,
+                       floor_rel, maxit, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha(CgStatus *st, const double *pq_part, int n, hipStream_t s) {
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kThreads), 0, s, st, pq_part, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_check(CgStatus *st, const double *rr_part, int n, double *hist, hipStream_t s) {
+    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(kThreads), 0, s, st, rr_part, n, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(void *x, void *r, const void *p, const void *q, long n_per_comp, int nc, long cs,
+                            int Nh, const CgStatus *st, double *partial, int nblocks, bool fp64, hipStream_t s) {
+    if (fp64) {
+        hipLaunchKernelGGL(cg_update_kernel<double>, dim3(nblocks), dim3(kThreads), 0, s, (double2 *)x,
+                           (double2 *)r, (const double2 *)p, (const double2 *)q, n_per_comp, nc, cs, Nh, st,
+                           partial);
+    } else {
+        hipLaunchKernelGGL(cg_update_kernel<float>, dim3(nblocks), dim3(kThreads), 0, s, (float2 *)x, (float2 *)r,
+                           (const float2 *)p, (const float2 *)q, n_per_comp, nc, cs, Nh, st, partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+    const size_t nw = bytes / 4;
+    if (nw == 0) return hipSuccess;
+    const int nb = (int)std::min<size_t>((nw + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(nb), dim3(kThreads), 0, s, (unsigned int *)p, nw);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f2d(double *dst, const float *src, size_t n, hipStream_t s) {
+    const int nb = (int)std::min<size_t>((n + kThreads - 1) / kThreads, 4096);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(f2d_kernel, dim3(nb), dim3(kThreads), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_d2f(float *dst, const double *src, size_t n, hipStream_t s) {
+    const int nb = (int)std::min<size_t>((n + kThreads - 1) / kThreads, 4096);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(d2f_kernel, dim3(nb), dim3(kThreads), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(double *out, const double *part, int nparts, int nvals, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kThreads), 0, s, out, part, nparts, nvals);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_stats(const double *img, long n, double *part, double *out, hipStream_t s) {
+    const int nb = 256;  // 3 * nb partials fit the plan's partial-sum region
+    hipLaunchKernelGGL(image_stats_kernel, dim3(nb), dim3(kThreads), 0, s, img, n, part);
+    hipLaunchKernelGGL(image_stats_reduce, dim3(1), dim3(kThreads), 0, s, part, nb, out);
+    hipLaunchKernelGGL(image_other_kernel, dim3(nb), dim3(kThreads), 0, s, img, n, out, part);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kThreads), 0, s, out + 3, part, nb, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_incl_coeff(void *out, int d, int L1, int L2, int Lh, const InclDev *incl, int n_incl,
+                             double w0, hipStream_t s) {
+    const long total = (d == 3 ? (long)L1 * L2 * Lh : (long)L1 * Lh);
+    const int nb = (int)std::min<long>((total + kThreads - 1) / kThreads, 8192);
+    hipLaunchKernelGGL(incl_coeff_kernel, dim3(nb), dim3(kThreads), 0, s, (double2 *)out, d, L1, L2, Lh, incl,
+                       n_incl, w0);
+    return hipGetLastError();
+}
+
+}  // namespace fftgal

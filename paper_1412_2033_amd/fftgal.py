@@ -1,0 +1,296 @@
+"""Thin Python binding of the fftgal C ABI (``include/fftgal.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``_lib/libfftgal.so``.  PyTorch supplies the device workspace and the
+stream.  There is no fallback: if the library is missing, loading raises.
+
+The module-level functions carry the C names (``fftgal_plan``,
+``fftgal_set_material``, ...); ``Plan`` is a small convenience wrapper that
+owns a torch workspace tensor.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libfftgal.so")
+
+FP64 = 0
+FP32_ITER = 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32_ITER, "fp32_iter": FP32_ITER}
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5: "ESTATE", -6: "EBREAKDOWN"}
+EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", "fftgal_set_material",
+           "fftgal_solve_primal", "fftgal_solve_dual", "fftgal_bounds", "fftgal_destroy",
+           "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing")
+KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
+                  "bounds", "setup")
+
+
+class FftgalError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Material(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("A0", ctypes.c_double * 9),
+        ("n_incl", ctypes.c_int32),
+        ("shape", ctypes.POINTER(ctypes.c_int32)),
+        ("center", ctypes.POINTER(ctypes.c_double)),
+        ("size", ctypes.POINTER(ctypes.c_double)),
+        ("A_in", ctypes.POINTER(ctypes.c_double)),
+        ("P", ctypes.c_int32 * 3),
+        ("image", ctypes.POINTER(ctypes.c_double)),
+        ("image_device", ctypes.c_int32),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_res", ctypes.c_double), ("res0", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iters": int(self.iters), "converged": bool(self.converged),
+                "rel_res": float(self.rel_res), "res0": float(self.res0)}
+
+
+_LIB = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libfftgal.so (after torch, so that both share one HIP runtime)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            "libfftgal.so is not built (%s); run python -m paper_1412_2033_amd.build" % path)
+    try:
+        import torch  # noqa: F401  (load the HIP runtime torch uses first)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    vp = ctypes.c_void_p
+    lib.fftgal_workspace_bytes.argtypes = [ctypes.c_int, i32p, ctypes.c_int]
+    lib.fftgal_workspace_bytes.restype = ctypes.c_size_t
+    lib.fftgal_workspace_bytes_p.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p]
+    lib.fftgal_workspace_bytes_p.restype = ctypes.c_size_t
+    lib.fftgal_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32p, ctypes.c_int, vp, ctypes.c_size_t, vp]
+    lib.fftgal_plan.restype = ctypes.c_int
+    lib.fftgal_set_material.argtypes = [vp, ctypes.POINTER(Material)]
+    lib.fftgal_set_material.restype = ctypes.c_int
+    for name in ("fftgal_solve_primal", "fftgal_solve_dual"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]
+        f.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.fftgal_bounds.argtypes = [vp, dp, dp, dp]
+    lib.fftgal_bounds.restype = ctypes.c_int
+    lib.fftgal_destroy.argtypes = [vp]
+    lib.fftgal_destroy.restype = ctypes.c_int
+    lib.fftgal_last_error.argtypes = [vp]
+    lib.fftgal_last_error.restype = ctypes.c_char_p
+    lib.fftgal_grid_size.argtypes = [vp, ctypes.c_int]
+    lib.fftgal_grid_size.restype = ctypes.c_int
+    lib.fftgal_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.fftgal_set_timing.restype = ctypes.c_int
+    lib.fftgal_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
+    lib.fftgal_read_timing.restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _i32(vals):
+    arr = (ctypes.c_int32 * 3)()
+    for i, v in enumerate(vals):
+        arr[i] = int(v)
+    return arr
+
+
+def _check(code, plan=None):
+    if code != 0:
+        msg = load_library().fftgal_last_error(plan).decode()
+        raise FftgalError(code, msg)
+
+
+# ---- C-named functions (marshalling only) ------------------------------------
+
+def fftgal_workspace_bytes(d, N, precision=FP64, P=None):
+    lib = load_library()
+    if P is None:
+        return int(lib.fftgal_workspace_bytes(d, _i32(N), precision))
+    return int(lib.fftgal_workspace_bytes_p(d, _i32(N), precision, _i32(P)))
+
+
+def fftgal_plan(d, N, precision, workspace_ptr, nbytes, stream_ptr):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    _check(lib.fftgal_plan(ctypes.byref(h), d, _i32(N), precision, ctypes.c_void_p(workspace_ptr),
+                           nbytes, ctypes.c_void_p(stream_ptr)), None)
+    return h
+
+
+def material_struct(micro):
+    """Marshal a ``synth`` microstructure dict into an fftgal_material (keeps arrays alive)."""
+    d = int(micro["d"])
+    m = Material()
+    keep = []
+    if micro["kind"] == "inclusions":
+        m.kind = 0
+        A0 = np.asarray(micro["A0"], float).reshape(d, d)
+        for i in range(d * d):
+            m.A0[i] = A0.ravel()[i]
+        shapes = np.array([0 if s == "rect" else 1 if s == "circ" else -1 for s in micro["shapes"]], np.int32)
+        centers = np.ascontiguousarray(micro["centers"], float).reshape(-1)
+        sizes = np.ascontiguousarray(micro["sizes"], float).reshape(-1)
+        ain = np.ascontiguousarray(micro["A_in"], float).reshape(-1)
+        keep += [shapes, centers, sizes, ain]
+        m.n_incl = len(shapes)
+        m.shape = shapes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        m.center = centers.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        m.size = sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        m.A_in = ain.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    elif micro["kind"] == "voxels":
+        m.kind = 1
+        for a in range(d):
+            m.P[a] = int(micro["P"][a])
+        img = micro["image"]
+        if hasattr(img, "data_ptr") and getattr(img, "is_cuda", False):
+            # a torch float64 tensor already resident on the device
+            if not img.is_contiguous() or str(img.dtype) != "torch.float64":
+                raise ValueError("device image must be a contiguous float64 tensor")
+            keep.append(img)
+            m.image = ctypes.cast(ctypes.c_void_p(img.data_ptr()), ctypes.POINTER(ctypes.c_double))
+            m.image_device = 1
+        else:
+            img = np.ascontiguousarray(img, float)
+            keep.append(img)
+            m.image = img.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    else:
+        raise ValueError(micro["kind"])
+    return m, keep
+
+
+def fftgal_set_material(plan, micro):
+    m, keep = material_struct(micro)
+    _check(load_library().fftgal_set_material(plan, ctypes.byref(m)), plan)
+    del keep
+
+
+def _solve(fn, plan, d, alpha, rtol, maxit):
+    n = d if alpha < 0 else 1
+    infos = (Info * n)()
+    code = fn(plan, alpha, rtol, maxit, infos)
+    if code not in (0, -4):
+        _check(code, plan)
+    return [i.as_dict() for i in infos], code
+
+
+def fftgal_solve_primal(plan, d, alpha=-1, rtol=1e-10, maxit=20000):
+    return _solve(load_library().fftgal_solve_primal, plan, d, alpha, rtol, maxit)
+
+
+def fftgal_solve_dual(plan, d, alpha=-1, rtol=1e-10, maxit=20000):
+    return _solve(load_library().fftgal_solve_dual, plan, d, alpha, rtol, maxit)
+
+
+def fftgal_bounds(plan, d):
+    up = (ctypes.c_double * (d * d))()
+    lo = (ctypes.c_double * (d * d))()
+    gap = ctypes.c_double()
+    _check(load_library().fftgal_bounds(plan, up, lo, ctypes.byref(gap)), plan)
+    return (np.array(up[:]).reshape(d, d), np.array(lo[:]).reshape(d, d), float(gap.value))
+
+
+def fftgal_destroy(plan):
+    return load_library().fftgal_destroy(plan)
+
+
+def fftgal_last_error(plan=None):
+    return load_library().fftgal_last_error(plan).decode()
+
+
+def fftgal_grid_size(plan, axis):
+    return int(load_library().fftgal_grid_size(plan, axis))
+
+
+def fftgal_set_timing(plan, enable):
+    _check(load_library().fftgal_set_timing(plan, int(bool(enable))), plan)
+
+
+def fftgal_read_timing(plan):
+    """{class: (milliseconds, launches)} since the previous read."""
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int32 * n)()
+    _check(load_library().fftgal_read_timing(plan, ms, cnt), plan)
+    return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(KERNEL_CLASSES)}
+
+
+# ---- convenience wrapper ------------------------------------------------------
+
+class Plan:
+    """A plan plus the torch device workspace it runs in."""
+
+    def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("fftgal needs a HIP device")
+        self.d = int(d)
+        self.N = tuple(int(n) for n in N)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.nbytes = fftgal_workspace_bytes(self.d, self.N, self.precision, P)
+        if self.nbytes == 0:
+            raise FftgalError(-1, "invalid plan arguments")
+        dev = torch.device(device)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.handle = fftgal_plan(self.d, self.N, self.precision, self.workspace.data_ptr(), self.nbytes,
+                                  self.stream.cuda_stream)
+        self.M = tuple(fftgal_grid_size(self.handle, a) for a in range(self.d))
+
+    def set_material(self, micro):
+        fftgal_set_material(self.handle, micro)
+
+    def solve_primal(self, alpha=-1, rtol=1e-10, maxit=20000):
+        return fftgal_solve_primal(self.handle, self.d, alpha, rtol, maxit)
+
+    def solve_dual(self, alpha=-1, rtol=1e-10, maxit=20000):
+        return fftgal_solve_dual(self.handle, self.d, alpha, rtol, maxit)
+
+    def bounds(self):
+        return fftgal_bounds(self.handle, self.d)
+
+    def set_timing(self, enable=True):
+        fftgal_set_timing(self.handle, enable)
+
+    def read_timing(self):
+        return fftgal_read_timing(self.handle)
+
+    def run(self, micro, rtol=1e-10, maxit=20000):
+        """set_material + all 2d solves + bounds; returns a result dict."""
+        self.set_material(micro)
+        ip, cp = self.solve_primal(-1, rtol, maxit)
+        idl, cd = self.solve_dual(-1, rtol, maxit)
+        up, lo, gap = self.bounds()
+        return {"upper": up, "lower": lo, "gap": gap, "info_primal": ip, "info_dual": idl,
+                "status_primal": cp, "status_dual": cd}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            fftgal_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

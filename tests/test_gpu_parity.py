@@ -1,0 +1,167 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: the FP64 path must match the oracle's bounds to 1e-10 relative
+(Frobenius); the FP32-iteration path to 1e-6 relative, and keep lower <= upper.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ga, material
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def fg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_2033_amd import fftgal
+    fftgal.load_library()
+    return fftgal
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _gpu(fg, micro, N, precision="fp64", rtol=1e-10, P=None):
+    print("case d=%d N=%s %s" % (len(N), N, precision), flush=True)
+    plan = fg.Plan(len(N), N, precision, P=P)
+    try:
+        return plan.run(micro, rtol=rtol)
+    finally:
+        plan.close()
+
+
+def _oracle(micro, N, tol=1e-10):
+    return ga.ga_bounds(material.make_material(micro), N, tol=tol)
+
+
+CASES = {
+    "square2d_N9": (lambda: synth.square_inclusion(2, 0.6, 1.0, 10.0), (9, 9)),
+    "square2d_N5x7": (lambda: synth.square_inclusion(2, 0.6, 1.0, 10.0, center=(0.1, 0.2)), (5, 7)),
+    "circle2d_N15": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0, center=(0.05, -0.1)), (15, 15)),
+    "twophase_iso_N9": (lambda: {"d": 2, "kind": "inclusions", "A0": np.eye(2), "shapes": ["rect", "circ"],
+                                 "centers": np.array([[0.1, -0.2], [-0.25, 0.2]]),
+                                 "sizes": np.array([[0.35, 0.2], [0.12, 0.0]]),
+                                 "A_in": np.array([12 * np.eye(2), 0.2 * np.eye(2)])}, (9, 9)),
+    "aniso3d_N5": (lambda: synth.cube_inclusion_aniso(0.5, 3), (5, 5, 5)),
+    "aniso3d_N7x5x9": (lambda: synth.cube_inclusion_aniso(0.45, 4), (7, 5, 9)),
+    "voxel2d_N7": (lambda: synth.grf_voxels(11, (9, 9), d=2, corr_len=0.15), (7, 7)),
+    "voxel3d_N5": (lambda: synth.grf_voxels(12, (9, 9, 9), d=3, corr_len=0.15), (5, 5, 5)),
+    "voxel3d_N7x5x9": (lambda: synth.grf_voxels(13, (15, 9, 21), d=3, corr_len=0.15), (7, 5, 9)),
+    "voxel2d_multi_N9": (lambda: {"d": 2, "kind": "voxels", "P": (15, 15),
+                                  "image": 1.0 + np.arange(225).reshape(15, 15) % 7}, (9, 9)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp64_matches_oracle(fg, name):
+    make, N = CASES[name]
+    micro = make()
+    P = micro.get("P")
+    res = _gpu(fg, micro, N, P=P)
+    ref = _oracle(micro, N)
+    assert _rel(res["upper"], ref["upper"]) < 1e-10
+    assert _rel(res["lower"], ref["lower"]) < 1e-10
+    # CG iteration counts depend on the rounding path at high contrast; they
+    # are not a parity quantity, only a sanity check.
+    for a, b in zip([i["iters"] for i in res["info_primal"]], ref["iters_primal"]):
+        assert abs(a - b) <= max(3, 0.25 * b)
+
+
+@pytest.mark.parametrize("name", ["square2d_N9", "circle2d_N15", "aniso3d_N5", "voxel3d_N5"])
+def test_fp32_iteration_form(fg, name):
+    make, N = CASES[name]
+    micro = make()
+    res = _gpu(fg, micro, N, "fp32", rtol=1e-5, P=micro.get("P"))
+    ref = _oracle(micro, N)
+    assert _rel(res["upper"], ref["upper"]) < 1e-6
+    assert _rel(res["lower"], ref["lower"]) < 1e-6
+    assert np.min(np.linalg.eigvalsh(res["upper"] - res["lower"])) > -1e-12
+
+
+def test_c1_full_size_against_golden(fg):
+    with open(os.path.join(HERE, "golden", "c1.json")) as f:
+        gold = json.load(f)
+    res = _gpu(fg, synth.square_inclusion(2, 0.6, 1.0, 10.0), (41, 41))
+    assert _rel(res["upper"], gold["upper"]) < 1e-10
+    assert _rel(res["lower"], gold["lower"]) < 1e-10
+
+
+def test_homogeneous_zero_iterations(fg):
+    A = synth.random_spd(7, 3)
+    micro = synth.cube_inclusion_aniso(0.5, 7)
+    micro["A0"] = A
+    micro["A_in"] = A.reshape(1, 3, 3).copy()
+    res = _gpu(fg, micro, (5, 7, 5))
+    np.testing.assert_allclose(res["upper"], A, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    np.testing.assert_allclose(res["lower"], A, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    assert all(i["iters"] == 0 for i in res["info_primal"] + res["info_dual"])
+
+
+def test_laminate_exact_entries(fg):
+    micro = synth.square_inclusion(2, 1.0, 1.0, 10.0)
+    micro["sizes"] = np.array([[0.4, 1.0]])
+    res = _gpu(fg, micro, (21, 21))
+    assert abs(res["upper"][1, 1] - 4.6) < 1e-12 * 4.6
+    assert abs(res["lower"][0, 0] - 1.5625) < 1e-12 * 1.5625
+
+
+def test_N1_gives_voigt_reuss(fg):
+    micro = synth.square_inclusion(2, 0.6, 1.0, 10.0)
+    res = _gpu(fg, micro, (1, 1))
+    voigt, reuss = ga.voigt_reuss(material.make_material(micro), 2)
+    np.testing.assert_allclose(res["upper"], voigt, rtol=1e-13)
+    np.testing.assert_allclose(res["lower"], reuss, rtol=1e-13)
+
+
+def test_deterministic(fg):
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0)
+    a = _gpu(fg, micro, (21, 21))
+    b = _gpu(fg, micro, (21, 21))
+    assert np.array_equal(a["upper"], b["upper"]) and np.array_equal(a["lower"], b["lower"])
+
+
+def test_error_paths(fg):
+    import torch
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(fg.FftgalError) as e:
+        fg.fftgal_plan(2, (40, 41), 0, ws.data_ptr(), ws.numel(), s)
+    assert e.value.code == -1
+    with pytest.raises(fg.FftgalError) as e:
+        fg.fftgal_plan(2, (41, 41), 0, ws.data_ptr(), 1024, s)
+    assert e.value.code == -2
+    plan = fg.Plan(2, (9, 9))
+    with pytest.raises(fg.FftgalError) as e:
+        plan.bounds()
+    assert e.value.code == -5
+    with pytest.raises(fg.FftgalError) as e:
+        plan.solve_primal()
+    assert e.value.code == -5
+    bad = synth.square_inclusion(2, 0.6, 1.0, 10.0)
+    bad["shapes"] = ["rect", "rect"]
+    bad["centers"] = np.array([[0.0, 0.0], [0.1, 0.1]])
+    bad["sizes"] = np.array([[0.3, 0.3], [0.3, 0.3]])
+    bad["A_in"] = np.array([10 * np.eye(2)] * 2)
+    with pytest.raises(fg.FftgalError) as e:
+        plan.set_material(bad)
+    assert e.value.code == -1 and "overlap" in str(e.value)
+    nonspd = synth.square_inclusion(2, 0.6, 1.0, -10.0)
+    with pytest.raises(fg.FftgalError) as e:
+        plan.set_material(nonspd)
+    assert e.value.code == -1
+    plan.set_material(synth.square_inclusion(2, 0.6, 1.0, 10.0))
+    infos, code = plan.solve_primal(0, 1e-12, 1)
+    assert code == -4 and infos[0]["iters"] == 1 and not infos[0]["converged"]
+    plan.close()
