@@ -27,6 +27,34 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SYMBOL = {"row": "row_kernel", "expand": "pencil_kernel", "pencil_inv": "pencil_kernel",
+                 "pencil_fwd": "pencil_kernel", "project": "pencil_kernel", "cg_update": "cg_update_kernel"}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fftgal_kernels.hip", "fftgal_internal.h"):
+        with open(os.path.join(ROOT, "paper_1412_2033_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when no summary exists for this kernel or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    sym = "%s<%s>" % (KERNEL_SYMBOL.get(cls, cls), "double" if precision == "fp64" else "float")
+    r = rec.get(sym)
+    if r is None or r.get("class") != cls or r.get("precision") != precision:
+        return None
+    if r.get("source_sha256_16") != kernel_source_hash():
+        return None
+    return int(1024 * (r["fetch_kib_median"] * r["fetch_scale"] + r["write_kib_median"] * r["write_scale"]))
 
 
 def algorithmic_bytes(cls, d, N, M, es, gs, nc):
@@ -93,6 +121,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--N", type=int, default=113)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 5 times (profiler counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards by independent solves/requests; "
@@ -101,6 +131,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "launches": 5}))
+        return
 
     import synth
     from paper_1412_2033_amd import fftgal
@@ -161,7 +200,8 @@ def main():
     dom_avg_s = timing[dom][0] * 1e-3 / timing[dom][1]
     achieved = dom_bytes / dom_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, args.precision), "kernel": dom,
                 "bytes_per_launch": int(dom_bytes), "avg_launch_us": round(dom_avg_s * 1e6, 2)}
 
     last = results[-1]
