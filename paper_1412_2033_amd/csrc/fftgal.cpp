@@ -38,6 +38,11 @@ bool is_smooth_odd(int n) { return n >= 1 && smooth_odd(n) == n; }
 
 std::vector<int> factor(int n) {
     std::vector<int> f;
+    const int fi = fast_index(n);
+    if (fi >= 0) {  // the schedule the specialised kernels are compiled for
+        for (int s = 0; s < kFastSched[fi].nst; ++s) f.push_back(kFastSched[fi].r[s]);
+        return f;
+    }
     for (int p : {7, 5, 3})
         while (n % p == 0) {
             f.push_back(p);
@@ -88,20 +93,6 @@ struct Layout {
     size_t tw_len, twP_len;  // complex entries per table region
     size_t part_len;         // doubles per partial region
 };
-
-int pencil_B(int n, int lacc, bool fp64, int Bmax) {
-    const size_t es = fp64 ? 16 : 8;
-    int B = Bmax;
-    while (B > 1 && es * ((size_t)2 * n * B + (size_t)lacc * B) > 80 * 1024) B /= 2;
-    return B;
-}
-
-int row_RP(int n, int nz, bool fp64) {
-    const size_t es = fp64 ? 16 : 8;
-    int RP = 8;
-    while (RP > 1 && es * (size_t)(nz + 1) * RP * n > 80 * 1024) RP /= 2;
-    return RP;
-}
 
 Layout make_layout(const Dims &D, int precision) {
     Layout L{};
@@ -157,18 +148,12 @@ Layout make_layout(const Dims &D, int precision) {
     L.gA32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.Mtot * 4 : 0);
     L.gB32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.Mtot * 4 : 0);
     // partial sums: the largest work-group count of any reducing launch
+    // (worst case: one pencil / one row pair per work-group)
     long nwg = kUpdateBlocks;
-    for (int fp = 0; fp < 2; ++fp) {
-        const bool f64 = fp == 1;
-        const int nbz = (d == 3) ? D.N[1] * D.Nh : D.Nh;
-        const int B = pencil_B(D.M[0], D.nc_max * D.N[0], f64, f64 ? 8 : 16);
-        nwg = std::max<long>(nwg, (nbz + B - 1) / B);
-        const long nrows = (d == 3) ? (long)D.M[0] * D.M[1] : D.M[0];
-        const int RP = row_RP(D.M[d - 1], d, f64);
-        nwg = std::max<long>(nwg, ((nrows + 1) / 2 + RP - 1) / RP);
-        const int RPg = row_RP(D.M[d - 1], (int)d2, true);
-        nwg = std::max<long>(nwg, (((nrows + 1) / 2 + RPg - 1) / RPg) * d2);
-    }
+    const long nbz = (d == 3) ? (long)D.N[1] * D.Nh : D.Nh;
+    const long nrows = (d == 3) ? (long)D.M[0] * D.M[1] : D.M[0];
+    nwg = std::max<long>(nwg, nbz);
+    nwg = std::max<long>(nwg, ((nrows + 1) / 2 + 1) * d2);
     L.part_len = (size_t)nwg + 64;
     L.part_a = take(L.part_len * 8);
     L.part_b = take(L.part_len * 8);
@@ -323,10 +308,8 @@ PencilArgs base_pencil(Plan *pl, const FftDesc &f, bool fp64, bool tabP = false)
 }
 
 int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int Bmax, int cls) {
-    int lacc = 0;
-    if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
-    if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
-    a.B = pencil_B(a.f.n, lacc, fp64, Bmax);
+    (void)Bmax;
+    configure_pencil(a, fp64);
     if (pencil_lds_bytes(a, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "transform length %d too large for one work-group", a.f.n);
     Timed t(pl, cls);
@@ -335,10 +318,7 @@ int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int Bmax, int cls
 }
 
 int run_row(Plan *pl, RowArgs &r, bool fp64, int cls) {
-    int nz = r.ncomp;
-    if (r.mode == ROW_RHS) nz = r.d;
-    if (r.mode == ROW_C2R || r.mode == ROW_R2C) nz = 1;
-    r.RP = row_RP(r.f.n, nz, fp64);
+    const int nz = r.mode == ROW_GRAM ? r.ncomp : r.d;
     if (row_lds_bytes(r, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "row length %d with %d components too large for one work-group", r.f.n, nz);
     Timed t(pl, cls);

@@ -23,6 +23,25 @@ struct FftDesc {
     int twoff[kMaxStages];
 };
 
+// Grid sizes with compile-time specialised kernels, and their radix
+// schedules (composite radices are done in registers).  The host builds the
+// twiddle tables of these lengths with the same schedule.
+struct FastSched {
+    int n;
+    int nst;
+    int r[4];
+};
+constexpr FastSched kFastSched[] = {
+    {81, 2, {9, 9, 0, 0}},      {125, 2, {25, 5, 0, 0}},  {225, 2, {15, 15, 0, 0}},
+    {245, 3, {7, 7, 5, 0}},     {729, 3, {9, 9, 9, 0}},   {2025, 3, {15, 15, 9, 0}},
+};
+constexpr int kNumFast = sizeof(kFastSched) / sizeof(kFastSched[0]);
+constexpr int fast_index(int n) {
+    for (int i = 0; i < kNumFast; ++i)
+        if (kFastSched[i].n == n) return i;
+    return -1;
+}
+
 // Device-resident state of one CG solve (Remark CG), advanced by the scalar
 // kernels; every kernel of an iteration returns at once when `done` is set.
 struct CgStatus {
@@ -66,6 +85,7 @@ struct PencilArgs {
     FftDesc f;
     const void *tw;
     int pro, epi;
+    int fast;     // set by configure_pencil: specialised kernel for this length
     // frequency decoding for EXPAND / PROJECT / WINDOW
     int d, kind, nc, Nmid, Nh;
     // EXPAND: state vectors (component stride st_cs, solution stride st_ss)
@@ -99,6 +119,7 @@ struct RowArgs {
     int d;
     int mode;
     int RP;           // row pairs per work-group
+    int fast;         // set by configure_row
     const void *g;    // material field g (M^d, precision of the kernel)
     double A0[9];     // A(x) = A0 + g(x) D
     double D[9];
@@ -123,6 +144,10 @@ struct InclDev {
 // ---- launchers (fftgal_kernels.hip) ----
 size_t pencil_lds_bytes(const PencilArgs &a, bool fp64);
 size_t row_lds_bytes(const RowArgs &a, bool fp64);
+// Choose pencils per work-group / row pairs per work-group (and whether the
+// specialised kernel runs) for a launch; sets a.B / r.RP.
+void configure_pencil(PencilArgs &a, bool fp64);
+void configure_row(RowArgs &r, bool fp64);
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s);
 hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s);
 int row_grid(const RowArgs &a);

@@ -108,6 +108,95 @@ __device__ __forceinline__ void dft(Vt<T> *u, T sg) {
     u[0] = tot;
 }
 
+constexpr double kPiD = 3.14159265358979323846;
+constexpr double cx_sin_small(double x) {
+    double x2 = x * x, t = x, s = x;
+    for (int k = 1; k < 14; ++k) {
+        t *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double cx_cos_small(double x) {
+    double x2 = x * x, t = 1.0, s = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        t *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+        s += t;
+    }
+    return s;
+}
+// cos and sin of 2 pi j / R by exact quadrant reduction of the rational j/R
+// and Taylor series on [0, pi/4] (evaluated at compile time).
+template <int R> struct TrigTab {
+    double c[R], s[R];
+    constexpr TrigTab() : c(), s() {
+        for (int j = 0; j < R; ++j) {
+            const int q = (4 * j) / R, r = 4 * j - q * R;
+            double cc = 0.0, ss = 0.0;
+            if (2 * r <= R) {
+                const double t = (kPiD / 2) * r / R;
+                cc = cx_cos_small(t);
+                ss = cx_sin_small(t);
+            } else {
+                const double u = (kPiD / 2) * (R - r) / R;
+                cc = cx_sin_small(u);
+                ss = cx_cos_small(u);
+            }
+            c[j] = q == 0 ? cc : q == 1 ? -ss : q == 2 ? -cc : ss;
+            s[j] = q == 0 ? ss : q == 1 ? cc : q == 2 ? -ss : -cc;
+        }
+    }
+};
+template <int R> struct Trig { static constexpr TrigTab<R> v{}; };
+
+constexpr int smallest_prime_factor(int n) {
+    for (int p = 2; p * p <= n; ++p)
+        if (n % p == 0) return p;
+    return n;
+}
+
+// In-register DFT of length R (any product of 3, 5, 7): prime lengths use the
+// symmetric butterflies above, composite ones R = R1 R2 a Cooley-Tukey split
+// (R2 DFTs of length R1, twiddles exp(sg 2 pi i n2 k1 / R), R1 DFTs of length
+// R2, output index k1 + R1 k2).
+template <typename T, int R>
+__device__ __forceinline__ void dftn(Vt<T> *u, T sg) {
+    if constexpr (R == 3 || R == 5 || R == 7) {
+        dft<T, R>(u, sg);
+    } else {
+        constexpr int R1 = smallest_prime_factor(R);
+        constexpr int R2 = R / R1;
+        Vt<T> y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            Vt<T> col[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) col[n1] = u[n1 * R2 + n2];
+            dftn<T, R1>(col, sg);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const int j = (n2 * k1) % R;
+                if (j == 0) {
+                    y[k1 * R2 + n2] = col[k1];
+                } else {
+                    const T c = T(Trig<R>::v.c[j]);
+                    const T sn = sg * T(Trig<R>::v.s[j]);
+                    y[k1 * R2 + n2] = mk<T>(col[k1].x * c - col[k1].y * sn, col[k1].x * sn + col[k1].y * c);
+                }
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            Vt<T> row[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) row[n2] = y[k1 * R2 + n2];
+            dftn<T, R2>(row, sg);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) u[k1 + R1 * k2] = row[k2];
+        }
+    }
+}
+
 // One Stockham stage of radix R over nb independent transforms of length n.
 // Butterfly i (k = i mod p) reads positions i + q n/R, applies the twiddles
 // exp(sg 2 pi i q k / (p R)), a length-R DFT, and writes positions
@@ -141,7 +230,7 @@ __device__ __forceinline__ void stage(const Vt<T> *X, Vt<T> *Y, int n, int p, in
                 u[q] = cmul(u[q], w);
             }
         }
-        dft<T, R>(u, sg);
+        dftn<T, R>(u, sg);
         const int j = (i - k) * R + k;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -164,12 +253,14 @@ __device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const V
     for (int s = 0; s < f.nst; ++s) {
         const int r = f.radix[s];
         const Vt<T> *t = tw + f.twoff[s];
-        if (r == 3)
-            stage<T, 3, ROWL>(X, Y, f.n, p, nb, t, sg);
-        else if (r == 5)
-            stage<T, 5, ROWL>(X, Y, f.n, p, nb, t, sg);
-        else
-            stage<T, 7, ROWL>(X, Y, f.n, p, nb, t, sg);
+        switch (r) {
+            case 3: stage<T, 3, ROWL>(X, Y, f.n, p, nb, t, sg); break;
+            case 5: stage<T, 5, ROWL>(X, Y, f.n, p, nb, t, sg); break;
+            case 7: stage<T, 7, ROWL>(X, Y, f.n, p, nb, t, sg); break;
+            case 9: stage<T, 9, ROWL>(X, Y, f.n, p, nb, t, sg); break;
+            case 15: stage<T, 15, ROWL>(X, Y, f.n, p, nb, t, sg); break;
+            default: stage<T, 25, ROWL>(X, Y, f.n, p, nb, t, sg); break;
+        }
         __syncthreads();
         Vt<T> *tmp = X;
         X = Y;
@@ -825,6 +916,400 @@ __global__ __launch_bounds__(kThreads) void incl_coeff_kernel(double2 *out, int 
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Specialised transforms for the grid sizes in kFastSched: compile-time
+// schedules with composite radices done in registers (Cooley-Tukey with
+// constant internal twiddles), in-place stages staged through registers (one
+// LDS buffer), and all d components of a batch transformed together.
+// ---------------------------------------------------------------------------
+// One in-place Stockham stage over NB transforms of length N: every thread
+// first loads all inputs of its butterflies into registers, then (after a
+// barrier) twiddles, transforms and stores them.
+template <typename T, int R, int N, int P, int NB, bool ROWL>
+__device__ __forceinline__ void stage_ip(Vt<T> *X, const Vt<T> *__restrict__ tw, T sg) {
+    constexpr int TQ = N / R;
+    constexpr int TOT = TQ * NB;
+    constexpr int PER = (TOT + kThreads - 1) / kThreads;
+    Vt<T> u[PER][R];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        if (PER * kThreads == TOT || idx < TOT) {
+            const int b = ROWL ? idx / TQ : idx % NB;
+            const int i = ROWL ? idx % TQ : idx / NB;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int pos = i + q * TQ;
+                u[t][q] = ROWL ? X[b * N + pos] : X[pos * NB + b];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        if (PER * kThreads == TOT || idx < TOT) {
+            const int b = ROWL ? idx / TQ : idx % NB;
+            const int i = ROWL ? idx % TQ : idx / NB;
+            const int k = i % P;
+            if constexpr (P > 1) {
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    Vt<T> w = tw[(q - 1) * P + k];
+                    w.y *= -sg;
+                    u[t][q] = cmul(u[t][q], w);
+                }
+            }
+            dftn<T, R>(u[t], sg);
+            const int j = (i - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int pos = j + q * P;
+                if (ROWL)
+                    X[b * N + pos] = u[t][q];
+                else
+                    X[pos * NB + b] = u[t][q];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int FI, int S, int P, int OFF, int NB, bool ROWL>
+__device__ __forceinline__ void fft_ip(Vt<T> *X, const Vt<T> *tw, T sg) {
+    if constexpr (S < kFastSched[FI].nst) {
+        constexpr int R = kFastSched[FI].r[S];
+        stage_ip<T, R, kFastSched[FI].n, P, NB, ROWL>(X, tw + OFF, sg);
+        fft_ip<T, FI, S + 1, P * R, OFF + (R - 1) * P, NB, ROWL>(X, tw, sg);
+    }
+}
+
+// pencils (or row pairs) per work-group so that one batch of all d
+// components stays within 48 KB of LDS
+constexpr int fast_batch(int n, int es, int d) {
+    int b = 16;
+    while (b > 1 && d * b * n * es > 48 * 1024) b /= 2;
+    return b;
+}
+
+template <typename T, int FI, int D>
+__global__ __launch_bounds__(kThreads) void pencil_fast(PencilArgs a) {
+    using V = Vt<T>;
+    constexpr int N = kFastSched[FI].n;
+    constexpr int B = fast_batch(N, sizeof(V), D);
+    constexpr int NB = D * B;  // LDS layout [pos][component][batch]
+    if (a.status != nullptr && a.status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    V *X = reinterpret_cast<V *>(smem_raw);
+    const int b0 = blockIdx.x * B;
+    const int o = blockIdx.y;
+    const int nbw = min(B, a.nb - b0);
+    const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
+    const T sg = T(a.sgn);
+    const T scale = T(a.scale);
+    const V zero = mk<T>(T(0), T(0));
+    auto freq = [&](int l, int L, int b, int *k1, int *k2, int *k3) {
+        *k1 = wrapi(l, L);
+        if (D == 3) {
+            *k2 = wrapi(b / a.Nh, a.Nmid);
+            *k3 = b % a.Nh;
+        } else {
+            *k2 = b % a.Nh;
+            *k3 = 0;
+        }
+    };
+    if (a.L_in < N || nbw < B) {
+        for (int idx = threadIdx.x; idx < N * NB; idx += kThreads) X[idx] = zero;
+        __syncthreads();
+    }
+    if (a.pro == PRO_EXPAND) {
+        const V *sr = reinterpret_cast<const V *>(a.st_r);
+        V *sp = reinterpret_cast<V *>(a.st_p);
+        const V *sx = reinterpret_cast<const V *>(a.st_x);
+        const T beta = (a.update_p && a.status) ? T(a.status->beta) : T(0);
+        for (int idx = threadIdx.x; idx < a.L_in * B; idx += kThreads) {
+            const int bb = idx % B;
+            const int l = idx / B;
+            if (bb >= nbw) continue;
+            int k1, k2, k3;
+            freq(l, a.L_in, b0 + bb, &k1, &k2, &k3);
+            T t[2][3];
+            const int nt = basis<T>(D, a.kind, k1, k2, k3, t);
+            V v[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                v[c] = zero;
+                if (c < a.nc) {
+                    const long off = c * a.st_cs + (long)l * a.in_ls + b0 + bb;
+                    if (a.update_p) {
+                        const V r = sr[off];
+                        const V pv = sp[off];
+                        v[c] = mk<T>(r.x + beta * pv.x, r.y + beta * pv.y);
+                        sp[off] = v[c];
+                    } else {
+                        v[c] = sx[off];
+                    }
+                }
+            }
+            const int pos = posmod(k1, N);
+#pragma unroll
+            for (int al = 0; al < D; ++al) {
+                T ex = T(0), ey = T(0);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (c < nt) {
+                        ex -= t[c][al] * v[c].y;
+                        ey += t[c][al] * v[c].x;
+                    }
+                }
+                X[pos * NB + al * B + bb] = mk<T>(ex, ey);
+            }
+        }
+    } else {
+        const V *in = reinterpret_cast<const V *>(a.in);
+        for (int idx = threadIdx.x; idx < a.L_in * NB; idx += kThreads) {
+            const int rr = idx % NB;
+            const int l = idx / NB;
+            const int c = rr / B;
+            const int bb = rr - c * B;
+            if (bb >= nbw) continue;
+            X[posmod(wrapi(l, a.L_in), N) * NB + rr] =
+                in[(long)c * a.in_cs + (long)o * a.in_os + (long)l * a.in_ls + b0 + bb];
+        }
+    }
+    __syncthreads();
+    fft_ip<T, FI, 0, 1, 0, NB, false>(X, tw, sg);
+    V *out = reinterpret_cast<V *>(a.out);
+    if (a.epi == EPI_PROJECT) {
+        const V *dv = reinterpret_cast<const V *>(a.st_dot);
+        double part = 0.0;
+        for (int idx = threadIdx.x; idx < a.L_out * B; idx += kThreads) {
+            const int bb = idx % B;
+            const int l = idx / B;
+            if (bb >= nbw) continue;
+            int k1, k2, k3;
+            freq(l, a.L_out, b0 + bb, &k1, &k2, &k3);
+            T t[2][3];
+            const int nt = basis<T>(D, a.kind, k1, k2, k3, t);
+            const int pos = posmod(k1, N);
+            V y[D];
+#pragma unroll
+            for (int al = 0; al < D; ++al) y[al] = X[pos * NB + al * B + bb];
+            const double w = ((b0 + bb) % a.Nh) == 0 ? 1.0 : 2.0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (c < a.nc) {
+                    T qx = T(0), qy = T(0);
+                    if (c < nt) {
+#pragma unroll
+                        for (int al = 0; al < D; ++al) {
+                            const T tt = t[c][al] * scale;
+                            qx += tt * y[al].y;
+                            qy -= tt * y[al].x;
+                        }
+                    }
+                    const long off = c * a.out_cs + (long)l * a.out_ls + b0 + bb;
+                    out[off] = mk<T>(qx, qy);
+                    if (dv != nullptr) {
+                        const V pv = dv[off];
+                        part += w * ((double)pv.x * (double)qx + (double)pv.y * (double)qy);
+                    } else {
+                        part += w * ((double)qx * (double)qx + (double)qy * (double)qy);
+                    }
+                }
+            }
+        }
+        const double s = block_sum(part);
+        if (threadIdx.x == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    } else {
+        for (int idx = threadIdx.x; idx < a.L_out * NB; idx += kThreads) {
+            const int rr = idx % NB;
+            const int l = idx / NB;
+            const int c = rr / B;
+            const int bb = rr - c * B;
+            if (bb >= nbw) continue;
+            V v = X[posmod(wrapi(l, a.L_out), N) * NB + rr];
+            v.x *= scale;
+            v.y *= scale;
+            out[(long)c * a.out_cs + (long)o * a.out_os + (long)l * a.out_ls + b0 + bb] = v;
+        }
+    }
+}
+
+template <typename T, int FI, int D>
+__global__ __launch_bounds__(kThreads) void row_fast(RowArgs a) {
+    using V = Vt<T>;
+    constexpr int N = kFastSched[FI].n;
+    constexpr int RP = fast_batch(N, sizeof(V), D);
+    constexpr int NB = D * RP;  // LDS layout [component][row pair][pos]
+    if (a.status != nullptr && a.status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    V *X = reinterpret_cast<V *>(smem_raw);
+    const int nh = a.Nh_row;
+    const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
+    V *data = reinterpret_cast<V *>(a.data);
+    const T *g = reinterpret_cast<const T *>(a.g);
+    const int pair0 = blockIdx.x * RP;
+    const int nvp = min(RP, (a.nrows + 1) / 2 - pair0);
+    const V zero = mk<T>(T(0), T(0));
+    T A0[D * D], Dm[D * D];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) {
+        A0[i] = T(a.A0[i]);
+        Dm[i] = T(a.D[i]);
+    }
+    if (a.mode == ROW_OPER) {
+        for (int idx = threadIdx.x; idx < N * NB; idx += kThreads) X[idx] = zero;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < NB * nh; idx += kThreads) {
+            const int pc = idx / nh;
+            const int kx = idx - pc * nh;
+            const int c = pc / RP;
+            const int j = pc - c * RP;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
+            const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+            if (kx == 0) {
+                X[pc * N] = mk<T>(u1.x, u2.x);
+            } else {
+                X[pc * N + kx] = mk<T>(u1.x - u2.y, u1.y + u2.x);
+                X[pc * N + N - kx] = mk<T>(u1.x + u2.y, u2.x - u1.y);
+            }
+        }
+        __syncthreads();
+        fft_ip<T, FI, 0, 1, 0, NB, true>(X, tw, T(1));
+        for (int idx = threadIdx.x; idx < RP * N; idx += kThreads) {
+            const int j = idx / N;
+            const int x = idx - j * N;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            const T g1 = g[(long)r1 * N + x];
+            const T g2 = (r2 < a.nrows) ? g[(long)r2 * N + x] : T(0);
+            V e[D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) e[b] = X[(b * RP + j) * N + x];
+#pragma unroll
+            for (int al = 0; al < D; ++al) {
+                T y1 = T(0), y2 = T(0);
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    y1 += (A0[al * D + b] + g1 * Dm[al * D + b]) * e[b].x;
+                    y2 += (A0[al * D + b] + g2 * Dm[al * D + b]) * e[b].y;
+                }
+                X[(al * RP + j) * N + x] = mk<T>(y1, y2);
+            }
+        }
+    } else {  // ROW_RHS: y = A(x) E on both rows, and |y|^2 partial sums
+        double load = 0.0;
+        for (int idx = threadIdx.x; idx < RP * N; idx += kThreads) {
+            const int j = idx / N;
+            const int x = idx - j * N;
+            V y[D];
+#pragma unroll
+            for (int al = 0; al < D; ++al) y[al] = zero;
+            if (j < nvp) {
+                const int r1 = 2 * (pair0 + j);
+                const int r2 = r1 + 1;
+                const bool v2 = r2 < a.nrows;
+                const T g1 = g[(long)r1 * N + x];
+                const T g2 = v2 ? g[(long)r2 * N + x] : T(0);
+#pragma unroll
+                for (int al = 0; al < D; ++al) {
+                    T y1 = T(0), y2 = T(0);
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        y1 += (A0[al * D + b] + g1 * Dm[al * D + b]) * T(a.E[b]);
+                        if (v2) y2 += (A0[al * D + b] + g2 * Dm[al * D + b]) * T(a.E[b]);
+                    }
+                    y[al] = mk<T>(y1, y2);
+                    load += (double)y1 * y1 + (double)y2 * y2;
+                }
+            }
+#pragma unroll
+            for (int al = 0; al < D; ++al) X[(al * RP + j) * N + x] = y[al];
+        }
+        const double s = block_sum(load);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+    }
+    __syncthreads();
+    fft_ip<T, FI, 0, 1, 0, NB, true>(X, tw, T(-1));
+    const T half = T(a.scale) * T(0.5);
+    for (int idx = threadIdx.x; idx < NB * nh; idx += kThreads) {
+        const int pc = idx / nh;
+        const int kx = idx - pc * nh;
+        const int c = pc / RP;
+        const int j = pc - c * RP;
+        if (j >= nvp) continue;
+        const int r1 = 2 * (pair0 + j);
+        const int r2 = r1 + 1;
+        const V w = X[pc * N + kx];
+        const V wm = X[pc * N + (kx == 0 ? 0 : N - kx)];
+        data[(long)c * a.cs + (long)r1 * nh + kx] = mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half);
+        if (r2 < a.nrows)
+            data[(long)c * a.cs + (long)r2 * nh + kx] = mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half);
+    }
+}
+
+template <typename T, int FI, int D>
+void launch_pencil_fast_t(const PencilArgs &a, int nouter, hipStream_t s) {
+    constexpr int N = kFastSched[FI].n;
+    constexpr int B = fast_batch(N, sizeof(Vt<T>), D);
+    const size_t lds = sizeof(Vt<T>) * (size_t)N * D * B;
+    hipLaunchKernelGGL((pencil_fast<T, FI, D>), dim3((a.nb + B - 1) / B, nouter), dim3(kThreads), lds, s, a);
+}
+
+template <typename T, int FI, int D>
+void launch_row_fast_t(const RowArgs &r, hipStream_t s) {
+    constexpr int N = kFastSched[FI].n;
+    constexpr int RP = fast_batch(N, sizeof(Vt<T>), D);
+    const size_t lds = sizeof(Vt<T>) * (size_t)N * D * RP;
+    hipLaunchKernelGGL((row_fast<T, FI, D>), dim3(((r.nrows + 1) / 2 + RP - 1) / RP), dim3(kThreads), lds, s, r);
+}
+
+template <typename T, int FI>
+void launch_pencil_fast_d(const PencilArgs &a, int nouter, hipStream_t s) {
+    if (a.d == 3)
+        launch_pencil_fast_t<T, FI, 3>(a, nouter, s);
+    else
+        launch_pencil_fast_t<T, FI, 2>(a, nouter, s);
+}
+
+template <typename T, int FI>
+void launch_row_fast_d(const RowArgs &r, hipStream_t s) {
+    if (r.d == 3)
+        launch_row_fast_t<T, FI, 3>(r, s);
+    else
+        launch_row_fast_t<T, FI, 2>(r, s);
+}
+
+template <typename T>
+void launch_pencil_fast(const PencilArgs &a, int nouter, hipStream_t s) {
+    switch (fast_index(a.f.n)) {
+        case 0: launch_pencil_fast_d<T, 0>(a, nouter, s); break;
+        case 1: launch_pencil_fast_d<T, 1>(a, nouter, s); break;
+        case 2: launch_pencil_fast_d<T, 2>(a, nouter, s); break;
+        case 3: launch_pencil_fast_d<T, 3>(a, nouter, s); break;
+        case 4: launch_pencil_fast_d<T, 4>(a, nouter, s); break;
+        default: launch_pencil_fast_d<T, 5>(a, nouter, s); break;
+    }
+}
+
+template <typename T>
+void launch_row_fast(const RowArgs &r, hipStream_t s) {
+    switch (fast_index(r.f.n)) {
+        case 0: launch_row_fast_d<T, 0>(r, s); break;
+        case 1: launch_row_fast_d<T, 1>(r, s); break;
+        case 2: launch_row_fast_d<T, 2>(r, s); break;
+        case 3: launch_row_fast_d<T, 3>(r, s); break;
+        case 4: launch_row_fast_d<T, 4>(r, s); break;
+        default: launch_row_fast_d<T, 5>(r, s); break;
+    }
+}
+
 // Device-side validation of a voxel image: per work-group min, max and the
 // number of entries that are not positive finite (part[3 b + 0..2]).
 __global__ __launch_bounds__(kThreads) void image_stats_kernel(const double *img, long n, double *part) {
@@ -894,6 +1379,7 @@ __global__ __launch_bounds__(kThreads) void image_other_kernel(const double *img
 // ---------------------------------------------------------------------------
 size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
+    if (a.fast) return es * (size_t)a.f.n * a.d * a.B;
     int lacc = 0;
     if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
     if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
@@ -902,6 +1388,7 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
+    if (a.fast) return es * (size_t)a.f.n * a.d * a.RP;
     int nz = a.ncomp;
     if (a.mode == ROW_RHS) nz = a.d;
     if (a.mode == ROW_R2C || a.mode == ROW_C2R) nz = 1;
@@ -911,7 +1398,56 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
 int pencil_grid_x(const PencilArgs &a) { return (a.nb + a.B - 1) / a.B; }
 int row_grid(const RowArgs &a) { return ((a.nrows + 1) / 2 + a.RP - 1) / a.RP; }
 
+static_assert(kNumFast == 6, "launch_*_fast switch covers six sizes");
+
+void configure_pencil(PencilArgs &a, bool fp64) {
+    const int fi = fast_index(a.f.n);
+    bool ok = fi >= 0 && a.nsol == 1 && a.ncomp == a.d && a.epi != EPI_WINDOW && (a.d == 2 || a.d == 3) &&
+              a.f.nst == kFastSched[fi].nst;
+    for (int s = 0; ok && s < a.f.nst; ++s) ok = a.f.radix[s] == kFastSched[fi].r[s];
+    if (ok) {
+        a.fast = 1;
+        a.B = fast_batch(a.f.n, fp64 ? 16 : 8, a.d);
+        return;
+    }
+    a.fast = 0;
+    int lacc = 0;
+    if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
+    if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
+    const size_t es = fp64 ? 16 : 8;
+    int B = fp64 ? 8 : 16;
+    while (B > 1 && es * ((size_t)2 * a.f.n * B + (size_t)lacc * B) > 80 * 1024) B /= 2;
+    a.B = B;
+}
+
+void configure_row(RowArgs &r, bool fp64) {
+    const int fi = fast_index(r.f.n);
+    bool ok = fi >= 0 && (r.mode == ROW_OPER || r.mode == ROW_RHS) && r.ncomp == r.d && (r.d == 2 || r.d == 3) &&
+              r.f.nst == kFastSched[fi].nst && r.Nh_row <= (r.f.n + 1) / 2;
+    for (int s = 0; ok && s < r.f.nst; ++s) ok = r.f.radix[s] == kFastSched[fi].r[s];
+    if (ok) {
+        r.fast = 1;
+        r.RP = fast_batch(r.f.n, fp64 ? 16 : 8, r.d);
+        return;
+    }
+    r.fast = 0;
+    int nz = r.ncomp;
+    if (r.mode == ROW_RHS) nz = r.d;
+    if (r.mode == ROW_R2C || r.mode == ROW_C2R) nz = 1;
+    const size_t es = fp64 ? 16 : 8;
+    int RP = 8;
+    while (RP > 1 && es * (size_t)(nz + 1) * RP * r.f.n > 80 * 1024) RP /= 2;
+    r.RP = RP;
+}
+
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s) {
+    if (a.fast) {
+        if (fp64)
+            launch_pencil_fast<double>(a, nouter, s);
+        else
+            launch_pencil_fast<float>(a, nouter, s);
+        return hipGetLastError();
+    }
     dim3 grid(pencil_grid_x(a), nouter);
     const size_t lds = pencil_lds_bytes(a, fp64);
     if (fp64) {
@@ -923,6 +1459,13 @@ hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t
 }
 
 hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s) {
+    if (a.fast) {
+        if (fp64)
+            launch_row_fast<double>(a, s);
+        else
+            launch_row_fast<float>(a, s);
+        return hipGetLastError();
+    }
     const size_t lds = row_lds_bytes(a, fp64);
     if (fp64) {
         hipLaunchKernelGGL(row_kernel<double>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);

@@ -59,6 +59,13 @@ CASES = {
     "voxel2d_N7": (lambda: synth.grf_voxels(11, (9, 9), d=2, corr_len=0.15), (7, 7)),
     "voxel3d_N5": (lambda: synth.grf_voxels(12, (9, 9, 9), d=3, corr_len=0.15), (5, 5, 5)),
     "voxel3d_N7x5x9": (lambda: synth.grf_voxels(13, (15, 9, 21), d=3, corr_len=0.15), (7, 5, 9)),
+    # grid sizes with specialised kernels (81, 125, 225, 245) along each axis
+    "square2d_N63": (lambda: synth.square_inclusion(2, 0.6, 1.0, 10.0, center=(0.03, -0.11)), (63, 41)),
+    "circle2d_N113": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0), (113, 113)),
+    "circle2d_N123": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 30.0, center=(0.2, 0.1)), (123, 63)),
+    "aniso3d_N41x5x63": (lambda: synth.cube_inclusion_aniso(0.45, 6), (41, 5, 63)),
+    "aniso3d_N5x113x9": (lambda: synth.cube_inclusion_aniso(0.4, 8), (5, 113, 9)),
+    "voxel3d_N113x5x5": (lambda: synth.grf_voxels(14, (225, 9, 9), d=3, corr_len=0.1), (113, 5, 5)),
     "voxel2d_multi_N9": (lambda: {"d": 2, "kind": "voxels", "P": (15, 15),
                                   "image": 1.0 + np.arange(225).reshape(15, 15) % 7}, (9, 9)),
 }
@@ -79,7 +86,8 @@ def test_fp64_matches_oracle(fg, name):
         assert abs(a - b) <= max(3, 0.25 * b)
 
 
-@pytest.mark.parametrize("name", ["square2d_N9", "circle2d_N15", "aniso3d_N5", "voxel3d_N5"])
+@pytest.mark.parametrize("name", ["square2d_N9", "circle2d_N15", "aniso3d_N5", "voxel3d_N5", "circle2d_N113",
+                                  "aniso3d_N41x5x63"])
 def test_fp32_iteration_form(fg, name):
     make, N = CASES[name]
     micro = make()
@@ -94,6 +102,20 @@ def test_c1_full_size_against_golden(fg):
     with open(os.path.join(HERE, "golden", "c1.json")) as f:
         gold = json.load(f)
     res = _gpu(fg, synth.square_inclusion(2, 0.6, 1.0, 10.0), (41, 41))
+    assert _rel(res["upper"], gold["upper"]) < 1e-10
+    assert _rel(res["lower"], gold["lower"]) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["c2_365", "c3"])
+def test_full_size_against_golden(fg, case):
+    path = os.path.join(HERE, "golden", case + ".json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    with open(path) as f:
+        gold = json.load(f)
+    N = tuple(gold["N"])
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0) if case.startswith("c2") else synth.cube_inclusion_aniso(0.5, 3)
+    res = _gpu(fg, micro, N, rtol=gold["tol"])
     assert _rel(res["upper"], gold["upper"]) < 1e-10
     assert _rel(res["lower"], gold["lower"]) < 1e-10
 
