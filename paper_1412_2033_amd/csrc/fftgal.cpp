@@ -318,6 +318,7 @@ int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int Bmax, int cls
 }
 
 int run_row(Plan *pl, RowArgs &r, bool fp64, int cls) {
+    configure_row(r, fp64);
     const int nz = r.mode == ROW_GRAM ? r.ncomp : r.d;
     if (row_lds_bytes(r, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "row length %d with %d components too large for one work-group", r.f.n, nz);

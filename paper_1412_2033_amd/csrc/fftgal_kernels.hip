@@ -1395,8 +1395,8 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     return es * (size_t)(nz + 1) * a.RP * a.f.n;
 }
 
-int pencil_grid_x(const PencilArgs &a) { return (a.nb + a.B - 1) / a.B; }
-int row_grid(const RowArgs &a) { return ((a.nrows + 1) / 2 + a.RP - 1) / a.RP; }
+int pencil_grid_x(const PencilArgs &a) { return a.B > 0 ? (a.nb + a.B - 1) / a.B : 0; }
+int row_grid(const RowArgs &a) { return a.RP > 0 ? ((a.nrows + 1) / 2 + a.RP - 1) / a.RP : 0; }
 
 static_assert(kNumFast == 6, "launch_*_fast switch covers six sizes");
 
@@ -1441,6 +1441,7 @@ void configure_row(RowArgs &r, bool fp64) {
 }
 
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s) {
+    if (a.B < 1 || nouter < 1) return hipErrorInvalidValue;
     if (a.fast) {
         if (fp64)
             launch_pencil_fast<double>(a, nouter, s);
@@ -1459,6 +1460,7 @@ hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t
 }
 
 hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s) {
+    if (a.RP < 1) return hipErrorInvalidValue;
     if (a.fast) {
         if (fp64)
             launch_row_fast<double>(a, s);
