@@ -11,9 +11,15 @@ a two-phase voxel image of 225^3 voxels from a seeded Gaussian random field
 timed region starts.
 
 The metric is Mpoint-CG-iter/s: (2N-1)^3 grid points times the CG iterations
-of all six solves, divided by the step time.
+of all six solves, divided by the step time, for the plain FP64 path.  The
+same steps are then timed in the FP32-iteration form (tolerance calibrated so
+that the bounds stay within 1e-6 of the FP64 path), and a sample of the 2D
+serving mix (random circles, contrast 10..1e4, N in {41, 63, 123, 365}) is
+run twice: sequentially through the plain FP64 path, and through the
+continuous-batching loop in the FP32-iteration form with Poisson arrivals at
+0.8x its measured capacity (p50/p99 latency, throughput).
 
-    python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--precision fp64|fp32]
+    python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--serve 32]
 """
 
 import argparse
@@ -117,8 +123,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="form whose rate is the headline value (default: the plain FP64 path)")
     ap.add_argument("--rtol", type=float, default=None)
+    ap.add_argument("--rtol32", type=float, default=5e-6, help="CG tolerance of the FP32-iteration form")
+    ap.add_argument("--serve", type=int, default=32, help="serving-mix requests (0: skip)")
     ap.add_argument("--N", type=int, default=113)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -147,94 +156,150 @@ def main():
     d = 3
     N = (args.N,) * d
     M = tuple(2 * n - 1 for n in N)
-    rtol = args.rtol if args.rtol is not None else 1e-8
-    print("bench: building workload d=3 N=%d M=%d (%s)" % (N[0], M[0], args.precision), file=sys.stderr, flush=True)
+    rtol64 = args.rtol if args.rtol is not None else 1e-8
+    print("bench: building workload d=3 N=%d M=%d" % (N[0], M[0]), file=sys.stderr, flush=True)
     micro = synth.grf_voxels(5, M, d=3, corr_len=0.05, vf=0.4, a_matrix=1.0, a_incl=100.0)
     dev = torch.device("cuda:0")
     micro_dev = dict(micro)
     micro_dev["image"] = torch.from_numpy(np.ascontiguousarray(micro["image"])).to(dev)
-    plan = fftgal.Plan(d, N, args.precision, device=dev, P=M)
-    es = 16 if args.precision == "fp64" else 8
-    gs = 8 if args.precision == "fp64" else 4
-
-    for w in range(args.warmup):
-        res = plan.run(micro_dev, rtol=rtol)
-        print("bench: warmup %d done, iters %s / %s" % (w, [i["iters"] for i in res["info_primal"]],
-                                                        [i["iters"] for i in res["info_dual"]]),
-              file=sys.stderr, flush=True)
-    plan.set_timing(True)
-    plan.read_timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for k in range(args.steps):
-        res = plan.run(micro_dev, rtol=rtol)
-        results.append(res)
-        print("bench: step %d done" % k, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timing = plan.read_timing()
-    plan.set_timing(False)
-
-    ms_per_step = 1e3 * elapsed / args.steps
     pts = M[0] * M[1] * M[2]
-    iters_p = [sum(i["iters"] for i in r["info_primal"]) for r in results]
-    iters_d = [sum(i["iters"] for i in r["info_dual"]) for r in results]
-    total_iters = sum(iters_p) + sum(iters_d)
-    value = pts * total_iters / elapsed / 1e6
 
-    # dominant kernel and its roofline (algorithmic bytes / measured duration)
-    nc_p, nc_d = 1, d - 1
-    per_cls = {}
-    for cls, (ms, cnt) in timing.items():
-        if cnt == 0:
-            continue
-        by = algorithmic_bytes(cls, d, N, M, es, gs, nc_p) * sum(iters_p) + \
-            algorithmic_bytes(cls, d, N, M, es, gs, nc_d) * sum(iters_d)
-        per_cls[cls] = {"ms": round(ms, 3), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 2),
-                        "GBs": round(by / (ms * 1e-3) / 1e9, 1) if by > 0 else None}
-    dom = max((c for c in per_cls if per_cls[c]["GBs"]), key=lambda c: per_cls[c]["ms"])
-    work_launches = total_iters
-    dom_bytes = (algorithmic_bytes(dom, d, N, M, es, gs, nc_p) * sum(iters_p) +
-                 algorithmic_bytes(dom, d, N, M, es, gs, nc_d) * sum(iters_d)) / work_launches
-    dom_avg_s = timing[dom][0] * 1e-3 / timing[dom][1]
-    achieved = dom_bytes / dom_avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, args.precision), "kernel": dom,
-                "bytes_per_launch": int(dom_bytes), "avg_launch_us": round(dom_avg_s * 1e6, 2)}
+    def time_form(precision, rtol):
+        plan = fftgal.Plan(d, N, precision, device=dev, P=M)
+        es = 16 if precision == "fp64" else 8
+        gs = 8 if precision == "fp64" else 4
+        for w in range(args.warmup):
+            res = plan.run(micro_dev, rtol=rtol)
+            print("bench: %s warmup %d done, iters %s / %s" % (
+                precision, w, [i["iters"] for i in res["info_primal"]], [i["iters"] for i in res["info_dual"]]),
+                file=sys.stderr, flush=True)
+        plan.set_timing(True)
+        plan.read_timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = []
+        for k in range(args.steps):
+            results.append(plan.run(micro_dev, rtol=rtol))
+            print("bench: %s step %d done" % (precision, k), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        timing = plan.read_timing()
+        plan.set_timing(False)
+        plan.close()
+        iters_p = sum(sum(i["iters"] for i in r["info_primal"]) for r in results)
+        iters_d = sum(sum(i["iters"] for i in r["info_dual"]) for r in results)
+        total_iters = iters_p + iters_d
+        # per-class rates and the dominant kernel's roofline (algorithmic bytes / measured duration)
+        per_cls = {}
+        for cls, (ms, cnt) in timing.items():
+            if cnt == 0:
+                continue
+            by = algorithmic_bytes(cls, d, N, M, es, gs, 1) * iters_p + \
+                algorithmic_bytes(cls, d, N, M, es, gs, d - 1) * iters_d
+            per_cls[cls] = {"ms": round(ms, 3), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 2),
+                            "GBs": round(by / (ms * 1e-3) / 1e9, 1) if by > 0 else None}
+        dom = max((c for c in per_cls if per_cls[c]["GBs"]), key=lambda c: per_cls[c]["ms"])
+        dom_bytes = (algorithmic_bytes(dom, d, N, M, es, gs, 1) * iters_p +
+                     algorithmic_bytes(dom, d, N, M, es, gs, d - 1) * iters_d) / total_iters
+        dom_avg_s = timing[dom][0] * 1e-3 / timing[dom][1]
+        achieved = dom_bytes / dom_avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, precision),
+                "kernel": dom, "bytes_per_launch": int(dom_bytes), "avg_launch_us": round(dom_avg_s * 1e6, 2)}
+        last = results[-1]
+        return {"elapsed": elapsed, "value": pts * total_iters / elapsed / 1e6, "ms_per_step": 1e3 * elapsed / args.steps,
+                "kernels": per_cls, "roofline": roof, "last": last,
+                "iters": {"primal": [i["iters"] for i in last["info_primal"]],
+                          "dual": [i["iters"] for i in last["info_dual"]]}}
 
-    last = results[-1]
+    main_prec = args.precision
+    main_rtol = rtol64 if main_prec == "fp64" else args.rtol32
+    prim = time_form(main_prec, main_rtol)
+    other_prec = "fp32" if main_prec == "fp64" else "fp64"
+    other = time_form(other_prec, args.rtol32 if other_prec == "fp32" else rtol64)
+    f64 = prim if main_prec == "fp64" else other
+    f32 = other if main_prec == "fp64" else prim
+
+    def rel(a, b):
+        return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+    last = prim["last"]
     out = {
         "metric": "Mpoint*CG-iter/s (time-to-bounds at d=3,N=113)",
-        "value": round(value, 2),
+        "value": round(prim["value"], 2),
         "unit": "Mpoint*CG-iter/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 2),
+        "ms_per_step": round(prim["ms_per_step"], 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": "f64" if main_prec == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "3D two-phase GRF voxel composite (corr. length 0.05, vf 0.4, contrast 1:100), "
-                               "Ga primal+dual CG to rel. residual %g, bounds in FP64" % rtol,
-                   "d": d, "N": N[0], "M": M[0], "P": M[0], "precision": args.precision},
-        "time_to_bounds_s": round(ms_per_step / 1e3, 4),
-        "cg_iterations": {"primal": [i["iters"] for i in last["info_primal"]],
-                          "dual": [i["iters"] for i in last["info_dual"]]},
+        "config": {"workload": "3D two-phase GRF voxel composite (225^3 voxels, corr. length 0.05, vf 0.4, "
+                               "contrast 1:100), Ga primal+dual CG to rel. residual %g, bounds in FP64" % main_rtol,
+                   "d": d, "N": N[0], "M": M[0], "P": M[0], "precision": main_prec},
+        "time_to_bounds_s": round(prim["ms_per_step"] / 1e3, 4),
+        "cg_iterations": prim["iters"],
         "upper_diag": [round(float(v), 10) for v in np.diag(last["upper"])],
         "lower_diag": [round(float(v), 10) for v in np.diag(last["lower"])],
         "gap": last["gap"],
-        "kernels": per_cls,
-        "roofline": roofline,
+        "kernels": prim["kernels"],
+        "roofline": prim["roofline"],
+        "fp32_iteration_form": {
+            "rtol": args.rtol32, "time_to_bounds_s": round(f32["ms_per_step"] / 1e3, 4),
+            "Mpoint_iter_per_s": round(f32["value"], 1), "cg_iterations": f32["iters"],
+            "bound_rel_err_vs_fp64": max(rel(f32["last"][k], f64["last"][k]) for k in ("upper", "lower")),
+            "speedup_vs_fp64": round(f64["ms_per_step"] / f32["ms_per_step"], 3),
+            "roofline": f32["roofline"]},
     }
-    plan.close()
+    if args.serve > 0:
+        out["serving"] = serving_bench(args.serve, args.rtol32)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(micro, N, d)
     print(json.dumps(out), flush=True)
+
+
+def serving_bench(n, rtol, seed=4):
+    """Serving-mix sample: sequential plain FP64 vs continuous-batched FP32 iterations, same tolerance."""
+    import numpy as np
+    import synth
+    from paper_1412_2033_amd import serve
+    base = synth.serving_requests(seed, n, rate_per_s=1.0)
+    print("bench: serving sample of %d requests: sequential FP64" % n, file=sys.stderr, flush=True)
+    seq, t_seq = serve.sequential(base, precision="fp64", rtol=rtol)
+    by = {r["id"]: r for r in seq}
+    at_once = [dict(r, arrival_s=0.0) for r in base]
+    srv = serve.Server(precision="fp32", rtol=rtol)
+    print("bench: serving: batched FP32, all requests at t=0", file=sys.stderr, flush=True)
+    rec0, st0 = srv.run(at_once)
+    capacity = n / st0["wall_s"]
+    rate = 0.8 * capacity
+    reqs = synth.serving_requests(seed, n, rate_per_s=rate)
+    print("bench: serving: Poisson arrivals at %.1f req/s" % rate, file=sys.stderr, flush=True)
+    rec, st = srv.run(reqs)
+    srv.close()
+    lat = [r["latency_s"] for r in rec]
+    seq_t = [r["seconds"] for r in seq]
+    err = max(float(np.linalg.norm(r[k] - by[r["id"]][k]) / np.linalg.norm(by[r["id"]][k]))
+              for r in rec for k in ("upper", "lower"))
+    bad = sum(1 for r in rec for s in r["status"] if s != 0)
+    return {"requests": n, "mix": "2D random circles k~U{5..50}, r~U[0.02,0.08], contrast logU[10,1e4], "
+                                  "N in {41,63,123,365}",
+            "rtol": rtol,
+            "sequential_fp64": {"wall_s": round(t_seq, 3), "req_per_s": round(n / t_seq, 2),
+                                "p50_s": round(serve.percentile(seq_t, 50), 4),
+                                "p99_s": round(serve.percentile(seq_t, 99), 4)},
+            "batched_fp32_capacity": {"wall_s": round(st0["wall_s"], 3), "req_per_s": round(capacity, 2),
+                                      "Mpoint_iter_per_s": round(st0["Mpoint_iter_per_s"], 1)},
+            "batched_fp32_poisson": {"rate_req_per_s": round(rate, 2), "wall_s": round(st["wall_s"], 3),
+                                     "p50_s": round(serve.percentile(lat, 50), 4),
+                                     "p99_s": round(serve.percentile(lat, 99), 4),
+                                     "Mpoint_iter_per_s": round(st["Mpoint_iter_per_s"], 1)},
+            "throughput_speedup_vs_sequential_fp64": round(capacity / (n / t_seq), 2),
+            "max_bound_rel_diff_vs_fp64": err, "solves_not_converged": bad}
 
 
 if __name__ == "__main__":

@@ -207,6 +207,41 @@ enum fftgal_kernel_class {
 int fftgal_set_timing(struct fftgal_plan *plan, int enable);
 int fftgal_read_timing(struct fftgal_plan *plan, double *ms, int32_t *count);
 
+/*
+ * Batched CG (continuous batching of solves across plans; not in the paper).
+ *
+ * A batch advances many solves at once: every launch of one CG iteration
+ * (each transform pass, the alpha/update/check kernels) covers all member
+ * solves that share a grid size, precision and dimension, with per-solve
+ * argument tables in the batch workspace.  Members join with
+ * fftgal_batch_add (which computes the right-hand side at once) and leave when
+ * their stopping test is met, so new solves can join while others run.  Each
+ * solve's reductions use only its own work-groups in a fixed order, so its
+ * result is bitwise identical whether it runs alone, through
+ * fftgal_solve_primal/dual, or in any mix.
+ *
+ * Every plan added must use the batch's stream, and a plan can have one solve
+ * in a batch at a time (its CG vectors and transform buffers are per plan).
+ * The workspace is caller-owned device memory of
+ * fftgal_batch_workspace_bytes(capacity) bytes.
+ */
+size_t fftgal_batch_workspace_bytes(int capacity);
+int fftgal_batch_create(struct fftgal_batch **out, int capacity, void *dev_workspace, size_t bytes,
+                        void *hip_stream);
+/* Start solve (kind 0 = primal, 1 = dual; alpha in 0..d-1) of `plan`; writes
+ * an identifier to *solve_id.  ESTATE if the plan has no material or already
+ * has a solve in the batch; ENOMEM if the batch is full. */
+int fftgal_batch_add(struct fftgal_batch *b, struct fftgal_plan *plan, int kind, int alpha, double rtol,
+                     int maxit, int *solve_id);
+/* Enqueue `iterations` batched CG iterations, wait, and retire finished
+ * solves; *n_active receives the number still running. */
+int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active);
+/* Pop one retired solve: returns 1 and fills *solve_id, *info and *status (the
+ * code fftgal_solve_* would have returned), or 0 if none is waiting. */
+int fftgal_batch_poll(struct fftgal_batch *b, int *solve_id, fftgal_info *info, int *status);
+int fftgal_batch_destroy(struct fftgal_batch *b);
+const char *fftgal_batch_last_error(const struct fftgal_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace fftgal;
@@ -20,6 +23,13 @@ namespace {
 thread_local std::string g_plan_error = "no error";
 
 constexpr int kMaxHist = 20000;      // CG history entries kept per solve
+// Device argument tables of the specialised kernels: one zero offset, the
+// captured passes of the current solve, its CG items, and a ring for
+// one-off launches (set-up, right-hand side).
+constexpr size_t kArgSlot = 1024;    // bytes per argument slot (>= sizeof PencilArgs / RowArgs)
+constexpr int kIterSlots = 8;
+constexpr int kRingSlots = 32;
+constexpr size_t kArgsBytes = kArgSlot * (2 + kIterSlots + kRingSlots);
 constexpr int kUpdateBlocks = 1024;  // fixed grid of the CG update kernel
 constexpr double kFloor64 = 1e-14;   // residual floor relative to ||A_M E|| (FP64)
 constexpr double kFloor32 = 1e-7;    // (FP32 iterations)
@@ -89,7 +99,7 @@ bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o) {
 
 struct Layout {
     size_t tw64, tw32, twP64, twP32, T1, T2, r, p, q, xsol, xsol64, gA64, gB64, gA32, gB32, part_a, part_b,
-        part_c, gram, status, hist, total;
+        part_c, gram, args, status, hist, total;
     size_t tw_len, twP_len;  // complex entries per table region
     size_t part_len;         // doubles per partial region
 };
@@ -159,6 +169,7 @@ Layout make_layout(const Dims &D, int precision) {
     L.part_b = take(L.part_len * 8);
     L.part_c = take(L.part_len * 8);
     L.gram = take(64 * 8);
+    L.args = take(kArgsBytes);
     L.status = take(6 * sizeof(CgStatus));
     L.hist = take((size_t)6 * 2 * (kMaxHist + 1) * 8);
     L.total = align256(off);
@@ -189,6 +200,17 @@ void build_fft(int n, size_t tw_base_entry, std::vector<double> &tab, FftDesc *f
 
 }  // namespace
 
+// One captured pass launch (see Plan::capture).
+struct PassRec {
+    int type;  // 0 pencil, 1 row
+    int cls;
+    int nouter;
+    int grid;
+    bool fp64;
+    PencilArgs pa;
+    RowArgs ra;
+};
+
 struct fftgal_plan {
     Dims D;
     Layout Lo;
@@ -204,6 +226,7 @@ struct fftgal_plan {
     double A0[9], DA[9], B0[9], DB[9];
     bool solved[2][3] = {{false, false, false}, {false, false, false}};
     fftgal_info last_info[2][3];
+    bool busy = false;     // a solve of this plan is a member of a batch
     bool hist_on = false;  // per-iteration (rr, alpha) history; only when maxit <= kMaxHist
     int cur_alpha = 0;
     // kernel timing (fftgal_set_timing)
@@ -216,6 +239,14 @@ struct fftgal_plan {
     std::vector<hipEvent_t> pool;
     double t_ms[FFTGAL_K_COUNT] = {0};
     int32_t t_cnt[FFTGAL_K_COUNT] = {0};
+    // pass capture: while non-null, pass launches are recorded instead of run
+    std::vector<PassRec> *capture = nullptr;
+    int ring = 0;
+    unsigned char ring_host[kRingSlots][kArgSlot];
+    unsigned char iter_host[kIterSlots][kArgSlot];
+    char *arg_slot(int i) { return ws + Lo.args + kArgSlot * (size_t)i; }  // 0: offsets {0}
+    char *iter_slot(int i) { return arg_slot(2 + i); }
+    char *ring_slot(int i) { return arg_slot(2 + kIterSlots + i); }
     std::string err = "no error";
 
     template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -307,11 +338,44 @@ PencilArgs base_pencil(Plan *pl, const FftDesc &f, bool fp64, bool tabP = false)
     return a;
 }
 
+// Copy a specialised kernel's arguments into the next ring slot (stream
+// ordered) and return the device address.
+template <typename A>
+void *ring_upload(Plan *pl, const A &a, hipError_t *err) {
+    static_assert(sizeof(A) <= kArgSlot, "argument slot too small");
+    const int i = pl->ring;
+    pl->ring = (pl->ring + 1) % kRingSlots;
+    std::memcpy(pl->ring_host[i], &a, sizeof(A));
+    *err = hipMemcpyAsync(pl->ring_slot(i), pl->ring_host[i], sizeof(A), hipMemcpyHostToDevice, pl->stream);
+    return pl->ring_slot(i);
+}
+
 int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int Bmax, int cls) {
     (void)Bmax;
     configure_pencil(a, fp64);
     if (pencil_lds_bytes(a, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "transform length %d too large for one work-group", a.f.n);
+    if (pl->capture) {
+        PassRec r{};
+        r.type = 0;
+        r.cls = cls;
+        r.nouter = nouter;
+        r.grid = pencil_grid(a, nouter);
+        r.fp64 = fp64;
+        r.pa = a;
+        pl->capture->push_back(r);
+        return FFTGAL_OK;
+    }
+    if (a.fast) {
+        hipError_t e;
+        void *dev = ring_upload(pl, a, &e);
+        HIPCHECK(pl, e);
+        Timed t(pl, cls);
+        HIPCHECK(pl, launch_pencil_multi(a, reinterpret_cast<const PencilArgs *>(dev),
+                                         reinterpret_cast<const int *>(pl->arg_slot(0)), 1, pencil_grid(a, nouter),
+                                         fp64, pl->stream));
+        return FFTGAL_OK;
+    }
     Timed t(pl, cls);
     HIPCHECK(pl, launch_pencil(a, nouter, fp64, pl->stream));
     return FFTGAL_OK;
@@ -322,6 +386,27 @@ int run_row(Plan *pl, RowArgs &r, bool fp64, int cls) {
     const int nz = r.mode == ROW_GRAM ? r.ncomp : r.d;
     if (row_lds_bytes(r, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "row length %d with %d components too large for one work-group", r.f.n, nz);
+    if (pl->capture) {
+        PassRec rec{};
+        rec.type = 1;
+        rec.cls = cls;
+        rec.nouter = 1;
+        rec.grid = row_grid(r);
+        rec.fp64 = fp64;
+        rec.ra = r;
+        pl->capture->push_back(rec);
+        return FFTGAL_OK;
+    }
+    if (r.fast) {
+        hipError_t e;
+        void *dev = ring_upload(pl, r, &e);
+        HIPCHECK(pl, e);
+        Timed t(pl, cls);
+        HIPCHECK(pl, launch_row_multi(r, reinterpret_cast<const RowArgs *>(dev),
+                                      reinterpret_cast<const int *>(pl->arg_slot(0)), 1, row_grid(r), fp64,
+                                      pl->stream));
+        return FFTGAL_OK;
+    }
     Timed t(pl, cls);
     HIPCHECK(pl, launch_row(r, fp64, pl->stream));
     return FFTGAL_OK;
@@ -710,36 +795,125 @@ bool overlap(int d, int s1, const double *c1, const double *h1, int s2, const do
 
 // ---- CG driver ---------------------------------------------------------------
 
-int enqueue_iteration(Plan *pl, int kind, CgStatus *st, void *x, bool fp64) {
+// One CG iteration of a solve in captured form: its transform passes (in
+// order) and the arguments of the multi-problem CG kernels.
+struct IterCfg {
+    std::vector<PassRec> passes;
+    UpdArgs upd;
+    CgItem item;
+    bool fp64 = true;
+};
+
+int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
     const Dims &D = pl->D;
+    CgStatus *st = pl->status(kind, alpha);
+    void *x = pl->xsol(kind, alpha);
+    cfg->passes.clear();
+    cfg->fp64 = fp64;
+    pl->capture = &cfg->passes;
     void *rows = nullptr;
-    int rc = inverse_passes(pl, fp64, kind, nullptr, 0, 1, true, st, &rows, FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV);
-    if (rc) return rc;
-    RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind);
-    r.status = st;
-    rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
-    if (rc) return rc;
     int npq = 0;
-    rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.q, pl->ws + pl->Lo.p, 1.0 / (double)D.Mtot, st,
-                        pl->at<double>(pl->Lo.part_a), &npq, FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT);
+    int rc = inverse_passes(pl, fp64, kind, nullptr, 0, 1, true, st, &rows, FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV);
+    if (!rc) {
+        RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind);
+        r.status = st;
+        rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
+    }
+    if (!rc)
+        rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.q, pl->ws + pl->Lo.p, 1.0 / (double)D.Mtot, st,
+                            pl->at<double>(pl->Lo.part_a), &npq, FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT);
+    pl->capture = nullptr;
     if (rc) return rc;
-    {
-        Timed t(pl, FFTGAL_K_CG_SCALAR);
-        HIPCHECK(pl, launch_cg_alpha(st, pl->at<double>(pl->Lo.part_a), npq, pl->stream));
-    }
     const int nc = pl->nc(kind);
-    {
-        Timed t(pl, FFTGAL_K_CG_UPDATE);
-        HIPCHECK(pl, launch_cg_update(x, pl->ws + pl->Lo.r, pl->ws + pl->Lo.p, pl->ws + pl->Lo.q, D.Ns, nc, D.Ns,
-                                      D.Nh, st, pl->at<double>(pl->Lo.part_c), kUpdateBlocks, fp64, pl->stream));
-    }
-    double *hist = pl->hist_on ? pl->hist(kind, pl->cur_alpha) : nullptr;
-    Timed t(pl, FFTGAL_K_CG_SCALAR);
-    HIPCHECK(pl, launch_cg_check(st, pl->at<double>(pl->Lo.part_c), kUpdateBlocks, hist, pl->stream));
+    UpdArgs u{};
+    u.x = x;
+    u.r = pl->ws + pl->Lo.r;
+    u.p = pl->ws + pl->Lo.p;
+    u.q = pl->ws + pl->Lo.q;
+    u.n_per_comp = D.Ns;
+    u.cs = D.Ns;
+    u.nc = nc;
+    u.Nh = D.Nh;
+    u.nblocks = update_blocks((long)nc * D.Ns);
+    u.st = st;
+    u.partial = pl->at<double>(pl->Lo.part_c);
+    cfg->upd = u;
+    CgItem it{};
+    it.st = st;
+    it.pq_part = pl->at<double>(pl->Lo.part_a);
+    it.npq = npq;
+    it.rr_part = pl->at<double>(pl->Lo.part_c);
+    it.nrr = u.nblocks;
+    it.hist = pl->hist_on ? pl->hist(kind, alpha) : nullptr;
+    it.hist_cap = kMaxHist + 1;
+    it.mirror = nullptr;
+    cfg->item = it;
     return FFTGAL_OK;
 }
 
-int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info *info) {
+// Upload a captured iteration into the plan's iteration argument slots.
+int upload_iteration(Plan *pl, const IterCfg &cfg) {
+    if (cfg.passes.size() > 5) return fail(pl, FFTGAL_EINVAL, "too many passes");
+    for (size_t i = 0; i < cfg.passes.size(); ++i) {
+        const PassRec &r = cfg.passes[i];
+        const bool fast = r.type == 0 ? r.pa.fast : r.ra.fast;
+        if (!fast) continue;
+        const size_t sz = r.type == 0 ? sizeof(PencilArgs) : sizeof(RowArgs);
+        std::memcpy(pl->iter_host[i], r.type == 0 ? (const void *)&r.pa : (const void *)&r.ra, sz);
+        HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot((int)i), pl->iter_host[i], sz, hipMemcpyHostToDevice, pl->stream));
+    }
+    std::memcpy(pl->iter_host[6], &cfg.upd, sizeof(UpdArgs));
+    std::memcpy(pl->iter_host[7], &cfg.item, sizeof(CgItem));
+    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(6), pl->iter_host[6], sizeof(UpdArgs), hipMemcpyHostToDevice, pl->stream));
+    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(7), pl->iter_host[7], sizeof(CgItem), hipMemcpyHostToDevice, pl->stream));
+    return FFTGAL_OK;
+}
+
+// Launch one captured pass of a single plan (specialised passes read their
+// arguments from `dev_args`).
+int launch_pass(Plan *pl, const PassRec &r, const void *dev_args) {
+    Timed t(pl, r.cls);
+    const int *woff0 = reinterpret_cast<const int *>(pl->arg_slot(0));
+    if (r.type == 0) {
+        if (r.pa.fast)
+            HIPCHECK(pl, launch_pencil_multi(r.pa, reinterpret_cast<const PencilArgs *>(dev_args), woff0, 1, r.grid,
+                                             r.fp64, pl->stream));
+        else
+            HIPCHECK(pl, launch_pencil(r.pa, r.nouter, r.fp64, pl->stream));
+    } else {
+        if (r.ra.fast)
+            HIPCHECK(pl, launch_row_multi(r.ra, reinterpret_cast<const RowArgs *>(dev_args), woff0, 1, r.grid, r.fp64,
+                                          pl->stream));
+        else
+            HIPCHECK(pl, launch_row(r.ra, r.fp64, pl->stream));
+    }
+    return FFTGAL_OK;
+}
+
+int enqueue_iteration(Plan *pl, const IterCfg &cfg) {
+    for (size_t i = 0; i < cfg.passes.size(); ++i) {
+        const int rc = launch_pass(pl, cfg.passes[i], pl->iter_slot((int)i));
+        if (rc) return rc;
+    }
+    const CgItem *item = reinterpret_cast<const CgItem *>(pl->iter_slot(7));
+    const UpdArgs *upd = reinterpret_cast<const UpdArgs *>(pl->iter_slot(6));
+    const int *woff0 = reinterpret_cast<const int *>(pl->arg_slot(0));
+    {
+        Timed t(pl, FFTGAL_K_CG_SCALAR);
+        HIPCHECK(pl, launch_cg_alpha_multi(item, 1, pl->stream));
+    }
+    {
+        Timed t(pl, FFTGAL_K_CG_UPDATE);
+        HIPCHECK(pl, launch_cg_update_multi(upd, woff0, 1, cfg.upd.nblocks, cfg.fp64, pl->stream));
+    }
+    Timed t(pl, FFTGAL_K_CG_SCALAR);
+    HIPCHECK(pl, launch_cg_check_multi(item, 1, pl->stream));
+    return FFTGAL_OK;
+}
+
+// Right-hand side r_0 = -P^* F_M (A_M E), ||A_M E||, status initialisation,
+// x = p = 0 (stream ordered; no host synchronisation).
+int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     const Dims &D = pl->D;
     const bool fp64 = pl->fp64_iter();
     CgStatus *st = pl->status(kind, alpha);
@@ -748,7 +922,6 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
     pl->cur_alpha = alpha;
     const size_t es = fp64 ? 16 : 8;
     const size_t vbytes = (size_t)pl->nc(kind) * D.Ns * es;
-    // right-hand side r_0 = -P^* F_M (A_M E) and ||A_M E||^2
     void *rows = pl->ws + (D.d == 3 ? pl->Lo.T2 : pl->Lo.T1);
     RowArgs r = base_row(pl, fp64, ROW_RHS, rows, kind);
     for (int a = 0; a < 3; ++a) r.E[a] = (a == alpha) ? 1.0 : 0.0;
@@ -760,15 +933,40 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
     rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.r, nullptr, -1.0 / (double)D.Mtot, nullptr,
                         pl->at<double>(pl->Lo.part_a), &nrr, FFTGAL_K_RHS, FFTGAL_K_RHS);
     if (rc) return rc;
-    {
-        // The load sums |A_M E|^2 over grid points; (., .)_{R^{d x M}} divides by |M|.
-        Timed t(pl, FFTGAL_K_CG_SCALAR);
-        HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload,
-                                    rtol, (fp64 ? kFloor64 : kFloor32) / std::sqrt((double)D.Mtot), maxit,
-                                    pl->hist(kind, alpha), pl->stream));
-        HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
-        HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
-    }
+    // The load sums |A_M E|^2 over grid points; (., .)_{R^{d x M}} divides by |M|.
+    Timed t(pl, FFTGAL_K_CG_SCALAR);
+    HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload, rtol,
+                                (fp64 ? kFloor64 : kFloor32) / std::sqrt((double)D.Mtot), maxit,
+                                pl->hist(kind, alpha), pl->stream));
+    HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
+    HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
+    return FFTGAL_OK;
+}
+
+int finish_solve(Plan *pl, int kind, int alpha, const CgStatus &h, fftgal_info *info) {
+    fftgal_info inf{};
+    inf.iters = h.iter;
+    inf.converged = h.converged;
+    inf.res0 = std::sqrt(std::max(0.0, h.rr0));
+    inf.rel_res = h.rr0 > 0 ? std::sqrt(std::max(0.0, h.rr) / h.rr0) : 0.0;
+    pl->last_info[kind][alpha] = inf;
+    if (info) *info = inf;
+    pl->solved[kind][alpha] = true;
+    if (h.breakdown) return fail(pl, FFTGAL_EBREAKDOWN, "CG breakdown (non-SPD or non-finite material)");
+    if (!h.converged) return fail(pl, FFTGAL_ENOTCONV, "CG did not converge in %d iterations", h.maxit);
+    return FFTGAL_OK;
+}
+
+int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info *info) {
+    const bool fp64 = pl->fp64_iter();
+    CgStatus *st = pl->status(kind, alpha);
+    int rc = start_solve(pl, kind, alpha, rtol, maxit);
+    if (rc) return rc;
+    IterCfg cfg;
+    rc = capture_iteration(pl, kind, alpha, fp64, &cfg);
+    if (rc) return rc;
+    rc = upload_iteration(pl, cfg);
+    if (rc) return rc;
     // Iterations are enqueued in chunks without host synchronisation; after a
     // chunk the host reads the status and sizes the next chunk from the
     // observed per-iteration residual reduction, so that few no-op launches
@@ -781,7 +979,7 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
     for (;;) {
         const int todo = std::min(chunk, std::max(0, maxit - enq));
         for (int i = 0; i < todo; ++i) {
-            rc = enqueue_iteration(pl, kind, st, x, fp64);
+            rc = enqueue_iteration(pl, cfg);
             if (rc) return rc;
         }
         enq += todo;
@@ -799,22 +997,13 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
         it_prev = h.iter;
         rr_prev = h.rr;
     }
-    fftgal_info inf{};
-    inf.iters = h.iter;
-    inf.converged = h.converged;
-    inf.res0 = std::sqrt(std::max(0.0, h.rr0));
-    inf.rel_res = h.rr0 > 0 ? std::sqrt(std::max(0.0, h.rr) / h.rr0) : 0.0;
-    pl->last_info[kind][alpha] = inf;
-    if (info) *info = inf;
-    pl->solved[kind][alpha] = true;
-    if (h.breakdown) return fail(pl, FFTGAL_EBREAKDOWN, "CG breakdown (non-SPD or non-finite material)");
-    if (!h.converged) return fail(pl, FFTGAL_ENOTCONV, "CG did not converge in %d iterations", maxit);
-    return FFTGAL_OK;
+    return finish_solve(pl, kind, alpha, h, info);
 }
 
 int solve_entry(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info *info) {
     if (!pl) return FFTGAL_EINVAL;
     if (!pl->have_mat) return fail(pl, FFTGAL_ESTATE, "no material set");
+    if (pl->busy) return fail(pl, FFTGAL_ESTATE, "the plan has a solve in a batch");
     if (alpha < -1 || alpha >= pl->D.d) return fail(pl, FFTGAL_EINVAL, "alpha %d out of range", alpha);
     if (!(rtol >= 0.0) || maxit < 0) return fail(pl, FFTGAL_EINVAL, "rtol must be >= 0 and maxit >= 0");
     int worst = FFTGAL_OK;
@@ -875,6 +1064,7 @@ int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision
     hipError_t e = hipMemcpyAsync(pl->ws + Lo.tw64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, pl->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pl->ws + Lo.tw32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess) e = launch_fill_zero(pl->ws + Lo.args, kArgsBytes, pl->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
     if (e != hipSuccess) {
         delete pl;
@@ -887,6 +1077,7 @@ int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision
 int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
     if (!pl) return FFTGAL_EINVAL;
     if (!m) return fail(pl, FFTGAL_EINVAL, "material is NULL");
+    if (pl->busy) return fail(pl, FFTGAL_ESTATE, "the plan has a solve in a batch");
     const Dims &D = pl->D;
     const int d = D.d;
     pl->have_mat = false;
@@ -1186,6 +1377,7 @@ int fftgal_read_timing(struct fftgal_plan *pl, double *ms, int32_t *count) {
 
 int fftgal_destroy(struct fftgal_plan *pl) {
     if (!pl) return FFTGAL_OK;
+    if (pl->busy) return fail(pl, FFTGAL_ESTATE, "the plan has a solve in a batch");
     if (!pl->evs.empty()) (void)hipStreamSynchronize(pl->stream);
     for (const auto &e : pl->evs) {
         (void)hipEventDestroy(e.a);
@@ -1204,5 +1396,296 @@ int fftgal_grid_size(const struct fftgal_plan *pl, int axis) {
     if (!pl || axis < 0 || axis >= pl->D.d) return 0;
     return pl->D.M[axis];
 }
+
+}  // extern "C"
+
+// ---- batched CG ------------------------------------------------------------
+
+struct fftgal_batch {
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t bytes = 0;
+    int cap = 0;
+    struct Member {
+        Plan *pl;
+        int kind, alpha, id;
+        IterCfg cfg;
+    };
+    std::vector<Member> members;
+    struct Done {
+        int id;
+        fftgal_info info;
+        int status;
+    };
+    std::deque<Done> done;
+    bool dirty = true;
+    struct Group {
+        size_t pass;
+        int np, total;
+        size_t args_off, woff_off;
+        PassRec proto;
+    };
+    std::vector<Group> groups;
+    struct UGroup {
+        bool fp64;
+        int np, total;
+        size_t args_off, woff_off;
+    };
+    std::vector<UGroup> ugroups;
+    size_t items_off = 0;
+    size_t blob_base = 0;  // device offset of the argument blob
+    std::vector<unsigned char> blob;
+    std::vector<CgStatus> mirror_host;
+    int next_id = 0;
+    std::string err = "no error";
+};
+typedef struct fftgal_batch Batch;
+
+namespace {
+
+int bfail(Batch *b, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    return code;
+}
+
+#define BHIPCHECK(b, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return bfail(b, FFTGAL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t blob_put(std::vector<unsigned char> &blob, const void *p, size_t n) {
+    const size_t off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + n);
+    std::memcpy(blob.data() + off, p, n);
+    return off;
+}
+
+bool pass_fast(const PassRec &r) { return r.type == 0 ? r.pa.fast != 0 : r.ra.fast != 0; }
+
+// Group the members' specialised passes by (pass index, kernel, length,
+// dimension, precision) and lay out their argument tables, work-group
+// offsets, CG update arguments and CG items in one blob; upload it.
+int batch_rebuild(Batch *b) {
+    b->blob.clear();
+    b->groups.clear();
+    b->ugroups.clear();
+    const size_t nm = b->members.size();
+    for (size_t i = 0; i < 5; ++i) {
+        std::map<std::tuple<int, int, int, int>, std::vector<size_t>> by;
+        for (size_t m = 0; m < nm; ++m) {
+            const auto &ps = b->members[m].cfg.passes;
+            if (i >= ps.size() || !pass_fast(ps[i])) continue;
+            const PassRec &r = ps[i];
+            const int n = r.type == 0 ? r.pa.f.n : r.ra.f.n;
+            const int d = r.type == 0 ? r.pa.d : r.ra.d;
+            by[std::make_tuple(r.type, n, d, (int)r.fp64)].push_back(m);
+        }
+        for (auto &kv : by) {
+            const auto &ms = kv.second;
+            const PassRec &proto = b->members[ms[0]].cfg.passes[i];
+            const size_t sz = proto.type == 0 ? sizeof(PencilArgs) : sizeof(RowArgs);
+            std::vector<unsigned char> tab(sz * ms.size());
+            std::vector<int> woff(ms.size());
+            int total = 0;
+            for (size_t j = 0; j < ms.size(); ++j) {
+                const PassRec &r = b->members[ms[j]].cfg.passes[i];
+                std::memcpy(tab.data() + j * sz, r.type == 0 ? (const void *)&r.pa : (const void *)&r.ra, sz);
+                woff[j] = total;
+                total += r.grid;
+            }
+            Batch::Group g;
+            g.pass = i;
+            g.np = (int)ms.size();
+            g.total = total;
+            g.proto = proto;
+            g.args_off = blob_put(b->blob, tab.data(), tab.size());
+            g.woff_off = blob_put(b->blob, woff.data(), woff.size() * sizeof(int));
+            b->groups.push_back(g);
+        }
+    }
+    for (int f = 0; f < 2; ++f) {
+        std::vector<UpdArgs> ua;
+        std::vector<int> woff;
+        int total = 0;
+        for (size_t m = 0; m < nm; ++m) {
+            const IterCfg &c = b->members[m].cfg;
+            if ((int)c.fp64 != f) continue;
+            ua.push_back(c.upd);
+            woff.push_back(total);
+            total += c.upd.nblocks;
+        }
+        if (ua.empty()) continue;
+        Batch::UGroup u;
+        u.fp64 = f == 1;
+        u.np = (int)ua.size();
+        u.total = total;
+        u.args_off = blob_put(b->blob, ua.data(), ua.size() * sizeof(UpdArgs));
+        u.woff_off = blob_put(b->blob, woff.data(), woff.size() * sizeof(int));
+        b->ugroups.push_back(u);
+    }
+    std::vector<CgItem> items(nm);
+    for (size_t m = 0; m < nm; ++m) {
+        items[m] = b->members[m].cfg.item;
+        items[m].mirror = reinterpret_cast<CgStatus *>(b->ws) + m;
+    }
+    b->items_off = blob_put(b->blob, items.data(), items.size() * sizeof(CgItem));
+    if (b->blob_base + b->blob.size() > b->bytes) return bfail(b, FFTGAL_ENOMEM, "batch workspace too small");
+    BHIPCHECK(b, hipMemcpyAsync(b->ws + b->blob_base, b->blob.data(), b->blob.size(), hipMemcpyHostToDevice,
+                                b->stream));
+    b->dirty = false;
+    return FFTGAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fftgal_batch_workspace_bytes(int capacity) {
+    if (capacity < 1 || capacity > 65536) return 0;
+    const size_t mirror = ((size_t)capacity * sizeof(CgStatus) + 255) & ~size_t(255);
+    // per member: at most 5 pass argument structs, one update struct, one item,
+    // and their offsets, each 256-byte aligned within its group
+    return mirror + (size_t)capacity * (5 * kArgSlot + sizeof(UpdArgs) + sizeof(CgItem) + 64) + 64 * 1024;
+}
+
+int fftgal_batch_create(struct fftgal_batch **out, int capacity, void *dev_workspace, size_t bytes, void *hip_stream) {
+    if (!out) return fail(nullptr, FFTGAL_EINVAL, "out is NULL");
+    *out = nullptr;
+    const size_t need = fftgal_batch_workspace_bytes(capacity);
+    if (need == 0) return fail(nullptr, FFTGAL_EINVAL, "capacity out of range");
+    if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))
+        return fail(nullptr, FFTGAL_EINVAL, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < need) return fail(nullptr, FFTGAL_ENOMEM, "batch workspace has %zu bytes, needs %zu", bytes, need);
+    auto *b = new Batch();
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->ws = reinterpret_cast<char *>(dev_workspace);
+    b->bytes = bytes;
+    b->cap = capacity;
+    b->blob_base = ((size_t)capacity * sizeof(CgStatus) + 255) & ~size_t(255);
+    *out = b;
+    return FFTGAL_OK;
+}
+
+int fftgal_batch_add(struct fftgal_batch *b, struct fftgal_plan *pl, int kind, int alpha, double rtol, int maxit,
+                     int *solve_id) {
+    if (!b) return FFTGAL_EINVAL;
+    if (!pl) return bfail(b, FFTGAL_EINVAL, "plan is NULL");
+    if (pl->stream != b->stream) return bfail(b, FFTGAL_EINVAL, "the plan must use the batch's stream");
+    if (kind != KIND_E && kind != KIND_J) return bfail(b, FFTGAL_EINVAL, "kind must be 0 (primal) or 1 (dual)");
+    if (alpha < 0 || alpha >= pl->D.d) return bfail(b, FFTGAL_EINVAL, "alpha %d out of range", alpha);
+    if (!(rtol >= 0.0) || maxit < 0) return bfail(b, FFTGAL_EINVAL, "rtol must be >= 0 and maxit >= 0");
+    if (!pl->have_mat) return bfail(b, FFTGAL_ESTATE, "plan has no material");
+    if (pl->busy) return bfail(b, FFTGAL_ESTATE, "plan already has a solve in a batch");
+    if ((int)b->members.size() >= b->cap) return bfail(b, FFTGAL_ENOMEM, "batch is full");
+    int rc = start_solve(pl, kind, alpha, rtol, maxit);
+    if (rc) return bfail(b, rc, "start of solve failed: %s", pl->err.c_str());
+    Batch::Member m;
+    m.pl = pl;
+    m.kind = kind;
+    m.alpha = alpha;
+    m.id = b->next_id++;
+    rc = capture_iteration(pl, kind, alpha, pl->fp64_iter(), &m.cfg);
+    if (rc) return bfail(b, rc, "capture failed: %s", pl->err.c_str());
+    pl->busy = true;
+    pl->solved[kind][alpha] = false;
+    b->members.push_back(std::move(m));
+    b->dirty = true;
+    if (solve_id) *solve_id = b->members.back().id;
+    return FFTGAL_OK;
+}
+
+int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
+    if (!b) return FFTGAL_EINVAL;
+    if (iterations < 0) return bfail(b, FFTGAL_EINVAL, "iterations must be >= 0");
+    const int nm = (int)b->members.size();
+    if (nm == 0 || iterations == 0) {
+        if (n_active) *n_active = nm;
+        return FFTGAL_OK;
+    }
+    if (b->dirty) {
+        const int rc = batch_rebuild(b);
+        if (rc) return rc;
+    }
+    char *base = b->ws + b->blob_base;
+    const CgItem *items = reinterpret_cast<const CgItem *>(base + b->items_off);
+    for (int it = 0; it < iterations; ++it) {
+        for (size_t i = 0; i < 5; ++i) {
+            for (const auto &g : b->groups) {
+                if (g.pass != i) continue;
+                const int *woff = reinterpret_cast<const int *>(base + g.woff_off);
+                if (g.proto.type == 0)
+                    BHIPCHECK(b, launch_pencil_multi(g.proto.pa, reinterpret_cast<const PencilArgs *>(base + g.args_off),
+                                                     woff, g.np, g.total, g.proto.fp64, b->stream));
+                else
+                    BHIPCHECK(b, launch_row_multi(g.proto.ra, reinterpret_cast<const RowArgs *>(base + g.args_off),
+                                                  woff, g.np, g.total, g.proto.fp64, b->stream));
+            }
+            for (auto &m : b->members) {
+                if (i >= m.cfg.passes.size() || pass_fast(m.cfg.passes[i])) continue;
+                const PassRec &r = m.cfg.passes[i];
+                if (r.type == 0)
+                    BHIPCHECK(b, launch_pencil(r.pa, r.nouter, r.fp64, b->stream));
+                else
+                    BHIPCHECK(b, launch_row(r.ra, r.fp64, b->stream));
+            }
+        }
+        BHIPCHECK(b, launch_cg_alpha_multi(items, nm, b->stream));
+        for (const auto &u : b->ugroups)
+            BHIPCHECK(b, launch_cg_update_multi(reinterpret_cast<const UpdArgs *>(base + u.args_off),
+                                                reinterpret_cast<const int *>(base + u.woff_off), u.np, u.total,
+                                                u.fp64, b->stream));
+        BHIPCHECK(b, launch_cg_check_multi(items, nm, b->stream));
+    }
+    b->mirror_host.resize(nm);
+    BHIPCHECK(b, hipMemcpyAsync(b->mirror_host.data(), b->ws, nm * sizeof(CgStatus), hipMemcpyDeviceToHost,
+                                b->stream));
+    BHIPCHECK(b, hipStreamSynchronize(b->stream));
+    std::vector<Batch::Member> keep;
+    keep.reserve(nm);
+    for (int m = 0; m < nm; ++m) {
+        Batch::Member &mem = b->members[m];
+        const CgStatus &h = b->mirror_host[m];
+        if (!h.done) {
+            keep.push_back(std::move(mem));
+            continue;
+        }
+        Batch::Done d;
+        d.id = mem.id;
+        d.status = finish_solve(mem.pl, mem.kind, mem.alpha, h, &d.info);
+        mem.pl->busy = false;
+        b->done.push_back(d);
+        b->dirty = true;
+    }
+    b->members.swap(keep);
+    if (n_active) *n_active = (int)b->members.size();
+    return FFTGAL_OK;
+}
+
+int fftgal_batch_poll(struct fftgal_batch *b, int *solve_id, fftgal_info *info, int *status) {
+    if (!b || b->done.empty()) return 0;
+    const Batch::Done d = b->done.front();
+    b->done.pop_front();
+    if (solve_id) *solve_id = d.id;
+    if (info) *info = d.info;
+    if (status) *status = d.status;
+    return 1;
+}
+
+int fftgal_batch_destroy(struct fftgal_batch *b) {
+    if (!b) return FFTGAL_OK;
+    if (!b->members.empty()) (void)hipStreamSynchronize(b->stream);
+    for (auto &m : b->members) m.pl->busy = false;
+    delete b;
+    return FFTGAL_OK;
+}
+
+const char *fftgal_batch_last_error(const struct fftgal_batch *b) { return b ? b->err.c_str() : "batch is NULL"; }
 
 }  // extern "C"

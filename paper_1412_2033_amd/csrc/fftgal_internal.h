@@ -134,6 +134,32 @@ struct RowArgs {
     const CgStatus *status;
 };
 
+// Per-problem arguments of the multi-problem CG kernels.
+struct UpdArgs {
+    void *x;
+    void *r;
+    const void *p;
+    const void *q;
+    long n_per_comp;
+    long cs;
+    int nc;
+    int Nh;
+    int nblocks;  // work-groups of this problem (fixes the reduction order)
+    const CgStatus *st;
+    double *partial;
+};
+
+struct CgItem {
+    CgStatus *st;
+    const double *pq_part;
+    int npq;
+    const double *rr_part;
+    int nrr;
+    double *hist;      // (rr, alpha) per iteration, or nullptr
+    int hist_cap;      // entries available in hist
+    CgStatus *mirror;  // copy of the status after each check, or nullptr
+};
+
 struct InclDev {
     int shape;
     double c[3];
@@ -156,11 +182,18 @@ int pencil_grid_x(const PencilArgs &a);
 hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part,
                           int n_load, double tol, double floor_rel, int maxit, double *hist,
                           hipStream_t s);
-hipError_t launch_cg_alpha(CgStatus *st, const double *pq_part, int n, hipStream_t s);
-hipError_t launch_cg_check(CgStatus *st, const double *rr_part, int n, double *hist, hipStream_t s);
-hipError_t launch_cg_update(void *x, void *r, const void *p, const void *q, long n_per_comp, int nc,
-                            long cs, int Nh, const CgStatus *st, double *partial, int nblocks,
+// Multi-problem launches: `args` and `woff` are device arrays; problem i
+// owns work-groups [woff[i], woff[i + 1]) of a grid of `total` work-groups.
+hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, const int *woff, int np,
+                               int total, bool fp64, hipStream_t s);
+hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int *woff, int np, int total,
                             bool fp64, hipStream_t s);
+hipError_t launch_cg_alpha_multi(const CgItem *items, int np, hipStream_t s);
+hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t s);
+hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, int total, bool fp64,
+                                  hipStream_t s);
+int pencil_grid(const PencilArgs &a, int nouter);  // work-groups of one problem
+int update_blocks(long n);                         // work-groups of one CG update
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_convert_f2d(double *dst, const float *src, size_t n, hipStream_t s);
 hipError_t launch_convert_d2f(float *dst, const double *src, size_t n, hipStream_t s);

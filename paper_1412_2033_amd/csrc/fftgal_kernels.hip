@@ -782,73 +782,8 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgStatus *st, const d
     }
 }
 
-__global__ __launch_bounds__(kThreads) void cg_alpha_kernel(CgStatus *st, const double *pq_part, int n) {
-    if (st->done) return;
-    const double pq = sum_fixed(pq_part, n);
-    if (threadIdx.x == 0) {
-        st->pq = pq;
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            st->breakdown = 1;
-            st->done = 1;
-        } else {
-            st->alpha = st->rr / pq;
-        }
-    }
-}
 
-__global__ __launch_bounds__(kThreads) void cg_check_kernel(CgStatus *st, const double *rr_part, int n,
-                                                            double *hist) {
-    if (st->done) return;
-    const double rr = sum_fixed(rr_part, n);
-    if (threadIdx.x == 0) {
-        const int it = st->iter + 1;
-        st->iter = it;
-        if (hist != nullptr) {
-            hist[2 * it] = rr;
-            hist[2 * it + 1] = st->alpha;
-        }
-        if (!isfinite(rr)) {
-            st->breakdown = 1;
-            st->done = 1;
-            return;
-        }
-        st->beta = rr / st->rr;
-        st->rr = rr;
-        if (rr <= st->tol2 * st->rr0 || rr <= st->floor2) {
-            st->converged = 1;
-            st->done = 1;
-        } else if (it >= st->maxit) {
-            st->done = 1;
-        }
-    }
-}
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void cg_update_kernel(Vt<T> *x, Vt<T> *r, const Vt<T> *p, const Vt<T> *q,
-                                                             long n_per_comp, int nc, long cs, int Nh,
-                                                             const CgStatus *st, double *partial) {
-    if (st->done) return;
-    const T alpha = T(st->alpha);
-    double part = 0.0;
-    const long total = n_per_comp * nc;
-    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-        const long c = idx / n_per_comp;
-        const long i = idx - c * n_per_comp;
-        const long off = c * cs + i;
-        Vt<T> xv = x[off], rv = r[off];
-        const Vt<T> pv = p[off], qv = q[off];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        rv.x -= alpha * qv.x;
-        rv.y -= alpha * qv.y;
-        x[off] = xv;
-        r[off] = rv;
-        const double w = (i % Nh) == 0 ? 1.0 : 2.0;
-        part += w * ((double)rv.x * rv.x + (double)rv.y * rv.y);
-    }
-    const double s = block_sum(part);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
 
 __global__ void fill_zero_kernel(unsigned int *p, size_t nwords) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
@@ -993,17 +928,37 @@ constexpr int fast_batch(int n, int es, int d) {
     return b;
 }
 
+// Problem owning this work-group in a multi-problem launch (binary search of
+// the work-group offsets); *lb receives the problem-local work-group index.
+__device__ __forceinline__ int find_problem(const int *__restrict__ woff, int np, int *lb) {
+    int lo = 0, hi = np - 1;
+    const int bx = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (woff[mid] <= bx)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    *lb = bx - woff[lo];
+    return lo;
+}
+
 template <typename T, int FI, int D>
-__global__ __launch_bounds__(kThreads) void pencil_fast(PencilArgs a) {
+__global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__restrict__ pa,
+                                                        const int *__restrict__ woff, int np) {
     using V = Vt<T>;
     constexpr int N = kFastSched[FI].n;
     constexpr int B = fast_batch(N, sizeof(V), D);
     constexpr int NB = D * B;  // LDS layout [pos][component][batch]
+    int lb;
+    const PencilArgs &a = pa[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
     extern __shared__ unsigned char smem_raw[];
     V *X = reinterpret_cast<V *>(smem_raw);
-    const int b0 = blockIdx.x * B;
-    const int o = blockIdx.y;
+    const int gx = (a.nb + B - 1) / B;
+    const int o = lb / gx;
+    const int b0 = (lb - o * gx) * B;
     const int nbw = min(B, a.nb - b0);
     const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
     const T sg = T(a.sgn);
@@ -1121,7 +1076,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(PencilArgs a) {
             }
         }
         const double s = block_sum(part);
-        if (threadIdx.x == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+        if (threadIdx.x == 0) a.partial[lb] = s;
     } else {
         for (int idx = threadIdx.x; idx < a.L_out * NB; idx += kThreads) {
             const int rr = idx % NB;
@@ -1138,11 +1093,14 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(PencilArgs a) {
 }
 
 template <typename T, int FI, int D>
-__global__ __launch_bounds__(kThreads) void row_fast(RowArgs a) {
+__global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__ ra, const int *__restrict__ woff,
+                                                     int np) {
     using V = Vt<T>;
     constexpr int N = kFastSched[FI].n;
     constexpr int RP = fast_batch(N, sizeof(V), D);
     constexpr int NB = D * RP;  // LDS layout [component][row pair][pos]
+    int lb;
+    const RowArgs &a = ra[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
     extern __shared__ unsigned char smem_raw[];
     V *X = reinterpret_cast<V *>(smem_raw);
@@ -1150,7 +1108,7 @@ __global__ __launch_bounds__(kThreads) void row_fast(RowArgs a) {
     const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
     V *data = reinterpret_cast<V *>(a.data);
     const T *g = reinterpret_cast<const T *>(a.g);
-    const int pair0 = blockIdx.x * RP;
+    const int pair0 = lb * RP;
     const int nvp = min(RP, (a.nrows + 1) / 2 - pair0);
     const V zero = mk<T>(T(0), T(0));
     T A0[D * D], Dm[D * D];
@@ -1233,7 +1191,7 @@ __global__ __launch_bounds__(kThreads) void row_fast(RowArgs a) {
             for (int al = 0; al < D; ++al) X[(al * RP + j) * N + x] = y[al];
         }
         const double s = block_sum(load);
-        if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) a.partial[lb] = s;
     }
     __syncthreads();
     fft_ip<T, FI, 0, 1, 0, NB, true>(X, tw, T(-1));
@@ -1255,59 +1213,139 @@ __global__ __launch_bounds__(kThreads) void row_fast(RowArgs a) {
 }
 
 template <typename T, int FI, int D>
-void launch_pencil_fast_t(const PencilArgs &a, int nouter, hipStream_t s) {
+void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
     constexpr int B = fast_batch(N, sizeof(Vt<T>), D);
     const size_t lds = sizeof(Vt<T>) * (size_t)N * D * B;
-    hipLaunchKernelGGL((pencil_fast<T, FI, D>), dim3((a.nb + B - 1) / B, nouter), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((pencil_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
 
 template <typename T, int FI, int D>
-void launch_row_fast_t(const RowArgs &r, hipStream_t s) {
+void launch_row_fast_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
     constexpr int RP = fast_batch(N, sizeof(Vt<T>), D);
     const size_t lds = sizeof(Vt<T>) * (size_t)N * D * RP;
-    hipLaunchKernelGGL((row_fast<T, FI, D>), dim3(((r.nrows + 1) / 2 + RP - 1) / RP), dim3(kThreads), lds, s, r);
+    hipLaunchKernelGGL((row_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
 
 template <typename T, int FI>
-void launch_pencil_fast_d(const PencilArgs &a, int nouter, hipStream_t s) {
-    if (a.d == 3)
-        launch_pencil_fast_t<T, FI, 3>(a, nouter, s);
+void launch_pencil_fast_d(int d, const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    if (d == 3)
+        launch_pencil_fast_t<T, FI, 3>(args, woff, np, total, s);
     else
-        launch_pencil_fast_t<T, FI, 2>(a, nouter, s);
+        launch_pencil_fast_t<T, FI, 2>(args, woff, np, total, s);
 }
 
 template <typename T, int FI>
-void launch_row_fast_d(const RowArgs &r, hipStream_t s) {
-    if (r.d == 3)
-        launch_row_fast_t<T, FI, 3>(r, s);
+void launch_row_fast_d(int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    if (d == 3)
+        launch_row_fast_t<T, FI, 3>(args, woff, np, total, s);
     else
-        launch_row_fast_t<T, FI, 2>(r, s);
+        launch_row_fast_t<T, FI, 2>(args, woff, np, total, s);
 }
 
 template <typename T>
-void launch_pencil_fast(const PencilArgs &a, int nouter, hipStream_t s) {
-    switch (fast_index(a.f.n)) {
-        case 0: launch_pencil_fast_d<T, 0>(a, nouter, s); break;
-        case 1: launch_pencil_fast_d<T, 1>(a, nouter, s); break;
-        case 2: launch_pencil_fast_d<T, 2>(a, nouter, s); break;
-        case 3: launch_pencil_fast_d<T, 3>(a, nouter, s); break;
-        case 4: launch_pencil_fast_d<T, 4>(a, nouter, s); break;
-        default: launch_pencil_fast_d<T, 5>(a, nouter, s); break;
+void launch_pencil_fast(int fi, int d, const PencilArgs *args, const int *woff, int np, int total,
+                        hipStream_t s) {
+    switch (fi) {
+        case 0: launch_pencil_fast_d<T, 0>(d, args, woff, np, total, s); break;
+        case 1: launch_pencil_fast_d<T, 1>(d, args, woff, np, total, s); break;
+        case 2: launch_pencil_fast_d<T, 2>(d, args, woff, np, total, s); break;
+        case 3: launch_pencil_fast_d<T, 3>(d, args, woff, np, total, s); break;
+        case 4: launch_pencil_fast_d<T, 4>(d, args, woff, np, total, s); break;
+        default: launch_pencil_fast_d<T, 5>(d, args, woff, np, total, s); break;
     }
 }
 
 template <typename T>
-void launch_row_fast(const RowArgs &r, hipStream_t s) {
-    switch (fast_index(r.f.n)) {
-        case 0: launch_row_fast_d<T, 0>(r, s); break;
-        case 1: launch_row_fast_d<T, 1>(r, s); break;
-        case 2: launch_row_fast_d<T, 2>(r, s); break;
-        case 3: launch_row_fast_d<T, 3>(r, s); break;
-        case 4: launch_row_fast_d<T, 4>(r, s); break;
-        default: launch_row_fast_d<T, 5>(r, s); break;
+void launch_row_fast(int fi, int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    switch (fi) {
+        case 0: launch_row_fast_d<T, 0>(d, args, woff, np, total, s); break;
+        case 1: launch_row_fast_d<T, 1>(d, args, woff, np, total, s); break;
+        case 2: launch_row_fast_d<T, 2>(d, args, woff, np, total, s); break;
+        case 3: launch_row_fast_d<T, 3>(d, args, woff, np, total, s); break;
+        case 4: launch_row_fast_d<T, 4>(d, args, woff, np, total, s); break;
+        default: launch_row_fast_d<T, 5>(d, args, woff, np, total, s); break;
     }
+}
+
+// ---- multi-problem CG kernels (one problem per work-group for the scalar ones) ----
+__global__ __launch_bounds__(kThreads) void cg_alpha_multi_kernel(const CgItem *__restrict__ items) {
+    const CgItem &it = items[blockIdx.x];
+    CgStatus *st = it.st;
+    if (st->done) return;
+    const double pq = sum_fixed(it.pq_part, it.npq);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            st->breakdown = 1;
+            st->done = 1;
+        } else {
+            st->alpha = st->rr / pq;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void cg_check_multi_kernel(const CgItem *__restrict__ items) {
+    const CgItem &it = items[blockIdx.x];
+    CgStatus *st = it.st;
+    if (!st->done) {
+        const double rr = sum_fixed(it.rr_part, it.nrr);
+        if (threadIdx.x == 0) {
+            const int iter = st->iter + 1;
+            st->iter = iter;
+            if (it.hist != nullptr && iter < it.hist_cap) {
+                it.hist[2 * iter] = rr;
+                it.hist[2 * iter + 1] = st->alpha;
+            }
+            if (!isfinite(rr)) {
+                st->breakdown = 1;
+                st->done = 1;
+            } else {
+                st->beta = rr / st->rr;
+                st->rr = rr;
+                if (rr <= st->tol2 * st->rr0 || rr <= st->floor2) {
+                    st->converged = 1;
+                    st->done = 1;
+                } else if (iter >= st->maxit) {
+                    st->done = 1;
+                }
+            }
+        }
+    }
+    if (it.mirror != nullptr && threadIdx.x == 0) *it.mirror = *st;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs *__restrict__ ua,
+                                                                   const int *__restrict__ woff, int np) {
+    int lb;
+    const UpdArgs &a = ua[find_problem(woff, np, &lb)];
+    if (a.st->done) return;
+    Vt<T> *x = reinterpret_cast<Vt<T> *>(a.x);
+    Vt<T> *r = reinterpret_cast<Vt<T> *>(a.r);
+    const Vt<T> *p = reinterpret_cast<const Vt<T> *>(a.p);
+    const Vt<T> *q = reinterpret_cast<const Vt<T> *>(a.q);
+    const T alpha = T(a.st->alpha);
+    double part = 0.0;
+    const long total = a.n_per_comp * a.nc;
+    for (long idx = lb * (long)kThreads + threadIdx.x; idx < total; idx += (long)a.nblocks * kThreads) {
+        const long c = idx / a.n_per_comp;
+        const long i = idx - c * a.n_per_comp;
+        const long off = c * a.cs + i;
+        Vt<T> xv = x[off], rv = r[off];
+        const Vt<T> pv = p[off], qv = q[off];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        rv.x -= alpha * qv.x;
+        rv.y -= alpha * qv.y;
+        x[off] = xv;
+        r[off] = rv;
+        const double w = (i % a.Nh) == 0 ? 1.0 : 2.0;
+        part += w * ((double)rv.x * rv.x + (double)rv.y * rv.y);
+    }
+    const double s = block_sum(part);
+    if (threadIdx.x == 0) a.partial[lb] = s;
 }
 
 // Device-side validation of a voxel image: per work-group min, max and the
@@ -1441,14 +1479,7 @@ void configure_row(RowArgs &r, bool fp64) {
 }
 
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s) {
-    if (a.B < 1 || nouter < 1) return hipErrorInvalidValue;
-    if (a.fast) {
-        if (fp64)
-            launch_pencil_fast<double>(a, nouter, s);
-        else
-            launch_pencil_fast<float>(a, nouter, s);
-        return hipGetLastError();
-    }
+    if (a.B < 1 || nouter < 1 || a.fast) return hipErrorInvalidValue;
     dim3 grid(pencil_grid_x(a), nouter);
     const size_t lds = pencil_lds_bytes(a, fp64);
     if (fp64) {
@@ -1460,20 +1491,56 @@ hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t
 }
 
 hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s) {
-    if (a.RP < 1) return hipErrorInvalidValue;
-    if (a.fast) {
-        if (fp64)
-            launch_row_fast<double>(a, s);
-        else
-            launch_row_fast<float>(a, s);
-        return hipGetLastError();
-    }
+    if (a.RP < 1 || a.fast) return hipErrorInvalidValue;
     const size_t lds = row_lds_bytes(a, fp64);
     if (fp64) {
         hipLaunchKernelGGL(row_kernel<double>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);
     } else {
         hipLaunchKernelGGL(row_kernel<float>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);
     }
+    return hipGetLastError();
+}
+
+int pencil_grid(const PencilArgs &a, int nouter) { return pencil_grid_x(a) * nouter; }
+int update_blocks(long n) { return (int)std::max<long>(1, std::min<long>(1024, (n + kThreads - 1) / kThreads)); }
+
+hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, const int *woff, int np, int total,
+                               bool fp64, hipStream_t s) {
+    const int fi = fast_index(proto.f.n);
+    if (!proto.fast || fi < 0 || np < 1 || total < 1) return hipErrorInvalidValue;
+    if (fp64)
+        launch_pencil_fast<double>(fi, proto.d, args, woff, np, total, s);
+    else
+        launch_pencil_fast<float>(fi, proto.d, args, woff, np, total, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int *woff, int np, int total, bool fp64,
+                            hipStream_t s) {
+    const int fi = fast_index(proto.f.n);
+    if (!proto.fast || fi < 0 || np < 1 || total < 1) return hipErrorInvalidValue;
+    if (fp64)
+        launch_row_fast<double>(fi, proto.d, args, woff, np, total, s);
+    else
+        launch_row_fast<float>(fi, proto.d, args, woff, np, total, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha_multi(const CgItem *items, int np, hipStream_t s) {
+    hipLaunchKernelGGL(cg_alpha_multi_kernel, dim3(np), dim3(kThreads), 0, s, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t s) {
+    hipLaunchKernelGGL(cg_check_multi_kernel, dim3(np), dim3(kThreads), 0, s, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, int total, bool fp64, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(cg_update_multi_kernel<double>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
+    else
+        hipLaunchKernelGGL(cg_update_multi_kernel<float>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
     return hipGetLastError();
 }
 
@@ -1484,28 +1551,8 @@ hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const d
     return hipGetLastError();
 }
 
-hipError_t launch_cg_alpha(CgStatus *st, const double *pq_part, int n, hipStream_t s) {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kThreads), 0, s, st, pq_part, n);
-    return hipGetLastError();
-}
 
-hipError_t launch_cg_check(CgStatus *st, const double *rr_part, int n, double *hist, hipStream_t s) {
-    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(kThreads), 0, s, st, rr_part, n, hist);
-    return hipGetLastError();
-}
 
-hipError_t launch_cg_update(void *x, void *r, const void *p, const void *q, long n_per_comp, int nc, long cs,
-                            int Nh, const CgStatus *st, double *partial, int nblocks, bool fp64, hipStream_t s) {
-    if (fp64) {
-        hipLaunchKernelGGL(cg_update_kernel<double>, dim3(nblocks), dim3(kThreads), 0, s, (double2 *)x,
-                           (double2 *)r, (const double2 *)p, (const double2 *)q, n_per_comp, nc, cs, Nh, st,
-                           partial);
-    } else {
-        hipLaunchKernelGGL(cg_update_kernel<float>, dim3(nblocks), dim3(kThreads), 0, s, (float2 *)x, (float2 *)r,
-                           (const float2 *)p, (const float2 *)q, n_per_comp, nc, cs, Nh, st, partial);
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
     const size_t nw = bytes / 4;

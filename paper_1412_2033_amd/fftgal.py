@@ -26,7 +26,9 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32_ITER, "fp32_iter": FP32_ITER}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5: "ESTATE", -6: "EBREAKDOWN"}
 EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", "fftgal_set_material",
            "fftgal_solve_primal", "fftgal_solve_dual", "fftgal_bounds", "fftgal_destroy",
-           "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing")
+           "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
+           "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
+           "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
                   "bounds", "setup")
 
@@ -104,6 +106,20 @@ def load_library(path=LIB_PATH):
     lib.fftgal_set_timing.restype = ctypes.c_int
     lib.fftgal_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
     lib.fftgal_read_timing.restype = ctypes.c_int
+    lib.fftgal_batch_workspace_bytes.argtypes = [ctypes.c_int]
+    lib.fftgal_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.fftgal_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_size_t, vp]
+    lib.fftgal_batch_create.restype = ctypes.c_int
+    lib.fftgal_batch_add.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, i32p]
+    lib.fftgal_batch_add.restype = ctypes.c_int
+    lib.fftgal_batch_step.argtypes = [vp, ctypes.c_int, i32p]
+    lib.fftgal_batch_step.restype = ctypes.c_int
+    lib.fftgal_batch_poll.argtypes = [vp, i32p, ctypes.POINTER(Info), i32p]
+    lib.fftgal_batch_poll.restype = ctypes.c_int
+    lib.fftgal_batch_destroy.argtypes = [vp]
+    lib.fftgal_batch_destroy.restype = ctypes.c_int
+    lib.fftgal_batch_last_error.argtypes = [vp]
+    lib.fftgal_batch_last_error.restype = ctypes.c_char_p
     _LIB = lib
     return lib
 
@@ -294,3 +310,90 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---- batched CG (continuous batching) --------------------------------------------
+
+def _bcheck(code, batch):
+    if code != 0:
+        raise FftgalError(code, load_library().fftgal_batch_last_error(batch).decode())
+
+
+def fftgal_batch_workspace_bytes(capacity):
+    return int(load_library().fftgal_batch_workspace_bytes(int(capacity)))
+
+
+def fftgal_batch_create(capacity, workspace_ptr, nbytes, stream_ptr):
+    h = ctypes.c_void_p()
+    code = load_library().fftgal_batch_create(ctypes.byref(h), int(capacity), ctypes.c_void_p(workspace_ptr),
+                                              nbytes, ctypes.c_void_p(stream_ptr))
+    if code != 0:
+        raise FftgalError(code, load_library().fftgal_last_error(None).decode())
+    return h
+
+
+def fftgal_batch_add(batch, plan, kind, alpha, rtol, maxit):
+    sid = ctypes.c_int32()
+    _bcheck(load_library().fftgal_batch_add(batch, plan, int(kind), int(alpha), float(rtol), int(maxit),
+                                            ctypes.byref(sid)), batch)
+    return int(sid.value)
+
+
+def fftgal_batch_step(batch, iterations):
+    n = ctypes.c_int32()
+    _bcheck(load_library().fftgal_batch_step(batch, int(iterations), ctypes.byref(n)), batch)
+    return int(n.value)
+
+
+def fftgal_batch_poll(batch):
+    """(solve_id, info dict, status code) of one retired solve, or None."""
+    sid = ctypes.c_int32()
+    info = Info()
+    st = ctypes.c_int32()
+    if load_library().fftgal_batch_poll(batch, ctypes.byref(sid), ctypes.byref(info), ctypes.byref(st)) == 0:
+        return None
+    return int(sid.value), info.as_dict(), int(st.value)
+
+
+def fftgal_batch_destroy(batch):
+    return load_library().fftgal_batch_destroy(batch)
+
+
+class Batch:
+    """A batch plus its torch device workspace; plans added must share its stream."""
+
+    def __init__(self, capacity=256, device="cuda", stream=None):
+        import torch
+        dev = torch.device(device)
+        self.capacity = int(capacity)
+        self.nbytes = fftgal_batch_workspace_bytes(self.capacity)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.handle = fftgal_batch_create(self.capacity, self.workspace.data_ptr(), self.nbytes,
+                                          self.stream.cuda_stream)
+
+    def add(self, plan, kind, alpha, rtol=1e-10, maxit=20000):
+        return fftgal_batch_add(self.handle, plan.handle, kind, alpha, rtol, maxit)
+
+    def step(self, iterations=8):
+        return fftgal_batch_step(self.handle, iterations)
+
+    def poll(self):
+        out = []
+        while True:
+            r = fftgal_batch_poll(self.handle)
+            if r is None:
+                return out
+            out.append(r)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            fftgal_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

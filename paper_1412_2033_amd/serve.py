@@ -1,0 +1,151 @@
+"""Continuous-batching request loop for guaranteed-bound requests.
+
+Requests (microstructures of any d and N) arrive over time.  A request is
+admitted when the batch has a free slot and its plan's workspace fits the HBM
+budget (plans are pooled per (d, N, precision) and kept on the device, so a
+later request of the same shape reuses one).  An admitted request's material
+fields are built at once; its 2d CG solves then run one after another as
+members of a shared batch (fftgal_batch_*), whose every launch advances all
+active solves of all requests together.  When a request's last solve retires,
+its bounds are evaluated (FP64 quadrature) and its latency recorded.
+
+All scheduling is host logic; every step of the computation runs in the HIP
+library.
+"""
+
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+
+from . import fftgal
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, float), q)) if len(xs) else float("nan")
+
+
+class Server:
+    def __init__(self, precision="fp32", rtol=5e-6, maxit=20000, capacity=256, hbm_budget=64 << 30,
+                 iters_per_step=8, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = precision
+        self.rtol = rtol
+        self.maxit = maxit
+        self.iters_per_step = iters_per_step
+        self.hbm_budget = int(hbm_budget)
+        self.batch = fftgal.Batch(capacity, device=self.device)
+        self.capacity = capacity
+        self.pool = collections.defaultdict(list)
+        self.used_bytes = 0
+        self.plans_created = 0
+
+    def _plan(self, d, N):
+        key = (d, N)
+        if self.pool[key]:
+            return self.pool[key].pop()
+        need = fftgal.fftgal_workspace_bytes(d, N, fftgal.PRECISIONS[self.precision])
+        # release idle plans of other shapes until the new one fits
+        for k in list(self.pool):
+            while self.used_bytes + need > self.hbm_budget and self.pool[k]:
+                p = self.pool[k].pop()
+                self.used_bytes -= p.nbytes
+                p.close()
+                p.workspace = None
+        if self.used_bytes + need > self.hbm_budget:
+            return None
+        self.used_bytes += need
+        self.plans_created += 1
+        return fftgal.Plan(d, N, self.precision, device=self.device, stream=self.batch.stream)
+
+    def run(self, requests, realtime=True):
+        """Serve `requests` (dicts with id, arrival_s, N, micro); returns per-request records."""
+        pending = collections.deque(sorted(requests, key=lambda r: r["arrival_s"]))
+        waiting = collections.deque()
+        active = {}
+        by_sid = {}
+        records = []
+        iter_points = 0.0
+        t0 = time.perf_counter()
+        clock = (lambda: time.perf_counter() - t0) if realtime else None
+        sim_now = 0.0
+        while pending or waiting or active:
+            now = clock() if realtime else sim_now
+            while pending and pending[0]["arrival_s"] <= now:
+                waiting.append(pending.popleft())
+            while waiting and len(active) < self.capacity:
+                req = waiting[0]
+                d = int(req["micro"]["d"])
+                N = (int(req["N"]),) * d
+                plan = self._plan(d, N)
+                if plan is None:
+                    break  # wait until a plan's memory is released
+                waiting.popleft()
+                plan.set_material(req["micro"])
+                seq = [(0, a) for a in range(d)] + [(1, a) for a in range(d)]
+                st = {"req": req, "plan": plan, "seq": seq, "k": 0, "t_admit": now, "iters": [], "status": [],
+                      "key": (d, N), "pts": float(np.prod([2 * n - 1 for n in N]))}
+                sid = self.batch.add(plan, *seq[0], self.rtol, self.maxit)
+                by_sid[sid] = st
+                active[id(plan)] = st
+            if active:
+                self.batch.step(self.iters_per_step)
+                for sid, info, status in self.batch.poll():
+                    st = by_sid.pop(sid)
+                    st["iters"].append(info["iters"])
+                    st["status"].append(status)
+                    iter_points += info["iters"] * st["pts"]
+                    st["k"] += 1
+                    if st["k"] < len(st["seq"]):
+                        by_sid[self.batch.add(st["plan"], *st["seq"][st["k"]], self.rtol, self.maxit)] = st
+                        continue
+                    up, lo, gap = st["plan"].bounds()
+                    t_done = clock() if realtime else sim_now
+                    req = st["req"]
+                    records.append({"id": req["id"], "N": req["N"], "arrival_s": req["arrival_s"],
+                                    "admit_s": st["t_admit"], "done_s": t_done,
+                                    "latency_s": t_done - req["arrival_s"], "iters": st["iters"],
+                                    "status": st["status"],
+                                    "upper": up, "lower": lo})
+                    del active[id(st["plan"])]
+                    self.pool[st["key"]].append(st["plan"])
+            elif pending:
+                if realtime:
+                    time.sleep(max(0.0, pending[0]["arrival_s"] - clock()))
+                else:
+                    sim_now = pending[0]["arrival_s"]
+        wall = time.perf_counter() - t0
+        return records, {"wall_s": wall, "Mpoint_iter_per_s": iter_points / wall / 1e6,
+                         "plans_created": self.plans_created, "hbm_bytes": self.used_bytes}
+
+    def close(self):
+        for plans in self.pool.values():
+            for p in plans:
+                p.close()
+        self.pool.clear()
+        self.batch.close()
+
+
+def sequential(requests, precision="fp64", rtol=1e-10, maxit=20000, device="cuda:0"):
+    """The same requests solved one at a time with the plain (unbatched) path."""
+    import torch
+    out = []
+    t0 = time.perf_counter()
+    plans = {}
+    for req in requests:
+        d = int(req["micro"]["d"])
+        N = (int(req["N"]),) * d
+        if N not in plans:
+            plans[N] = fftgal.Plan(d, N, precision, device=torch.device(device))
+        t = time.perf_counter()
+        res = plans[N].run(req["micro"], rtol=rtol, maxit=maxit)
+        out.append({"id": req["id"], "seconds": time.perf_counter() - t, "upper": res["upper"],
+                    "lower": res["lower"]})
+    wall = time.perf_counter() - t0
+    for p in plans.values():
+        p.close()
+    return out, wall

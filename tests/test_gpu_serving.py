@@ -1,0 +1,97 @@
+"""GPU tests of batched CG and the continuous-batching request loop.
+
+A solve run inside a batch, next to other solves of other sizes, precisions
+and stages, must give bitwise the same result as the same solve run alone
+(each solve's reductions use only its own work-groups in a fixed order).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_2033_amd import fftgal
+    fftgal.load_library()
+    return fftgal
+
+
+def _alone(fg, micro, N, precision, rtol):
+    plan = fg.Plan(len(N), N, precision)
+    try:
+        return plan.run(micro, rtol=rtol)
+    finally:
+        plan.close()
+
+
+def test_batch_alone_equals_mix(fg):
+    cases = [(synth.random_circles(1), (41, 41), "fp32"), (synth.random_circles(2), (63, 63), "fp32"),
+             (synth.random_circles(3), (21, 21), "fp64"), (synth.random_circles(4), (41, 41), "fp64"),
+             (synth.cube_inclusion_aniso(0.5, 3), (9, 9, 9), "fp32"),
+             (synth.grf_voxels(7, (45, 45, 45), d=3, corr_len=0.1), (23, 23, 23), "fp32")]
+    rtol = 1e-7
+    alone = [_alone(fg, m, N, p, rtol) for m, N, p in cases]
+    print("alone done", flush=True)
+    batch = fg.Batch(capacity=16)
+    plans, seqs, k = [], [], []
+    for m, N, p in cases:
+        pl = fg.Plan(len(N), N, p, stream=batch.stream, P=m.get("P"))
+        pl.set_material(m)
+        plans.append(pl)
+        d = len(N)
+        seqs.append([(0, a) for a in range(d)] + [(1, a) for a in range(d)])
+        k.append(0)
+    owner = {}
+    # stagger the starts so that solves of different stages share launches
+    for i, pl in enumerate(plans):
+        owner[batch.add(pl, *seqs[i][0], rtol=rtol)] = i
+        batch.step(3)
+        for sid, info, st in batch.poll():
+            j = owner.pop(sid)
+            k[j] += 1
+            if k[j] < len(seqs[j]):
+                owner[batch.add(plans[j], *seqs[j][k[j]], rtol=rtol)] = j
+    while owner:
+        batch.step(5)
+        for sid, info, st in batch.poll():
+            j = owner.pop(sid)
+            k[j] += 1
+            if k[j] < len(seqs[j]):
+                owner[batch.add(plans[j], *seqs[j][k[j]], rtol=rtol)] = j
+    for i, pl in enumerate(plans):
+        up, lo, gap = pl.bounds()
+        assert np.array_equal(up, alone[i]["upper"]), i
+        assert np.array_equal(lo, alone[i]["lower"]), i
+        pl.close()
+    batch.close()
+
+
+def test_server_mix_matches_fp64(fg):
+    from paper_1412_2033_amd import serve
+    reqs = synth.serving_requests(11, 12, rate_per_s=1e6, N_choices=(21, 41, 63))
+    # FP32 iterations reach a relative residual of ~1e-6 at contrast 1e4; 5e-6
+    # keeps every bound within 1e-6 of the FP64 path (energy error is
+    # quadratic in the field error)
+    srv = serve.Server(precision="fp32", rtol=5e-6, capacity=8, iters_per_step=6)
+    records, stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert len(records) == len(reqs)
+    assert all(st == 0 for rec in records for st in rec["status"])
+    seq, wall = serve.sequential(reqs, precision="fp64", rtol=1e-10)
+    by = {r["id"]: r for r in seq}
+    worst = 0.0
+    for rec in records:
+        ref = by[rec["id"]]
+        for key in ("upper", "lower"):
+            err = np.linalg.norm(rec[key] - ref[key]) / np.linalg.norm(ref[key])
+            worst = max(worst, err)
+        assert np.min(np.linalg.eigvalsh(rec["upper"] - rec["lower"])) > -1e-12
+    print("worst FP32-served vs FP64 bound error %.2e" % worst)
+    assert worst < 1e-6
