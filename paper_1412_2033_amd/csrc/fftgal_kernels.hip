@@ -930,9 +930,20 @@ constexpr int fast_batch(int n, int es, int d) {
 
 // Problem owning this work-group in a multi-problem launch (binary search of
 // the work-group offsets); *lb receives the problem-local work-group index.
+// Work-groups are dispatched to the 8 XCDs round-robin (physical index mod 8);
+// each XCD has its own L2.  Map the physical index to a logical one so that
+// every XCD receives a contiguous range of logical tiles: neighbouring tiles
+// (which share 128-byte lines of the strided operands) then meet in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_logical(int b, int total) {
+    const int q = total / kXcds, r = total % kXcds;
+    const int x = b % kXcds, k = b / kXcds;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 __device__ __forceinline__ int find_problem(const int *__restrict__ woff, int np, int *lb) {
     int lo = 0, hi = np - 1;
-    const int bx = blockIdx.x;
+    const int bx = xcd_logical(blockIdx.x, gridDim.x);
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (woff[mid] <= bx)
