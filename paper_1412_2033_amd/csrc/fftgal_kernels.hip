@@ -920,6 +920,23 @@ __device__ __forceinline__ void fft_ip(Vt<T> *X, const Vt<T> *tw, T sg) {
     }
 }
 
+
+// Copy the n - 1 twiddles of a specialised transform into LDS (read by every
+// stage; a global read per butterfly twiddle would stall each stage).
+// Only short tables are staged: for n = 2025 the table (32 KB in FP64) would
+// cost more occupancy than its reads cost latency.
+constexpr bool tw_in_lds(int n, int es) { return n * es <= 12 * 1024; }
+constexpr size_t tw_lds_entries(int n, int es) { return tw_in_lds(n, es) ? (size_t)n : 0; }
+template <typename T, int N>
+__device__ __forceinline__ const Vt<T> *twiddles_to_lds(Vt<T> *dst, const Vt<T> *__restrict__ src) {
+    if constexpr (!tw_in_lds(N, sizeof(Vt<T>))) {
+        return src;
+    } else {
+        for (int i = threadIdx.x; i < N - 1; i += kThreads) dst[i] = src[i];
+        return dst;
+    }
+}
+
 // pencils (or row pairs) per work-group so that one batch of all d
 // components stays within 48 KB of LDS
 constexpr int fast_batch(int n, int es, int d) {
@@ -971,7 +988,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     const int o = lb / gx;
     const int b0 = (lb - o * gx) * B;
     const int nbw = min(B, a.nb - b0);
-    const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
+    const V *tw = twiddles_to_lds<T, N>(X + N * NB, reinterpret_cast<const V *>(a.tw) + a.f.twoff[0]);
     const T sg = T(a.sgn);
     const T scale = T(a.scale);
     const V zero = mk<T>(T(0), T(0));
@@ -1116,7 +1133,7 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
     extern __shared__ unsigned char smem_raw[];
     V *X = reinterpret_cast<V *>(smem_raw);
     const int nh = a.Nh_row;
-    const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
+    const V *tw = twiddles_to_lds<T, N>(X + N * NB, reinterpret_cast<const V *>(a.tw) + a.f.twoff[0]);
     V *data = reinterpret_cast<V *>(a.data);
     const T *g = reinterpret_cast<const T *>(a.g);
     const int pair0 = lb * RP;
@@ -1127,6 +1144,23 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
     for (int i = 0; i < D * D; ++i) {
         A0[i] = T(a.A0[i]);
         Dm[i] = T(a.D[i]);
+    }
+    // material values of this thread's grid points, loaded before the
+    // transforms so that their latency overlaps them
+    constexpr int MP = (RP * N + kThreads - 1) / kThreads;
+    T gv1[MP], gv2[MP];
+#pragma unroll
+    for (int t = 0; t < MP; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        const int j = idx / N;
+        const int x = idx - j * N;
+        gv1[t] = T(0);
+        gv2[t] = T(0);
+        if (idx < RP * N && j < nvp) {
+            const int r1 = 2 * (pair0 + j);
+            gv1[t] = g[(long)r1 * N + x];
+            if (r1 + 1 < a.nrows) gv2[t] = g[(long)(r1 + 1) * N + x];
+        }
     }
     if (a.mode == ROW_OPER) {
         for (int idx = threadIdx.x; idx < N * NB; idx += kThreads) X[idx] = zero;
@@ -1150,14 +1184,14 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
         }
         __syncthreads();
         fft_ip<T, FI, 0, 1, 0, NB, true>(X, tw, T(1));
-        for (int idx = threadIdx.x; idx < RP * N; idx += kThreads) {
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
             const int j = idx / N;
             const int x = idx - j * N;
-            if (j >= nvp) continue;
-            const int r1 = 2 * (pair0 + j);
-            const int r2 = r1 + 1;
-            const T g1 = g[(long)r1 * N + x];
-            const T g2 = (r2 < a.nrows) ? g[(long)r2 * N + x] : T(0);
+            if (idx >= RP * N || j >= nvp) continue;
+            const T g1 = gv1[t];
+            const T g2 = gv2[t];
             V e[D];
 #pragma unroll
             for (int b = 0; b < D; ++b) e[b] = X[(b * RP + j) * N + x];
@@ -1174,7 +1208,10 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
         }
     } else {  // ROW_RHS: y = A(x) E on both rows, and |y|^2 partial sums
         double load = 0.0;
-        for (int idx = threadIdx.x; idx < RP * N; idx += kThreads) {
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
+            if (idx >= RP * N) continue;
             const int j = idx / N;
             const int x = idx - j * N;
             V y[D];
@@ -1184,8 +1221,8 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
                 const int r1 = 2 * (pair0 + j);
                 const int r2 = r1 + 1;
                 const bool v2 = r2 < a.nrows;
-                const T g1 = g[(long)r1 * N + x];
-                const T g2 = v2 ? g[(long)r2 * N + x] : T(0);
+                const T g1 = gv1[t];
+                const T g2 = gv2[t];
 #pragma unroll
                 for (int al = 0; al < D; ++al) {
                     T y1 = T(0), y2 = T(0);
@@ -1227,7 +1264,7 @@ template <typename T, int FI, int D>
 void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
     constexpr int B = fast_batch(N, sizeof(Vt<T>), D);
-    const size_t lds = sizeof(Vt<T>) * (size_t)N * D * B;
+    const size_t lds = sizeof(Vt<T>) * ((size_t)N * D * B + tw_lds_entries(N, sizeof(Vt<T>)));
     hipLaunchKernelGGL((pencil_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
 
@@ -1235,7 +1272,7 @@ template <typename T, int FI, int D>
 void launch_row_fast_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
     constexpr int RP = fast_batch(N, sizeof(Vt<T>), D);
-    const size_t lds = sizeof(Vt<T>) * (size_t)N * D * RP;
+    const size_t lds = sizeof(Vt<T>) * ((size_t)N * D * RP + tw_lds_entries(N, sizeof(Vt<T>)));
     hipLaunchKernelGGL((row_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
 
@@ -1277,6 +1314,137 @@ void launch_row_fast(int fi, int d, const RowArgs *args, const int *woff, int np
         case 3: launch_row_fast_d<T, 3>(d, args, woff, np, total, s); break;
         case 4: launch_row_fast_d<T, 4>(d, args, woff, np, total, s); break;
         default: launch_row_fast_d<T, 5>(d, args, woff, np, total, s); break;
+    }
+}
+
+
+// Energy Gram quadrature (ROW_GRAM) for the specialised lengths: all d^2
+// component fields of the d solutions are transformed to the grid in one
+// in-place batch, then (A_M (E_s + e_s), E_t + e_t) is summed over the rows.
+constexpr int gram_batch(int n, int es, int d) {
+    int b = 8;
+    while (b > 1 && d * d * b * n * es > 144 * 1024) b /= 2;
+    return b;
+}
+
+template <typename T, int FI, int D>
+__global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restrict__ ra, const int *__restrict__ woff,
+                                                          int np) {
+    using V = Vt<T>;
+    constexpr int N = kFastSched[FI].n;
+    constexpr int RP = gram_batch(N, sizeof(V), D);
+    constexpr int NC = D * D;
+    constexpr int NB = NC * RP;  // LDS layout [component][row pair][pos]
+    int lb;
+    const RowArgs &a = ra[find_problem(woff, np, &lb)];
+    extern __shared__ unsigned char smem_raw[];
+    V *X = reinterpret_cast<V *>(smem_raw);
+    const int nh = a.Nh_row;
+    const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
+    const V *data = reinterpret_cast<const V *>(a.data);
+    const T *g = reinterpret_cast<const T *>(a.g);
+    const int pair0 = lb * RP;
+    const int nvp = min(RP, (a.nrows + 1) / 2 - pair0);
+    const V zero = mk<T>(T(0), T(0));
+    for (int idx = threadIdx.x; idx < N * NB; idx += kThreads) X[idx] = zero;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NB * nh; idx += kThreads) {
+        const int pc = idx / nh;
+        const int kx = idx - pc * nh;
+        const int c = pc / RP;
+        const int j = pc - c * RP;
+        if (j >= nvp) continue;
+        const int r1 = 2 * (pair0 + j);
+        const int r2 = r1 + 1;
+        const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
+        const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+        if (kx == 0) {
+            X[pc * N] = mk<T>(u1.x, u2.x);
+        } else {
+            X[pc * N + kx] = mk<T>(u1.x - u2.y, u1.y + u2.x);
+            X[pc * N + N - kx] = mk<T>(u1.x + u2.y, u2.x - u1.y);
+        }
+    }
+    __syncthreads();
+    fft_ip<T, FI, 0, 1, 0, NB, true>(X, tw, T(1));
+    T A0[D * D], Dm[D * D];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) {
+        A0[i] = T(a.A0[i]);
+        Dm[i] = T(a.D[i]);
+    }
+    double gs[D * D];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) gs[i] = 0.0;
+    for (int idx = threadIdx.x; idx < RP * N; idx += kThreads) {
+        const int j = idx / N;
+        const int x = idx - j * N;
+        if (j >= nvp) continue;
+        const int r1 = 2 * (pair0 + j);
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int r = r1 + half;
+            if (r >= a.nrows) continue;
+            const T gg = g[(long)r * N + x];
+            T f[D][D];
+#pragma unroll
+            for (int sol = 0; sol < D; ++sol)
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    const V zv = X[((sol * D + b) * RP + j) * N + x];
+                    f[sol][b] = (half ? zv.y : zv.x) + (sol == b ? T(1) : T(0));
+                }
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                T af[D];
+#pragma unroll
+                for (int al = 0; al < D; ++al) {
+                    T y = T(0);
+#pragma unroll
+                    for (int b = 0; b < D; ++b) y += (A0[al * D + b] + gg * Dm[al * D + b]) * f[t][b];
+                    af[al] = y;
+                }
+#pragma unroll
+                for (int sol = 0; sol < D; ++sol) {
+                    T dot = T(0);
+#pragma unroll
+                    for (int al = 0; al < D; ++al) dot += f[sol][al] * af[al];
+                    gs[sol * D + t] += dot;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) {
+        const double sum = block_sum(gs[i]);
+        if (threadIdx.x == 0) a.partial[(long)lb * D * D + i] = sum;
+    }
+}
+
+template <int FI, int D>
+void launch_gram_fast_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    constexpr int N = kFastSched[FI].n;
+    constexpr int RP = gram_batch(N, 16, D);
+    const size_t lds = (size_t)16 * N * D * D * RP;
+    hipLaunchKernelGGL((row_gram_fast<double, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
+}
+
+template <int FI>
+void launch_gram_fast_d(int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    if (d == 3)
+        launch_gram_fast_t<FI, 3>(args, woff, np, total, s);
+    else
+        launch_gram_fast_t<FI, 2>(args, woff, np, total, s);
+}
+
+void launch_gram_fast(int fi, int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    switch (fi) {
+        case 0: launch_gram_fast_d<0>(d, args, woff, np, total, s); break;
+        case 1: launch_gram_fast_d<1>(d, args, woff, np, total, s); break;
+        case 2: launch_gram_fast_d<2>(d, args, woff, np, total, s); break;
+        case 3: launch_gram_fast_d<3>(d, args, woff, np, total, s); break;
+        case 4: launch_gram_fast_d<4>(d, args, woff, np, total, s); break;
+        default: launch_gram_fast_d<5>(d, args, woff, np, total, s); break;
     }
 }
 
@@ -1428,7 +1596,7 @@ __global__ __launch_bounds__(kThreads) void image_other_kernel(const double *img
 // ---------------------------------------------------------------------------
 size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
-    if (a.fast) return es * (size_t)a.f.n * a.d * a.B;
+    if (a.fast) return es * ((size_t)a.f.n * a.d * a.B + tw_lds_entries(a.f.n, (int)es));
     int lacc = 0;
     if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
     if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
@@ -1437,7 +1605,9 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
-    if (a.fast) return es * (size_t)a.f.n * a.d * a.RP;
+    if (a.fast)
+        return es * ((size_t)a.f.n * (a.mode == ROW_GRAM ? a.d * a.d : a.d) * a.RP +
+                     (a.mode == ROW_GRAM ? 0 : tw_lds_entries(a.f.n, (int)es)));
     int nz = a.ncomp;
     if (a.mode == ROW_RHS) nz = a.d;
     if (a.mode == ROW_R2C || a.mode == ROW_C2R) nz = 1;
@@ -1477,6 +1647,15 @@ void configure_row(RowArgs &r, bool fp64) {
     if (ok) {
         r.fast = 1;
         r.RP = fast_batch(r.f.n, fp64 ? 16 : 8, r.d);
+        return;
+    }
+    const bool gram_ok = fi >= 0 && fp64 && r.mode == ROW_GRAM && r.ncomp == r.d * r.d && (r.d == 2 || r.d == 3) &&
+                         r.f.nst == kFastSched[fi].nst && r.Nh_row <= (r.f.n + 1) / 2;
+    bool sched = gram_ok;
+    for (int s = 0; sched && s < r.f.nst; ++s) sched = r.f.radix[s] == kFastSched[fi].r[s];
+    if (sched) {
+        r.fast = 1;
+        r.RP = gram_batch(r.f.n, 16, r.d);
         return;
     }
     r.fast = 0;
@@ -1530,6 +1709,11 @@ hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int
                             hipStream_t s) {
     const int fi = fast_index(proto.f.n);
     if (!proto.fast || fi < 0 || np < 1 || total < 1) return hipErrorInvalidValue;
+    if (proto.mode == ROW_GRAM) {
+        if (!fp64) return hipErrorInvalidValue;
+        launch_gram_fast(fi, proto.d, args, woff, np, total, s);
+        return hipGetLastError();
+    }
     if (fp64)
         launch_row_fast<double>(fi, proto.d, args, woff, np, total, s);
     else

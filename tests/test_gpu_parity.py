@@ -106,7 +106,7 @@ def test_c1_full_size_against_golden(fg):
     assert _rel(res["lower"], gold["lower"]) < 1e-10
 
 
-@pytest.mark.parametrize("case", ["c2_365", "c3"])
+@pytest.mark.parametrize("case", ["c2_365", "c3", "c2_1013"])
 def test_full_size_against_golden(fg, case):
     path = os.path.join(HERE, "golden", case + ".json")
     if not os.path.exists(path):
