@@ -252,7 +252,7 @@ def main():
             "Mpoint_iter_per_s": round(f32["value"], 1), "cg_iterations": f32["iters"],
             "bound_rel_err_vs_fp64": max(rel(f32["last"][k], f64["last"][k]) for k in ("upper", "lower")),
             "speedup_vs_fp64": round(f64["ms_per_step"] / f32["ms_per_step"], 3),
-            "roofline": f32["roofline"]},
+            "kernels": f32["kernels"], "roofline": f32["roofline"]},
     }
     if args.serve > 0:
         out["serving"] = serving_bench(args.serve, args.rtol32)

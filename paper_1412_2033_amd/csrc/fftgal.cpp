@@ -567,6 +567,13 @@ RowArgs base_row(Plan *pl, bool fp64, int mode, void *rows, int kind) {
         r.A0[i] = c0[i];
         r.D[i] = c1[i];
     }
+    // isotropic when both matrices are exact multiples of the identity
+    r.iso = 1;
+    for (int i = 0; i < D.d; ++i)
+        for (int j = 0; j < D.d; ++j) {
+            const int k = i * D.d + j;
+            if (i == j ? (c0[k] != c0[0] || c1[k] != c1[0]) : (c0[k] != 0.0 || c1[k] != 0.0)) r.iso = 0;
+        }
     return r;
 }
 
@@ -1470,7 +1477,7 @@ size_t blob_put(std::vector<unsigned char> &blob, const void *p, size_t n) {
 bool pass_fast(const PassRec &r) { return r.type == 0 ? r.pa.fast != 0 : r.ra.fast != 0; }
 
 // Group the members' specialised passes by (pass index, kernel, length,
-// dimension, precision) and lay out their argument tables, work-group
+// dimension, precision, kernel variant) and lay out their argument tables, work-group
 // offsets, CG update arguments and CG items in one blob; upload it.
 int batch_rebuild(Batch *b) {
     b->blob.clear();
@@ -1485,7 +1492,8 @@ int batch_rebuild(Batch *b) {
             const PassRec &r = ps[i];
             const int n = r.type == 0 ? r.pa.f.n : r.ra.f.n;
             const int d = r.type == 0 ? r.pa.d : r.ra.d;
-            by[std::make_tuple(r.type, n, d, (int)r.fp64)].push_back(m);
+            const int fm = r.type == 0 ? r.pa.fast : r.ra.fast;
+            by[std::make_tuple(r.type, n, d, (int)r.fp64 * 4 + fm)].push_back(m);
         }
         for (auto &kv : by) {
             const auto &ms = kv.second;

@@ -25,7 +25,10 @@ struct FftDesc {
 
 // Grid sizes with compile-time specialised kernels, and their radix
 // schedules (composite radices are done in registers).  The host builds the
-// twiddle tables of these lengths with the same schedule.
+// twiddle tables of these lengths with the same schedule.  Schedules read the
+// same forwards and backwards where the length allows: then the last stage of
+// an inverse transform leaves each thread holding exactly the points that the
+// first stage of a forward transform consumes.
 struct FastSched {
     int n;
     int nst;
@@ -33,7 +36,7 @@ struct FastSched {
 };
 constexpr FastSched kFastSched[] = {
     {81, 2, {9, 9, 0, 0}},      {125, 2, {25, 5, 0, 0}},  {225, 2, {15, 15, 0, 0}},
-    {245, 3, {7, 7, 5, 0}},     {729, 3, {9, 9, 9, 0}},   {2025, 3, {15, 15, 9, 0}},
+    {245, 3, {7, 5, 7, 0}},     {729, 3, {9, 9, 9, 0}},   {2025, 3, {15, 9, 15, 0}},
 };
 constexpr int kNumFast = sizeof(kFastSched) / sizeof(kFastSched[0]);
 constexpr int fast_index(int n) {
@@ -119,7 +122,8 @@ struct RowArgs {
     int d;
     int mode;
     int RP;           // row pairs per work-group
-    int fast;         // set by configure_row
+    int fast;         // set by configure_row (1 specialised, 2 specialised isotropic)
+    int iso;          // A0 and D are multiples of the identity
     const void *g;    // material field g (M^d, precision of the kernel)
     double A0[9];     // A(x) = A0 + g(x) D
     double D[9];

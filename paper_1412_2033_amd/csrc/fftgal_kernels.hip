@@ -861,16 +861,16 @@ __global__ __launch_bounds__(kThreads) void incl_coeff_kernel(double2 *out, int 
 // One in-place Stockham stage over NB transforms of length N: every thread
 // first loads all inputs of its butterflies into registers, then (after a
 // barrier) twiddles, transforms and stores them.
-template <typename T, int R, int N, int P, int NB, bool ROWL>
+template <typename T, int R, int N, int P, int NB, bool ROWL, int NT = kThreads>
 __device__ __forceinline__ void stage_ip(Vt<T> *X, const Vt<T> *__restrict__ tw, T sg) {
     constexpr int TQ = N / R;
     constexpr int TOT = TQ * NB;
-    constexpr int PER = (TOT + kThreads - 1) / kThreads;
+    constexpr int PER = (TOT + NT - 1) / NT;
     Vt<T> u[PER][R];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-        const int idx = threadIdx.x + t * kThreads;
-        if (PER * kThreads == TOT || idx < TOT) {
+        const int idx = threadIdx.x + t * NT;
+        if (PER * NT == TOT || idx < TOT) {
             const int b = ROWL ? idx / TQ : idx % NB;
             const int i = ROWL ? idx % TQ : idx / NB;
 #pragma unroll
@@ -883,8 +883,8 @@ __device__ __forceinline__ void stage_ip(Vt<T> *X, const Vt<T> *__restrict__ tw,
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-        const int idx = threadIdx.x + t * kThreads;
-        if (PER * kThreads == TOT || idx < TOT) {
+        const int idx = threadIdx.x + t * NT;
+        if (PER * NT == TOT || idx < TOT) {
             const int b = ROWL ? idx / TQ : idx % NB;
             const int i = ROWL ? idx % TQ : idx / NB;
             const int k = i % P;
@@ -1260,6 +1260,187 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Operator row pass for isotropic materials, A(x) = (a0 + g(x) dA) I.  Every
+// component row is multiplied by the same scalar field, so each packed row
+// pair (two real rows as one complex transform) is independent of the others.
+// The first inverse stage reads its points straight from the half-spectrum
+// rows (Hermitian extension and zero padding on the fly); the last inverse
+// stage leaves each thread holding the points x = i + q N/R, where the
+// material multiply is applied and the first forward stage (same radix, same
+// points) follows in registers.  Only the middle stages, the exchanges
+// between stages and the final Hermitian unpacking go through LDS.
+constexpr bool palindromic(int fi) {
+    const int s = kFastSched[fi].nst;
+    for (int i = 0; i < s; ++i)
+        if (kFastSched[fi].r[i] != kFastSched[fi].r[s - 1 - i]) return false;
+    return true;
+}
+constexpr int sched_p(int fi, int st) {
+    int p = 1;
+    for (int i = 0; i < st; ++i) p *= kFastSched[fi].r[i];
+    return p;
+}
+constexpr int sched_off(int fi, int st) {
+    int off = 0, p = 1;
+    for (int i = 0; i < st; ++i) {
+        off += (kFastSched[fi].r[i] - 1) * p;
+        p *= kFastSched[fi].r[i];
+    }
+    return off;
+}
+// transforms per work-group and work-group size: every thread of the first
+// and last stages owns one butterfly of radix r[0]
+constexpr int iso_tb(int fi) {
+    const int tq = kFastSched[fi].n / kFastSched[fi].r[0];
+    return tq <= 64 ? 128 / tq : (tq <= 128 ? 256 / tq : 320 / tq);
+}
+constexpr int iso_nt(int fi) {
+    const int tq = kFastSched[fi].n / kFastSched[fi].r[0];
+    return (iso_tb(fi) * tq + 63) / 64 * 64;
+}
+
+template <typename T, int FI, int S, int SEND, int NB, int NT>
+__device__ __forceinline__ void fft_mid(Vt<T> *X, const Vt<T> *tw, T sg) {
+    if constexpr (S < SEND) {
+        stage_ip<T, kFastSched[FI].r[S], kFastSched[FI].n, sched_p(FI, S), NB, true, NT>(X, tw + sched_off(FI, S),
+                                                                                          sg);
+        fft_mid<T, FI, S + 1, SEND, NB, NT>(X, tw, sg);
+    }
+}
+
+template <typename T, int FI>
+__global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__restrict__ ra,
+                                                           const int *__restrict__ woff, int np) {
+    using V = Vt<T>;
+    constexpr int N = kFastSched[FI].n;
+    constexpr int S = kFastSched[FI].nst;
+    constexpr int R = kFastSched[FI].r[0];
+    constexpr int TQ = N / R;  // butterflies per transform in the first and last stages
+    constexpr int TB = iso_tb(FI);
+    constexpr int NT = iso_nt(FI);
+    constexpr int OFFL = sched_off(FI, S - 1);  // twiddles of the last stage (P = TQ)
+    static_assert(palindromic(FI) && S >= 2 && sched_p(FI, S - 1) == TQ, "schedule must be palindromic");
+    int lb;
+    const RowArgs &a = ra[find_problem(woff, np, &lb)];
+    if (a.status != nullptr && a.status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    V *X = reinterpret_cast<V *>(smem_raw);  // [transform][pos]
+    V *tws = X + TB * N;
+    const V *twg = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
+    for (int i = threadIdx.x; i < N - 1; i += NT) tws[i] = twg[i];
+    const V zero = mk<T>(T(0), T(0));
+    const int nh = a.Nh_row;
+    const int npairs = (a.nrows + 1) / 2;
+    const int ntr = a.d * npairs;
+    const int tl = threadIdx.x / TQ;
+    const int i = threadIdx.x - tl * TQ;
+    const int tb = lb * TB + tl;
+    const bool act = tl < TB && tb < ntr;
+    // transforms ordered pair-major (components fastest), so that the d
+    // transforms reading one row pair's material values share a work-group
+    int c = 0, r1 = 0;
+    if (act) {
+        const int pr = tb / a.d;
+        c = tb - pr * a.d;
+        r1 = 2 * pr;
+    }
+    const bool v2 = act && r1 + 1 < a.nrows;
+    const V *data = reinterpret_cast<const V *>(a.data);
+    const V *row1 = data + (long)c * a.cs + (long)r1 * nh;
+    const V *row2 = row1 + nh;
+    const T *g = reinterpret_cast<const T *>(a.g);
+    T g1[R], g2[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int x = i + q * TQ;
+        g1[q] = act ? g[(long)r1 * N + x] : T(0);
+        g2[q] = v2 ? g[(long)(r1 + 1) * N + x] : T(0);
+    }
+    const T a0 = T(a.A0[0]);
+    const T da = T(a.D[0]);
+    V u[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int pos = i + q * TQ;
+        u[q] = zero;
+        if (act) {
+            if (pos < nh) {
+                const V u1 = row1[pos];
+                const V u2 = v2 ? row2[pos] : zero;
+                u[q] = pos == 0 ? mk<T>(u1.x, u2.x) : mk<T>(u1.x - u2.y, u1.y + u2.x);
+            } else if (pos > N - nh) {
+                const V u1 = row1[N - pos];
+                const V u2 = v2 ? row2[N - pos] : zero;
+                u[q] = mk<T>(u1.x + u2.y, u2.x - u1.y);
+            }
+        }
+    }
+    // first inverse stage (P = 1): outputs at i R + q
+    dftn<T, R>(u, T(1));
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) X[tl * N + i * R + q] = u[q];
+    }
+    __syncthreads();
+    fft_mid<T, FI, 1, S - 1, TB, NT>(X, tws, T(1));
+    // last inverse stage: inputs and outputs at i + q TQ (own points only)
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) u[q] = X[tl * N + i + q * TQ];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+        V w = tws[OFFL + (q - 1) * TQ + i];
+        w.y = -w.y;
+        u[q] = cmul(u[q], w);
+    }
+    dftn<T, R>(u, T(1));
+    // the two real rows at x = i + q TQ: multiply by a0 + g da
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        u[q].x *= a0 + g1[q] * da;
+        u[q].y *= a0 + g2[q] * da;
+    }
+    // first forward stage on the same points
+    dftn<T, R>(u, T(-1));
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) X[tl * N + i * R + q] = u[q];
+    }
+    __syncthreads();
+    fft_mid<T, FI, 1, S - 1, TB, NT>(X, tws, T(-1));
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) u[q] = X[tl * N + i + q * TQ];
+#pragma unroll
+        for (int q = 1; q < R; ++q) u[q] = cmul(u[q], tws[OFFL + (q - 1) * TQ + i]);
+        dftn<T, R>(u, T(-1));
+#pragma unroll
+        for (int q = 0; q < R; ++q) X[tl * N + i + q * TQ] = u[q];
+    }
+    __syncthreads();
+    // unpack the two rows of each transform and keep the first nh frequencies
+    V *out = reinterpret_cast<V *>(a.data);
+    const T half = T(a.scale) * T(0.5);
+    for (int o = threadIdx.x; o < TB * nh; o += NT) {
+        const int t = o / nh;
+        const int kx = o - t * nh;
+        const int tbo = lb * TB + t;
+        if (tbo >= ntr) continue;
+        const int po = tbo / a.d;
+        const int co = tbo - po * a.d;
+        const int ro = 2 * po;
+        const V w = X[t * N + kx];
+        const V wm = X[t * N + (kx == 0 ? 0 : N - kx)];
+        V *orow = out + (long)co * a.cs + (long)ro * nh;
+        orow[kx] = mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half);
+        if (ro + 1 < a.nrows) orow[nh + kx] = mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half);
+    }
+}
+
 template <typename T, int FI, int D>
 void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
@@ -1314,6 +1495,28 @@ void launch_row_fast(int fi, int d, const RowArgs *args, const int *woff, int np
         case 3: launch_row_fast_d<T, 3>(d, args, woff, np, total, s); break;
         case 4: launch_row_fast_d<T, 4>(d, args, woff, np, total, s); break;
         default: launch_row_fast_d<T, 5>(d, args, woff, np, total, s); break;
+    }
+}
+
+
+template <typename T, int FI>
+void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    if constexpr (palindromic(FI)) {
+        constexpr int N = kFastSched[FI].n;
+        const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + N);
+        hipLaunchKernelGGL((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
+    }
+}
+
+template <typename T>
+void launch_row_iso(int fi, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    switch (fi) {
+        case 0: launch_row_iso_t<T, 0>(args, woff, np, total, s); break;
+        case 1: launch_row_iso_t<T, 1>(args, woff, np, total, s); break;
+        case 2: launch_row_iso_t<T, 2>(args, woff, np, total, s); break;
+        case 3: launch_row_iso_t<T, 3>(args, woff, np, total, s); break;
+        case 4: launch_row_iso_t<T, 4>(args, woff, np, total, s); break;
+        default: launch_row_iso_t<T, 5>(args, woff, np, total, s); break;
     }
 }
 
@@ -1605,6 +1808,7 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
+    if (a.fast == 2) return es * ((size_t)a.RP * a.f.n + a.f.n);
     if (a.fast)
         return es * ((size_t)a.f.n * (a.mode == ROW_GRAM ? a.d * a.d : a.d) * a.RP +
                      (a.mode == ROW_GRAM ? 0 : tw_lds_entries(a.f.n, (int)es)));
@@ -1615,7 +1819,11 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
 }
 
 int pencil_grid_x(const PencilArgs &a) { return a.B > 0 ? (a.nb + a.B - 1) / a.B : 0; }
-int row_grid(const RowArgs &a) { return a.RP > 0 ? ((a.nrows + 1) / 2 + a.RP - 1) / a.RP : 0; }
+int row_grid(const RowArgs &a) {
+    if (a.RP < 1) return 0;
+    const int pairs = (a.nrows + 1) / 2;
+    return a.fast == 2 ? (a.d * pairs + a.RP - 1) / a.RP : (pairs + a.RP - 1) / a.RP;
+}
 
 static_assert(kNumFast == 6, "launch_*_fast switch covers six sizes");
 
@@ -1644,6 +1852,11 @@ void configure_row(RowArgs &r, bool fp64) {
     bool ok = fi >= 0 && (r.mode == ROW_OPER || r.mode == ROW_RHS) && r.ncomp == r.d && (r.d == 2 || r.d == 3) &&
               r.f.nst == kFastSched[fi].nst && r.Nh_row <= (r.f.n + 1) / 2;
     for (int s = 0; ok && s < r.f.nst; ++s) ok = r.f.radix[s] == kFastSched[fi].r[s];
+    if (ok && r.iso && r.mode == ROW_OPER && palindromic(fi)) {
+        r.fast = 2;
+        r.RP = iso_tb(fi);
+        return;
+    }
     if (ok) {
         r.fast = 1;
         r.RP = fast_batch(r.f.n, fp64 ? 16 : 8, r.d);
@@ -1712,6 +1925,14 @@ hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int
     if (proto.mode == ROW_GRAM) {
         if (!fp64) return hipErrorInvalidValue;
         launch_gram_fast(fi, proto.d, args, woff, np, total, s);
+        return hipGetLastError();
+    }
+    if (proto.fast == 2) {
+        if (!palindromic(fi) || proto.mode != ROW_OPER) return hipErrorInvalidValue;
+        if (fp64)
+            launch_row_iso<double>(fi, args, woff, np, total, s);
+        else
+            launch_row_iso<float>(fi, args, woff, np, total, s);
         return hipGetLastError();
     }
     if (fp64)
