@@ -7,6 +7,8 @@
 // and no Nyquist frequency ever occurs.
 #include "fftgal_internal.h"
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,12 +23,40 @@ template <> struct VecOf<double> { using type = double2; };
 
 template <typename T> using Vt = typename VecOf<T>::type;
 
+// The argument tables hold generic pointers; operands known to live in device
+// global memory are cast to that address space so that the compiler emits
+// global (not flat) accesses and may move them past LDS accesses.
+template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T *gbl(T *p) {
+    return (__attribute__((address_space(1))) T *)(p);
+}
+
 template <typename T>
 __device__ __forceinline__ Vt<T> mk(T a, T b) {
     Vt<T> v;
     v.x = a;
     v.y = b;
     return v;
+}
+// complex loads and stores through global-address-space pointers, as one
+// 8- or 16-byte access of a native two-element vector
+template <typename V> struct ScalarOf;
+template <> struct ScalarOf<float2> { using type = float; };
+template <> struct ScalarOf<double2> { using type = double; };
+template <typename S> using NVec2 = S __attribute__((ext_vector_type(2)));
+template <typename V> __device__ __forceinline__ V gld(const __attribute__((address_space(1))) V *p) {
+    using S = typename ScalarOf<V>::type;
+    const NVec2<S> w = *reinterpret_cast<const __attribute__((address_space(1))) NVec2<S> *>(p);
+    V v;
+    v.x = w.x;
+    v.y = w.y;
+    return v;
+}
+template <typename V> __device__ __forceinline__ void gst(__attribute__((address_space(1))) V *p, V v) {
+    using S = typename ScalarOf<V>::type;
+    NVec2<S> w;
+    w.x = v.x;
+    w.y = v.y;
+    *reinterpret_cast<__attribute__((address_space(1))) NVec2<S> *>(p) = w;
 }
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) {
     a.x += b.x;
@@ -163,6 +193,25 @@ template <typename T, int R>
 __device__ __forceinline__ void dftn(Vt<T> *u, T sg) {
     if constexpr (R == 3 || R == 5 || R == 7) {
         dft<T, R>(u, sg);
+    } else if constexpr (R == 15) {
+        // Good-Thomas split 15 = 3 * 5 (coprime, no twiddles): input index
+        // (5 n1 + 3 n2) mod 15, output index (10 k1 + 6 k2) mod 15
+        Vt<T> y[3][5];
+#pragma unroll
+        for (int n2 = 0; n2 < 5; ++n2) {
+            Vt<T> col[3];
+#pragma unroll
+            for (int n1 = 0; n1 < 3; ++n1) col[n1] = u[(5 * n1 + 3 * n2) % 15];
+            dft<T, 3>(col, sg);
+#pragma unroll
+            for (int k1 = 0; k1 < 3; ++k1) y[k1][n2] = col[k1];
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            dft<T, 5>(y[k1], sg);
+#pragma unroll
+            for (int k2 = 0; k2 < 5; ++k2) u[(10 * k1 + 6 * k2) % 15] = y[k1][k2];
+        }
     } else {
         constexpr int R1 = smallest_prime_factor(R);
         constexpr int R2 = R / R1;
@@ -1002,36 +1051,68 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
             *k3 = 0;
         }
     };
-    if (a.L_in < N || nbw < B) {
-        for (int idx = threadIdx.x; idx < N * NB; idx += kThreads) X[idx] = zero;
-        __syncthreads();
-    }
+    // Global loads of a phase are issued together (branch-free, with idle
+    // slots reading an in-range address) into scalar register arrays, then
+    // written to LDS; the slots no input reaches (outside the input
+    // frequencies, idle pencils) are zeroed by a disjoint loop.  The trip
+    // counts are compile-time bounds: inputs of at most (N + 1) / 2 points
+    // (zero-padded transforms) or of N points.
+    const int klo = -(a.L_in / 2), khi = (a.L_in + 1) / 2;  // input frequencies k in [klo, khi)
+    auto zero_band = [&](int nper) {  // nper LDS slots per position
+        for (int idx = threadIdx.x; idx < N * nper; idx += kThreads) {
+            const int pos = idx / nper;
+            const int bb = (idx - pos * nper) % B;
+            const int k = pos < (N + 1) / 2 ? pos : pos - N;
+            if (!(k >= klo && k < khi && bb < nbw)) X[idx] = zero;
+        }
+    };
     if (a.pro == PRO_EXPAND) {
-        const V *sr = reinterpret_cast<const V *>(a.st_r);
-        V *sp = reinterpret_cast<V *>(a.st_p);
-        const V *sx = reinterpret_cast<const V *>(a.st_x);
+        // L_in <= (N + 1) / 2: the CG vectors live on the coarse grid
+        constexpr int PE = ((N + 1) / 2 * B + kThreads - 1) / kThreads;
+        const auto *sr = gbl(reinterpret_cast<const V *>(a.st_r));
+        auto *sp = gbl(reinterpret_cast<V *>(a.st_p));
+        const auto *sx = gbl(reinterpret_cast<const V *>(a.st_x));
         const T beta = (a.update_p && a.status) ? T(a.status->beta) : T(0);
-        for (int idx = threadIdx.x; idx < a.L_in * B; idx += kThreads) {
+        T ax[PE][2], ay[PE][2], bx[PE][2], by[PE][2];
+#pragma unroll
+        for (int t = 0; t < PE; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
             const int bb = idx % B;
             const int l = idx / B;
-            if (bb >= nbw) continue;
+            const bool ok = idx < a.L_in * B && bb < nbw;
+            const long off = ok ? (long)l * a.in_ls + b0 + bb : (long)b0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const long o2 = (c < a.nc ? c : 0) * a.st_cs + off;
+                const V va = a.update_p ? gld(sr + o2) : gld(sx + o2);
+                const V vb = a.update_p ? gld(sp + o2) : zero;
+                ax[t][c] = va.x;
+                ay[t][c] = va.y;
+                bx[t][c] = vb.x;
+                by[t][c] = vb.y;
+            }
+        }
+        zero_band(NB);
+#pragma unroll
+        for (int t = 0; t < PE; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
+            const int bb = idx % B;
+            const int l = idx / B;
+            if (idx >= a.L_in * B || bb >= nbw) continue;
             int k1, k2, k3;
             freq(l, a.L_in, b0 + bb, &k1, &k2, &k3);
-            T t[2][3];
-            const int nt = basis<T>(D, a.kind, k1, k2, k3, t);
+            T tb[2][3];
+            const int nt = basis<T>(D, a.kind, k1, k2, k3, tb);
             V v[2];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 v[c] = zero;
                 if (c < a.nc) {
-                    const long off = c * a.st_cs + (long)l * a.in_ls + b0 + bb;
                     if (a.update_p) {
-                        const V r = sr[off];
-                        const V pv = sp[off];
-                        v[c] = mk<T>(r.x + beta * pv.x, r.y + beta * pv.y);
-                        sp[off] = v[c];
+                        v[c] = mk<T>(ax[t][c] + beta * bx[t][c], ay[t][c] + beta * by[t][c]);
+                        gst(sp + c * a.st_cs + (long)l * a.in_ls + b0 + bb, v[c]);
                     } else {
-                        v[c] = sx[off];
+                        v[c] = mk<T>(ax[t][c], ay[t][c]);
                     }
                 }
             }
@@ -1042,39 +1123,77 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     if (c < nt) {
-                        ex -= t[c][al] * v[c].y;
-                        ey += t[c][al] * v[c].x;
+                        ex -= tb[c][al] * v[c].y;
+                        ey += tb[c][al] * v[c].x;
                     }
                 }
                 X[pos * NB + al * B + bb] = mk<T>(ex, ey);
             }
         }
     } else {
-        const V *in = reinterpret_cast<const V *>(a.in);
-        for (int idx = threadIdx.x; idx < a.L_in * NB; idx += kThreads) {
-            const int rr = idx % NB;
-            const int l = idx / NB;
-            const int c = rr / B;
-            const int bb = rr - c * B;
-            if (bb >= nbw) continue;
-            X[posmod(wrapi(l, a.L_in), N) * NB + rr] =
-                in[(long)c * a.in_cs + (long)o * a.in_os + (long)l * a.in_ls + b0 + bb];
-        }
+        const auto *in = gbl(reinterpret_cast<const V *>(a.in) + (long)o * a.in_os + b0);
+        auto load = [&](auto cap) {
+            constexpr int P = (decltype(cap)::value * NB + kThreads - 1) / kThreads;
+            T vx[P], vy[P];
+            int dst[P];
+#pragma unroll
+            for (int t = 0; t < P; ++t) {
+                const int idx = threadIdx.x + t * kThreads;
+                const int rr = idx % NB;
+                const int l = idx / NB;
+                const int c = rr / B;
+                const int bb = rr - c * B;
+                const bool ok = idx < a.L_in * NB && bb < nbw;
+                const V v = gld(in + (ok ? (long)c * a.in_cs + (long)l * a.in_ls + bb : 0L));
+                vx[t] = v.x;
+                vy[t] = v.y;
+                dst[t] = ok ? posmod(wrapi(l, a.L_in), N) * NB + rr : -1;
+            }
+            zero_band(NB);
+#pragma unroll
+            for (int t = 0; t < P; ++t)
+                if (dst[t] >= 0) X[dst[t]] = mk<T>(vx[t], vy[t]);
+        };
+        if (2 * a.L_in <= N + 1)
+            load(std::integral_constant<int, (N + 1) / 2>{});
+        else
+            load(std::integral_constant<int, N>{});
     }
     __syncthreads();
     fft_ip<T, FI, 0, 1, 0, NB, false>(X, tw, sg);
-    V *out = reinterpret_cast<V *>(a.out);
+    auto *out = gbl(reinterpret_cast<V *>(a.out));
     if (a.epi == EPI_PROJECT) {
-        const V *dv = reinterpret_cast<const V *>(a.st_dot);
+        // L_out <= (N + 1) / 2: the projected vector lives on the coarse grid
+        constexpr int PE = ((N + 1) / 2 * B + kThreads - 1) / kThreads;
+        const auto *dv = gbl(reinterpret_cast<const V *>(a.st_dot));
+        T dx[PE][2], dy[PE][2];
+        if (a.st_dot != nullptr) {
+#pragma unroll
+            for (int t = 0; t < PE; ++t) {
+                const int idx = threadIdx.x + t * kThreads;
+                const int bb = idx % B;
+                const int l = idx / B;
+                const bool ok = idx < a.L_out * B && bb < nbw;
+                const long off = ok ? (long)l * a.out_ls + b0 + bb : (long)b0;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const V v = gld(dv + (c < a.nc ? c : 0) * a.out_cs + off);
+                    dx[t][c] = v.x;
+                    dy[t][c] = v.y;
+                }
+            }
+        }
         double part = 0.0;
-        for (int idx = threadIdx.x; idx < a.L_out * B; idx += kThreads) {
+#pragma unroll
+        for (int t = 0; t < PE; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
             const int bb = idx % B;
             const int l = idx / B;
-            if (bb >= nbw) continue;
+            if (idx >= a.L_out * B || bb >= nbw) continue;
             int k1, k2, k3;
             freq(l, a.L_out, b0 + bb, &k1, &k2, &k3);
-            T t[2][3];
-            const int nt = basis<T>(D, a.kind, k1, k2, k3, t);
+            T tb[2][3];
+            const int nt = basis<T>(D, a.kind, k1, k2, k3, tb);
             const int pos = posmod(k1, N);
             V y[D];
 #pragma unroll
@@ -1087,16 +1206,15 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                     if (c < nt) {
 #pragma unroll
                         for (int al = 0; al < D; ++al) {
-                            const T tt = t[c][al] * scale;
+                            const T tt = tb[c][al] * scale;
                             qx += tt * y[al].y;
                             qy -= tt * y[al].x;
                         }
                     }
                     const long off = c * a.out_cs + (long)l * a.out_ls + b0 + bb;
-                    out[off] = mk<T>(qx, qy);
-                    if (dv != nullptr) {
-                        const V pv = dv[off];
-                        part += w * ((double)pv.x * (double)qx + (double)pv.y * (double)qy);
+                    gst(out + off, mk<T>(qx, qy));
+                    if (a.st_dot != nullptr) {
+                        part += w * ((double)dx[t][c] * (double)qx + (double)dy[t][c] * (double)qy);
                     } else {
                         part += w * ((double)qx * (double)qx + (double)qy * (double)qy);
                     }
@@ -1115,7 +1233,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
             V v = X[posmod(wrapi(l, a.L_out), N) * NB + rr];
             v.x *= scale;
             v.y *= scale;
-            out[(long)c * a.out_cs + (long)o * a.out_os + (long)l * a.out_ls + b0 + bb] = v;
+            gst(out + (long)c * a.out_cs + (long)o * a.out_os + (long)l * a.out_ls + b0 + bb, v);
         }
     }
 }
@@ -1163,18 +1281,42 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
         }
     }
     if (a.mode == ROW_OPER) {
-        for (int idx = threadIdx.x; idx < N * NB; idx += kThreads) X[idx] = zero;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < NB * nh; idx += kThreads) {
+        // both rows of every pair, all loads in flight together (nh <= (N + 1) / 2),
+        // then the packed Hermitian extension; the zero band nh <= x <= N - nh
+        // is written by a disjoint loop
+        constexpr int PLR = (NB * ((N + 1) / 2) + kThreads - 1) / kThreads;
+        const auto *dg = gbl(reinterpret_cast<const V *>(a.data));
+        T p1x[PLR], p1y[PLR], p2x[PLR], p2y[PLR];
+#pragma unroll
+        for (int t = 0; t < PLR; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
             const int pc = idx / nh;
             const int kx = idx - pc * nh;
             const int c = pc / RP;
             const int j = pc - c * RP;
-            if (j >= nvp) continue;
             const int r1 = 2 * (pair0 + j);
-            const int r2 = r1 + 1;
-            const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
-            const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+            const bool ok = idx < NB * nh && j < nvp;
+            const bool ok2 = ok && r1 + 1 < a.nrows;
+            const long off = ok ? (long)c * a.cs + (long)r1 * nh + kx : 0L;
+            const V u1 = gld(dg + off);
+            const V u2 = gld(dg + (ok2 ? off + nh : off));
+            p1x[t] = u1.x;
+            p1y[t] = u1.y;
+            p2x[t] = ok2 ? u2.x : T(0);
+            p2y[t] = ok2 ? u2.y : T(0);
+        }
+        for (int idx = threadIdx.x; idx < NB * (N - 2 * nh + 1); idx += kThreads) {
+            const int pc = idx / (N - 2 * nh + 1);
+            X[pc * N + nh + (idx - pc * (N - 2 * nh + 1))] = zero;
+        }
+#pragma unroll
+        for (int t = 0; t < PLR; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
+            const int pc = idx / nh;
+            const int kx = idx - pc * nh;
+            if (idx >= NB * nh) continue;
+            const V u1 = mk<T>(p1x[t], p1y[t]);
+            const V u2 = mk<T>(p2x[t], p2y[t]);
             if (kx == 0) {
                 X[pc * N] = mk<T>(u1.x, u2.x);
             } else {
@@ -1349,32 +1491,45 @@ __global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__rest
     const bool v2 = act && r1 + 1 < a.nrows;
     const V *data = reinterpret_cast<const V *>(a.data);
     const V *row1 = data + (long)c * a.cs + (long)r1 * nh;
-    const V *row2 = row1 + nh;
     const T *g = reinterpret_cast<const T *>(a.g);
     T g1[R], g2[R];
+    {
+        // idle lanes read row r1 (in range); their products are never stored
+        const T *gr1 = g + (long)r1 * N + i;
+        const T *gr2 = v2 ? gr1 + N : gr1;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int x = i + q * TQ;
-        g1[q] = act ? g[(long)r1 * N + x] : T(0);
-        g2[q] = v2 ? g[(long)(r1 + 1) * N + x] : T(0);
+        for (int q = 0; q < R; ++q) {
+            g1[q] = gr1[q * TQ];
+            g2[q] = gr2[q * TQ];
+        }
     }
     const T a0 = T(a.A0[0]);
     const T da = T(a.D[0]);
     V u[R];
+    {
+        // all loads first (idle points read entry 0 of the pair), then the
+        // Hermitian packing by selects
+        T l1x[R], l1y[R], l2x[R], l2y[R];
+        const auto *rg = gbl(row1);
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int pos = i + q * TQ;
-        u[q] = zero;
-        if (act) {
-            if (pos < nh) {
-                const V u1 = row1[pos];
-                const V u2 = v2 ? row2[pos] : zero;
-                u[q] = pos == 0 ? mk<T>(u1.x, u2.x) : mk<T>(u1.x - u2.y, u1.y + u2.x);
-            } else if (pos > N - nh) {
-                const V u1 = row1[N - pos];
-                const V u2 = v2 ? row2[N - pos] : zero;
-                u[q] = mk<T>(u1.x + u2.y, u2.x - u1.y);
-            }
+        for (int q = 0; q < R; ++q) {
+            const int pos = i + q * TQ;
+            const int kx = pos < nh ? pos : (pos > N - nh ? N - pos : 0);
+            const V a1 = gld(rg + kx);
+            const V a2 = gld(rg + (v2 ? nh + kx : kx));
+            l1x[q] = a1.x;
+            l1y[q] = a1.y;
+            l2x[q] = a2.x;
+            l2y[q] = a2.y;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int pos = i + q * TQ;
+            const V u1 = mk<T>(l1x[q], l1y[q]);
+            const V u2 = v2 ? mk<T>(l2x[q], l2y[q]) : zero;
+            const V lo = pos == 0 ? mk<T>(u1.x, u2.x) : mk<T>(u1.x - u2.y, u1.y + u2.x);
+            const V hi = mk<T>(u1.x + u2.y, u2.x - u1.y);
+            u[q] = !act ? zero : (pos < nh ? lo : (pos > N - nh ? hi : zero));
         }
     }
     // first inverse stage (P = 1): outputs at i R + q
@@ -1441,6 +1596,185 @@ __global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__rest
     }
 }
 
+// FP64 variant for two-stage schedules: every exchange between stages moves
+// the real parts through LDS first and the imaginary parts second, so a
+// transform needs n doubles of LDS instead of n complex values; with the
+// material values loaded at the multiply (not held in registers) this doubles
+// the resident waves, which hides the latencies of the stages.
+constexpr int split_tb(int fi) { return iso_tb(fi); }
+constexpr int split_nt(int fi) { return iso_nt(fi); }
+
+template <int FI>
+__global__ __launch_bounds__(split_nt(FI)) __attribute__((amdgpu_waves_per_eu(4))) void row_iso_split(const RowArgs *__restrict__ ra,
+                                                             const int *__restrict__ woff, int np) {
+    using T = double;
+    using V = Vt<T>;
+    constexpr int N = kFastSched[FI].n;
+    constexpr int R = kFastSched[FI].r[0];
+    constexpr int TQ = N / R;
+    constexpr int TB = split_tb(FI);
+    constexpr int NT = split_nt(FI);
+    constexpr int OFFL = sched_off(FI, 1);
+    static_assert(kFastSched[FI].nst == 2 && kFastSched[FI].r[1] == R, "two-stage palindromic schedule");
+    int lb;
+    const RowArgs &a = ra[find_problem(woff, np, &lb)];
+    if (a.status != nullptr && a.status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *Bf = reinterpret_cast<T *>(smem_raw);            // [transform][pos], one part at a time
+    V *tws = reinterpret_cast<V *>(Bf + TB * N);        // last-stage twiddles
+    const V *twg = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
+    for (int i = threadIdx.x; i < N - 1; i += NT) tws[i] = twg[i];
+    const V zero = mk<T>(T(0), T(0));
+    const int nh = a.Nh_row;
+    const int npairs = (a.nrows + 1) / 2;
+    const int ntr = a.d * npairs;
+    const int tl = threadIdx.x / TQ;
+    const int i = threadIdx.x - tl * TQ;
+    const int tb = lb * TB + tl;
+    const bool act = tl < TB && tb < ntr;
+    int c = 0, r1 = 0;
+    if (act) {
+        const int pr = tb / a.d;
+        c = tb - pr * a.d;
+        r1 = 2 * pr;
+    }
+    const bool v2 = act && r1 + 1 < a.nrows;
+    V *data = reinterpret_cast<V *>(a.data);
+    V *row1 = data + (long)c * a.cs + (long)r1 * nh;
+    V *row2 = row1 + nh;
+    const T *g = reinterpret_cast<const T *>(a.g);
+    T *Bt = Bf + (act ? tl : 0) * N;
+    // exchange: write own values at positions wp(q), read positions rp(q)
+    auto xchg = [&](V *u, auto wp, auto rp) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (act) Bt[wp(q)] = u[q].x;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (act) u[q].x = Bt[rp(q)];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (act) Bt[wp(q)] = u[q].y;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (act) u[q].y = Bt[rp(q)];
+        __syncthreads();
+    };
+    auto stage_out = [&](int q) { return i * R + q; };
+    auto own = [&](int q) { return i + q * TQ; };
+    V u[R];
+    {
+        // all loads first (idle points read entry 0 of the pair), then the
+        // Hermitian packing by selects
+        T l1x[R], l1y[R], l2x[R], l2y[R];
+        const auto *rg = gbl(row1);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int pos = i + q * TQ;
+            const int kx = pos < nh ? pos : (pos > N - nh ? N - pos : 0);
+            const V a1 = gld(rg + kx);
+            const V a2 = gld(rg + (v2 ? nh + kx : kx));
+            l1x[q] = a1.x;
+            l1y[q] = a1.y;
+            l2x[q] = a2.x;
+            l2y[q] = a2.y;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int pos = i + q * TQ;
+            const V u1 = mk<T>(l1x[q], l1y[q]);
+            const V u2 = v2 ? mk<T>(l2x[q], l2y[q]) : zero;
+            const V lo = pos == 0 ? mk<T>(u1.x, u2.x) : mk<T>(u1.x - u2.y, u1.y + u2.x);
+            const V hi = mk<T>(u1.x + u2.y, u2.x - u1.y);
+            u[q] = !act ? zero : (pos < nh ? lo : (pos > N - nh ? hi : zero));
+        }
+    }
+    dftn<T, R>(u, T(1));
+    xchg(u, stage_out, own);
+    // last-stage twiddles exp(-2 pi i q i' / N) = w^q, w = exp(-2 pi i i' / N),
+    // by repeated multiplication (FP64: the recurrence error stays ~1e-15)
+    const V w1 = tws[OFFL + i];
+    {
+        V w = w1;
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+            u[q] = cmul(u[q], mk<T>(w.x, -w.y));
+            w = cmul(w, w1);
+        }
+    }
+    dftn<T, R>(u, T(1));
+    {
+        // material values in groups of five loads, issued only here (the
+        // empty asm statements keep the compiler from hoisting them over
+        // the transform, where they would hold registers)
+        const T a0 = T(a.A0[0]);
+        const T da = T(a.D[0]);
+        const T *g1 = g + (long)r1 * N + i;
+        const T *g2 = v2 ? g1 + N : g1;
+        constexpr int GQ = 5;
+#pragma unroll
+        for (int q0 = 0; q0 < R; q0 += GQ) {
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int q = q0; q < q0 + GQ && q < R; ++q) {
+                const T ga = g1[q * TQ];
+                const T gb = g2[q * TQ];
+                u[q].x *= a0 + ga * da;
+                u[q].y *= a0 + gb * da;
+            }
+        }
+        asm volatile("" ::: "memory");
+    }
+    dftn<T, R>(u, T(-1));
+    xchg(u, stage_out, own);
+    {
+        V w = w1;
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+            u[q] = cmul(u[q], w);
+            w = cmul(w, w1);
+        }
+    }
+    dftn<T, R>(u, T(-1));
+    // Hermitian unpacking: each thread pairs its points p < nh with N - p
+    // (nh <= (N + 1) / 2, so only the first QH of its points are kept)
+    constexpr int QH = ((N + 1) / 2 + TQ - 1) / TQ;
+    V m[QH];
+    auto partner = [&](int q) {
+        const int p = i + q * TQ;
+        return p == 0 ? 0 : N - p;
+    };
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        if (act) Bt[own(q)] = u[q].x;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QH; ++q)
+        if (act) m[q].x = Bt[partner(q)];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        if (act) Bt[own(q)] = u[q].y;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QH; ++q)
+        if (act) m[q].y = Bt[partner(q)];
+    const T half = T(a.scale) * T(0.5);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        const int p = i + q * TQ;
+        if (act && p < nh) {
+            const V w = u[q];
+            const V wm = m[q];
+            row1[p] = mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half);
+            if (v2) row2[p] = mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half);
+        }
+    }
+}
+
 template <typename T, int FI, int D>
 void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
@@ -1503,8 +1837,13 @@ template <typename T, int FI>
 void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
     if constexpr (palindromic(FI)) {
         constexpr int N = kFastSched[FI].n;
-        const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + N);
-        hipLaunchKernelGGL((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
+        if constexpr (sizeof(T) == 8 && kFastSched[FI].nst == 2 && kFastSched[FI].r[0] <= 9) {
+            const size_t lds = sizeof(double) * (size_t)split_tb(FI) * N + sizeof(Vt<T>) * N;
+            hipLaunchKernelGGL((row_iso_split<FI>), dim3(total), dim3(split_nt(FI)), lds, s, args, woff, np);
+        } else {
+            const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + N);
+            hipLaunchKernelGGL((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
+        }
     }
 }
 
@@ -1808,7 +2147,12 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
-    if (a.fast == 2) return es * ((size_t)a.RP * a.f.n + a.f.n);
+    if (a.fast == 2) {
+        const int fi = fast_index(a.f.n);
+        if (fp64 && fi >= 0 && kFastSched[fi].nst == 2 && kFastSched[fi].r[0] <= 9)
+            return 8 * (size_t)a.RP * a.f.n + es * a.f.n;
+        return es * ((size_t)a.RP * a.f.n + a.f.n);
+    }
     if (a.fast)
         return es * ((size_t)a.f.n * (a.mode == ROW_GRAM ? a.d * a.d : a.d) * a.RP +
                      (a.mode == ROW_GRAM ? 0 : tw_lds_entries(a.f.n, (int)es)));
@@ -1830,7 +2174,8 @@ static_assert(kNumFast == 6, "launch_*_fast switch covers six sizes");
 void configure_pencil(PencilArgs &a, bool fp64) {
     const int fi = fast_index(a.f.n);
     bool ok = fi >= 0 && a.nsol == 1 && a.ncomp == a.d && a.epi != EPI_WINDOW && (a.d == 2 || a.d == 3) &&
-              a.f.nst == kFastSched[fi].nst;
+              a.f.nst == kFastSched[fi].nst && a.L_in <= a.f.n && a.L_out <= a.f.n &&
+              (a.pro != PRO_EXPAND || 2 * a.L_in <= a.f.n + 1) && (a.epi != EPI_PROJECT || 2 * a.L_out <= a.f.n + 1);
     for (int s = 0; ok && s < a.f.nst; ++s) ok = a.f.radix[s] == kFastSched[fi].r[s];
     if (ok) {
         a.fast = 1;
