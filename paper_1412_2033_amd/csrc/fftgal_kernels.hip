@@ -987,10 +987,12 @@ __device__ __forceinline__ const Vt<T> *twiddles_to_lds(Vt<T> *dst, const Vt<T> 
 }
 
 // pencils (or row pairs) per work-group so that one batch of all d
-// components stays within 48 KB of LDS
+// components stays within 24 KB of LDS (the passes are latency-bound:
+// smaller work-groups put more of them on a CU)
 constexpr int fast_batch(int n, int es, int d) {
+    const int cap = 24 * 1024;
     int b = 16;
-    while (b > 1 && d * b * n * es > 48 * 1024) b /= 2;
+    while (b > 1 && d * b * n * es > cap) b /= 2;
     return b;
 }
 
@@ -1605,7 +1607,7 @@ constexpr int split_tb(int fi) { return iso_tb(fi); }
 constexpr int split_nt(int fi) { return iso_nt(fi); }
 
 template <int FI>
-__global__ __launch_bounds__(split_nt(FI)) __attribute__((amdgpu_waves_per_eu(4))) void row_iso_split(const RowArgs *__restrict__ ra,
+__global__ __launch_bounds__(split_nt(FI)) void row_iso_split(const RowArgs *__restrict__ ra,
                                                              const int *__restrict__ woff, int np) {
     using T = double;
     using V = Vt<T>;
@@ -1667,43 +1669,46 @@ __global__ __launch_bounds__(split_nt(FI)) __attribute__((amdgpu_waves_per_eu(4)
     auto own = [&](int q) { return i + q * TQ; };
     V u[R];
     {
-        // all loads first (idle points read entry 0 of the pair), then the
-        // Hermitian packing by selects
-        T l1x[R], l1y[R], l2x[R], l2y[R];
+        // loads in two groups (idle points read entry 0 of the pair), each
+        // followed by the Hermitian packing by selects; the empty asm
+        // statements keep the second group from being hoisted, which bounds
+        // the registers the staged values need
         const auto *rg = gbl(row1);
+        constexpr int LG = (R + 1) / 2;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int pos = i + q * TQ;
-            const int kx = pos < nh ? pos : (pos > N - nh ? N - pos : 0);
-            const V a1 = gld(rg + kx);
-            const V a2 = gld(rg + (v2 ? nh + kx : kx));
-            l1x[q] = a1.x;
-            l1y[q] = a1.y;
-            l2x[q] = a2.x;
-            l2y[q] = a2.y;
-        }
+        for (int q0 = 0; q0 < R; q0 += LG) {
+            asm volatile("" ::: "memory");
+            T l1x[LG], l1y[LG], l2x[LG], l2y[LG];
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int pos = i + q * TQ;
-            const V u1 = mk<T>(l1x[q], l1y[q]);
-            const V u2 = v2 ? mk<T>(l2x[q], l2y[q]) : zero;
-            const V lo = pos == 0 ? mk<T>(u1.x, u2.x) : mk<T>(u1.x - u2.y, u1.y + u2.x);
-            const V hi = mk<T>(u1.x + u2.y, u2.x - u1.y);
-            u[q] = !act ? zero : (pos < nh ? lo : (pos > N - nh ? hi : zero));
+            for (int q = q0; q < q0 + LG && q < R; ++q) {
+                const int pos = i + q * TQ;
+                const int kx = pos < nh ? pos : (pos > N - nh ? N - pos : 0);
+                const V a1 = gld(rg + kx);
+                const V a2 = gld(rg + (v2 ? nh + kx : kx));
+                l1x[q - q0] = a1.x;
+                l1y[q - q0] = a1.y;
+                l2x[q - q0] = a2.x;
+                l2y[q - q0] = a2.y;
+            }
+#pragma unroll
+            for (int q = q0; q < q0 + LG && q < R; ++q) {
+                const int pos = i + q * TQ;
+                const V u1 = mk<T>(l1x[q - q0], l1y[q - q0]);
+                const V u2 = v2 ? mk<T>(l2x[q - q0], l2y[q - q0]) : zero;
+                const V lo = pos == 0 ? mk<T>(u1.x, u2.x) : mk<T>(u1.x - u2.y, u1.y + u2.x);
+                const V hi = mk<T>(u1.x + u2.y, u2.x - u1.y);
+                u[q] = !act ? zero : (pos < nh ? lo : (pos > N - nh ? hi : zero));
+            }
         }
+        asm volatile("" ::: "memory");
     }
     dftn<T, R>(u, T(1));
     xchg(u, stage_out, own);
-    // last-stage twiddles exp(-2 pi i q i' / N) = w^q, w = exp(-2 pi i i' / N),
-    // by repeated multiplication (FP64: the recurrence error stays ~1e-15)
-    const V w1 = tws[OFFL + i];
-    {
-        V w = w1;
 #pragma unroll
-        for (int q = 1; q < R; ++q) {
-            u[q] = cmul(u[q], mk<T>(w.x, -w.y));
-            w = cmul(w, w1);
-        }
+    for (int q = 1; q < R; ++q) {
+        V w = tws[OFFL + (q - 1) * TQ + i];
+        w.y = -w.y;
+        u[q] = cmul(u[q], w);
     }
     dftn<T, R>(u, T(1));
     {
@@ -1730,14 +1735,8 @@ __global__ __launch_bounds__(split_nt(FI)) __attribute__((amdgpu_waves_per_eu(4)
     }
     dftn<T, R>(u, T(-1));
     xchg(u, stage_out, own);
-    {
-        V w = w1;
 #pragma unroll
-        for (int q = 1; q < R; ++q) {
-            u[q] = cmul(u[q], w);
-            w = cmul(w, w1);
-        }
-    }
+    for (int q = 1; q < R; ++q) u[q] = cmul(u[q], tws[OFFL + (q - 1) * TQ + i]);
     dftn<T, R>(u, T(-1));
     // Hermitian unpacking: each thread pairs its points p < nh with N - p
     // (nh <= (N + 1) / 2, so only the first QH of its points are kept)
@@ -1837,7 +1836,7 @@ template <typename T, int FI>
 void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
     if constexpr (palindromic(FI)) {
         constexpr int N = kFastSched[FI].n;
-        if constexpr (sizeof(T) == 8 && kFastSched[FI].nst == 2 && kFastSched[FI].r[0] <= 9) {
+        if constexpr (sizeof(T) == 8 && kFastSched[FI].nst == 2) {
             const size_t lds = sizeof(double) * (size_t)split_tb(FI) * N + sizeof(Vt<T>) * N;
             hipLaunchKernelGGL((row_iso_split<FI>), dim3(total), dim3(split_nt(FI)), lds, s, args, woff, np);
         } else {
@@ -2149,8 +2148,7 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
     if (a.fast == 2) {
         const int fi = fast_index(a.f.n);
-        if (fp64 && fi >= 0 && kFastSched[fi].nst == 2 && kFastSched[fi].r[0] <= 9)
-            return 8 * (size_t)a.RP * a.f.n + es * a.f.n;
+        if (fp64 && fi >= 0 && kFastSched[fi].nst == 2) return 8 * (size_t)a.RP * a.f.n + es * a.f.n;
         return es * ((size_t)a.RP * a.f.n + a.f.n);
     }
     if (a.fast)
