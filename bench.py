@@ -33,10 +33,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SYMBOL = {"row": "row_kernel", "expand": "pencil_kernel", "pencil_inv": "pencil_kernel",
-                 "pencil_fwd": "pencil_kernel", "project": "pencil_kernel", "cg_update": "cg_update_kernel"}
-
-
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -47,18 +43,16 @@ def kernel_source_hash():
 
 
 def measured_traffic(cls, precision):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when no summary exists for this kernel or the kernel source changed since."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE medians scaled by the copy calibration), or None
+    when no summary exists for this class or the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    sym = "%s<%s>" % (KERNEL_SYMBOL.get(cls, cls), "double" if precision == "fp64" else "float")
-    r = rec.get(sym)
-    if r is None or r.get("class") != cls or r.get("precision") != precision:
-        return None
-    if r.get("source_sha256_16") != kernel_source_hash():
+    r = rec.get("%s/%s" % (cls, precision))
+    if r is None or r.get("source_sha256_16") != kernel_source_hash():
         return None
     return int(1024 * (r["fetch_kib_median"] * r["fetch_scale"] + r["write_kib_median"] * r["write_scale"]))
 
