@@ -113,8 +113,8 @@ typedef struct fftgal_material {
 typedef struct fftgal_info {
     int32_t iters;      /* CG iterations taken                                  */
     int32_t converged;  /* 1 if the stopping test was met within maxit          */
-    double rel_res;     /* ||r_k|| / ||r_0|| at exit (0 if r_0 = 0)             */
-    double res0;        /* ||r_0|| in the (.,.)_{R^{d x M}} norm                */
+    double rel_res;     /* ||r_k|| / ||b|| at exit (0 if b = 0)                  */
+    double res0;        /* ||b|| (= ||r_0|| from e_0 = 0), (.,.)_{R^{d x M}}    */
 } fftgal_info;
 
 /*
@@ -148,8 +148,9 @@ int fftgal_set_material(struct fftgal_plan *plan, const fftgal_material *m);
 
 /*
  * Solve the primal cell problem G A_M e = -G A_M E (eq. Ga_linsys_orig) by CG
- * from e_0 = 0 for E = e_alpha (alpha in 0..d-1) or for all d unit fields
- * (alpha = -1).  Stops when ||r_k|| <= rtol ||r_0||, or when ||r_k|| <=
+ * from e_0 = 0 -- or from the initial iterate placed by fftgal_warm_start --
+ * for E = e_alpha (alpha in 0..d-1) or for all d unit fields (alpha = -1).
+ * Stops when ||r_k|| <= rtol ||b|| with b = -G A_M E (= r_0 from e_0 = 0), or when ||r_k|| <=
  * 1e-14 ||A_M E|| (FP64) / 1e-7 ||A_M E|| (FP32_ITER) -- a right-hand side at
  * rounding level of the load is treated as zero -- or at maxit.  `info` (may be
  * NULL; an array of d entries when alpha = -1) receives the outcome.  Returns
@@ -172,6 +173,39 @@ int fftgal_solve_dual(struct fftgal_plan *plan, int alpha, double rtol, int maxi
  * solves exist.
  */
 int fftgal_bounds(struct fftgal_plan *plan, double *upper, double *lower, double *gap);
+
+/*
+ * Coarse-to-fine warm start (Sec. 6.4: a solution on a coarse grid used as
+ * the initial approximation on a fine grid, through the prolongation
+ * I_N o I_M^{-1}).  For every solve (primal/dual, alpha) that `coarse` has
+ * finished, the fine plan's next solve of the same (kind, alpha) starts from
+ * the coarse field: the coefficients of the frequencies of Z_{N_coarse} are
+ * copied and all others are zero, so the trigonometric polynomial -- and its
+ * exact energy -- is the same on both grids (along an axis where the fine
+ * grid is smaller the field is truncated, which is still admissible).  The
+ * plans must have the same d and may differ in N, grid and precision; the
+ * fine plan must have its material set (setting a material clears pending
+ * warm starts).  The coarse plan's stream is synchronised if it differs.
+ * Returns OK, ESTATE (no material / nothing solved / a plan in a batch) or
+ * EINVAL.
+ */
+int fftgal_warm_start(struct fftgal_plan *fine, struct fftgal_plan *coarse);
+
+/*
+ * Energies of the CG iterates of the last solve of (kind 0 primal / 1 dual,
+ * alpha) on the plan (Sec. 6.4: bounds during the iterations).  energy[k] =
+ * (A_M (E + e_k), E + e_k) for the primal (B_M, J for the dual), k = 0 ..
+ * iters: energy[0] is the exact energy of the initial iterate (the Voigt entry
+ * <A>_{alpha alpha} from e_0 = 0); later entries follow the CG recurrence
+ * energy_k = energy_{k-1} - alpha_k (r_{k-1}, r_{k-1}), which holds in exact
+ * arithmetic and here accumulates rounding (and, in FP32_ITER, the FP32
+ * iterates' error): a monitor, not a guaranteed bound -- fftgal_bounds
+ * evaluates the guaranteed ones.  Primal entries decrease towards
+ * A_{H,N}[alpha, alpha]; the reciprocal of a dual entry increases towards a
+ * lower bound on A_H[alpha, alpha].  Writes min(cap, iters + 1) values and
+ * *n = iters + 1.  ESTATE unless the solve was run with maxit <= 20000.
+ */
+int fftgal_history(struct fftgal_plan *plan, int kind, int alpha, double *energy, int cap, int *n);
 
 /* Release the plan (host memory only; the workspace stays the caller's). */
 int fftgal_destroy(struct fftgal_plan *plan);

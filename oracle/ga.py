@@ -11,12 +11,15 @@ Follows, in order:
 * Algorithm 2 -- y = A_M x; y = F_M y; y = Ghat y; y = F_M^{-1} y.
 * Remark CG -- conjugate gradients (Saad, Alg. 6.18) from e_0 = 0, in the inner
   product (u, v)_{R^{d x M}} = (1/|M|) sum_k u^k . v^k of Sec. 4.1.
+* Sec. 6.4 -- bounds during the CG iterations, and a coarse-grid solution
+  carried to a finer grid (Fourier zero padding) as the initial approximation.
 * Def. Ga and Prop. struct_bounds -- A_{H,N} E.E is the exact energy
   (A(E + e), E + e)_{L^2}, which Lemma integ_eval_VM evaluates exactly as
   (A_M (E + e), E + e)_{R^{d x M}}; upper bound A_{H,N}, lower bound B_{H,N}^{-1}.
 
 Readings where the paper is silent: stopping on the relative residual
-||r_k|| / ||r_0|| <= tol, or once ||r_k|| <= floor * ||A_M E|| (floor = 1e-14:
+||r_k|| / ||b|| <= tol (b = r_0 from e_0 = 0; the same absolute target when
+CG starts from a coarse-grid field), or once ||r_k|| <= floor * ||A_M E|| (floor = 1e-14:
 a right-hand side at the rounding level of the load, as for a laminate loaded
 along its layers, is treated as zero instead of being iterated on); the d x d matrix is the
 energy Gram matrix of the d solutions for E = e_1..e_d, symmetrised; the
@@ -72,22 +75,30 @@ def energy(AM, E, e):
     return inner(material.apply_pointwise(AM, f), f)
 
 
-def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0):
-    """Conjugate gradients (Remark CG; Saad Alg. 6.18) from x_0 = 0.
+def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0, x0=None):
+    """Conjugate gradients (Remark CG; Saad Alg. 6.18) from x_0 = 0, or from an
+    initial approximation x0 in the minimisation space (Sec. 6.4).
 
-    Stops when ||r_k|| <= tol ||r_0|| or ||r_k|| <= abs_stop.  Returns (x, info)
-    with info = {"iters", "rel_res", "res_history"}; ``monitor`` is called with
-    the iterate after every step.
+    Stops when ||r_k|| <= tol ||b|| (= tol ||r_0|| from x_0 = 0) or ||r_k|| <=
+    abs_stop.  Returns (x, info) with info = {"iters", "rel_res",
+    "res_history", "alphas", "rr"}: alphas[k] is the step of iteration k + 1 and
+    rr[k] = (r_k, r_k); ``monitor`` is called with the iterate after every step
+    (and with x_0 before the first).
     """
-    x = np.zeros_like(b)
-    r = b.copy()
+    if x0 is None:
+        x = np.zeros_like(b)
+        r = b.copy()
+    else:
+        x = np.array(x0, dtype=float, copy=True)
+        r = b - apply(x)
     rr = inner(r, r)
-    rr0 = rr
-    hist = [1.0 if rr0 > 0 else 0.0]
+    rr0 = inner(b, b)
+    hist = [float(np.sqrt(rr / rr0)) if rr0 > 0 else 0.0]
+    alphas, rrs = [], [rr]
     if monitor is not None:
         monitor(x)
-    if rr0 == 0.0 or np.sqrt(rr0) <= abs_stop:
-        return x, {"iters": 0, "rel_res": 0.0 if rr0 == 0.0 else 1.0, "res_history": hist}
+    if rr0 == 0.0 or rr == 0.0 or np.sqrt(rr) <= abs_stop or np.sqrt(rr / rr0) <= tol:
+        return x, {"iters": 0, "rel_res": hist[0], "res_history": hist, "alphas": alphas, "rr": rrs}
     p = r.copy()
     it = 0
     while it < maxit and np.sqrt(rr / rr0) > tol and np.sqrt(rr) > abs_stop:
@@ -100,19 +111,40 @@ def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0):
         p = r + beta * p
         rr = rr_new
         it += 1
+        alphas.append(float(alpha))
+        rrs.append(float(rr))
         hist.append(float(np.sqrt(rr / rr0)))
         if monitor is not None:
             monitor(x)
-    return x, {"iters": it, "rel_res": float(np.sqrt(rr / rr0)), "res_history": hist}
+    return x, {"iters": it, "rel_res": float(np.sqrt(rr / rr0)), "res_history": hist, "alphas": alphas, "rr": rrs}
+
+
+def prolong(e, N_coarse, M):
+    """Prolongation I_N o I_M^{-1} of Sec. 6.4: the trigonometric polynomial of
+    order N_coarse sampled on its own grid (shape (d, *M_coarse)) is sampled on
+    the grid M -- the Fourier coefficients of Z_{N_coarse} are carried over (DFT
+    on the coarse grid, zero padding, inverse DFT on M).  No approximation is
+    made when every M_a > N_coarse_a."""
+    Mc = e.shape[1:]
+    axes = tuple(range(1, e.ndim))
+    eh = grids.dft(e, axes=axes)
+    kc = grids.freq_grid(Mc)
+    keep = grids.in_Z(kc, N_coarse)
+    out = np.zeros((e.shape[0],) + tuple(M), dtype=complex)
+    idx = tuple(np.mod(kc[a][keep], M[a]) for a in range(len(M)))
+    for c in range(e.shape[0]):
+        out[c][idx] = eh[c][keep]
+    return np.real(grids.idft(out, axes=axes))
 
 
 RESIDUAL_FLOOR = 1e-14
 
 
-def solve(AM, N, E, kind, tol=1e-10, maxit=10_000, track_energy=False):
+def solve(AM, N, E, kind, tol=1e-10, maxit=10_000, track_energy=False, x0=None):
     """Minimiser of Def. Ga for one macroscopic E (primal, kind 'E') or J (dual, 'J').
 
-    Solves G A_M e = -G A_M E by CG (Cor. Ga_linsys), then re-projects e with G.
+    Solves G A_M e = -G A_M E by CG (Cor. Ga_linsys) from 0 or from the
+    admissible field x0, then re-projects e with G.
     """
     M = next(a for a in AM.values() if a is not None).shape
     d = len(M)
@@ -122,7 +154,7 @@ def solve(AM, N, E, kind, tol=1e-10, maxit=10_000, track_energy=False):
     floor = RESIDUAL_FLOOR * np.sqrt(inner(load, load))
     energies = []
     mon = (lambda x: energies.append(energy(AM, E, x))) if track_energy else None
-    e, info = cg(lambda p: matvec(AM, p, N, kind), b, tol, maxit, mon, abs_stop=floor)
+    e, info = cg(lambda p: matvec(AM, p, N, kind), b, tol, maxit, mon, abs_stop=floor, x0=x0)
     e = project(e, N, kind)
     info["energies"] = energies
     return e, info
@@ -143,29 +175,37 @@ def gram(AM, fields):
     return out
 
 
-def ga_bounds(mat, N, M=None, tol=1e-10, maxit=10_000, track_energy=False):
+def ga_bounds(mat, N, M=None, tol=1e-10, maxit=10_000, track_energy=False, warm=None):
     """Guaranteed bounds of Prop. struct_bounds from the Ga scheme (Def. Ga).
 
     Returns a dict with ``upper`` = A_{H,N}, ``lower`` = B_{H,N}^{-1}, the
-    unsymmetrised Gram matrices, the CG iteration counts and (optionally) the
-    per-iteration energies of each primal/dual solve.
+    unsymmetrised Gram matrices, the CG iteration counts, the fields, the CG
+    scalars and (optionally) the per-iteration energies of each primal/dual
+    solve.  ``warm`` (the result of a coarser ga_bounds) starts every solve
+    from the prolongation of the coarse field (Sec. 6.4).
     """
     N = tuple(int(n) for n in N)
     d = len(N)
     M = tuple(2 * n - 1 for n in N) if M is None else tuple(int(m) for m in M)
     out = {"N": N, "M": M, "iters_primal": [], "iters_dual": [],
-           "energies_primal": [], "energies_dual": []}
+           "energies_primal": [], "energies_dual": [], "fields_primal": [], "fields_dual": [],
+           "cg_primal": [], "cg_dual": []}
     for kind, which in (("E", "A"), ("J", "B")):
         AM = material.double_grid_matrix(mat, N, M, which)
         fields = []
+        key = "primal" if kind == "E" else "dual"
         for a in range(d):
             E = np.zeros(d)
             E[a] = 1.0
-            e, info = solve(AM, N, E, kind, tol, maxit, track_energy)
+            x0 = None
+            if warm is not None:
+                x0 = prolong(warm["fields_" + key][a], warm["N"], M)
+            e, info = solve(AM, N, E, kind, tol, maxit, track_energy, x0=x0)
             fields.append(e)
-            key = "primal" if kind == "E" else "dual"
             out["iters_" + key].append(info["iters"])
             out["energies_" + key].append(info["energies"])
+            out["fields_" + key].append(e)
+            out["cg_" + key].append({"alphas": info["alphas"], "rr": info["rr"]})
         g = gram(AM, fields)
         if kind == "E":
             out["gram_A"] = g

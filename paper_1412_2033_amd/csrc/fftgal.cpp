@@ -225,6 +225,8 @@ struct fftgal_plan {
     bool separate_gB = false;
     double A0[9], DA[9], B0[9], DB[9];
     bool solved[2][3] = {{false, false, false}, {false, false, false}};
+    bool warm[2][3] = {{false, false, false}, {false, false, false}};  // x holds an initial iterate
+    bool hist_valid[2][3] = {{false, false, false}, {false, false, false}};
     fftgal_info last_info[2][3];
     bool busy = false;     // a solve of this plan is a member of a batch
     bool hist_on = false;  // per-iteration (rr, alpha) history; only when maxit <= kMaxHist
@@ -926,6 +928,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     CgStatus *st = pl->status(kind, alpha);
     void *x = pl->xsol(kind, alpha);
     pl->hist_on = maxit <= kMaxHist;
+    pl->hist_valid[kind][alpha] = pl->hist_on;
     pl->cur_alpha = alpha;
     const size_t es = fp64 ? 16 : 8;
     const size_t vbytes = (size_t)pl->nc(kind) * D.Ns * es;
@@ -933,6 +936,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     RowArgs r = base_row(pl, fp64, ROW_RHS, rows, kind);
     for (int a = 0; a < 3; ++a) r.E[a] = (a == alpha) ? 1.0 : 0.0;
     r.partial = pl->at<double>(pl->Lo.part_b);
+    r.partial2 = pl->at<double>(pl->Lo.part_c);
     int rc = run_row(pl, r, fp64, FFTGAL_K_RHS);
     if (rc) return rc;
     const int nload = row_grid(r);
@@ -941,11 +945,52 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
                         pl->at<double>(pl->Lo.part_a), &nrr, FFTGAL_K_RHS, FFTGAL_K_RHS);
     if (rc) return rc;
     // The load sums |A_M E|^2 over grid points; (., .)_{R^{d x M}} divides by |M|.
+    const double floor_rel = (fp64 ? kFloor64 : kFloor32) / std::sqrt((double)D.Mtot);
+    if (!pl->warm[kind][alpha]) {
+        Timed t(pl, FFTGAL_K_CG_SCALAR);
+        HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload,
+                                    pl->at<double>(pl->Lo.part_c), 1.0 / (double)D.Mtot, rtol, floor_rel, maxit,
+                                    pl->hist(kind, alpha), pl->stream));
+        HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
+        HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
+        return FFTGAL_OK;
+    }
+    // Warm start from the iterate x0 already in x: keep (b, b), |A_M E|^2 and
+    // (A_M E).E as scalars, apply the operator to x0, then r_0 = b - K x0.
+    pl->warm[kind][alpha] = false;
+    double *scal = pl->at<double>(pl->Lo.gram) + 32;
+    {
+        Timed t(pl, FFTGAL_K_CG_SCALAR);
+        HIPCHECK(pl, launch_sum_partials(scal, pl->at<double>(pl->Lo.part_a), nrr, 1, pl->stream));
+        HIPCHECK(pl, launch_sum_partials(scal + 1, pl->at<double>(pl->Lo.part_b), nload, 1, pl->stream));
+        HIPCHECK(pl, launch_sum_partials(scal + 2, pl->at<double>(pl->Lo.part_c), nload, 1, pl->stream));
+    }
+    void *rows0 = nullptr;
+    rc = inverse_passes(pl, fp64, kind, x, 0, 1, false, nullptr, &rows0, FFTGAL_K_RHS, FFTGAL_K_RHS);
+    if (rc) return rc;
+    RowArgs ro = base_row(pl, fp64, ROW_OPER, rows0, kind);
+    rc = run_row(pl, ro, fp64, FFTGAL_K_RHS);
+    if (rc) return rc;
+    int nq = 0;
+    rc = forward_passes(pl, fp64, kind, rows0, pl->ws + pl->Lo.q, nullptr, 1.0 / (double)D.Mtot, nullptr,
+                        pl->at<double>(pl->Lo.part_a), &nq, FFTGAL_K_RHS, FFTGAL_K_RHS);
+    if (rc) return rc;
+    UpdArgs u{};
+    u.x = x;
+    u.r = pl->ws + pl->Lo.r;
+    u.p = nullptr;
+    u.q = pl->ws + pl->Lo.q;
+    u.n_per_comp = D.Ns;
+    u.cs = D.Ns;
+    u.nc = pl->nc(kind);
+    u.Nh = D.Nh;
+    u.nblocks = update_blocks((long)u.nc * D.Ns);
     Timed t(pl, FFTGAL_K_CG_SCALAR);
-    HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload, rtol,
-                                (fp64 ? kFloor64 : kFloor32) / std::sqrt((double)D.Mtot), maxit,
-                                pl->hist(kind, alpha), pl->stream));
-    HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
+    HIPCHECK(pl, launch_warm_residual(u, pl->at<double>(pl->Lo.part_a), pl->at<double>(pl->Lo.part_b),
+                                      pl->at<double>(pl->Lo.part_c), fp64, pl->stream));
+    HIPCHECK(pl, launch_cg_init_warm(st, pl->at<double>(pl->Lo.part_a), pl->at<double>(pl->Lo.part_b),
+                                     pl->at<double>(pl->Lo.part_c), u.nblocks, scal, (double)D.Mtot, rtol, floor_rel,
+                                     maxit, pl->hist(kind, alpha), pl->stream));
     HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
     return FFTGAL_OK;
 }
@@ -1089,6 +1134,8 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
     const int d = D.d;
     pl->have_mat = false;
     for (auto &row : pl->solved)
+        for (bool &s : row) s = false;
+    for (auto &row : pl->warm)
         for (bool &s : row) s = false;
     double *gA = pl->at<double>(pl->Lo.gA64);
     double *gB = pl->at<double>(pl->Lo.gB64);
@@ -1378,6 +1425,49 @@ int fftgal_read_timing(struct fftgal_plan *pl, double *ms, int32_t *count) {
         if (count) count[c] = pl->t_cnt[c];
         pl->t_ms[c] = 0.0;
         pl->t_cnt[c] = 0;
+    }
+    return FFTGAL_OK;
+}
+
+int fftgal_warm_start(struct fftgal_plan *fine, struct fftgal_plan *coarse) {
+    if (!fine) return FFTGAL_EINVAL;
+    if (!coarse || coarse == fine) return fail(fine, FFTGAL_EINVAL, "coarse plan is NULL or the fine plan itself");
+    if (!fine->have_mat) return fail(fine, FFTGAL_ESTATE, "no material set on the fine plan");
+    if (fine->busy || coarse->busy) return fail(fine, FFTGAL_ESTATE, "a plan has a solve in a batch");
+    const int d = fine->D.d;
+    if (coarse->D.d != d) return fail(fine, FFTGAL_EINVAL, "plans of different dimension");
+    int n = 0;
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < d; ++a) n += coarse->solved[k][a] ? 1 : 0;
+    if (n == 0) return fail(fine, FFTGAL_ESTATE, "the coarse plan has no finished solve");
+    if (coarse->stream != fine->stream) HIPCHECK(fine, hipStreamSynchronize(coarse->stream));
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < d; ++a) {
+            if (!coarse->solved[k][a]) continue;
+            HIPCHECK(fine, launch_prolong(coarse->xsol(k, a), coarse->fp64_iter(), fine->xsol(k, a), fine->fp64_iter(),
+                                          d, fine->nc(k), fine->D.N, coarse->D.N, fine->stream));
+            fine->warm[k][a] = true;
+        }
+    return FFTGAL_OK;
+}
+
+int fftgal_history(struct fftgal_plan *pl, int kind, int alpha, double *energy, int cap, int *n) {
+    if (!pl) return FFTGAL_EINVAL;
+    if (kind < 0 || kind > 1 || alpha < 0 || alpha >= pl->D.d || cap < 0 || (cap > 0 && !energy) || !n)
+        return fail(pl, FFTGAL_EINVAL, "bad kind, alpha or output arrays");
+    if (!pl->solved[kind][alpha] || !pl->hist_valid[kind][alpha])
+        return fail(pl, FFTGAL_ESTATE, "no recorded solve (maxit must be <= %d)", kMaxHist);
+    const int iters = pl->last_info[kind][alpha].iters;
+    std::vector<double> h((size_t)2 * (iters + 1));
+    HIPCHECK(pl, hipMemcpyAsync(h.data(), pl->hist(kind, alpha), h.size() * 8, hipMemcpyDeviceToHost, pl->stream));
+    HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+    // energy_k = energy_{k-1} - alpha_k (r_{k-1}, r_{k-1})  (CG on a quadratic
+    // functional: phi(e_k) = phi(e_{k-1}) - alpha_k |r_{k-1}|^2 / 2)
+    double e = h[1];
+    *n = iters + 1;
+    for (int k = 0; k <= iters; ++k) {
+        if (k > 0) e -= h[2 * k + 1] * h[2 * (k - 1)];
+        if (k < cap) energy[k] = e;
     }
     return FFTGAL_OK;
 }

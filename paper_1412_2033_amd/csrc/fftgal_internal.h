@@ -135,6 +135,7 @@ struct RowArgs {
     double vmax;
     double scale;
     double *partial;  // RHS: |A_M E|^2 sums; GRAM: d*d sums per work-group
+    double *partial2; // RHS: sums of (A_M E).E per work-group (may be null)
     const CgStatus *status;
 };
 
@@ -183,9 +184,9 @@ hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s);
 int row_grid(const RowArgs &a);
 int pencil_grid_x(const PencilArgs &a);
 
-hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part,
-                          int n_load, double tol, double floor_rel, int maxit, double *hist,
-                          hipStream_t s);
+hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part, int n_load,
+                          const double *work_part, double inv_mtot, double tol, double floor_rel, int maxit,
+                          double *hist, hipStream_t s);
 // Multi-problem launches: `args` and `woff` are device arrays; problem i
 // owns work-groups [woff[i], woff[i + 1]) of a grid of `total` work-groups.
 hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, const int *woff, int np,
@@ -199,6 +200,20 @@ hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, in
 int pencil_grid(const PencilArgs &a, int nouter);  // work-groups of one problem
 int update_blocks(long n);                         // work-groups of one CG update
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// Warm start: r <- r - q (r holds b on entry), partials of (r, r), (b, x0),
+// (r, x0) into part_rr / part_bx / part_rx (one per work-group, update grid).
+hipError_t launch_warm_residual(const UpdArgs &u, double *part_rr, double *part_bx, double *part_rx, bool fp64,
+                                hipStream_t s);
+// Status of a warm-started solve: rr = sum part_rr, reference rr0 = scal[0]
+// ((b, b)), load2 = scal[1], energy at the initial iterate
+// scal[2] / mtot - sum part_bx - sum part_rx (history slot 1).
+hipError_t launch_cg_init_warm(CgStatus *st, const double *part_rr, const double *part_bx, const double *part_rx,
+                               int nparts, const double *scal, double mtot, double tol, double floor_rel, int maxit,
+                               double *hist, hipStream_t s);
+// Copy the coefficient arrays of a coarse solve into a fine one: entries of
+// frequencies inside the coarse grid are copied, all others set to zero.
+hipError_t launch_prolong(const void *src, bool src64, void *dst, bool dst64, int d, int nc, const int *Nf,
+                          const int *Nc, hipStream_t s);
 hipError_t launch_convert_f2d(double *dst, const float *src, size_t n, hipStream_t s);
 hipError_t launch_convert_d2f(float *dst, const double *src, size_t n, hipStream_t s);
 hipError_t launch_sum_partials(double *out, const double *part, int nparts, int nvals,

@@ -678,7 +678,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             D[i] = T(a.D[i]);
         }
         for (int i = 0; i < 3; ++i) E[i] = T(a.E[i]);
-        double load = 0.0;
+        double load = 0.0, work = 0.0;
         for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) {
             const int j = idx / n;
             const int x = idx - j * n;
@@ -707,12 +707,17 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                 }
                 zbuf(al)[idx] = mk<T>(y1, y2);
                 load += (double)y1 * y1 + (double)y2 * y2;
+                if (a.mode == ROW_RHS) work += ((double)y1 + (double)y2) * a.E[al];
             }
         }
         __syncthreads();
         if (a.mode == ROW_RHS) {
             const double s = block_sum(load);
-            if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+            const double s2 = block_sum(work);
+            if (threadIdx.x == 0) {
+                a.partial[blockIdx.x] = s;
+                if (a.partial2 != nullptr) a.partial2[blockIdx.x] = s2;
+            }
         }
     } else if (a.mode == ROW_GRAM) {
         // (A_M (E_s + e_s), E_t + e_t) summed over the rows' grid points
@@ -805,11 +810,15 @@ __device__ double sum_fixed(const double *part, int n) {
     return block_sum(v);
 }
 
+// hist[0] = (r_0, r_0); hist[1] = the energy (A_M E, E) of the initial iterate
+// e_0 = 0 (the Voigt entry), from the right-hand side pass's sums of (A_M E).E.
 __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgStatus *st, const double *rr_part, int n_rr,
-                                                           const double *load_part, int n_load, double tol,
+                                                           const double *load_part, int n_load,
+                                                           const double *work_part, double inv_mtot, double tol,
                                                            double floor_rel, int maxit, double *hist) {
     const double rr = sum_fixed(rr_part, n_rr);
     const double load = sum_fixed(load_part, n_load);
+    const double work = work_part != nullptr ? sum_fixed(work_part, n_load) : 0.0;
     if (threadIdx.x == 0) {
         st->rr = rr;
         st->rr0 = rr;
@@ -826,8 +835,111 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgStatus *st, const d
         st->done = st->converged || st->breakdown || maxit <= 0;
         if (hist != nullptr) {
             hist[0] = rr;
-            hist[1] = 0.0;
+            hist[1] = work * inv_mtot;
         }
+    }
+}
+
+// Warm start from an admissible initial iterate x0 (Remark CG: CG from an
+// initial approximation in the minimisation space): r_0 = b - K x0 with r
+// holding b and q = K x0 on entry; partial sums of (r_0, r_0), (b, x0) and
+// (r_0, x0) in the weights of the half-spectrum storage.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void warm_residual_kernel(UpdArgs a, double *part_rr, double *part_bx,
+                                                                 double *part_rx) {
+    Vt<T> *r = reinterpret_cast<Vt<T> *>(a.r);
+    const Vt<T> *x = reinterpret_cast<const Vt<T> *>(a.x);
+    const Vt<T> *q = reinterpret_cast<const Vt<T> *>(a.q);
+    double prr = 0.0, pbx = 0.0, prx = 0.0;
+    const long total = a.n_per_comp * a.nc;
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)a.nblocks * kThreads) {
+        const long c = idx / a.n_per_comp;
+        const long i = idx - c * a.n_per_comp;
+        const long off = c * a.cs + i;
+        const Vt<T> bv = r[off], qv = q[off], xv = x[off];
+        Vt<T> rv = bv;
+        rv.x -= qv.x;
+        rv.y -= qv.y;
+        r[off] = rv;
+        const double w = (i % a.Nh) == 0 ? 1.0 : 2.0;
+        prr += w * ((double)rv.x * rv.x + (double)rv.y * rv.y);
+        pbx += w * ((double)bv.x * xv.x + (double)bv.y * xv.y);
+        prx += w * ((double)rv.x * xv.x + (double)rv.y * xv.y);
+    }
+    const double s1 = block_sum(prr);
+    const double s2 = block_sum(pbx);
+    const double s3 = block_sum(prx);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = s1;
+        part_bx[blockIdx.x] = s2;
+        part_rx[blockIdx.x] = s3;
+    }
+}
+
+// Energy at x0: (A(E + x0), E + x0) = (A E, E) + 2 phi(x0), phi(x) =
+// (K x, x) / 2 - (b, x), and (K x0, x0) = (b - r_0, x0).
+__global__ __launch_bounds__(kThreads) void cg_init_warm_kernel(CgStatus *st, const double *part_rr,
+                                                                const double *part_bx, const double *part_rx,
+                                                                int nparts, const double *scal, double mtot,
+                                                                double tol, double floor_rel, int maxit,
+                                                                double *hist) {
+    const double rr = sum_fixed(part_rr, nparts);
+    const double bx = sum_fixed(part_bx, nparts);
+    const double rx = sum_fixed(part_rx, nparts);
+    if (threadIdx.x == 0) {
+        const double bb = scal[0];
+        const double load = scal[1];
+        st->rr = rr;
+        st->rr0 = bb;
+        st->pq = 0.0;
+        st->alpha = 0.0;
+        st->beta = 0.0;
+        st->tol2 = tol * tol;
+        st->load2 = load;
+        st->floor2 = floor_rel * floor_rel * load;
+        st->iter = 0;
+        st->maxit = maxit;
+        st->breakdown = !isfinite(rr) || !isfinite(load) || !isfinite(bb);
+        st->converged = (rr == 0.0 || rr <= st->tol2 * bb || rr <= st->floor2) && !st->breakdown;
+        st->done = st->converged || st->breakdown || maxit <= 0;
+        if (hist != nullptr) {
+            hist[0] = rr;
+            hist[1] = scal[2] / mtot - bx - rx;
+        }
+    }
+}
+
+// Prolongation of the coefficients of a coarse solve (grid Nc) to a fine one
+// (grid Nf): the trigonometric polynomial is kept (Fourier zero padding), so
+// the entries of frequencies k in Z_Nc move and all others are zero.  Storage
+// [c][k1][k2][k3 >= 0] (2D: [c][k1][k2 >= 0]) with wrapped indices.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(kThreads) void prolong_kernel(const Vt<TS> *src, Vt<TD> *dst, int d, int nc, int f1,
+                                                           int f2, int f3h, int c1, int c2, int c3h) {
+    const long nsf = (long)f1 * f2 * f3h;  // 2D: f2 = 1
+    const long nsc = (long)c1 * c2 * c3h;
+    const long total = nsf * nc;
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)gridDim.x * kThreads) {
+        const long c = idx / nsf;
+        long rem = idx - c * nsf;
+        const int i3 = (int)(rem % f3h);
+        rem /= f3h;
+        const int i2 = (int)(rem % f2);
+        const int i1 = (int)(rem / f2);
+        const int k1 = wrapi(i1, f1);
+        const int k2 = d == 3 ? wrapi(i2, f2) : 0;
+        const bool in = (k1 >= -(c1 / 2) && k1 < (c1 + 1) / 2) && (d == 2 || (k2 >= -(c2 / 2) && k2 < (c2 + 1) / 2)) &&
+                        i3 < c3h;
+        Vt<TD> v;
+        v.x = TD(0);
+        v.y = TD(0);
+        if (in) {
+            const long j = ((long)posmod(k1, c1) * c2 + (d == 3 ? posmod(k2, c2) : 0)) * c3h + i3;
+            const Vt<TS> u = src[c * nsc + j];
+            v.x = TD(u.x);
+            v.y = TD(u.y);
+        }
+        dst[idx] = v;
     }
 }
 
@@ -1350,8 +1462,8 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
                 X[(al * RP + j) * N + x] = mk<T>(y1, y2);
             }
         }
-    } else {  // ROW_RHS: y = A(x) E on both rows, and |y|^2 partial sums
-        double load = 0.0;
+    } else {  // ROW_RHS: y = A(x) E on both rows, |y|^2 and y.E partial sums
+        double load = 0.0, work = 0.0;
 #pragma unroll
         for (int t = 0; t < MP; ++t) {
             const int idx = threadIdx.x + t * kThreads;
@@ -1377,13 +1489,18 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
                     }
                     y[al] = mk<T>(y1, y2);
                     load += (double)y1 * y1 + (double)y2 * y2;
+                    work += ((double)y1 + (double)y2) * a.E[al];
                 }
             }
 #pragma unroll
             for (int al = 0; al < D; ++al) X[(al * RP + j) * N + x] = y[al];
         }
         const double s = block_sum(load);
-        if (threadIdx.x == 0) a.partial[lb] = s;
+        const double s2 = block_sum(work);
+        if (threadIdx.x == 0) {
+            a.partial[lb] = s;
+            if (a.partial2 != nullptr) a.partial2[lb] = s2;
+        }
     }
     __syncthreads();
     fft_ip<T, FI, 0, 1, 0, NB, true>(X, tw, T(-1));
@@ -2304,9 +2421,54 @@ hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, in
 }
 
 hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part, int n_load,
-                          double tol, double floor_rel, int maxit, double *hist, hipStream_t s) {
-    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kThreads), 0, s, st, rr_part, n_rr, load_part, n_load, tol,
-                       floor_rel, maxit, hist);
+                          const double *work_part, double inv_mtot, double tol, double floor_rel, int maxit,
+                          double *hist, hipStream_t s) {
+    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kThreads), 0, s, st, rr_part, n_rr, load_part, n_load, work_part,
+                       inv_mtot, tol, floor_rel, maxit, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_residual(const UpdArgs &u, double *part_rr, double *part_bx, double *part_rx, bool fp64,
+                                hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(warm_residual_kernel<double>, dim3(u.nblocks), dim3(kThreads), 0, s, u, part_rr, part_bx,
+                           part_rx);
+    else
+        hipLaunchKernelGGL(warm_residual_kernel<float>, dim3(u.nblocks), dim3(kThreads), 0, s, u, part_rr, part_bx,
+                           part_rx);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_init_warm(CgStatus *st, const double *part_rr, const double *part_bx, const double *part_rx,
+                               int nparts, const double *scal, double mtot, double tol, double floor_rel, int maxit,
+                               double *hist, hipStream_t s) {
+    hipLaunchKernelGGL(cg_init_warm_kernel, dim3(1), dim3(kThreads), 0, s, st, part_rr, part_bx, part_rx, nparts,
+                       scal, mtot, tol, floor_rel, maxit, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const void *src, bool src64, void *dst, bool dst64, int d, int nc, const int *Nf,
+                          const int *Nc, hipStream_t s) {
+    const int f1 = Nf[0], f2 = d == 3 ? Nf[1] : 1, f3h = (Nf[d - 1] + 1) / 2;
+    const int c1 = Nc[0], c2 = d == 3 ? Nc[1] : 1, c3h = (Nc[d - 1] + 1) / 2;
+    const long total = (long)f1 * f2 * f3h * nc;
+    const int blocks = (int)std::max<long>(1, std::min<long>(1024, (total + kThreads - 1) / kThreads));
+    if (src64 && dst64)
+        hipLaunchKernelGGL((prolong_kernel<double, double>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const double2 *>(src), static_cast<double2 *>(dst), d, nc, f1, f2, f3h, c1, c2,
+                           c3h);
+    else if (src64)
+        hipLaunchKernelGGL((prolong_kernel<double, float>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const double2 *>(src), static_cast<float2 *>(dst), d, nc, f1, f2, f3h, c1, c2,
+                           c3h);
+    else if (dst64)
+        hipLaunchKernelGGL((prolong_kernel<float, double>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const float2 *>(src), static_cast<double2 *>(dst), d, nc, f1, f2, f3h, c1, c2,
+                           c3h);
+    else
+        hipLaunchKernelGGL((prolong_kernel<float, float>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const float2 *>(src), static_cast<float2 *>(dst), d, nc, f1, f2, f3h, c1, c2,
+                           c3h);
     return hipGetLastError();
 }
 

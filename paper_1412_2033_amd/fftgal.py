@@ -27,6 +27,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5
 EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", "fftgal_set_material",
            "fftgal_solve_primal", "fftgal_solve_dual", "fftgal_bounds", "fftgal_destroy",
            "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
+           "fftgal_warm_start", "fftgal_history",
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
@@ -106,6 +107,11 @@ def load_library(path=LIB_PATH):
     lib.fftgal_set_timing.restype = ctypes.c_int
     lib.fftgal_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
     lib.fftgal_read_timing.restype = ctypes.c_int
+    lib.fftgal_warm_start.argtypes = [vp, vp]
+    lib.fftgal_warm_start.restype = ctypes.c_int
+    lib.fftgal_history.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                   i32p]
+    lib.fftgal_history.restype = ctypes.c_int
     lib.fftgal_batch_workspace_bytes.argtypes = [ctypes.c_int]
     lib.fftgal_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.fftgal_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_size_t, vp]
@@ -251,6 +257,18 @@ def fftgal_read_timing(plan):
     return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(KERNEL_CLASSES)}
 
 
+def fftgal_warm_start(fine, coarse):
+    _check(load_library().fftgal_warm_start(fine, coarse), fine)
+
+
+def fftgal_history(plan, kind, alpha, cap=20001):
+    """Energies of the CG iterates of the last (kind 0 primal / 1 dual, alpha) solve."""
+    buf = (ctypes.c_double * cap)()
+    n = ctypes.c_int32()
+    _check(load_library().fftgal_history(plan, int(kind), int(alpha), buf, int(cap), ctypes.byref(n)), plan)
+    return np.array(buf[:min(cap, n.value)])
+
+
 # ---- convenience wrapper ------------------------------------------------------
 
 class Plan:
@@ -291,9 +309,19 @@ class Plan:
     def read_timing(self):
         return fftgal_read_timing(self.handle)
 
-    def run(self, micro, rtol=1e-10, maxit=20000):
-        """set_material + all 2d solves + bounds; returns a result dict."""
+    def warm_start(self, coarse):
+        """Start the next solves from the finished solves of `coarse` (a Plan)."""
+        fftgal_warm_start(self.handle, coarse.handle)
+
+    def history(self, kind, alpha):
+        return fftgal_history(self.handle, kind, alpha)
+
+    def run(self, micro, rtol=1e-10, maxit=20000, warm_from=None):
+        """set_material (+ warm start from the solved Plan `warm_from`) + all 2d
+        solves + bounds; returns a result dict."""
         self.set_material(micro)
+        if warm_from is not None:
+            self.warm_start(warm_from)
         ip, cp = self.solve_primal(-1, rtol, maxit)
         idl, cd = self.solve_dual(-1, rtol, maxit)
         up, lo, gap = self.bounds()
