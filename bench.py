@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--serve", type=int, default=32, help="serving-mix requests (0: skip)")
     ap.add_argument("--N", type=int, default=113)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-coarse", type=int, default=41,
+                    help="coarse N of the warm-start / bound-monitoring section (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (profiler counter scale)")
     args = ap.parse_args()
@@ -167,7 +169,23 @@ def main():
             print("bench: %s warmup %d done, iters %s / %s" % (
                 precision, w, [i["iters"] for i in res["info_primal"]], [i["iters"] for i in res["info_dual"]]),
                 file=sys.stderr, flush=True)
+        # one fully traced step (outside the timed region): per-class breakdown
         plan.set_timing(True)
+        plan.read_timing()
+        traced = plan.run(micro_dev, rtol=rtol)
+        breakdown = plan.read_timing()
+        it_p = sum(i["iters"] for i in traced["info_primal"])
+        it_d = sum(i["iters"] for i in traced["info_dual"])
+        per_cls = {}
+        for cls, (ms, cnt) in breakdown.items():
+            if cnt == 0:
+                continue
+            by = algorithmic_bytes(cls, d, N, M, es, gs, 1) * it_p + algorithmic_bytes(cls, d, N, M, es, gs, d - 1) * it_d
+            per_cls[cls] = {"ms": round(ms, 3), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 2),
+                            "GBs": round(by / (ms * 1e-3) / 1e9, 1) if by > 0 else None}
+        dom = max((c for c in per_cls if per_cls[c]["GBs"]), key=lambda c: per_cls[c]["ms"])
+        # timed steps: only the dominant class is bracketed by HIP events
+        plan.set_timing(True, classes=(dom,))
         plan.read_timing()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -183,23 +201,14 @@ def main():
         iters_p = sum(sum(i["iters"] for i in r["info_primal"]) for r in results)
         iters_d = sum(sum(i["iters"] for i in r["info_dual"]) for r in results)
         total_iters = iters_p + iters_d
-        # per-class rates and the dominant kernel's roofline (algorithmic bytes / measured duration)
-        per_cls = {}
-        for cls, (ms, cnt) in timing.items():
-            if cnt == 0:
-                continue
-            by = algorithmic_bytes(cls, d, N, M, es, gs, 1) * iters_p + \
-                algorithmic_bytes(cls, d, N, M, es, gs, d - 1) * iters_d
-            per_cls[cls] = {"ms": round(ms, 3), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 2),
-                            "GBs": round(by / (ms * 1e-3) / 1e9, 1) if by > 0 else None}
-        dom = max((c for c in per_cls if per_cls[c]["GBs"]), key=lambda c: per_cls[c]["ms"])
         dom_bytes = (algorithmic_bytes(dom, d, N, M, es, gs, 1) * iters_p +
                      algorithmic_bytes(dom, d, N, M, es, gs, d - 1) * iters_d) / total_iters
         dom_avg_s = timing[dom][0] * 1e-3 / timing[dom][1]
         achieved = dom_bytes / dom_avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, precision),
-                "kernel": dom, "bytes_per_launch": int(dom_bytes), "avg_launch_us": round(dom_avg_s * 1e6, 2)}
+                "kernel": dom, "bytes_per_launch": int(dom_bytes), "avg_launch_us": round(dom_avg_s * 1e6, 2),
+                "launches_timed": timing[dom][1]}
         last = results[-1]
         return {"elapsed": elapsed, "value": pts * total_iters / elapsed / 1e6, "ms_per_step": 1e3 * elapsed / args.steps,
                 "kernels": per_cls, "roofline": roof, "last": last,
@@ -248,12 +257,76 @@ def main():
             "speedup_vs_fp64": round(f64["ms_per_step"] / f32["ms_per_step"], 3),
             "kernels": f32["kernels"], "roofline": f32["roofline"]},
     }
+    if args.warm_coarse > 0:
+        out["warm_start"] = warm_start_bench(fftgal, micro_dev, d, N, M, args.warm_coarse, rtol64, dev)
     if args.serve > 0:
         out["serving"] = serving_bench(args.serve, args.rtol32)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(micro, N, d)
     print(json.dumps(out), flush=True)
+
+
+BOUND_TOL = 1e-6  # bound tolerance of the monitoring section (the FP32-iteration form's stated accuracy)
+
+
+def warm_start_bench(fftgal, micro_dev, d, N, M, Nc, rtol, dev):
+    """Bound monitoring and coarse-to-fine warm start on the benchmark workload
+    (FP64): time to bounds and CG iterations from e_0 = 0, from the prolonged
+    solution of an N = Nc plan, and with the bound test at BOUND_TOL; the first
+    bound of each start, and the iterations after which the monitored bound
+    entries are within 1e-4 / 1e-6 / 1e-8 of their final values."""
+    import numpy as np
+    import torch
+    print("bench: warm start from N=%d" % Nc, file=sys.stderr, flush=True)
+
+    def within(h, tol):
+        fin = h[-1]
+        return [int(np.argmax(np.abs(h - fin) <= t * abs(fin))) for t in tol]
+
+    out = {"coarse_N": Nc, "rtol": rtol, "btol": BOUND_TOL}
+    tols = (1e-4, 1e-6, 1e-8)
+    for mode in ("cold", "warm", "bound_tol"):
+        fine = fftgal.Plan(d, N, "fp64", device=dev, P=M)
+        coarse = fftgal.Plan(d, (Nc,) * d, "fp64", device=dev, P=M) if mode == "warm" else None
+        if mode == "bound_tol":
+            fine.set_bound_tol(BOUND_TOL)
+        try:
+            for rep in range(2):  # the second repetition is timed
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t_coarse = 0.0
+                if coarse is not None:
+                    coarse.run(micro_dev, rtol=rtol)
+                    torch.cuda.synchronize()
+                    t_coarse = time.perf_counter() - t0
+                res = fine.run(micro_dev, rtol=rtol, warm_from=coarse)
+                torch.cuda.synchronize()
+                elapsed = time.perf_counter() - t0
+            hist = {(k, a): fine.history(k, a) for k in (0, 1) for a in range(d)}
+        finally:
+            fine.close()
+            if coarse is not None:
+                coarse.close()
+        out[mode] = {
+            "time_to_bounds_s": round(elapsed, 4), "coarse_s": round(t_coarse, 4),
+            "cg_iterations": {"primal": [i["iters"] for i in res["info_primal"]],
+                              "dual": [i["iters"] for i in res["info_dual"]]},
+            "first_upper_diag": [round(float(hist[(0, a)][0]), 6) for a in range(d)],
+            "first_lower_diag": [round(float(1.0 / hist[(1, a)][0]), 6) for a in range(d)],
+            "iters_to_bound_rel_1e-4_1e-6_1e-8": {"primal": [within(hist[(0, a)], tols) for a in range(d)],
+                                                   "dual": [within(hist[(1, a)], tols) for a in range(d)]},
+            "upper_diag": [round(float(v), 10) for v in np.diag(res["upper"])],
+        }
+        if mode == "bound_tol":
+            ref = out["cold"]["_bounds"]
+            out[mode]["bound_rel_diff_vs_cold"] = max(
+                float(np.linalg.norm(res[k] - ref[k]) / np.linalg.norm(ref[k])) for k in ("upper", "lower"))
+            out[mode]["speedup_vs_cold"] = round(out["cold"]["time_to_bounds_s"] / elapsed, 3)
+        out[mode]["_bounds"] = {"upper": res["upper"], "lower": res["lower"]}
+    for mode in ("cold", "warm", "bound_tol"):
+        del out[mode]["_bounds"]
+    return out
 
 
 def serving_bench(n, rtol, seed=4):

@@ -207,6 +207,18 @@ int fftgal_warm_start(struct fftgal_plan *fine, struct fftgal_plan *coarse);
  */
 int fftgal_history(struct fftgal_plan *plan, int kind, int alpha, double *energy, int cap, int *n);
 
+/*
+ * Stop on the bound as well as on the residual (Sec. 6.4: the energy of every
+ * CG iterate is a guaranteed bound, and it decreases monotonically).  With
+ * btol > 0 the plan's later solves also stop once the estimated remaining
+ * decrease of the bound entry -- the last decrease d_k times q / (1 - q), q =
+ * d_k / d_{k-1} -- is below btol times the entry (after at least two steps).
+ * The bounds fftgal_bounds returns stay guaranteed; btol states how far they
+ * are estimated to be from the converged Ga bounds.  0 (the default)
+ * disables the test.  EINVAL for a negative or non-finite btol.
+ */
+int fftgal_set_bound_tol(struct fftgal_plan *plan, double btol);
+
 /* Release the plan (host memory only; the workspace stays the caller's). */
 int fftgal_destroy(struct fftgal_plan *plan);
 
@@ -239,6 +251,9 @@ enum fftgal_kernel_class {
     FFTGAL_K_COUNT = 10
 };
 int fftgal_set_timing(struct fftgal_plan *plan, int enable);
+/* As fftgal_set_timing, for the classes whose bit (1 << class) is set only
+ * (0 disables timing). */
+int fftgal_set_timing_classes(struct fftgal_plan *plan, uint32_t mask);
 int fftgal_read_timing(struct fftgal_plan *plan, double *ms, int32_t *count);
 
 /*

@@ -97,6 +97,20 @@ bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o) {
     return true;
 }
 
+// Device scratch the voxel setup needs for an image of resolution P: the
+// image (or its partially transformed form) and the R2C rows.
+void voxel_scratch(const Dims &D, const int *P, size_t *need_u, size_t *need_w) {
+    const int d = D.d;
+    long Ptot = 1;
+    for (int a = 0; a < d; ++a) Ptot *= P[a];
+    *need_u = (size_t)Ptot * 8;
+    *need_w = (size_t)(Ptot / P[d - 1]) * D.Lh * 16;
+    if (d == 3) {
+        *need_u = std::max(*need_u, (size_t)P[0] * D.L[1] * D.Lh * 16);
+        *need_w = std::max(*need_w, (size_t)D.L[0] * D.L[1] * D.Lh * 16);
+    }
+}
+
 struct Layout {
     size_t tw64, tw32, twP64, twP32, T1, T2, r, p, q, xsol, xsol64, gA64, gB64, gA32, gB32, part_a, part_b,
         part_c, gram, args, status, hist, total;
@@ -227,12 +241,16 @@ struct fftgal_plan {
     bool solved[2][3] = {{false, false, false}, {false, false, false}};
     bool warm[2][3] = {{false, false, false}, {false, false, false}};  // x holds an initial iterate
     bool hist_valid[2][3] = {{false, false, false}, {false, false, false}};
+    // voxel setup scratch: the layout's regions, or the workspace tail beyond
+    // the layout when the image resolution exceeds what the layout provisions
+    size_t vox_tw64 = 0, vox_tw32 = 0, vox_u = 0, vox_w = 0;
     fftgal_info last_info[2][3];
     bool busy = false;     // a solve of this plan is a member of a batch
     bool hist_on = false;  // per-iteration (rr, alpha) history; only when maxit <= kMaxHist
     int cur_alpha = 0;
-    // kernel timing (fftgal_set_timing)
-    bool timing = false;
+    double btol = 0.0;  // bound tolerance of the stopping test (fftgal_set_bound_tol)
+    // kernel timing (fftgal_set_timing): classes recorded
+    unsigned timing_mask = 0;
     struct Ev {
         int cls;
         hipEvent_t a, b;
@@ -284,13 +302,13 @@ struct Timed {
     int cls;
     hipEvent_t a = nullptr;
     Timed(Plan *p, int c) : pl(p), cls(c) {
-        if (pl->timing) {
+        if ((pl->timing_mask >> cls) & 1u) {
             a = pool_event(pl);
             if (a) (void)hipEventRecord(a, pl->stream);
         }
     }
     ~Timed() {
-        if (pl->timing && a) {
+        if (a) {
             hipEvent_t b = pool_event(pl);
             if (b) {
                 (void)hipEventRecord(b, pl->stream);
@@ -331,7 +349,7 @@ int fail(Plan *pl, int code, const char *fmt, ...) {
 PencilArgs base_pencil(Plan *pl, const FftDesc &f, bool fp64, bool tabP = false) {
     PencilArgs a{};
     a.f = f;
-    a.tw = pl->ws + (fp64 ? (tabP ? pl->Lo.twP64 : pl->Lo.tw64) : (tabP ? pl->Lo.twP32 : pl->Lo.tw32));
+    a.tw = pl->ws + (fp64 ? (tabP ? pl->vox_tw64 : pl->Lo.tw64) : (tabP ? pl->vox_tw32 : pl->Lo.tw32));
     a.d = pl->D.d;
     a.Nh = pl->D.Nh;
     a.Nmid = pl->D.d == 3 ? pl->D.N[1] : 0;
@@ -652,8 +670,8 @@ int voxel_series(Plan *pl, const double *img_dev, int imgmap, double vmax, void 
     const Dims &D = pl->D;
     const int d = D.d;
     const int *P = pl->Pcur;
-    void *U = pl->ws + pl->Lo.T2;
-    void *W = pl->ws + pl->Lo.T1;
+    void *U = pl->ws + pl->vox_u;
+    void *W = pl->ws + pl->vox_w;
     long Ptot = 1;
     for (int a = 0; a < d; ++a) Ptot *= P[a];
     // rows along the last axis: R2C, keep n_d in [0, N_d)
@@ -663,7 +681,7 @@ int voxel_series(Plan *pl, const double *img_dev, int imgmap, double vmax, void 
     r.Nh_row = D.Lh;
     r.cs = 0;
     r.f = pl->fP[d - 1];
-    r.tw = pl->ws + pl->Lo.twP64;
+    r.tw = pl->ws + pl->vox_tw64;
     r.ncomp = 1;
     r.d = d;
     r.mode = ROW_R2C;
@@ -950,7 +968,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
         Timed t(pl, FFTGAL_K_CG_SCALAR);
         HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload,
                                     pl->at<double>(pl->Lo.part_c), 1.0 / (double)D.Mtot, rtol, floor_rel, maxit,
-                                    pl->hist(kind, alpha), pl->stream));
+                                    pl->btol, pl->hist(kind, alpha), pl->stream));
         HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
         HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
         return FFTGAL_OK;
@@ -990,7 +1008,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
                                       pl->at<double>(pl->Lo.part_c), fp64, pl->stream));
     HIPCHECK(pl, launch_cg_init_warm(st, pl->at<double>(pl->Lo.part_a), pl->at<double>(pl->Lo.part_b),
                                      pl->at<double>(pl->Lo.part_c), u.nblocks, scal, (double)D.Mtot, rtol, floor_rel,
-                                     maxit, pl->hist(kind, alpha), pl->stream));
+                                     maxit, pl->btol, pl->hist(kind, alpha), pl->stream));
     HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
     return FFTGAL_OK;
 }
@@ -1076,8 +1094,22 @@ extern "C" {
 size_t fftgal_workspace_bytes_p(int d, const int32_t *N, int precision, const int32_t *P) {
     Dims D;
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
-    if (!make_dims(d, N, P, &D)) return 0;
-    return make_layout(D, precision).total;
+    if (!make_dims(d, N, nullptr, &D)) return 0;
+    const size_t base = make_layout(D, precision).total;
+    if (P == nullptr) return base;
+    Dims DP;
+    if (!make_dims(d, N, P, &DP)) return 0;
+    // a plan lays out its regions without P: an image that does not fit them
+    // uses a tail of twiddles, U and W regions after the layout
+    int Pv[3] = {1, 1, 1};
+    size_t entry = 0;
+    for (int a = 0; a < d; ++a) {
+        Pv[a] = P[a];
+        entry += (size_t)P[a];
+    }
+    size_t need_u = 0, need_w = 0;
+    voxel_scratch(D, Pv, &need_u, &need_w);
+    return base + align256(entry * 16) + align256(entry * 8) + align256(need_u) + align256(need_w);
 }
 
 size_t fftgal_workspace_bytes(int d, const int32_t *N, int precision) {
@@ -1242,17 +1274,10 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
             Ptot *= m->P[a];
         }
         if (!m->image) return fail(pl, FFTGAL_EINVAL, "image is NULL");
-        // the image and its R2C rows must fit the scratch regions of this plan
-        const size_t ubytes = pl->Lo.r - pl->Lo.T2;
-        const size_t wbytes = pl->Lo.T2 - pl->Lo.T1;
-        size_t need_u = (size_t)Ptot * 8, need_w = (size_t)(Ptot / m->P[d - 1]) * D.Lh * 16;
-        if (d == 3) {
-            need_u = std::max(need_u, (size_t)m->P[0] * D.L[1] * D.Lh * 16);
-            need_w = std::max(need_w, (size_t)D.L[0] * D.L[1] * D.Lh * 16);
-        }
-        if (need_u > ubytes || need_w > wbytes)
-            return fail(pl, FFTGAL_ENOMEM, "voxel image too large for this workspace (use fftgal_workspace_bytes_p)");
-        // twiddles for the image axes
+        // the image, its R2C rows and the image twiddles must fit the scratch
+        // regions of this plan, or else the workspace tail beyond its layout
+        size_t need_u = 0, need_w = 0;
+        voxel_scratch(D, m->P, &need_u, &need_w);
         std::vector<double> tab;
         size_t entry = 0;
         FftDesc fP[3];
@@ -1260,20 +1285,36 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
             build_fft(m->P[a], entry, tab, &fP[a]);
             entry = tab.size() / 2;
         }
-        if (entry > pl->Lo.twP_len) return fail(pl, FFTGAL_ENOMEM, "voxel resolution exceeds the plan's provision");
+        const size_t ubytes = pl->Lo.r - pl->Lo.T2;
+        const size_t wbytes = pl->Lo.T2 - pl->Lo.T1;
+        if (need_u <= ubytes && need_w <= wbytes && entry <= pl->Lo.twP_len) {
+            pl->vox_tw64 = pl->Lo.twP64;
+            pl->vox_tw32 = pl->Lo.twP32;
+            pl->vox_u = pl->Lo.T2;
+            pl->vox_w = pl->Lo.T1;
+        } else {
+            const size_t t0 = pl->Lo.total;
+            pl->vox_tw64 = t0;
+            pl->vox_tw32 = pl->vox_tw64 + align256(entry * 16);
+            pl->vox_u = pl->vox_tw32 + align256(entry * 8);
+            pl->vox_w = pl->vox_u + align256(need_u);
+            if (pl->vox_w + need_w > pl->ws_bytes)
+                return fail(pl, FFTGAL_ENOMEM,
+                            "voxel image too large for this workspace (size it with fftgal_workspace_bytes_p)");
+        }
         for (int a = 0; a < d; ++a) {
             pl->Pcur[a] = m->P[a];
             pl->fP[a] = fP[a];
         }
         std::vector<float> tab32(tab.begin(), tab.end());
-        HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->Lo.twP64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice,
+        HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->vox_tw64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice,
                                     pl->stream));
-        HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->Lo.twP32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice,
+        HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->vox_tw32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice,
                                     pl->stream));
         // the image is read from the caller's device buffer, or from a staging
         // copy at the start of the U scratch region (re-uploaded per pass,
         // since the transforms overwrite U)
-        double *staging = pl->at<double>(pl->Lo.T2);
+        double *staging = pl->at<double>(pl->vox_u);
         const double *img = m->image_device ? m->image : staging;
         auto upload = [&]() -> int {
             if (!m->image_device)
@@ -1403,7 +1444,20 @@ int fftgal_bounds(struct fftgal_plan *pl, double *upper, double *lower, double *
 
 int fftgal_set_timing(struct fftgal_plan *pl, int enable) {
     if (!pl) return FFTGAL_EINVAL;
-    pl->timing = enable != 0;
+    pl->timing_mask = enable != 0 ? (1u << FFTGAL_K_COUNT) - 1u : 0u;
+    return FFTGAL_OK;
+}
+
+int fftgal_set_timing_classes(struct fftgal_plan *pl, uint32_t mask) {
+    if (!pl) return FFTGAL_EINVAL;
+    pl->timing_mask = mask & ((1u << FFTGAL_K_COUNT) - 1u);
+    return FFTGAL_OK;
+}
+
+int fftgal_set_bound_tol(struct fftgal_plan *pl, double btol) {
+    if (!pl) return FFTGAL_EINVAL;
+    if (!(btol >= 0.0) || !std::isfinite(btol)) return fail(pl, FFTGAL_EINVAL, "bound tolerance must be >= 0");
+    pl->btol = btol;
     return FFTGAL_OK;
 }
 

@@ -56,6 +56,9 @@ struct CgStatus {
     double tol2;     // rtol^2
     double floor2;   // (floor * ||A_M E||)^2
     double load2;    // ||A_M E||^2
+    double energy;   // energy of the current iterate (CG recurrence)
+    double dprev;    // energy decrease of the previous step
+    double btol;     // bound tolerance (0: residual test only)
     int32_t iter;
     int32_t maxit;
     int32_t done;
@@ -186,7 +189,7 @@ int pencil_grid_x(const PencilArgs &a);
 
 hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part, int n_load,
                           const double *work_part, double inv_mtot, double tol, double floor_rel, int maxit,
-                          double *hist, hipStream_t s);
+                          double btol, double *hist, hipStream_t s);
 // Multi-problem launches: `args` and `woff` are device arrays; problem i
 // owns work-groups [woff[i], woff[i + 1]) of a grid of `total` work-groups.
 hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, const int *woff, int np,
@@ -209,7 +212,7 @@ hipError_t launch_warm_residual(const UpdArgs &u, double *part_rr, double *part_
 // scal[2] / mtot - sum part_bx - sum part_rx (history slot 1).
 hipError_t launch_cg_init_warm(CgStatus *st, const double *part_rr, const double *part_bx, const double *part_rx,
                                int nparts, const double *scal, double mtot, double tol, double floor_rel, int maxit,
-                               double *hist, hipStream_t s);
+                               double btol, double *hist, hipStream_t s);
 // Copy the coefficient arrays of a coarse solve into a fine one: entries of
 // frequencies inside the coarse grid are copied, all others set to zero.
 hipError_t launch_prolong(const void *src, bool src64, void *dst, bool dst64, int d, int nc, const int *Nf,

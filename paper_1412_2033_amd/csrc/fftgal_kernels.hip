@@ -815,7 +815,7 @@ __device__ double sum_fixed(const double *part, int n) {
 __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgStatus *st, const double *rr_part, int n_rr,
                                                            const double *load_part, int n_load,
                                                            const double *work_part, double inv_mtot, double tol,
-                                                           double floor_rel, int maxit, double *hist) {
+                                                           double floor_rel, int maxit, double btol, double *hist) {
     const double rr = sum_fixed(rr_part, n_rr);
     const double load = sum_fixed(load_part, n_load);
     const double work = work_part != nullptr ? sum_fixed(work_part, n_load) : 0.0;
@@ -830,12 +830,15 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgStatus *st, const d
         st->floor2 = floor_rel * floor_rel * load;
         st->iter = 0;
         st->maxit = maxit;
+        st->energy = work * inv_mtot;
+        st->dprev = 0.0;
+        st->btol = btol;
         st->breakdown = !isfinite(rr) || !isfinite(load);
         st->converged = (rr == 0.0 || rr <= st->floor2) && !st->breakdown;
         st->done = st->converged || st->breakdown || maxit <= 0;
         if (hist != nullptr) {
             hist[0] = rr;
-            hist[1] = work * inv_mtot;
+            hist[1] = st->energy;
         }
     }
 }
@@ -881,7 +884,7 @@ __global__ __launch_bounds__(kThreads) void warm_residual_kernel(UpdArgs a, doub
 __global__ __launch_bounds__(kThreads) void cg_init_warm_kernel(CgStatus *st, const double *part_rr,
                                                                 const double *part_bx, const double *part_rx,
                                                                 int nparts, const double *scal, double mtot,
-                                                                double tol, double floor_rel, int maxit,
+                                                                double tol, double floor_rel, int maxit, double btol,
                                                                 double *hist) {
     const double rr = sum_fixed(part_rr, nparts);
     const double bx = sum_fixed(part_bx, nparts);
@@ -899,12 +902,15 @@ __global__ __launch_bounds__(kThreads) void cg_init_warm_kernel(CgStatus *st, co
         st->floor2 = floor_rel * floor_rel * load;
         st->iter = 0;
         st->maxit = maxit;
+        st->energy = scal[2] / mtot - bx - rx;
+        st->dprev = 0.0;
+        st->btol = btol;
         st->breakdown = !isfinite(rr) || !isfinite(load) || !isfinite(bb);
         st->converged = (rr == 0.0 || rr <= st->tol2 * bb || rr <= st->floor2) && !st->breakdown;
         st->done = st->converged || st->breakdown || maxit <= 0;
         if (hist != nullptr) {
             hist[0] = rr;
-            hist[1] = scal[2] / mtot - bx - rx;
+            hist[1] = st->energy;
         }
     }
 }
@@ -2139,14 +2145,27 @@ __global__ __launch_bounds__(kThreads) void cg_check_multi_kernel(const CgItem *
                 st->breakdown = 1;
                 st->done = 1;
             } else {
+                // energy of the new iterate: one CG step lowers it by
+                // alpha_k (r_{k-1}, r_{k-1})
+                const double dstep = st->alpha * st->rr;
+                st->energy -= dstep;
                 st->beta = rr / st->rr;
                 st->rr = rr;
                 if (rr <= st->tol2 * st->rr0 || rr <= st->floor2) {
                     st->converged = 1;
                     st->done = 1;
+                } else if (st->btol > 0.0 && iter >= 2 && st->dprev > 0.0 &&
+                           dstep <= st->btol * fabs(st->energy) *
+                                        (1.0 - fmin(fmax(dstep / st->dprev, 0.0), 0.99))) {
+                    // bound test: the remaining decrease, estimated from the
+                    // ratio q of the last two steps as dstep q / (1 - q), is
+                    // below btol times the bound entry
+                    st->converged = 1;
+                    st->done = 1;
                 } else if (iter >= st->maxit) {
                     st->done = 1;
                 }
+                st->dprev = dstep;
             }
         }
     }
@@ -2422,9 +2441,9 @@ hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, in
 
 hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part, int n_load,
                           const double *work_part, double inv_mtot, double tol, double floor_rel, int maxit,
-                          double *hist, hipStream_t s) {
+                          double btol, double *hist, hipStream_t s) {
     hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kThreads), 0, s, st, rr_part, n_rr, load_part, n_load, work_part,
-                       inv_mtot, tol, floor_rel, maxit, hist);
+                       inv_mtot, tol, floor_rel, maxit, btol, hist);
     return hipGetLastError();
 }
 
@@ -2441,9 +2460,9 @@ hipError_t launch_warm_residual(const UpdArgs &u, double *part_rr, double *part_
 
 hipError_t launch_cg_init_warm(CgStatus *st, const double *part_rr, const double *part_bx, const double *part_rx,
                                int nparts, const double *scal, double mtot, double tol, double floor_rel, int maxit,
-                               double *hist, hipStream_t s) {
+                               double btol, double *hist, hipStream_t s) {
     hipLaunchKernelGGL(cg_init_warm_kernel, dim3(1), dim3(kThreads), 0, s, st, part_rr, part_bx, part_rx, nparts,
-                       scal, mtot, tol, floor_rel, maxit, hist);
+                       scal, mtot, tol, floor_rel, maxit, btol, hist);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5
 EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", "fftgal_set_material",
            "fftgal_solve_primal", "fftgal_solve_dual", "fftgal_bounds", "fftgal_destroy",
            "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
-           "fftgal_warm_start", "fftgal_history",
+           "fftgal_warm_start", "fftgal_history", "fftgal_set_timing_classes", "fftgal_set_bound_tol",
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
@@ -107,6 +107,10 @@ def load_library(path=LIB_PATH):
     lib.fftgal_set_timing.restype = ctypes.c_int
     lib.fftgal_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
     lib.fftgal_read_timing.restype = ctypes.c_int
+    lib.fftgal_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
+    lib.fftgal_set_timing_classes.restype = ctypes.c_int
+    lib.fftgal_set_bound_tol.argtypes = [vp, ctypes.c_double]
+    lib.fftgal_set_bound_tol.restype = ctypes.c_int
     lib.fftgal_warm_start.argtypes = [vp, vp]
     lib.fftgal_warm_start.restype = ctypes.c_int
     lib.fftgal_history.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
@@ -248,6 +252,17 @@ def fftgal_set_timing(plan, enable):
     _check(load_library().fftgal_set_timing(plan, int(bool(enable))), plan)
 
 
+def fftgal_set_timing_classes(plan, classes):
+    mask = 0
+    for c in classes:
+        mask |= 1 << KERNEL_CLASSES.index(c)
+    _check(load_library().fftgal_set_timing_classes(plan, mask), plan)
+
+
+def fftgal_set_bound_tol(plan, btol):
+    _check(load_library().fftgal_set_bound_tol(plan, float(btol)), plan)
+
+
 def fftgal_read_timing(plan):
     """{class: (milliseconds, launches)} since the previous read."""
     n = len(KERNEL_CLASSES)
@@ -303,8 +318,15 @@ class Plan:
     def bounds(self):
         return fftgal_bounds(self.handle, self.d)
 
-    def set_timing(self, enable=True):
-        fftgal_set_timing(self.handle, enable)
+    def set_timing(self, enable=True, classes=None):
+        """Time every launch (enable), or only the given kernel classes."""
+        if classes is None:
+            fftgal_set_timing(self.handle, enable)
+        else:
+            fftgal_set_timing_classes(self.handle, classes if enable else ())
+
+    def set_bound_tol(self, btol):
+        fftgal_set_bound_tol(self.handle, btol)
 
     def read_timing(self):
         return fftgal_read_timing(self.handle)

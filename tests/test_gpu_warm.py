@@ -132,3 +132,32 @@ def test_warm_start_errors(fg):
         a.close()
         b.close()
         c.close()
+
+
+@pytest.mark.parametrize("btol", [1e-4, 1e-7])
+def test_bound_tolerance_matches_oracle(fg, btol):
+    # the bound test stops CG early on the device; each bound entry must equal
+    # the oracle's exact energy of its iterate with the same number of steps,
+    # and stay on the guaranteed side of the converged Ga bounds
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 200.0, center=(0.05, -0.1))
+    N = (41, 41)
+    print("bound tolerance %g circle2d N=41" % btol, flush=True)
+    plan = fg.Plan(2, N, "fp64")
+    try:
+        plan.set_bound_tol(btol)
+        res = plan.run(micro, rtol=1e-12)
+    finally:
+        plan.close()
+    mat = material.make_material(micro)
+    ref = ga.ga_bounds(mat, N, tol=1e-12, track_energy=True)
+    ob = ga.ga_bounds(mat, N, tol=1e-12, btol=btol)
+    gB = np.linalg.inv(res["lower"])
+    for a in range(2):
+        kp = res["info_primal"][a]["iters"]
+        kd = res["info_dual"][a]["iters"]
+        assert kp < ref["iters_primal"][a] and abs(kp - ob["iters_primal"][a]) <= 1
+        assert kd < ref["iters_dual"][a] and abs(kd - ob["iters_dual"][a]) <= 1
+        assert abs(res["upper"][a, a] - ref["energies_primal"][a][kp]) <= 1e-9 * res["upper"][a, a]
+        assert abs(gB[a, a] - ref["energies_dual"][a][kd]) <= 1e-9 * gB[a, a]
+        assert res["upper"][a, a] >= ref["upper"][a, a] * (1 - 1e-12)
+        assert res["lower"][a, a] <= ref["lower"][a, a] * (1 + 1e-12)

@@ -119,3 +119,20 @@ def test_cold_start_energy_is_voigt():
     voigt, _ = ga.voigt_reuss(mat, 2)
     for a in range(2):
         assert abs(res["energies_primal"][a][0] - voigt[a, a]) <= 1e-12 * voigt[a, a]
+
+
+@pytest.mark.parametrize("btol", [1e-4, 1e-6, 1e-8])
+def test_bound_tolerance_stop(btol):
+    # the bound test stops CG early; the bounds stay guaranteed (upper above,
+    # lower below the converged Ga bounds, Prop. struct_bounds) and within a
+    # small multiple of btol of them
+    mat = _circle(200.0)
+    N = (21, 21)
+    ref = ga.ga_bounds(mat, N, tol=1e-12)
+    res = ga.ga_bounds(mat, N, tol=1e-12, btol=btol)
+    assert sum(res["iters_primal"]) < sum(ref["iters_primal"])
+    for a in range(2):
+        up, lo = res["upper"][a, a], res["lower"][a, a]
+        assert up >= ref["upper"][a, a] * (1 - 1e-13) and lo <= ref["lower"][a, a] * (1 + 1e-13)
+        assert (up - ref["upper"][a, a]) / ref["upper"][a, a] <= 20 * btol
+        assert (ref["lower"][a, a] - lo) / ref["lower"][a, a] <= 20 * btol
