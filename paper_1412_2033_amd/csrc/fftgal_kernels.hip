@@ -1721,18 +1721,18 @@ __global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__rest
     }
 }
 
-// FP64 variant for two-stage schedules: every exchange between stages moves
-// the real parts through LDS first and the imaginary parts second, so a
-// transform needs n doubles of LDS instead of n complex values; with the
-// material values loaded at the multiply (not held in registers) this doubles
-// the resident waves, which hides the latencies of the stages.
+// Variant for two-stage schedules: every exchange between stages moves the
+// real parts through LDS first and the imaginary parts second, so a transform
+// needs n reals of LDS instead of n complex values; with the material values
+// loaded at the multiply (not held in registers) this raises the resident
+// waves, which hides the latencies of the stages, and each thread unpacks its
+// own points (no index division).
 constexpr int split_tb(int fi) { return iso_tb(fi); }
 constexpr int split_nt(int fi) { return iso_nt(fi); }
 
-template <int FI>
+template <typename T, int FI>
 __global__ __launch_bounds__(split_nt(FI)) void row_iso_split(const RowArgs *__restrict__ ra,
                                                              const int *__restrict__ woff, int np) {
-    using T = double;
     using V = Vt<T>;
     constexpr int N = kFastSched[FI].n;
     constexpr int R = kFastSched[FI].r[0];
@@ -1959,9 +1959,9 @@ template <typename T, int FI>
 void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
     if constexpr (palindromic(FI)) {
         constexpr int N = kFastSched[FI].n;
-        if constexpr (sizeof(T) == 8 && kFastSched[FI].nst == 2) {
-            const size_t lds = sizeof(double) * (size_t)split_tb(FI) * N + sizeof(Vt<T>) * N;
-            hipLaunchKernelGGL((row_iso_split<FI>), dim3(total), dim3(split_nt(FI)), lds, s, args, woff, np);
+        if constexpr (kFastSched[FI].nst == 2) {
+            const size_t lds = sizeof(T) * (size_t)split_tb(FI) * N + sizeof(Vt<T>) * N;
+            hipLaunchKernelGGL((row_iso_split<T, FI>), dim3(total), dim3(split_nt(FI)), lds, s, args, woff, np);
         } else {
             const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + N);
             hipLaunchKernelGGL((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
@@ -2284,7 +2284,7 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
     if (a.fast == 2) {
         const int fi = fast_index(a.f.n);
-        if (fp64 && fi >= 0 && kFastSched[fi].nst == 2) return 8 * (size_t)a.RP * a.f.n + es * a.f.n;
+        if (fi >= 0 && kFastSched[fi].nst == 2) return es / 2 * (size_t)a.RP * a.f.n + es * a.f.n;
         return es * ((size_t)a.RP * a.f.n + a.f.n);
     }
     if (a.fast)
