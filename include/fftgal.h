@@ -219,6 +219,32 @@ int fftgal_history(struct fftgal_plan *plan, int kind, int alpha, double *energy
  */
 int fftgal_set_bound_tol(struct fftgal_plan *plan, double btol);
 
+/*
+ * GaNi plans (Def. GaNi, Algorithm 1): the material is sampled at the grid
+ * points x = k / N of the grid of the approximation order N (a point on an
+ * inclusion boundary counts as outside; a voxel p covers [p/P - 1/(2P),
+ * p/P + 1/(2P))), and the transforms run on that grid, so every N_a must be
+ * odd and 3,5,7-smooth.  The solve and bounds calls then return the GaNi
+ * minimisers and A~_{H,N} (upper) and B~_{H,N}^{-1} (lower) -- equal for odd
+ * N (Remark duality_gani) and NOT guaranteed bounds; fftgal_bounds_of turns
+ * the minimisers into guaranteed ones.  Workspace, arguments and errors as
+ * for fftgal_plan / fftgal_workspace_bytes_p (P may be NULL).
+ */
+size_t fftgal_workspace_bytes_gani(int d, const int32_t *N, int precision, const int32_t *P);
+int fftgal_plan_gani(struct fftgal_plan **out, int d, const int32_t *N, int precision,
+                     void *dev_workspace, size_t bytes, void *hip_stream);
+
+/*
+ * A-posteriori guaranteed bounds (eq. GaNi_apost; Prop. struct_bounds): the
+ * exact energies, on this plan's double grid, of the fields of all 2d solves
+ * of `src` (e.g. a GaNi plan of the same N), carried over as in
+ * fftgal_warm_start.  `plan` must be a Ga plan with its material set; its
+ * solution storage is overwritten and its solves are marked done.  Outputs as
+ * fftgal_bounds.  ESTATE unless `src` has all 2d solves.
+ */
+int fftgal_bounds_of(struct fftgal_plan *plan, struct fftgal_plan *src, double *upper, double *lower,
+                     double *gap);
+
 /* Release the plan (host memory only; the workspace stays the caller's). */
 int fftgal_destroy(struct fftgal_plan *plan);
 

@@ -77,19 +77,22 @@ struct Dims {
     int nc_max = 1;
 };
 
-bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o) {
+// gani: the transforms run on the grid of the approximation order N itself
+// (Def. GaNi, Algorithm 1), which must then be 3,5,7-smooth.
+bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, bool gani = false) {
     if (d != 2 && d != 3 || N == nullptr) return false;
     o->d = d;
     for (int a = 0; a < d; ++a) {
         if (N[a] < 1 || N[a] % 2 == 0 || N[a] > 100000) return false;
+        if (gani && !is_smooth_odd(N[a])) return false;
         o->N[a] = N[a];
-        o->L[a] = 2 * N[a] - 1;
-        o->M[a] = smooth_odd(2 * N[a] - 1);
+        o->L[a] = gani ? N[a] : 2 * N[a] - 1;
+        o->M[a] = gani ? N[a] : smooth_odd(2 * N[a] - 1);
         o->P[a] = P ? std::max<int>(P[a], o->M[a]) : o->M[a];
         if (P && !is_smooth_odd(P[a])) return false;
     }
     o->Nh = (o->N[d - 1] + 1) / 2;
-    o->Lh = o->N[d - 1];
+    o->Lh = gani ? o->Nh : o->N[d - 1];
     o->Ns = (d == 3 ? (long)o->N[0] * o->N[1] : (long)o->N[0]) * o->Nh;
     o->Mtot = 1;
     for (int a = 0; a < d; ++a) o->Mtot *= o->M[a];
@@ -249,6 +252,7 @@ struct fftgal_plan {
     bool hist_on = false;  // per-iteration (rr, alpha) history; only when maxit <= kMaxHist
     int cur_alpha = 0;
     double btol = 0.0;  // bound tolerance of the stopping test (fftgal_set_bound_tol)
+    bool gani = false;  // material sampled at the grid points of the order-N grid
     // kernel timing (fftgal_set_timing): classes recorded
     unsigned timing_mask = 0;
     struct Ev {
@@ -1089,16 +1093,16 @@ int solve_entry(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_in
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-size_t fftgal_workspace_bytes_p(int d, const int32_t *N, int precision, const int32_t *P) {
+size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P, bool gani) {
     Dims D;
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
-    if (!make_dims(d, N, nullptr, &D)) return 0;
+    if (!make_dims(d, N, nullptr, &D, gani)) return 0;
     const size_t base = make_layout(D, precision).total;
     if (P == nullptr) return base;
     Dims DP;
-    if (!make_dims(d, N, P, &DP)) return 0;
+    if (!make_dims(d, N, P, &DP, gani)) return 0;
     // a plan lays out its regions without P: an image that does not fit them
     // uses a tail of twiddles, U and W regions after the layout
     int Pv[3] = {1, 1, 1};
@@ -1112,19 +1116,17 @@ size_t fftgal_workspace_bytes_p(int d, const int32_t *N, int precision, const in
     return base + align256(entry * 16) + align256(entry * 8) + align256(need_u) + align256(need_w);
 }
 
-size_t fftgal_workspace_bytes(int d, const int32_t *N, int precision) {
-    return fftgal_workspace_bytes_p(d, N, precision, nullptr);
-}
-
-int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace, size_t bytes,
-                void *hip_stream) {
+int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace, size_t bytes,
+              void *hip_stream, bool gani) {
     if (out == nullptr) return fail(nullptr, FFTGAL_EINVAL, "out is NULL");
     *out = nullptr;
     Dims D;
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
         return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
-    if (!make_dims(d, N, nullptr, &D))
-        return fail(nullptr, FFTGAL_EINVAL, "d must be 2 or 3 and every N odd and >= 1");
+    if (!make_dims(d, N, nullptr, &D, gani))
+        return fail(nullptr, FFTGAL_EINVAL,
+                    gani ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
+                         : "d must be 2 or 3 and every N odd and >= 1");
     if (dev_workspace == nullptr || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))
         return fail(nullptr, FFTGAL_EINVAL, "workspace must be a 256-byte aligned device pointer");
     Layout Lo = make_layout(D, precision);
@@ -1134,6 +1136,7 @@ int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision
     auto *pl = new Plan();
     pl->D = D;
     pl->Lo = Lo;
+    pl->gani = gani;
     pl->precision = precision;
     pl->stream = reinterpret_cast<hipStream_t>(hip_stream);
     pl->ws = reinterpret_cast<char *>(dev_workspace);
@@ -1157,6 +1160,34 @@ int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision
     *out = pl;
     return FFTGAL_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+
+size_t fftgal_workspace_bytes_p(int d, const int32_t *N, int precision, const int32_t *P) {
+    return workspace_bytes(d, N, precision, P, false);
+}
+
+size_t fftgal_workspace_bytes_gani(int d, const int32_t *N, int precision, const int32_t *P) {
+    return workspace_bytes(d, N, precision, P, true);
+}
+
+size_t fftgal_workspace_bytes(int d, const int32_t *N, int precision) {
+    return fftgal_workspace_bytes_p(d, N, precision, nullptr);
+}
+
+int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace, size_t bytes,
+                void *hip_stream) {
+    return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, false);
+}
+
+int fftgal_plan_gani(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace,
+                     size_t bytes, void *hip_stream) {
+    return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, true);
+}
+
 
 int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
     if (!pl) return FFTGAL_EINVAL;
@@ -1256,13 +1287,20 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
             for (int i = 0; i < n; ++i) inc[i].w = pass == 0 ? wA[i] : wB[i];
             HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
                                         pl->stream));
-            {
+            if (pl->gani) {
+                // Def. GaNi: the material at the grid points, not a Fourier series
                 Timed t(pl, FFTGAL_K_SETUP);
-                HIPCHECK(pl, launch_incl_coeff(U, d, D.L[0], D.L[1], D.Lh, inc_dev, n, pass == 0 ? wA0 : wB0,
-                                               pl->stream));
+                HIPCHECK(pl, launch_sample_incl(pass == 0 ? gA : gB, d, D.M, inc_dev, n, pass == 0 ? wA0 : wB0,
+                                                pl->stream));
+            } else {
+                {
+                    Timed t(pl, FFTGAL_K_SETUP);
+                    HIPCHECK(pl, launch_incl_coeff(U, d, D.L[0], D.L[1], D.Lh, inc_dev, n, pass == 0 ? wA0 : wB0,
+                                                   pl->stream));
+                }
+                rc = series_to_field(pl, U, pass == 0 ? gA : gB);
+                if (rc) return rc;
             }
-            rc = series_to_field(pl, U, pass == 0 ? gA : gB);
-            if (rc) return rc;
             HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // host table reused
         }
     } else if (m->kind == FFTGAL_VOXELS) {
@@ -1354,6 +1392,11 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
         for (int pass = 0; pass < npass; ++pass) {
             if (pass > 0 && (rc = upload())) return rc;
             const int map = two ? (vmax == vmin ? 3 : 1) : (pass == 0 ? 0 : 2);
+            if (pl->gani) {
+                Timed t(pl, FFTGAL_K_SETUP);
+                HIPCHECK(pl, launch_sample_voxel(pass == 0 ? gA : gB, img, d, m->P, D.M, map, vmax, pl->stream));
+                continue;
+            }
             void *coef = nullptr;
             rc = voxel_series(pl, img, map, vmax, &coef);
             if (rc) return rc;
@@ -1503,6 +1546,30 @@ int fftgal_warm_start(struct fftgal_plan *fine, struct fftgal_plan *coarse) {
             fine->warm[k][a] = true;
         }
     return FFTGAL_OK;
+}
+
+int fftgal_bounds_of(struct fftgal_plan *pl, struct fftgal_plan *src, double *upper, double *lower, double *gap) {
+    if (!pl) return FFTGAL_EINVAL;
+    if (!src || src == pl) return fail(pl, FFTGAL_EINVAL, "source plan is NULL or the plan itself");
+    if (!pl->have_mat) return fail(pl, FFTGAL_ESTATE, "no material set");
+    if (pl->busy || src->busy) return fail(pl, FFTGAL_ESTATE, "a plan has a solve in a batch");
+    const int d = pl->D.d;
+    if (src->D.d != d) return fail(pl, FFTGAL_EINVAL, "plans of different dimension");
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < d; ++a)
+            if (!src->solved[k][a])
+                return fail(pl, FFTGAL_ESTATE, "the source plan needs all %d primal and dual solves", d);
+    if (src->stream != pl->stream) HIPCHECK(pl, hipStreamSynchronize(src->stream));
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < d; ++a) {
+            HIPCHECK(pl, launch_prolong(src->xsol(k, a), src->fp64_iter(), pl->xsol(k, a), pl->fp64_iter(), d,
+                                        pl->nc(k), pl->D.N, src->D.N, pl->stream));
+            pl->solved[k][a] = true;
+            pl->warm[k][a] = false;
+            pl->hist_valid[k][a] = false;
+            pl->last_info[k][a] = src->last_info[k][a];
+        }
+    return fftgal_bounds(pl, upper, lower, gap);
 }
 
 int fftgal_history(struct fftgal_plan *pl, int kind, int alpha, double *energy, int cap, int *n) {

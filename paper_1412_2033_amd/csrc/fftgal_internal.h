@@ -176,6 +176,13 @@ struct InclDev {
 };
 
 // ---- launchers (fftgal_kernels.hip) ----
+// GaNi material at the grid points x = k / M (centred): w0 + sum_i w_i chi_i(x)
+// for inclusions (periodic minimum image; boundary points outside), and the
+// mapped value of the voxel containing x for images (voxel p covers
+// [p/P - 1/(2P), p/P + 1/(2P))).  Output layout [x1][x2][x3], FP64.
+hipError_t launch_sample_incl(double *g, int d, const int *M, const InclDev *inc, int n, double w0, hipStream_t s);
+hipError_t launch_sample_voxel(double *g, const double *img, int d, const int *P, const int *M, int map, double vmax,
+                               hipStream_t s);
 size_t pencil_lds_bytes(const PencilArgs &a, bool fp64);
 size_t row_lds_bytes(const RowArgs &a, bool fp64);
 // Choose pencils per work-group / row pairs per work-group (and whether the

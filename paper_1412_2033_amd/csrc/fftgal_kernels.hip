@@ -596,6 +596,51 @@ __device__ __forceinline__ T map_voxel(T v, int mode, double vmax) {
     return v;
 }
 
+// GaNi material (Def. GaNi: the rectangle rule samples A at the grid points).
+__global__ __launch_bounds__(kThreads) void sample_incl_kernel(double *g, int d, int m0, int m1, int m2,
+                                                               const InclDev *inc, int n, double w0) {
+    const long total = (long)m0 * m1 * m2;
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)gridDim.x * kThreads) {
+        const int j2 = (int)(idx % m2);
+        const int j1 = (int)((idx / m2) % m1);
+        const int j0 = (int)(idx / ((long)m2 * m1));
+        double x[3];
+        x[0] = (double)wrapi(j0, m0) / m0;
+        x[1] = (double)wrapi(j1, m1) / m1;
+        x[2] = (double)wrapi(j2, m2) / m2;  // 2D: m2 = 1, x[2] unused
+        double v = w0;
+        for (int i = 0; i < n; ++i) {
+            double r2 = 0.0;
+            bool inside = true;
+            for (int a = 0; a < d; ++a) {
+                double dx = x[a] - inc[i].c[a];
+                dx -= rint(dx);
+                if (inc[i].shape == 0)
+                    inside = inside && fabs(dx) < 0.5 * inc[i].h[a];
+                else
+                    r2 += dx * dx;
+            }
+            if (inc[i].shape != 0) inside = r2 < inc[i].h[0] * inc[i].h[0];
+            if (inside) v += inc[i].w;
+        }
+        g[idx] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void sample_voxel_kernel(double *g, const double *img, int d, int p0, int p1,
+                                                                int p2, int m0, int m1, int m2, int map, double vmax) {
+    const long total = (long)m0 * m1 * m2;
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)gridDim.x * kThreads) {
+        const int j2 = (int)(idx % m2);
+        const int j1 = (int)((idx / m2) % m1);
+        const int j0 = (int)(idx / ((long)m2 * m1));
+        const int q0 = posmod((int)rint((double)wrapi(j0, m0) * p0 / m0), p0);
+        const int q1 = posmod((int)rint((double)wrapi(j1, m1) * p1 / m1), p1);
+        const int q2 = posmod((int)rint((double)wrapi(j2, m2) * p2 / m2), p2);
+        g[idx] = map_voxel<double>(img[((long)q0 * p1 + q1) * p2 + q2], map, vmax);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass: real transforms along the last axis, two rows per complex DFT.
 // ---------------------------------------------------------------------------
@@ -2463,6 +2508,25 @@ hipError_t launch_cg_init_warm(CgStatus *st, const double *part_rr, const double
                                double btol, double *hist, hipStream_t s) {
     hipLaunchKernelGGL(cg_init_warm_kernel, dim3(1), dim3(kThreads), 0, s, st, part_rr, part_bx, part_rx, nparts,
                        scal, mtot, tol, floor_rel, maxit, btol, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_incl(double *g, int d, const int *M, const InclDev *inc, int n, double w0, hipStream_t s) {
+    const int m0 = M[0], m1 = M[1], m2 = d == 3 ? M[2] : 1;
+    const long total = (long)m0 * m1 * m2;
+    const int blocks = (int)std::max<long>(1, std::min<long>(2048, (total + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(sample_incl_kernel, dim3(blocks), dim3(kThreads), 0, s, g, d, m0, m1, m2, inc, n, w0);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_voxel(double *g, const double *img, int d, const int *P, const int *M, int map, double vmax,
+                               hipStream_t s) {
+    const int m0 = M[0], m1 = M[1], m2 = d == 3 ? M[2] : 1;
+    const int p0 = P[0], p1 = P[1], p2 = d == 3 ? P[2] : 1;
+    const long total = (long)m0 * m1 * m2;
+    const int blocks = (int)std::max<long>(1, std::min<long>(2048, (total + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(sample_voxel_kernel, dim3(blocks), dim3(kThreads), 0, s, g, img, d, p0, p1, p2, m0, m1, m2, map,
+                       vmax);
     return hipGetLastError();
 }
 

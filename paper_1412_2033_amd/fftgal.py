@@ -28,6 +28,7 @@ EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", 
            "fftgal_solve_primal", "fftgal_solve_dual", "fftgal_bounds", "fftgal_destroy",
            "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
            "fftgal_warm_start", "fftgal_history", "fftgal_set_timing_classes", "fftgal_set_bound_tol",
+           "fftgal_workspace_bytes_gani", "fftgal_plan_gani", "fftgal_bounds_of",
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
@@ -111,6 +112,13 @@ def load_library(path=LIB_PATH):
     lib.fftgal_set_timing_classes.restype = ctypes.c_int
     lib.fftgal_set_bound_tol.argtypes = [vp, ctypes.c_double]
     lib.fftgal_set_bound_tol.restype = ctypes.c_int
+    lib.fftgal_workspace_bytes_gani.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p]
+    lib.fftgal_workspace_bytes_gani.restype = ctypes.c_size_t
+    lib.fftgal_plan_gani.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32p, ctypes.c_int, vp, ctypes.c_size_t, vp]
+    lib.fftgal_plan_gani.restype = ctypes.c_int
+    lib.fftgal_bounds_of.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.fftgal_bounds_of.restype = ctypes.c_int
     lib.fftgal_warm_start.argtypes = [vp, vp]
     lib.fftgal_warm_start.restype = ctypes.c_int
     lib.fftgal_history.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
@@ -149,19 +157,30 @@ def _check(code, plan=None):
 
 # ---- C-named functions (marshalling only) ------------------------------------
 
-def fftgal_workspace_bytes(d, N, precision=FP64, P=None):
+def fftgal_workspace_bytes(d, N, precision=FP64, P=None, scheme="ga"):
     lib = load_library()
+    if scheme == "gani":
+        return int(lib.fftgal_workspace_bytes_gani(d, _i32(N), precision, None if P is None else _i32(P)))
     if P is None:
         return int(lib.fftgal_workspace_bytes(d, _i32(N), precision))
     return int(lib.fftgal_workspace_bytes_p(d, _i32(N), precision, _i32(P)))
 
 
-def fftgal_plan(d, N, precision, workspace_ptr, nbytes, stream_ptr):
+def fftgal_plan(d, N, precision, workspace_ptr, nbytes, stream_ptr, scheme="ga"):
     lib = load_library()
     h = ctypes.c_void_p()
-    _check(lib.fftgal_plan(ctypes.byref(h), d, _i32(N), precision, ctypes.c_void_p(workspace_ptr),
-                           nbytes, ctypes.c_void_p(stream_ptr)), None)
+    fn = lib.fftgal_plan_gani if scheme == "gani" else lib.fftgal_plan
+    _check(fn(ctypes.byref(h), d, _i32(N), precision, ctypes.c_void_p(workspace_ptr), nbytes,
+              ctypes.c_void_p(stream_ptr)), None)
     return h
+
+
+def fftgal_bounds_of(plan, src, d):
+    up = (ctypes.c_double * (d * d))()
+    lo = (ctypes.c_double * (d * d))()
+    gap = ctypes.c_double()
+    _check(load_library().fftgal_bounds_of(plan, src, up, lo, ctypes.byref(gap)), plan)
+    return (np.array(up[:]).reshape(d, d), np.array(lo[:]).reshape(d, d), float(gap.value))
 
 
 def material_struct(micro):
@@ -289,21 +308,22 @@ def fftgal_history(plan, kind, alpha, cap=20001):
 class Plan:
     """A plan plus the torch device workspace it runs in."""
 
-    def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None):
+    def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None, scheme="ga"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fftgal needs a HIP device")
         self.d = int(d)
         self.N = tuple(int(n) for n in N)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        self.nbytes = fftgal_workspace_bytes(self.d, self.N, self.precision, P)
+        self.scheme = scheme
+        self.nbytes = fftgal_workspace_bytes(self.d, self.N, self.precision, P, scheme)
         if self.nbytes == 0:
             raise FftgalError(-1, "invalid plan arguments")
         dev = torch.device(device)
         self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.handle = fftgal_plan(self.d, self.N, self.precision, self.workspace.data_ptr(), self.nbytes,
-                                  self.stream.cuda_stream)
+                                  self.stream.cuda_stream, scheme)
         self.M = tuple(fftgal_grid_size(self.handle, a) for a in range(self.d))
 
     def set_material(self, micro):
@@ -330,6 +350,10 @@ class Plan:
 
     def read_timing(self):
         return fftgal_read_timing(self.handle)
+
+    def bounds_of(self, src):
+        """Guaranteed bounds from the fields of the solved Plan `src` (e.g. GaNi)."""
+        return fftgal_bounds_of(self.handle, src.handle, self.d)
 
     def warm_start(self, coarse):
         """Start the next solves from the finished solves of `coarse` (a Plan)."""
