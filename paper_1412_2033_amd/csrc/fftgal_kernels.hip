@@ -1232,8 +1232,10 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
         }
     };
     if (a.pro == PRO_EXPAND) {
-        // L_in <= (N + 1) / 2: the CG vectors live on the coarse grid
-        constexpr int PE = ((N + 1) / 2 * B + kThreads - 1) / kThreads;
+      // the CG vectors hold at most (N + 1) / 2 frequencies per axis (Ga), or N
+      // (GaNi, transforms on the grid of the approximation order itself)
+      auto expand = [&](auto cap) {
+        constexpr int PE = (decltype(cap)::value * B + kThreads - 1) / kThreads;
         const auto *sr = gbl(reinterpret_cast<const V *>(a.st_r));
         auto *sp = gbl(reinterpret_cast<V *>(a.st_p));
         const auto *sx = gbl(reinterpret_cast<const V *>(a.st_x));
@@ -1295,6 +1297,11 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                 X[pos * NB + al * B + bb] = mk<T>(ex, ey);
             }
         }
+      };
+      if (2 * a.L_in <= N + 1)
+          expand(std::integral_constant<int, (N + 1) / 2>{});
+      else
+          expand(std::integral_constant<int, N>{});
     } else {
         const auto *in = gbl(reinterpret_cast<const V *>(a.in) + (long)o * a.in_os + b0);
         auto load = [&](auto cap) {
@@ -1328,8 +1335,9 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     fft_ip<T, FI, 0, 1, 0, NB, false>(X, tw, sg);
     auto *out = gbl(reinterpret_cast<V *>(a.out));
     if (a.epi == EPI_PROJECT) {
-        // L_out <= (N + 1) / 2: the projected vector lives on the coarse grid
-        constexpr int PE = ((N + 1) / 2 * B + kThreads - 1) / kThreads;
+      // the projected vector holds at most (N + 1) / 2 frequencies per axis (Ga) or N (GaNi)
+      auto project = [&](auto cap) -> double {
+        constexpr int PE = (decltype(cap)::value * B + kThreads - 1) / kThreads;
         const auto *dv = gbl(reinterpret_cast<const V *>(a.st_dot));
         T dx[PE][2], dy[PE][2];
         if (a.st_dot != nullptr) {
@@ -1386,6 +1394,10 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                 }
             }
         }
+        return part;
+      };
+      const double part = (2 * a.L_out <= N + 1) ? project(std::integral_constant<int, (N + 1) / 2>{})
+                                                 : project(std::integral_constant<int, N>{});
         const double s = block_sum(part);
         if (threadIdx.x == 0) a.partial[lb] = s;
     } else {
@@ -2353,8 +2365,7 @@ static_assert(kNumFast == 6, "launch_*_fast switch covers six sizes");
 void configure_pencil(PencilArgs &a, bool fp64) {
     const int fi = fast_index(a.f.n);
     bool ok = fi >= 0 && a.nsol == 1 && a.ncomp == a.d && a.epi != EPI_WINDOW && (a.d == 2 || a.d == 3) &&
-              a.f.nst == kFastSched[fi].nst && a.L_in <= a.f.n && a.L_out <= a.f.n &&
-              (a.pro != PRO_EXPAND || 2 * a.L_in <= a.f.n + 1) && (a.epi != EPI_PROJECT || 2 * a.L_out <= a.f.n + 1);
+              a.f.nst == kFastSched[fi].nst && a.L_in <= a.f.n && a.L_out <= a.f.n;
     for (int s = 0; ok && s < a.f.nst; ++s) ok = a.f.radix[s] == kFastSched[fi].r[s];
     if (ok) {
         a.fast = 1;
