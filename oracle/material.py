@@ -80,8 +80,12 @@ class GridComposite:
         self.d = int(micro["d"])
         self.P = tuple(int(p) for p in micro["P"])
         self.image = np.asarray(micro["image"], float)
+        # an optional second image for the dual side (Lemma bounds_bounds: the
+        # primal uses an upper approximation of A, the dual a lower one)
+        dual = micro.get("image_dual")
+        self.image_dual = self.image if dual is None else np.asarray(dual, float)
         self._chat_A = grids.dft(self.image)
-        self._chat_B = grids.dft(1.0 / self.image)
+        self._chat_B = grids.dft(1.0 / self.image_dual)
 
     def _coeff(self, k, chat):
         idx = tuple(np.mod(k[a], self.P[a]) for a in range(self.d))
