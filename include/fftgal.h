@@ -107,6 +107,11 @@ typedef struct fftgal_material {
     int32_t P[3];
     const double *image;
     int32_t image_device;
+    /* optional second image of the same resolution and residency for the dual
+     * side (NULL: the same image): the primal solves use `image`, the dual
+     * solves its voxel-wise inverse 1 / image_dual -- upper and lower
+     * approximations of A for Lemma bounds_bounds */
+    const double *image_dual;
 } fftgal_material;
 
 /* Outcome of one CG solve (Remark CG). */
@@ -244,6 +249,23 @@ int fftgal_plan_gani(struct fftgal_plan **out, int d, const int32_t *N, int prec
  */
 int fftgal_bounds_of(struct fftgal_plan *plan, struct fftgal_plan *src, double *upper, double *lower,
                      double *gap);
+
+/*
+ * Upper and lower voxel approximations of an inclusion composite (Remark
+ * adjusting_A, for Lemma bounds_bounds): on the P-grid of voxels (voxel p
+ * centred at p/P with sides 1/P), `upper` receives the largest and `lower` the
+ * smallest eigenvalue of the phases that meet the voxel with positive measure
+ * (the matrix counts unless one inclusion contains the whole voxel), so that
+ * lower I <= A(x) <= upper I almost everywhere.  `upper` and `lower` are
+ * device buffers of P^d doubles (row-major, P[0] slowest) written on the
+ * plan's stream; the plan supplies d, the stream and scratch for the tables
+ * (it must not be in a batch; its state is otherwise untouched).  Passing them
+ * as `image` and `image_dual` of a voxel material yields guaranteed
+ * upper-upper and lower-lower bounds.  EINVAL for a material that is not an
+ * inclusion description or fails validation; ENOMEM if the tables do not fit.
+ */
+int fftgal_envelope_images(struct fftgal_plan *plan, const fftgal_material *m, const int32_t *P, double *upper,
+                           double *lower);
 
 /* Release the plan (host memory only; the workspace stays the caller's). */
 int fftgal_destroy(struct fftgal_plan *plan);

@@ -1091,6 +1091,83 @@ int solve_entry(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_in
     return worst;
 }
 
+// Validate an inclusion description (eq. inclcomp: SPD phases, boxes with
+// sides in (0, 1], discs of radius in (0, 1/2] in 2D, no overlaps under the
+// periodic minimum image) and build its device table.
+int parse_inclusions(Plan *pl, const fftgal_material *m, int d, std::vector<InclDev> *out) {
+    if (!chol_spd(m->A0, d)) return fail(pl, FFTGAL_EINVAL, "A0 is not symmetric positive definite");
+    const int n = m->n_incl;
+    if (n < 0 || n > 100000) return fail(pl, FFTGAL_EINVAL, "n_incl out of range");
+    if (n > 0 && (!m->shape || !m->center || !m->size || !m->A_in))
+        return fail(pl, FFTGAL_EINVAL, "inclusion arrays must not be NULL");
+    std::vector<InclDev> &inc = *out;
+    inc.assign(n, InclDev{});
+    for (int i = 0; i < n; ++i) {
+        const int s = m->shape[i];
+        if (s != FFTGAL_RECT && s != FFTGAL_CIRC) return fail(pl, FFTGAL_EINVAL, "inclusion %d: bad shape", i);
+        if (s == FFTGAL_CIRC && d != 2) return fail(pl, FFTGAL_EINVAL, "inclusion %d: CIRC needs d = 2", i);
+        inc[i].shape = s;
+        for (int a = 0; a < 3; ++a) {
+            inc[i].c[a] = a < d ? m->center[i * d + a] : 0.0;
+            inc[i].h[a] = a < d ? m->size[i * d + a] : 0.0;
+        }
+        for (int a = 0; a < d; ++a)
+            if (!std::isfinite(inc[i].c[a])) return fail(pl, FFTGAL_EINVAL, "inclusion %d: bad centre", i);
+        if (s == FFTGAL_RECT) {
+            for (int a = 0; a < d; ++a)
+                if (!(inc[i].h[a] > 0.0 && inc[i].h[a] <= 1.0))
+                    return fail(pl, FFTGAL_EINVAL, "inclusion %d: side must be in (0, 1]", i);
+        } else if (!(inc[i].h[0] > 0.0 && inc[i].h[0] <= 0.5)) {
+            return fail(pl, FFTGAL_EINVAL, "inclusion %d: radius must be in (0, 1/2]", i);
+        }
+        if (!chol_spd(m->A_in + (size_t)i * d * d, d))
+            return fail(pl, FFTGAL_EINVAL, "inclusion %d: A_in is not symmetric positive definite", i);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (overlap(d, inc[i].shape, inc[i].c, inc[i].h, inc[j].shape, inc[j].c, inc[j].h))
+                return fail(pl, FFTGAL_EINVAL, "inclusions %d and %d overlap", i, j);
+    return FFTGAL_OK;
+}
+
+// Extreme eigenvalues of a symmetric d x d matrix (cyclic Jacobi rotations in
+// long double; d <= 3).
+void sym_extremes(const double *A, int d, double *hi, double *lo) {
+    long double a[3][3];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) a[i][j] = 0.5L * ((long double)A[i * d + j] + (long double)A[j * d + i]);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        long double off = 0.0L;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) off += a[p][q] * a[p][q];
+        if (off == 0.0L) break;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) {
+                if (a[p][q] == 0.0L) continue;
+                const long double th = (a[q][q] - a[p][p]) / (2.0L * a[p][q]);
+                const long double t = (th >= 0 ? 1.0L : -1.0L) / (fabsl(th) + sqrtl(th * th + 1.0L));
+                const long double c = 1.0L / sqrtl(t * t + 1.0L), sn = t * c;
+                for (int k = 0; k < d; ++k) {  // columns p, q
+                    const long double akp = a[k][p], akq = a[k][q];
+                    a[k][p] = c * akp - sn * akq;
+                    a[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < d; ++k) {  // rows p, q
+                    const long double apk = a[p][k], aqk = a[q][k];
+                    a[p][k] = c * apk - sn * aqk;
+                    a[q][k] = sn * apk + c * aqk;
+                }
+            }
+    }
+    long double h = a[0][0], l = a[0][0];
+    for (int i = 1; i < d; ++i) {
+        h = std::max(h, a[i][i]);
+        l = std::min(l, a[i][i]);
+    }
+    *hi = (double)h;
+    *lo = (double)l;
+}
+
 }  // namespace
 
 namespace {
@@ -1204,37 +1281,9 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
     double *gB = pl->at<double>(pl->Lo.gB64);
     int rc = FFTGAL_OK;
     if (m->kind == FFTGAL_INCLUSIONS) {
-        if (!chol_spd(m->A0, d)) return fail(pl, FFTGAL_EINVAL, "A0 is not symmetric positive definite");
         const int n = m->n_incl;
-        if (n < 0 || n > 100000) return fail(pl, FFTGAL_EINVAL, "n_incl out of range");
-        if (n > 0 && (!m->shape || !m->center || !m->size || !m->A_in))
-            return fail(pl, FFTGAL_EINVAL, "inclusion arrays must not be NULL");
-        std::vector<InclDev> inc(n);
-        for (int i = 0; i < n; ++i) {
-            const int s = m->shape[i];
-            if (s != FFTGAL_RECT && s != FFTGAL_CIRC) return fail(pl, FFTGAL_EINVAL, "inclusion %d: bad shape", i);
-            if (s == FFTGAL_CIRC && d != 2) return fail(pl, FFTGAL_EINVAL, "inclusion %d: CIRC needs d = 2", i);
-            inc[i].shape = s;
-            for (int a = 0; a < 3; ++a) {
-                inc[i].c[a] = a < d ? m->center[i * d + a] : 0.0;
-                inc[i].h[a] = a < d ? m->size[i * d + a] : 0.0;
-            }
-            for (int a = 0; a < d; ++a)
-                if (!std::isfinite(inc[i].c[a])) return fail(pl, FFTGAL_EINVAL, "inclusion %d: bad centre", i);
-            if (s == FFTGAL_RECT) {
-                for (int a = 0; a < d; ++a)
-                    if (!(inc[i].h[a] > 0.0 && inc[i].h[a] <= 1.0))
-                        return fail(pl, FFTGAL_EINVAL, "inclusion %d: side must be in (0, 1]", i);
-            } else if (!(inc[i].h[0] > 0.0 && inc[i].h[0] <= 0.5)) {
-                return fail(pl, FFTGAL_EINVAL, "inclusion %d: radius must be in (0, 1/2]", i);
-            }
-            if (!chol_spd(m->A_in + (size_t)i * d * d, d))
-                return fail(pl, FFTGAL_EINVAL, "inclusion %d: A_in is not symmetric positive definite", i);
-        }
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j)
-                if (overlap(d, inc[i].shape, inc[i].c, inc[i].h, inc[j].shape, inc[j].c, inc[j].h))
-                    return fail(pl, FFTGAL_EINVAL, "inclusions %d and %d overlap", i, j);
+        std::vector<InclDev> inc;
+        if ((rc = parse_inclusions(pl, m, d, &inc))) return rc;
         bool same = true;
         for (int i = 1; i < n && same; ++i)
             for (int k = 0; k < d * d; ++k)
@@ -1353,26 +1402,38 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
         // copy at the start of the U scratch region (re-uploaded per pass,
         // since the transforms overwrite U)
         double *staging = pl->at<double>(pl->vox_u);
-        const double *img = m->image_device ? m->image : staging;
-        auto upload = [&]() -> int {
-            if (!m->image_device)
-                HIPCHECK(pl, hipMemcpyAsync(staging, m->image, (size_t)Ptot * 8, hipMemcpyHostToDevice, pl->stream));
+        // an optional dual image: the primal side uses `image`, the dual side
+        // 1 / image_dual (Lemma bounds_bounds: upper and lower approximations)
+        const bool dual = m->image_dual != nullptr;
+        auto img_of = [&](int which) -> const double * {
+            const double *src = (which == 1 && dual) ? m->image_dual : m->image;
+            return m->image_device ? src : staging;
+        };
+        auto upload = [&](int which) -> int {
+            if (!m->image_device) {
+                const double *src = (which == 1 && dual) ? m->image_dual : m->image;
+                HIPCHECK(pl, hipMemcpyAsync(staging, src, (size_t)Ptot * 8, hipMemcpyHostToDevice, pl->stream));
+            }
             return FFTGAL_OK;
         };
-        if ((rc = upload())) return rc;
         double stats[4];
-        {
-            Timed t(pl, FFTGAL_K_SETUP);
-            HIPCHECK(pl, launch_image_stats(img, Ptot, pl->at<double>(pl->Lo.part_a), pl->at<double>(pl->Lo.gram),
-                                            pl->stream));
+        for (int which = dual ? 1 : 0; which >= 0; --which) {
+            if ((rc = upload(which))) return rc;
+            {
+                Timed t(pl, FFTGAL_K_SETUP);
+                HIPCHECK(pl, launch_image_stats(img_of(which), Ptot, pl->at<double>(pl->Lo.part_a),
+                                                pl->at<double>(pl->Lo.gram), pl->stream));
+            }
+            HIPCHECK(pl, hipMemcpyAsync(stats, pl->at<double>(pl->Lo.gram), sizeof stats, hipMemcpyDeviceToHost,
+                                        pl->stream));
+            HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+            if (stats[2] != 0.0)
+                return fail(pl, FFTGAL_EINVAL, "%.0f voxels %sare not positive finite conductivities", stats[2],
+                            which == 1 ? "of the dual image " : "");
         }
-        HIPCHECK(pl, hipMemcpyAsync(stats, pl->at<double>(pl->Lo.gram), sizeof stats, hipMemcpyDeviceToHost,
-                                    pl->stream));
-        HIPCHECK(pl, hipStreamSynchronize(pl->stream));
-        if (stats[2] != 0.0)
-            return fail(pl, FFTGAL_EINVAL, "%.0f voxels are not positive finite conductivities", stats[2]);
+        const double *img = img_of(0);
         const double vmin = stats[0], vmax = stats[1];
-        const bool two = stats[3] == 0.0;
+        const bool two = stats[3] == 0.0 && !dual;
         std::memset(pl->DA, 0, sizeof pl->DA);
         std::memset(pl->DB, 0, sizeof pl->DB);
         std::memset(pl->A0, 0, sizeof pl->A0);
@@ -1390,7 +1451,8 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
         }
         const int npass = two ? 1 : 2;
         for (int pass = 0; pass < npass; ++pass) {
-            if (pass > 0 && (rc = upload())) return rc;
+            if (pass > 0 && (rc = upload(1))) return rc;
+            if (pass > 0) img = img_of(1);
             const int map = two ? (vmax == vmin ? 3 : 1) : (pass == 0 ? 0 : 2);
             if (pl->gani) {
                 Timed t(pl, FFTGAL_K_SETUP);
@@ -1545,6 +1607,41 @@ int fftgal_warm_start(struct fftgal_plan *fine, struct fftgal_plan *coarse) {
                                           d, fine->nc(k), fine->D.N, coarse->D.N, fine->stream));
             fine->warm[k][a] = true;
         }
+    return FFTGAL_OK;
+}
+
+int fftgal_envelope_images(struct fftgal_plan *pl, const fftgal_material *m, const int32_t *P, double *upper,
+                           double *lower) {
+    if (!pl) return FFTGAL_EINVAL;
+    if (!m || !P || !upper || !lower) return fail(pl, FFTGAL_EINVAL, "NULL argument");
+    if (m->kind != FFTGAL_INCLUSIONS) return fail(pl, FFTGAL_EINVAL, "envelopes are built from inclusions");
+    if (pl->busy) return fail(pl, FFTGAL_ESTATE, "the plan has a solve in a batch");
+    const int d = pl->D.d;
+    for (int a = 0; a < d; ++a)
+        if (P[a] < 1 || P[a] > 100000) return fail(pl, FFTGAL_EINVAL, "P[%d] out of range", a);
+    std::vector<InclDev> inc;
+    int rc = parse_inclusions(pl, m, d, &inc);
+    if (rc) return rc;
+    const int n = (int)inc.size();
+    // table: inclusions, then the extreme eigenvalues of the matrix and of
+    // every inclusion phase
+    std::vector<double> ext(2 * (n + 1));
+    sym_extremes(m->A0, d, &ext[0], &ext[1]);
+    for (int i = 0; i < n; ++i) sym_extremes(m->A_in + (size_t)i * d * d, d, &ext[2 + 2 * i], &ext[3 + 2 * i]);
+    const size_t inc_bytes = align256((size_t)std::max(n, 1) * sizeof(InclDev));
+    if (inc_bytes + ext.size() * 8 > pl->Lo.T2 - pl->Lo.T1)
+        return fail(pl, FFTGAL_ENOMEM, "too many inclusions for this plan's scratch");
+    InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1);
+    double *ext_dev = reinterpret_cast<double *>(pl->ws + pl->Lo.T1 + inc_bytes);
+    if (n > 0)
+        HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
+                                    pl->stream));
+    HIPCHECK(pl, hipMemcpyAsync(ext_dev, ext.data(), ext.size() * 8, hipMemcpyHostToDevice, pl->stream));
+    {
+        Timed t(pl, FFTGAL_K_SETUP);
+        HIPCHECK(pl, launch_envelope(upper, lower, d, P, inc_dev, n, ext_dev, pl->stream));
+    }
+    HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // host tables
     return FFTGAL_OK;
 }
 

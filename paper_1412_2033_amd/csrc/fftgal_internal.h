@@ -183,6 +183,12 @@ struct InclDev {
 hipError_t launch_sample_incl(double *g, int d, const int *M, const InclDev *inc, int n, double w0, hipStream_t s);
 hipError_t launch_sample_voxel(double *g, const double *img, int d, const int *P, const int *M, int map, double vmax,
                                hipStream_t s);
+// Upper / lower voxel images of an inclusion composite (Remark adjusting_A):
+// per voxel (centre p/P, sides 1/P) the largest / smallest eigenvalue of the
+// phases meeting it with positive measure; ext = (hi, lo) of the matrix, then
+// of each inclusion phase.
+hipError_t launch_envelope(double *upper, double *lower, int d, const int *P, const InclDev *inc, int n,
+                           const double *ext, hipStream_t s);
 size_t pencil_lds_bytes(const PencilArgs &a, bool fp64);
 size_t row_lds_bytes(const RowArgs &a, bool fp64);
 // Choose pencils per work-group / row pairs per work-group (and whether the

@@ -641,6 +641,56 @@ __global__ __launch_bounds__(kThreads) void sample_voxel_kernel(double *g, const
     }
 }
 
+// Upper and lower voxel images (Remark adjusting_A).
+__global__ __launch_bounds__(kThreads) void envelope_kernel(double *up, double *lo, int d, int p0, int p1, int p2,
+                                                            const InclDev *inc, int n, const double *ext) {
+    const long total = (long)p0 * p1 * p2;
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)gridDim.x * kThreads) {
+        const int j2 = (int)(idx % p2);
+        const int j1 = (int)((idx / p2) % p1);
+        const int j0 = (int)(idx / ((long)p2 * p1));
+        const int pp[3] = {p0, p1, p2};
+        const double x[3] = {(double)wrapi(j0, p0) / p0, (double)wrapi(j1, p1) / p1, (double)wrapi(j2, p2) / p2};
+        double hi = -HUGE_VAL, lw = HUGE_VAL;
+        bool matrix = true;
+        for (int i = 0; i < n; ++i) {
+            bool meets = true, contains = true;
+            double near2 = 0.0, far2 = 0.0;
+            for (int a = 0; a < d; ++a) {
+                double dc = x[a] - inc[i].c[a];
+                dc = fabs(dc - rint(dc));
+                const double half = 0.5 / pp[a];
+                if (inc[i].shape == 0) {
+                    meets = meets && dc < 0.5 * inc[i].h[a] + half;
+                    contains = contains && dc + half <= 0.5 * inc[i].h[a];
+                } else {
+                    // unfused, so that a voxel exactly on the circle is classified
+                    // as in plain rounded arithmetic
+                    const double nr = fmax(dc - half, 0.0), fr = dc + half;
+                    near2 = __dadd_rn(near2, __dmul_rn(nr, nr));
+                    far2 = __dadd_rn(far2, __dmul_rn(fr, fr));
+                }
+            }
+            if (inc[i].shape != 0) {
+                const double r2 = __dmul_rn(inc[i].h[0], inc[i].h[0]);
+                meets = near2 < r2;
+                contains = far2 <= r2;
+            }
+            if (meets) {
+                hi = fmax(hi, ext[2 + 2 * i]);
+                lw = fmin(lw, ext[3 + 2 * i]);
+            }
+            if (contains) matrix = false;
+        }
+        if (matrix) {
+            hi = fmax(hi, ext[0]);
+            lw = fmin(lw, ext[1]);
+        }
+        up[idx] = hi;
+        lo[idx] = lw;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass: real transforms along the last axis, two rows per complex DFT.
 // ---------------------------------------------------------------------------
@@ -2538,6 +2588,15 @@ hipError_t launch_sample_voxel(double *g, const double *img, int d, const int *P
     const int blocks = (int)std::max<long>(1, std::min<long>(2048, (total + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(sample_voxel_kernel, dim3(blocks), dim3(kThreads), 0, s, g, img, d, p0, p1, p2, m0, m1, m2, map,
                        vmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_envelope(double *upper, double *lower, int d, const int *P, const InclDev *inc, int n,
+                           const double *ext, hipStream_t s) {
+    const int p0 = P[0], p1 = P[1], p2 = d == 3 ? P[2] : 1;
+    const long total = (long)p0 * p1 * p2;
+    const int blocks = (int)std::max<long>(1, std::min<long>(2048, (total + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(envelope_kernel, dim3(blocks), dim3(kThreads), 0, s, upper, lower, d, p0, p1, p2, inc, n, ext);
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", 
            "fftgal_solve_primal", "fftgal_solve_dual", "fftgal_bounds", "fftgal_destroy",
            "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
            "fftgal_warm_start", "fftgal_history", "fftgal_set_timing_classes", "fftgal_set_bound_tol",
-           "fftgal_workspace_bytes_gani", "fftgal_plan_gani", "fftgal_bounds_of",
+           "fftgal_workspace_bytes_gani", "fftgal_plan_gani", "fftgal_bounds_of", "fftgal_envelope_images",
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
@@ -53,6 +53,7 @@ class Material(ctypes.Structure):
         ("P", ctypes.c_int32 * 3),
         ("image", ctypes.POINTER(ctypes.c_double)),
         ("image_device", ctypes.c_int32),
+        ("image_dual", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -119,6 +120,8 @@ def load_library(path=LIB_PATH):
     lib.fftgal_bounds_of.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.fftgal_bounds_of.restype = ctypes.c_int
+    lib.fftgal_envelope_images.argtypes = [vp, ctypes.POINTER(Material), i32p, vp, vp]
+    lib.fftgal_envelope_images.restype = ctypes.c_int
     lib.fftgal_warm_start.argtypes = [vp, vp]
     lib.fftgal_warm_start.restype = ctypes.c_int
     lib.fftgal_history.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
@@ -208,17 +211,26 @@ def material_struct(micro):
         for a in range(d):
             m.P[a] = int(micro["P"][a])
         img = micro["image"]
-        if hasattr(img, "data_ptr") and getattr(img, "is_cuda", False):
-            # a torch float64 tensor already resident on the device
-            if not img.is_contiguous() or str(img.dtype) != "torch.float64":
-                raise ValueError("device image must be a contiguous float64 tensor")
-            keep.append(img)
-            m.image = ctypes.cast(ctypes.c_void_p(img.data_ptr()), ctypes.POINTER(ctypes.c_double))
-            m.image_device = 1
-        else:
-            img = np.ascontiguousarray(img, float)
-            keep.append(img)
-            m.image = img.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        dual = micro.get("image_dual")
+        on_device = hasattr(img, "data_ptr") and getattr(img, "is_cuda", False)
+        if dual is not None and (hasattr(dual, "data_ptr") and getattr(dual, "is_cuda", False)) != on_device:
+            raise ValueError("image and image_dual must both be host arrays or both device tensors")
+
+        def ptr(a):
+            if on_device:
+                # a torch float64 tensor already resident on the device
+                if not a.is_contiguous() or str(a.dtype) != "torch.float64":
+                    raise ValueError("device image must be a contiguous float64 tensor")
+                keep.append(a)
+                return ctypes.cast(ctypes.c_void_p(a.data_ptr()), ctypes.POINTER(ctypes.c_double))
+            a = np.ascontiguousarray(a, float)
+            keep.append(a)
+            return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+        m.image = ptr(img)
+        m.image_device = 1 if on_device else 0
+        if dual is not None:
+            m.image_dual = ptr(dual)
     else:
         raise ValueError(micro["kind"])
     return m, keep
@@ -350,6 +362,19 @@ class Plan:
 
     def read_timing(self):
         return fftgal_read_timing(self.handle)
+
+    def envelope_images(self, micro, P):
+        """Upper and lower voxel images (device float64 tensors of shape P) of an
+        inclusion description, for upper-upper / lower-lower bounds."""
+        import torch
+        P = tuple(int(p) for p in P)
+        up = torch.empty(P, dtype=torch.float64, device=self.workspace.device)
+        lo = torch.empty(P, dtype=torch.float64, device=self.workspace.device)
+        m, keep = material_struct(micro)
+        _check(load_library().fftgal_envelope_images(self.handle, ctypes.byref(m), _i32(P), up.data_ptr(),
+                                                     lo.data_ptr()), self.handle)
+        del keep
+        return up, lo
 
     def bounds_of(self, src):
         """Guaranteed bounds from the fields of the solved Plan `src` (e.g. GaNi)."""
