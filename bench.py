@@ -128,6 +128,8 @@ def main():
                     help="grid of the GaNi section (the paper compares GaNi of order 2N-1; 0: skip)")
     ap.add_argument("--warm-coarse", type=int, default=41,
                     help="coarse N of the warm-start / bound-monitoring section (0: skip)")
+    ap.add_argument("--envelope", type=int, default=1,
+                    help="upper-upper / lower-lower bounds section on an anisotropic cube inclusion (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (profiler counter scale)")
     args = ap.parse_args()
@@ -263,6 +265,8 @@ def main():
         out["warm_start"] = warm_start_bench(fftgal, micro_dev, d, N, M, args.warm_coarse, rtol64, dev)
     if args.gani > 0:
         out["gani"] = gani_bench(fftgal, micro_dev, d, M, args.gani, rtol64, last, dev)
+    if args.envelope:
+        out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.serve > 0:
         out["serving"] = serving_bench(args.serve, args.rtol32)
     if not args.no_cpu_baseline:
@@ -372,6 +376,50 @@ def gani_bench(fftgal, micro_dev, d, P, Ng, rtol, ga_last, dev):
             "apost_upper_diag": diag(up), "apost_lower_diag": diag(lo), "apost_gap": round(gap, 6),
             "ga_N113_upper_diag": diag(ga_last["upper"]), "ga_N113_lower_diag": diag(ga_last["lower"]),
             "ga_N113_gap": round(float(ga_last["gap"]), 6)}
+
+
+def envelope_bench(fftgal, d, N, M, rtol, dev):
+    """Upper-upper / lower-lower bounds (Lemma bounds_bounds) on an anisotropic
+    cube inclusion whose faces cut the voxels: the voxel envelope images on the
+    P = M grid, the Ga bounds of the envelope material (primal with the upper
+    image, dual with the lower), against the Ga bounds of the exact inclusion
+    material on the same plan size."""
+    import numpy as np
+    import torch
+    import synth
+    print("bench: envelope bounds", file=sys.stderr, flush=True)
+    micro = synth.cube_inclusion_aniso(0.45, 5)
+    plan = fftgal.Plan(d, N, "fp64", device=dev, P=M)
+    try:
+        times = {}
+        for rep in range(2):  # the second repetition is timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            up, lo = plan.envelope_images(micro, M)
+            torch.cuda.synchronize()
+            times["images_s"] = time.perf_counter() - t0
+            env = plan.run({"d": d, "kind": "voxels", "P": M, "image": up, "image_dual": lo}, rtol=rtol)
+            torch.cuda.synchronize()
+            times["envelope_to_bounds_s"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            exact = plan.run(micro, rtol=rtol)
+            torch.cuda.synchronize()
+            times["exact_to_bounds_s"] = time.perf_counter() - t0
+        cut = int(torch.count_nonzero(up != lo).item())
+    finally:
+        plan.close()
+
+    def diag(m):
+        return [round(float(v), 6) for v in np.diag(m)]
+
+    scale = np.abs(exact["upper"]).max()
+    return {"microstructure": "cube inclusion, side 0.45, anisotropic SPD phases (seed 5)", "P": M[0], "N": N[0],
+            "rtol": rtol, **{k: round(v, 4) for k, v in times.items()}, "cut_voxels": cut,
+            "envelope_upper_diag": diag(env["upper"]), "envelope_lower_diag": diag(env["lower"]),
+            "exact_upper_diag": diag(exact["upper"]), "exact_lower_diag": diag(exact["lower"]),
+            "envelope_gap": round(float(env["gap"]), 6), "exact_gap": round(float(exact["gap"]), 6),
+            "brackets_exact": bool(np.min(np.linalg.eigvalsh(env["upper"] - exact["upper"])) >= -1e-10 * scale and
+                                   np.min(np.linalg.eigvalsh(exact["lower"] - env["lower"])) >= -1e-10 * scale)}
 
 
 def serving_bench(n, rtol, seed=4):

@@ -351,50 +351,32 @@ __device__ __forceinline__ int posmod(int k, int n) {
 // is real exactly when each c_a is Hermitian.  Returns 0 at k = 0.
 template <typename T>
 __device__ __forceinline__ int basis(int d, int kind, int k1, int k2, int k3, T t[2][3]) {
+    // straight-line code (selects, no branches): written per branch, the
+    // compiler keeps the partially written rows of t on the stack
     const T a = T(k1), b = T(k2), c = T(d == 3 ? k3 : 0);
     const T nn = a * a + b * b + c * c;
-    if (nn == T(0)) return 0;
-    const T inv = T(1) / sqrt(nn);
+    const T inv = nn == T(0) ? T(0) : T(1) / sqrt(nn);
     const T h1 = a * inv, h2 = b * inv, h3 = c * inv;
-    if (kind == KIND_E) {
-        t[0][0] = h1;
-        t[0][1] = h2;
-        t[0][2] = h3;
-        return 1;
-    }
-    if (d == 2) {
-        t[0][0] = -h2;
-        t[0][1] = h1;
-        t[0][2] = T(0);
-        return 1;
-    }
     const int ab1 = k1 < 0 ? -k1 : k1, ab2 = k2 < 0 ? -k2 : k2, ab3 = k3 < 0 ? -k3 : k3;
-    T u1, u2, u3;
-    if (ab1 <= ab2 && ab1 <= ab3) {  // k x e_1
-        u1 = T(0);
-        u2 = c;
-        u3 = -b;
-    } else if (ab2 <= ab3) {  // k x e_2
-        u1 = -c;
-        u2 = T(0);
-        u3 = a;
-    } else {  // k x e_3
-        u1 = b;
-        u2 = -a;
-        u3 = T(0);
-    }
-    const T un = T(1) / sqrt(u1 * u1 + u2 * u2 + u3 * u3);
+    const bool x1 = ab1 <= ab2 && ab1 <= ab3;  // k x e_1
+    const bool x2 = !x1 && ab2 <= ab3;         // k x e_2, else k x e_3
+    T u1 = x1 ? T(0) : x2 ? -c : b;
+    T u2 = x1 ? c : x2 ? T(0) : -a;
+    T u3 = x1 ? -b : x2 ? a : T(0);
+    const T uu = u1 * u1 + u2 * u2 + u3 * u3;
+    const T un = uu == T(0) ? T(0) : T(1) / sqrt(uu);
     u1 *= un;
     u2 *= un;
     u3 *= un;
     const T s = (k1 != 0) ? (k1 > 0 ? T(1) : T(-1)) : (k2 != 0) ? (k2 > 0 ? T(1) : T(-1)) : (k3 > 0 ? T(1) : T(-1));
-    t[0][0] = u1;
-    t[0][1] = u2;
-    t[0][2] = u3;
+    const bool primal = kind == KIND_E, two = d == 2;
+    t[0][0] = primal ? h1 : two ? -h2 : u1;
+    t[0][1] = primal ? h2 : two ? h1 : u2;
+    t[0][2] = primal ? h3 : two ? T(0) : u3;
     t[1][0] = s * (h2 * u3 - h3 * u2);
     t[1][1] = s * (h3 * u1 - h1 * u3);
     t[1][2] = s * (h1 * u2 - h2 * u1);
-    return 2;
+    return nn == T(0) ? 0 : (primal || two) ? 1 : 2;
 }
 
 __device__ __forceinline__ double sinc_pi(double x) {
