@@ -125,7 +125,8 @@ struct RowArgs {
     int d;
     int mode;
     int RP;           // row pairs per work-group
-    int fast;         // set by configure_row (1 specialised, 2 specialised isotropic)
+    int fast;         // set by configure_row (1 specialised, 2 specialised isotropic, 3 isotropic
+                      // with all loads of a work-group staged in LDS)
     int iso;          // A0 and D are multiples of the identity
     const void *g;    // material field g (M^d, precision of the kernel)
     double A0[9];     // A(x) = A0 + g(x) D

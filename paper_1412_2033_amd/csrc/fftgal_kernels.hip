@@ -1986,6 +1986,234 @@ __global__ __launch_bounds__(split_nt(FI)) void row_iso_split(const RowArgs *__r
     }
 }
 
+// Variant for the row lengths of Ga plans (half-spectrum rows of at most
+// (N + 3) / 4 points: order (N + 1) / 2 on the grid N).  Every global load of
+// a work-group -- its half-spectrum rows, the material rows of its pairs and
+// the last-stage twiddles -- is issued at once and parked in LDS, so a
+// work-group waits for memory once.  Work-groups own whole row pairs (all D
+// components of each, pair-major), so each material row is fetched once.
+// Lanes beyond the last transform repeat the work of the last one (same
+// inputs, same instructions, so their LDS writes store the values already
+// there) instead of branching around every LDS access; only the final stores
+// are guarded.  The transform is that of row_iso_split; per-transform LDS
+// rows are padded so that the stride exchanges of neighbouring transforms
+// fall into different banks.
+constexpr int staged_nhc(int n) { return (n + 3) / 4; }
+constexpr int staged_nt(int fi, int d) {
+    const int tq = kFastSched[fi].n / kFastSched[fi].r[0];
+    int best = 128, bu = 0;  // utilisation in 1/1024
+    for (int nt = 128; nt <= 256; nt += 64) {
+        const int tb = (nt / tq) / d * d;
+        const int u = tb * tq * 1024 / nt;
+        if (u > bu) {
+            bu = u;
+            best = nt;
+        }
+    }
+    return best;
+}
+constexpr int staged_tb(int fi, int d) {
+    return (staged_nt(fi, d) / (kFastSched[fi].n / kFastSched[fi].r[0])) / d * d;
+}
+// LDS row stride of one transform (in reals): 240 = 16 (mod 32) for n = 225
+constexpr int staged_stride(int fi) { return kFastSched[fi].n == 225 ? 240 : kFastSched[fi].n; }
+// compact twiddle table: w_n^k for k = q i (1 <= q < r, 0 <= i < n / r)
+constexpr int staged_ntp(int fi) {
+    return (kFastSched[fi].r[0] - 1) * (kFastSched[fi].n / kFastSched[fi].r[0] - 1) + 1;
+}
+template <typename T>
+constexpr size_t staged_lds(int fi, int d) {
+    const int n = kFastSched[fi].n, tb = staged_tb(fi, d);
+    const size_t work = std::max(sizeof(Vt<T>) * tb * 2 * (staged_nhc(n) + 1), sizeof(T) * tb * staged_stride(fi));
+    const size_t gm = sizeof(T) * (tb / d) * 2 * n;
+    return (gm + 15) / 16 * 16 + sizeof(Vt<T>) * staged_ntp(fi) + work;
+}
+
+template <typename T, int FI, int D>
+__global__ __launch_bounds__(staged_nt(FI, D)) void row_iso_staged(const RowArgs *__restrict__ ra,
+                                                                  const int *__restrict__ woff, int np) {
+    using V = Vt<T>;
+    constexpr int N = kFastSched[FI].n;
+    constexpr int R = kFastSched[FI].r[0];
+    constexpr int TQ = N / R;
+    constexpr int TB = staged_tb(FI, D);
+    constexpr int PW = TB / D;  // row pairs per work-group
+    constexpr int NT = staged_nt(FI, D);
+    constexpr int NHC = staged_nhc(N);
+    constexpr int SR = NHC + 1;  // staged row: NHC points and a zero slot
+    constexpr int S = staged_stride(FI);
+    constexpr int NTP = staged_ntp(FI);
+    constexpr int OFFL = sched_off(FI, 1);
+    static_assert(kFastSched[FI].nst == 2 && kFastSched[FI].r[1] == R, "two-stage palindromic schedule");
+    static_assert(TB * TQ <= NT && TB % D == 0 && NT - TB * TQ <= TQ, "work-group shape");
+    int lb;
+    const RowArgs &a = ra[find_problem(woff, np, &lb)];
+    if (a.status != nullptr && a.status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *Gs = reinterpret_cast<T *>(smem_raw);                                           // [2 PW][N] material
+    V *tp = reinterpret_cast<V *>(smem_raw + (sizeof(T) * PW * 2 * N + 15) / 16 * 16);  // [NTP] twiddles
+    V *St = tp + NTP;                      // [TB][2][SR] staged half-spectrum rows ...
+    T *Bf = reinterpret_cast<T *>(St);     // ... later [TB][S], one part at a time
+    const int nh = a.Nh_row;
+    const int npairs = (a.nrows + 1) / 2;
+    const int pr0 = lb * PW;
+    const int npr = min(PW, npairs - pr0);
+    const int nrow_wg = min(2 * npr, a.nrows - 2 * pr0);  // rows of this work-group
+    // ---- all global loads in flight together, then parked in LDS
+    constexpr int GP = (PW * 2 * N + NT - 1) / NT;
+    constexpr int SP = (TB * 2 * SR + NT - 1) / NT;
+    constexpr int NW = (R - 1) * TQ;  // stage-1 twiddles
+    constexpr int WP = (NW + NT - 1) / NT;
+    const auto *gsrc = gbl(reinterpret_cast<const T *>(a.g) + (long)2 * pr0 * N);
+    const auto *dsrc = gbl(reinterpret_cast<const V *>(a.data));
+    const auto *twg = gbl(reinterpret_cast<const V *>(a.tw) + a.f.twoff[0] + OFFL);
+    const int gcnt = nrow_wg * N;
+    T gv[GP];
+    T sx[SP], sy[SP];
+    T wx[WP], wy[WP];
+#pragma unroll
+    for (int t = 0; t < GP; ++t) {
+        const int idx = threadIdx.x + t * NT;
+        gv[t] = gsrc[idx < gcnt ? idx : 0];
+    }
+#pragma unroll
+    for (int t = 0; t < SP; ++t) {
+        const int idx = threadIdx.x + t * NT;
+        const int row = idx / SR;  // staged row: transform row / 2, second row of the pair row % 2
+        const int k = idx - row * SR;
+        const int tt = row >> 1;
+        const int lp = tt / D;
+        const bool ok = idx < TB * 2 * SR && k < nh && lp < npr && 2 * lp + (row & 1) < nrow_wg;
+        const long off = (long)(tt - lp * D) * a.cs + (long)(2 * (pr0 + lp) + (row & 1)) * nh + k;
+        const V v = gld(dsrc + (ok ? off : 0L));
+        sx[t] = ok ? v.x : T(0);
+        sy[t] = ok ? v.y : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+        const int idx = threadIdx.x + t * NT;
+        const V v = gld(twg + (idx < NW ? idx : 0));
+        wx[t] = v.x;
+        wy[t] = v.y;
+    }
+#pragma unroll
+    for (int t = 0; t < GP; ++t) {
+        const int idx = threadIdx.x + t * NT;
+        if (idx < PW * 2 * N) Gs[idx] = idx < gcnt ? gv[t] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < SP; ++t) {
+        const int idx = threadIdx.x + t * NT;
+        if (idx < TB * 2 * SR) St[idx] = mk<T>(sx[t], sy[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+        // stage-1 entry (q - 1) TQ + i is w_N^(q i); equal products hold equal values
+        const int idx = threadIdx.x + t * NT;
+        const int q = idx / TQ + 1;
+        if (idx < NW) tp[q * (idx - (q - 1) * TQ)] = mk<T>(wx[t], wy[t]);
+    }
+    __syncthreads();
+    // ---- packed Hermitian extension of the two rows of this thread's transform
+    const int tr = threadIdx.x / TQ;
+    const int tl = tr < TB ? tr : TB - 1;  // lanes past the last transform repeat it
+    const int i = threadIdx.x - tr * TQ;
+    const int lp = tl / D;                 // pair within the work-group
+    const int c = tl - lp * D;             // component
+    const bool owner = tr < TB && lp < npr;
+    V u[R];
+    {
+        const V *s1 = St + tl * 2 * SR;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            // z = u1 + i u2 at p < nh, conj(u1) + i conj(u2) at p > N - nh,
+            // (u1.x, u2.x) at p = 0, zero between (the zero slot)
+            const int pos = i + q * TQ;
+            const bool low = pos < nh;
+            const int kx = low ? pos : (pos > N - nh ? N - pos : NHC);
+            const V u1 = s1[kx];
+            const V u2 = s1[SR + kx];
+            const T sg = low ? (pos == 0 ? T(0) : T(1)) : T(-1);
+            u[q] = mk<T>(u1.x - sg * u2.y, u2.x + sg * u1.y);
+        }
+    }
+    __syncthreads();  // St is reused as Bf
+    T *Bt = Bf + tl * S;
+    auto xchg = [&](V *w, auto wp, auto rp) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) Bt[wp(q)] = w[q].x;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q) w[q].x = Bt[rp(q)];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q) Bt[wp(q)] = w[q].y;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q) w[q].y = Bt[rp(q)];
+        __syncthreads();
+    };
+    auto stage_out = [&](int q) { return i * R + q; };
+    auto own = [&](int q) { return i + q * TQ; };
+    dftn<T, R>(u, T(1));
+    xchg(u, stage_out, own);
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+        V w = tp[q * i];
+        w.y = -w.y;
+        u[q] = cmul(u[q], w);
+    }
+    dftn<T, R>(u, T(1));
+    {
+        const T a0 = T(a.A0[0]);
+        const T da = T(a.D[0]);
+        const T *g1 = Gs + 2 * lp * N + i;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            u[q].x *= a0 + g1[q * TQ] * da;
+            u[q].y *= a0 + g1[N + q * TQ] * da;
+        }
+    }
+    dftn<T, R>(u, T(-1));
+    xchg(u, stage_out, own);
+#pragma unroll
+    for (int q = 1; q < R; ++q) u[q] = cmul(u[q], tp[q * i]);
+    dftn<T, R>(u, T(-1));
+    // Hermitian unpacking (as in row_iso_split)
+    constexpr int QH = ((N + 1) / 2 + TQ - 1) / TQ;
+    V m[QH];
+    auto partner = [&](int q) {
+        const int p = i + q * TQ;
+        return p == 0 ? 0 : N - p;
+    };
+#pragma unroll
+    for (int q = 0; q < R; ++q) Bt[own(q)] = u[q].x;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QH; ++q) m[q].x = Bt[partner(q)];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) Bt[own(q)] = u[q].y;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QH; ++q) m[q].y = Bt[partner(q)];
+    if (!owner) return;
+    const int r1 = 2 * (pr0 + lp);
+    const bool v2 = 2 * lp + 1 < nrow_wg;
+    auto *row1 = gbl(reinterpret_cast<V *>(a.data) + (long)c * a.cs + (long)r1 * nh);
+    const T half = T(a.scale) * T(0.5);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        const int p = i + q * TQ;
+        if (p < nh) {
+            const V w = u[q];
+            const V wm = m[q];
+            gst(row1 + p, mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half));
+            if (v2) gst(row1 + nh + p, mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half));
+        }
+    }
+}
+
 template <typename T, int FI, int D>
 void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
@@ -2055,6 +2283,27 @@ void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, h
             const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + N);
             hipLaunchKernelGGL((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
         }
+    }
+}
+
+template <typename T, int FI>
+void launch_row_staged_t(int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    if constexpr (palindromic(FI) && kFastSched[FI].nst == 2) {
+        if (d == 3)
+            hipLaunchKernelGGL((row_iso_staged<T, FI, 3>), dim3(total), dim3(staged_nt(FI, 3)), staged_lds<T>(FI, 3),
+                               s, args, woff, np);
+        else
+            hipLaunchKernelGGL((row_iso_staged<T, FI, 2>), dim3(total), dim3(staged_nt(FI, 2)), staged_lds<T>(FI, 2),
+                               s, args, woff, np);
+    }
+}
+
+template <typename T>
+void launch_row_staged(int fi, int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+    switch (fi) {
+        case 0: launch_row_staged_t<T, 0>(d, args, woff, np, total, s); break;
+        case 2: launch_row_staged_t<T, 2>(d, args, woff, np, total, s); break;
+        default: break;
     }
 }
 
@@ -2371,6 +2620,11 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     const size_t es = fp64 ? 16 : 8;
+    if (a.fast == 3) {
+        const int fi = fast_index(a.f.n);
+        if (fi == 0) return fp64 ? staged_lds<double>(0, a.d) : staged_lds<float>(0, a.d);
+        return fp64 ? staged_lds<double>(2, a.d) : staged_lds<float>(2, a.d);
+    }
     if (a.fast == 2) {
         const int fi = fast_index(a.f.n);
         if (fi >= 0 && kFastSched[fi].nst == 2) return es / 2 * (size_t)a.RP * a.f.n + es * a.f.n;
@@ -2389,6 +2643,7 @@ int pencil_grid_x(const PencilArgs &a) { return a.B > 0 ? (a.nb + a.B - 1) / a.B
 int row_grid(const RowArgs &a) {
     if (a.RP < 1) return 0;
     const int pairs = (a.nrows + 1) / 2;
+    if (a.fast == 3) return (pairs + a.RP / a.d - 1) / (a.RP / a.d);
     return a.fast == 2 ? (a.d * pairs + a.RP - 1) / a.RP : (pairs + a.RP - 1) / a.RP;
 }
 
@@ -2419,6 +2674,14 @@ void configure_row(RowArgs &r, bool fp64) {
     bool ok = fi >= 0 && (r.mode == ROW_OPER || r.mode == ROW_RHS) && r.ncomp == r.d && (r.d == 2 || r.d == 3) &&
               r.f.nst == kFastSched[fi].nst && r.Nh_row <= (r.f.n + 1) / 2;
     for (int s = 0; ok && s < r.f.nst; ++s) ok = r.f.radix[s] == kFastSched[fi].r[s];
+    // the staged variant pays in FP64 (three waves per SIMD either way); in
+    // FP32 its register count would cost occupancy
+    if (ok && fp64 && r.iso && r.mode == ROW_OPER && palindromic(fi) && kFastSched[fi].nst == 2 &&
+        r.Nh_row <= staged_nhc(r.f.n)) {
+        r.fast = 3;
+        r.RP = fi == 0 ? staged_tb(0, r.d) : staged_tb(2, r.d);
+        return;
+    }
     if (ok && r.iso && r.mode == ROW_OPER && palindromic(fi)) {
         r.fast = 2;
         r.RP = iso_tb(fi);
@@ -2492,6 +2755,14 @@ hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int
     if (proto.mode == ROW_GRAM) {
         if (!fp64) return hipErrorInvalidValue;
         launch_gram_fast(fi, proto.d, args, woff, np, total, s);
+        return hipGetLastError();
+    }
+    if (proto.fast == 3) {
+        if (!(fi == 0 || fi == 2) || proto.mode != ROW_OPER) return hipErrorInvalidValue;
+        if (fp64)
+            launch_row_staged<double>(fi, proto.d, args, woff, np, total, s);
+        else
+            launch_row_staged<float>(fi, proto.d, args, woff, np, total, s);
         return hipGetLastError();
     }
     if (proto.fast == 2) {
