@@ -2029,8 +2029,10 @@ constexpr size_t staged_lds(int fi, int d) {
     return (gm + 15) / 16 * 16 + sizeof(Vt<T>) * staged_ntp(fi) + work;
 }
 
+// three waves per SIMD: what four work-groups of LDS per CU allow in FP64
 template <typename T, int FI, int D>
-__global__ __launch_bounds__(staged_nt(FI, D)) void row_iso_staged(const RowArgs *__restrict__ ra,
+__global__ __launch_bounds__(staged_nt(FI, D)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1)))
+void row_iso_staged(const RowArgs *__restrict__ ra,
                                                                   const int *__restrict__ woff, int np) {
     using V = Vt<T>;
     constexpr int N = kFastSched[FI].n;
@@ -2121,11 +2123,20 @@ __global__ __launch_bounds__(staged_nt(FI, D)) void row_iso_staged(const RowArgs
     const int lp = tl / D;                 // pair within the work-group
     const int c = tl - lp * D;             // component
     const bool owner = tr < TB && lp < npr;
+    // Points i + q TQ of this thread that lie in the zero band for every
+    // thread (NHC <= q TQ and q TQ + TQ - 1 <= N - NHC) are zero on input and
+    // not needed on output: with the band known at compile time the compiler
+    // drops their arithmetic from the first inverse and the last forward stage.
+    auto zband = [](int q) { return q * TQ >= NHC && q * TQ + TQ - 1 <= N - NHC; };
     V u[R];
     {
         const V *s1 = St + tl * 2 * SR;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
+            if (zband(q)) {
+                u[q] = mk<T>(T(0), T(0));
+                continue;
+            }
             // z = u1 + i u2 at p < nh, conj(u1) + i conj(u2) at p > N - nh,
             // (u1.x, u2.x) at p = 0, zero between (the zero slot)
             const int pos = i + q * TQ;
@@ -2179,21 +2190,27 @@ __global__ __launch_bounds__(staged_nt(FI, D)) void row_iso_staged(const RowArgs
 #pragma unroll
     for (int q = 1; q < R; ++q) u[q] = cmul(u[q], tp[q * i]);
     dftn<T, R>(u, T(-1));
-    // Hermitian unpacking (as in row_iso_split)
-    constexpr int QH = ((N + 1) / 2 + TQ - 1) / TQ;
+    // Hermitian unpacking: outputs p < nh <= NHC pair with N - p > N - NHC,
+    // so only the points that can lie there go through LDS
+    constexpr int QH = (NHC + TQ - 1) / TQ;
     V m[QH];
     auto partner = [&](int q) {
         const int p = i + q * TQ;
         return p == 0 ? 0 : N - p;
     };
+    auto high = [](int q) { return q * TQ + TQ - 1 > N - NHC; };
 #pragma unroll
-    for (int q = 0; q < R; ++q) Bt[own(q)] = u[q].x;
+    for (int q = 0; q < R; ++q)
+        if (high(q)) Bt[own(q)] = u[q].x;
+    Bt[own(0)] = u[0].x;  // p = 0 pairs with itself
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < QH; ++q) m[q].x = Bt[partner(q)];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < R; ++q) Bt[own(q)] = u[q].y;
+    for (int q = 0; q < R; ++q)
+        if (high(q)) Bt[own(q)] = u[q].y;
+    Bt[own(0)] = u[0].y;
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < QH; ++q) m[q].y = Bt[partner(q)];
@@ -2676,7 +2693,7 @@ void configure_row(RowArgs &r, bool fp64) {
     for (int s = 0; ok && s < r.f.nst; ++s) ok = r.f.radix[s] == kFastSched[fi].r[s];
     // the staged variant pays in FP64 (three waves per SIMD either way); in
     // FP32 its register count would cost occupancy
-    if (ok && fp64 && r.iso && r.mode == ROW_OPER && palindromic(fi) && kFastSched[fi].nst == 2 &&
+    if (ok && r.iso && r.mode == ROW_OPER && palindromic(fi) && kFastSched[fi].nst == 2 &&
         r.Nh_row <= staged_nhc(r.f.n)) {
         r.fast = 3;
         r.RP = fi == 0 ? staged_tb(0, r.d) : staged_tb(2, r.d);
