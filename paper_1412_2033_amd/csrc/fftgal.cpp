@@ -30,7 +30,6 @@ constexpr size_t kArgSlot = 1024;    // bytes per argument slot (>= sizeof Penci
 constexpr int kIterSlots = 8;
 constexpr int kRingSlots = 32;
 constexpr size_t kArgsBytes = kArgSlot * (2 + kIterSlots + kRingSlots);
-constexpr int kUpdateBlocks = 1024;  // fixed grid of the CG update kernel
 constexpr double kFloor64 = 1e-14;   // residual floor relative to ||A_M E|| (FP64)
 constexpr double kFloor32 = 1e-7;    // (FP32 iterations)
 
@@ -176,7 +175,7 @@ Layout make_layout(const Dims &D, int precision) {
     L.gB32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.Mtot * 4 : 0);
     // partial sums: the largest work-group count of any reducing launch
     // (worst case: one pencil / one row pair per work-group)
-    long nwg = kUpdateBlocks;
+    long nwg = update_blocks(2L * D.Ns);  // CG update of at most two coefficient components
     const long nbz = (d == 3) ? (long)D.N[1] * D.Nh : D.Nh;
     const long nrows = (d == 3) ? (long)D.M[0] * D.M[1] : D.M[0];
     nwg = std::max<long>(nwg, nbz);

@@ -2527,33 +2527,54 @@ __global__ __launch_bounds__(kThreads) void cg_check_multi_kernel(const CgItem *
     if (it.mirror != nullptr && threadIdx.x == 0) *it.mirror = *st;
 }
 
+// CG update: kUpdPer elements per thread in one pass (the grid, and with it
+// the reduction order, depends only on the problem size)
+constexpr int kUpdPer = 2;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs *__restrict__ ua,
                                                                    const int *__restrict__ woff, int np) {
+    constexpr int U = kUpdPer;
     int lb;
     const UpdArgs &a = ua[find_problem(woff, np, &lb)];
     if (a.st->done) return;
-    Vt<T> *x = reinterpret_cast<Vt<T> *>(a.x);
-    Vt<T> *r = reinterpret_cast<Vt<T> *>(a.r);
-    const Vt<T> *p = reinterpret_cast<const Vt<T> *>(a.p);
-    const Vt<T> *q = reinterpret_cast<const Vt<T> *>(a.q);
+    auto *x = gbl(reinterpret_cast<Vt<T> *>(a.x));
+    auto *r = gbl(reinterpret_cast<Vt<T> *>(a.r));
+    const auto *p = gbl(reinterpret_cast<const Vt<T> *>(a.p));
+    const auto *q = gbl(reinterpret_cast<const Vt<T> *>(a.q));
     const T alpha = T(a.st->alpha);
+    const int npc = (int)a.n_per_comp;
+    const int total = npc * a.nc;
+    // all loads of the thread's U elements in flight together
+    T xx[U], xy[U], rx[U], ry[U], px[U], py[U], qx[U], qy[U];
+    long off[U];
+    int ii[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const int idx = lb * (kThreads * U) + j * kThreads + threadIdx.x;
+        const int c = idx / npc;
+        ii[j] = idx - c * npc;
+        off[j] = idx < total ? (long)c * a.cs + ii[j] : -1L;
+        const long o = off[j] < 0 ? 0L : off[j];
+        const Vt<T> xv = gld(x + o), rv = gld(r + o), pv = gld(p + o), qv = gld(q + o);
+        xx[j] = xv.x;
+        xy[j] = xv.y;
+        rx[j] = rv.x;
+        ry[j] = rv.y;
+        px[j] = pv.x;
+        py[j] = pv.y;
+        qx[j] = qv.x;
+        qy[j] = qv.y;
+    }
     double part = 0.0;
-    const long total = a.n_per_comp * a.nc;
-    for (long idx = lb * (long)kThreads + threadIdx.x; idx < total; idx += (long)a.nblocks * kThreads) {
-        const long c = idx / a.n_per_comp;
-        const long i = idx - c * a.n_per_comp;
-        const long off = c * a.cs + i;
-        Vt<T> xv = x[off], rv = r[off];
-        const Vt<T> pv = p[off], qv = q[off];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        rv.x -= alpha * qv.x;
-        rv.y -= alpha * qv.y;
-        x[off] = xv;
-        r[off] = rv;
-        const double w = (i % a.Nh) == 0 ? 1.0 : 2.0;
-        part += w * ((double)rv.x * rv.x + (double)rv.y * rv.y);
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        if (off[j] < 0) continue;
+        const T nxx = xx[j] + alpha * px[j], nxy = xy[j] + alpha * py[j];
+        const T nrx = rx[j] - alpha * qx[j], nry = ry[j] - alpha * qy[j];
+        gst(x + off[j], mk<T>(nxx, nxy));
+        gst(r + off[j], mk<T>(nrx, nry));
+        const double w = (ii[j] % a.Nh) == 0 ? 1.0 : 2.0;
+        part += w * ((double)nrx * nrx + (double)nry * nry);
     }
     const double s = block_sum(part);
     if (threadIdx.x == 0) a.partial[lb] = s;
@@ -2752,7 +2773,7 @@ hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s) {
 }
 
 int pencil_grid(const PencilArgs &a, int nouter) { return pencil_grid_x(a) * nouter; }
-int update_blocks(long n) { return (int)std::max<long>(1, std::min<long>(1024, (n + kThreads - 1) / kThreads)); }
+int update_blocks(long n) { return (int)std::max<long>(1, (n + (long)kThreads * kUpdPer - 1) / ((long)kThreads * kUpdPer)); }
 
 hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, const int *woff, int np, int total,
                                bool fp64, hipStream_t s) {
