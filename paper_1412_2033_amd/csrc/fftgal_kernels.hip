@@ -1992,18 +1992,26 @@ __global__ __launch_bounds__(split_nt(FI)) void row_iso_split(const RowArgs *__r
 // the last-stage twiddles -- is issued at once and parked in LDS, so a
 // work-group waits for memory once.  Work-groups own whole row pairs (all D
 // components of each, pair-major), so each material row is fetched once.
-// Lanes beyond the last transform repeat the work of the last one (same
-// inputs, same instructions, so their LDS writes store the values already
-// there) instead of branching around every LDS access; only the final stores
-// are guarded.  The transform is that of row_iso_split; per-transform LDS
-// rows are padded so that the stride exchanges of neighbouring transforms
-// fall into different banks.
+// Lanes beyond the last transform repeat the work of the last one, and the
+// spare lane of a 16-lane group that of the group's 15th (same inputs, same
+// instructions, so their LDS writes store the values already there) instead
+// of branching around every LDS access; only the final stores are guarded.
+// The transform is that of row_iso_split; per-transform LDS rows are padded
+// so that the stride exchanges of neighbouring transforms fall into
+// different banks.
 constexpr int staged_nhc(int n) { return (n + 3) / 4; }
+// lanes per transform: 15 butterflies get an aligned group of 16 lanes (the
+// last lane repeats the 15th), so that the lanes of one LDS access pass belong
+// to whole transforms
+constexpr int staged_lg(int fi) {
+    const int tq = kFastSched[fi].n / kFastSched[fi].r[0];
+    return tq == 15 ? 16 : tq;
+}
 constexpr int staged_nt(int fi, int d) {
     const int tq = kFastSched[fi].n / kFastSched[fi].r[0];
     int best = 128, bu = 0;  // utilisation in 1/1024
     for (int nt = 128; nt <= 256; nt += 64) {
-        const int tb = (nt / tq) / d * d;
+        const int tb = (nt / staged_lg(fi)) / d * d;
         const int u = tb * tq * 1024 / nt;
         if (u > bu) {
             bu = u;
@@ -2012,15 +2020,12 @@ constexpr int staged_nt(int fi, int d) {
     }
     return best;
 }
-constexpr int staged_tb(int fi, int d) {
-    return (staged_nt(fi, d) / (kFastSched[fi].n / kFastSched[fi].r[0])) / d * d;
-}
+constexpr int staged_tb(int fi, int d) { return (staged_nt(fi, d) / staged_lg(fi)) / d * d; }
 // LDS row stride of one transform (in reals): 240 = 16 (mod 32) for n = 225
 constexpr int staged_stride(int fi) { return kFastSched[fi].n == 225 ? 240 : kFastSched[fi].n; }
-// compact twiddle table: w_n^k for k = q i (1 <= q < r, 0 <= i < n / r)
-constexpr int staged_ntp(int fi) {
-    return (kFastSched[fi].r[0] - 1) * (kFastSched[fi].n / kFastSched[fi].r[0] - 1) + 1;
-}
+// twiddles of the second stage: w_n^(q i) at (q - 1) n / r + i (1 <= q < r,
+// 0 <= i < n / r), so that the lanes of a transform read consecutive entries
+constexpr int staged_ntp(int fi) { return (kFastSched[fi].r[0] - 1) * (kFastSched[fi].n / kFastSched[fi].r[0]); }
 template <typename T>
 constexpr size_t staged_lds(int fi, int d) {
     const int n = kFastSched[fi].n, tb = staged_tb(fi, d);
@@ -2046,14 +2051,15 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     constexpr int S = staged_stride(FI);
     constexpr int NTP = staged_ntp(FI);
     constexpr int OFFL = sched_off(FI, 1);
+    constexpr int LG = staged_lg(FI);
     static_assert(kFastSched[FI].nst == 2 && kFastSched[FI].r[1] == R, "two-stage palindromic schedule");
-    static_assert(TB * TQ <= NT && TB % D == 0 && NT - TB * TQ <= TQ, "work-group shape");
+    static_assert(TB * LG <= NT && TB % D == 0 && NT - TB * LG <= LG && LG >= TQ, "work-group shape");
     int lb;
     const RowArgs &a = ra[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
     extern __shared__ unsigned char smem_raw[];
     T *Gs = reinterpret_cast<T *>(smem_raw);                                           // [2 PW][N] material
-    V *tp = reinterpret_cast<V *>(smem_raw + (sizeof(T) * PW * 2 * N + 15) / 16 * 16);  // [NTP] twiddles
+    V *tp = reinterpret_cast<V *>(smem_raw + (sizeof(T) * PW * 2 * N + 15) / 16 * 16);  // [NTP] stage twiddles
     V *St = tp + NTP;                      // [TB][2][SR] staged half-spectrum rows ...
     T *Bf = reinterpret_cast<T *>(St);     // ... later [TB][S], one part at a time
     const int nh = a.Nh_row;
@@ -2110,19 +2116,18 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     }
 #pragma unroll
     for (int t = 0; t < WP; ++t) {
-        // stage-1 entry (q - 1) TQ + i is w_N^(q i); equal products hold equal values
         const int idx = threadIdx.x + t * NT;
-        const int q = idx / TQ + 1;
-        if (idx < NW) tp[q * (idx - (q - 1) * TQ)] = mk<T>(wx[t], wy[t]);
+        if (idx < NW) tp[idx] = mk<T>(wx[t], wy[t]);
     }
     __syncthreads();
     // ---- packed Hermitian extension of the two rows of this thread's transform
-    const int tr = threadIdx.x / TQ;
+    const int tr = threadIdx.x / LG;
+    const int lane = threadIdx.x - tr * LG;
     const int tl = tr < TB ? tr : TB - 1;  // lanes past the last transform repeat it
-    const int i = threadIdx.x - tr * TQ;
+    const int i = lane < TQ ? lane : TQ - 1;  // and spare lanes of a group repeat its last
     const int lp = tl / D;                 // pair within the work-group
     const int c = tl - lp * D;             // component
-    const bool owner = tr < TB && lp < npr;
+    const bool owner = tr < TB && lane < TQ && lp < npr;
     // Points i + q TQ of this thread that lie in the zero band for every
     // thread (NHC <= q TQ and q TQ + TQ - 1 <= N - NHC) are zero on input and
     // not needed on output: with the band known at compile time the compiler
@@ -2170,7 +2175,7 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     xchg(u, stage_out, own);
 #pragma unroll
     for (int q = 1; q < R; ++q) {
-        V w = tp[q * i];
+        V w = tp[(q - 1) * TQ + i];
         w.y = -w.y;
         u[q] = cmul(u[q], w);
     }
@@ -2188,7 +2193,7 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     dftn<T, R>(u, T(-1));
     xchg(u, stage_out, own);
 #pragma unroll
-    for (int q = 1; q < R; ++q) u[q] = cmul(u[q], tp[q * i]);
+    for (int q = 1; q < R; ++q) u[q] = cmul(u[q], tp[(q - 1) * TQ + i]);
     dftn<T, R>(u, T(-1));
     // Hermitian unpacking: outputs p < nh <= NHC pair with N - p > N - NHC,
     // so only the points that can lie there go through LDS
