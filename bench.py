@@ -205,14 +205,18 @@ def main():
         iters_p = sum(sum(i["iters"] for i in r["info_primal"]) for r in results)
         iters_d = sum(sum(i["iters"] for i in r["info_dual"]) for r in results)
         total_iters = iters_p + iters_d
-        dom_bytes = (algorithmic_bytes(dom, d, N, M, es, gs, 1) * iters_p +
-                     algorithmic_bytes(dom, d, N, M, es, gs, d - 1) * iters_d) / total_iters
-        dom_avg_s = timing[dom][0] * 1e-3 / timing[dom][1]
-        achieved = dom_bytes / dom_avg_s / 1e9
+        # algorithmic bytes of all operator launches of the class over the timed
+        # steps, divided by their total event-timed duration (launches of
+        # solves that already stopped return at once; their time is included)
+        dom_bytes_total = (algorithmic_bytes(dom, d, N, M, es, gs, 1) * iters_p +
+                           algorithmic_bytes(dom, d, N, M, es, gs, d - 1) * iters_d)
+        dom_bytes = dom_bytes_total / total_iters
+        dom_avg_s = timing[dom][0] * 1e-3 / total_iters
+        achieved = dom_bytes_total / (timing[dom][0] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, precision),
                 "kernel": dom, "bytes_per_launch": int(dom_bytes), "avg_launch_us": round(dom_avg_s * 1e6, 2),
-                "launches_timed": timing[dom][1]}
+                "launches_timed": timing[dom][1], "iterations_timed": total_iters}
         last = results[-1]
         return {"elapsed": elapsed, "value": pts * total_iters / elapsed / 1e6, "ms_per_step": 1e3 * elapsed / args.steps,
                 "kernels": per_cls, "roofline": roof, "last": last,
