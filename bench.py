@@ -142,12 +142,21 @@ def main():
     import torch
 
     if args.copy_calibration:
+        # a plain device copy: the profiler's counter scale, and the streaming
+        # rate this machine reaches (read + write bytes over event time)
         src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
-        for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        dst.copy_(src)
+        e0.record()
+        for _ in range(4):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "launches": 5}))
+        ms = e0.elapsed_time(e1) / 4
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "launches": 5,
+                          "copy_GBs": round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)}))
         return
 
     import synth
