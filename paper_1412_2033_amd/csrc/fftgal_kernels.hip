@@ -1225,6 +1225,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     constexpr int N = kFastSched[FI].n;
     constexpr int B = fast_batch(N, sizeof(V), D);
     constexpr int NB = D * B;  // LDS layout [pos][component][batch]
+    constexpr int LPI = kThreads / NB;  // positions per step of the plain prologue / epilogue
     int lb;
     const PencilArgs &a = pa[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
@@ -1335,28 +1336,34 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
       else
           expand(std::integral_constant<int, N>{});
     } else {
-        const auto *in = gbl(reinterpret_cast<const V *>(a.in) + (long)o * a.in_os + b0);
+        // every thread owns one LDS slot rr (component c, pencil bb) of LPI
+        // positions per step, so its addresses advance by a constant stride;
+        // slots of idle pencils in the input range are written as zeros, the
+        // zero band outside it by a loop over the band alone
+        const int rr = threadIdx.x % NB;
+        const int l0 = threadIdx.x / NB;
+        const bool act = threadIdx.x < LPI * NB;
+        const int c = rr / B;
+        const int bb = rr - c * B;
+        const auto *in = gbl(reinterpret_cast<const V *>(a.in) + (long)o * a.in_os + b0 + (long)c * a.in_cs + bb);
         auto load = [&](auto cap) {
-            constexpr int P = (decltype(cap)::value * NB + kThreads - 1) / kThreads;
+            constexpr int P = (decltype(cap)::value + LPI - 1) / LPI;
             T vx[P], vy[P];
-            int dst[P];
 #pragma unroll
             for (int t = 0; t < P; ++t) {
-                const int idx = threadIdx.x + t * kThreads;
-                const int rr = idx % NB;
-                const int l = idx / NB;
-                const int c = rr / B;
-                const int bb = rr - c * B;
-                const bool ok = idx < a.L_in * NB && bb < nbw;
-                const V v = gld(in + (ok ? (long)c * a.in_cs + (long)l * a.in_ls + bb : 0L));
-                vx[t] = v.x;
-                vy[t] = v.y;
-                dst[t] = ok ? posmod(wrapi(l, a.L_in), N) * NB + rr : -1;
+                const int l = l0 + t * LPI;
+                const bool ok = act && l < a.L_in && bb < nbw;
+                const V v = gld(in + (ok ? (long)l * a.in_ls : 0L));
+                vx[t] = ok ? v.x : T(0);
+                vy[t] = ok ? v.y : T(0);
             }
-            zero_band(NB);
+            const int nz = N - a.L_in;  // zero band: positions khi .. khi + nz - 1
+            for (int l = l0; act && l < nz; l += LPI) X[(khi + l) * NB + rr] = zero;
 #pragma unroll
-            for (int t = 0; t < P; ++t)
-                if (dst[t] >= 0) X[dst[t]] = mk<T>(vx[t], vy[t]);
+            for (int t = 0; t < P; ++t) {
+                const int l = l0 + t * LPI;
+                if (act && l < a.L_in) X[posmod(wrapi(l, a.L_in), N) * NB + rr] = mk<T>(vx[t], vy[t]);
+            }
         };
         if (2 * a.L_in <= N + 1)
             load(std::integral_constant<int, (N + 1) / 2>{});
@@ -1433,16 +1440,17 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
         const double s = block_sum(part);
         if (threadIdx.x == 0) a.partial[lb] = s;
     } else {
-        for (int idx = threadIdx.x; idx < a.L_out * NB; idx += kThreads) {
-            const int rr = idx % NB;
-            const int l = idx / NB;
-            const int c = rr / B;
-            const int bb = rr - c * B;
-            if (bb >= nbw) continue;
-            V v = X[posmod(wrapi(l, a.L_out), N) * NB + rr];
-            v.x *= scale;
-            v.y *= scale;
-            gst(out + (long)c * a.out_cs + (long)o * a.out_os + (long)l * a.out_ls + b0 + bb, v);
+        const int rr = threadIdx.x % NB;
+        const int c = rr / B;
+        const int bb = rr - c * B;
+        if (threadIdx.x < LPI * NB && bb < nbw) {
+            auto *ob = out + (long)c * a.out_cs + (long)o * a.out_os + b0 + bb;
+            for (int l = threadIdx.x / NB; l < a.L_out; l += LPI) {
+                V v = X[posmod(wrapi(l, a.L_out), N) * NB + rr];
+                v.x *= scale;
+                v.y *= scale;
+                gst(ob + (long)l * a.out_ls, v);
+            }
         }
     }
 }
