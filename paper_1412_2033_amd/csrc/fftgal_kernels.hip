@@ -1239,31 +1239,40 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     const T sg = T(a.sgn);
     const T scale = T(a.scale);
     const V zero = mk<T>(T(0), T(0));
-    auto freq = [&](int l, int L, int b, int *k1, int *k2, int *k3) {
+    // pencil b0 + bb sits at (b0 + bb) / Nh, (b0 + bb) % Nh: one division per
+    // work-group, then at most one carry per pencil (B <= Nh is not assumed)
+    const int q0 = b0 / a.Nh, r0 = b0 - q0 * a.Nh;
+    auto split = [&](int bb, int *qb, int *rb) {
+        int r = r0 + bb, q = q0;
+        while (r >= a.Nh) {
+            r -= a.Nh;
+            ++q;
+        }
+        *qb = q;
+        *rb = r;
+    };
+    auto freq = [&](int l, int L, int bb, int *k1, int *k2, int *k3) {
         *k1 = wrapi(l, L);
+        int qb, rb;
+        split(bb, &qb, &rb);
         if (D == 3) {
-            *k2 = wrapi(b / a.Nh, a.Nmid);
-            *k3 = b % a.Nh;
+            *k2 = wrapi(qb, a.Nmid);
+            *k3 = rb;
         } else {
-            *k2 = b % a.Nh;
+            *k2 = rb;
             *k3 = 0;
         }
     };
     // Global loads of a phase are issued together (branch-free, with idle
     // slots reading an in-range address) into scalar register arrays, then
-    // written to LDS; the slots no input reaches (outside the input
-    // frequencies, idle pencils) are zeroed by a disjoint loop.  The trip
-    // counts are compile-time bounds: inputs of at most (N + 1) / 2 points
-    // (zero-padded transforms) or of N points.
-    const int klo = -(a.L_in / 2), khi = (a.L_in + 1) / 2;  // input frequencies k in [klo, khi)
-    auto zero_band = [&](int nper) {  // nper LDS slots per position
-        for (int idx = threadIdx.x; idx < N * nper; idx += kThreads) {
-            const int pos = idx / nper;
-            const int bb = (idx - pos * nper) % B;
-            const int k = pos < (N + 1) / 2 ? pos : pos - N;
-            if (!(k >= klo && k < khi && bb < nbw)) X[idx] = zero;
-        }
-    };
+    // written to LDS.  The input frequencies k in [-(L_in / 2), khi) sit at
+    // positions 0 .. khi - 1 and N - L_in / 2 .. N - 1, so the positions
+    // khi .. khi + N - L_in - 1 form one contiguous zero band of the LDS batch,
+    // written by a loop of its own; slots of idle pencils in the input range
+    // are written as zeros by the loading threads.  The trip counts are
+    // compile-time bounds: inputs of at most (N + 1) / 2 points (zero-padded
+    // transforms) or of N points.
+    const int khi = (a.L_in + 1) / 2;
     if (a.pro == PRO_EXPAND) {
       // the CG vectors hold at most (N + 1) / 2 frequencies per axis (Ga), or N
       // (GaNi, transforms on the grid of the approximation order itself)
@@ -1292,15 +1301,21 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                 by[t][c] = vb.y;
             }
         }
-        zero_band(NB);
+        for (int idx = threadIdx.x; idx < (N - a.L_in) * NB; idx += kThreads) X[khi * NB + idx] = zero;
 #pragma unroll
         for (int t = 0; t < PE; ++t) {
             const int idx = threadIdx.x + t * kThreads;
             const int bb = idx % B;
             const int l = idx / B;
-            if (idx >= a.L_in * B || bb >= nbw) continue;
+            if (idx >= a.L_in * B) continue;
+            if (bb >= nbw) {  // idle pencil of a ragged tile
+                const int pos = posmod(wrapi(l, a.L_in), N);
+#pragma unroll
+                for (int al = 0; al < D; ++al) X[pos * NB + al * B + bb] = zero;
+                continue;
+            }
             int k1, k2, k3;
-            freq(l, a.L_in, b0 + bb, &k1, &k2, &k3);
+            freq(l, a.L_in, bb, &k1, &k2, &k3);
             T tb[2][3];
             const int nt = basis<T>(D, a.kind, k1, k2, k3, tb);
             V v[2];
@@ -1403,14 +1418,14 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
             const int l = idx / B;
             if (idx >= a.L_out * B || bb >= nbw) continue;
             int k1, k2, k3;
-            freq(l, a.L_out, b0 + bb, &k1, &k2, &k3);
+            freq(l, a.L_out, bb, &k1, &k2, &k3);
             T tb[2][3];
             const int nt = basis<T>(D, a.kind, k1, k2, k3, tb);
             const int pos = posmod(k1, N);
             V y[D];
 #pragma unroll
             for (int al = 0; al < D; ++al) y[al] = X[pos * NB + al * B + bb];
-            const double w = ((b0 + bb) % a.Nh) == 0 ? 1.0 : 2.0;
+            const double w = (D == 3 ? k3 : k2) == 0 ? 1.0 : 2.0;  // half spectrum: k_d > 0 counts twice
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (c < a.nc) {
