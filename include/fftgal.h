@@ -251,6 +251,26 @@ int fftgal_bounds_of(struct fftgal_plan *plan, struct fftgal_plan *src, double *
                      double *gap);
 
 /*
+ * Reduced Ga plan (Lemma reduce_grid, eq. Ga_linsys_R, Algorithm 3): the same
+ * guaranteed bounds as fftgal_plan, with every transform of size N on the grid
+ * of the approximation order itself.  The double grid of 2N points per axis is
+ * split into its 2^d interleaved N-grids (k = 2r - s, s in {0,1}^d); the
+ * material is the double-grid series (eq. MBA_GA) evaluated on each of them
+ * (the series on Z_{2N-1} folded onto Z_N with the phase of s, then one
+ * inverse DFT of size N), and every operator application runs the transform
+ * passes once per shift with the phases S(s), S*(s) of the lemma, summing the
+ * projected results.  Every N_a must be odd and 3,5,7-smooth (EINVAL
+ * otherwise; 81, 125, 225, 245, 729 and 2025 run the specialised kernels).  Solves, bounds, history and
+ * the bound tolerance work as for fftgal_plan; warm starts, a-posteriori
+ * bounds and batches are not available (EINVAL).  The workspace holds 2^d
+ * material fields of |N| values and transform intermediates of the N-grid:
+ * fftgal_workspace_bytes_reduced (P as in fftgal_workspace_bytes_p).
+ */
+size_t fftgal_workspace_bytes_reduced(int d, const int32_t *N, int precision, const int32_t *P);
+int fftgal_plan_reduced(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace,
+                        size_t bytes, void *hip_stream);
+
+/*
  * Upper and lower voxel approximations of an inclusion composite (Remark
  * adjusting_A, for Lemma bounds_bounds): on the P-grid of voxels (voxel p
  * centred at p/P with sides 1/P), `upper` receives the largest and `lower` the

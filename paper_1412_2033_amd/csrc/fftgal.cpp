@@ -27,7 +27,8 @@ constexpr int kMaxHist = 20000;      // CG history entries kept per solve
 // captured passes of the current solve, its CG items, and a ring for
 // one-off launches (set-up, right-hand side).
 constexpr size_t kArgSlot = 1024;    // bytes per argument slot (>= sizeof PencilArgs / RowArgs)
-constexpr int kIterSlots = 8;
+constexpr int kMaxPasses = 40;  // operator passes of one CG iteration (reduced Ga, 3D: 5 x 8)
+constexpr int kIterSlots = kMaxPasses + 2;  // passes, then the update and the CG item
 constexpr int kRingSlots = 32;
 constexpr size_t kArgsBytes = kArgSlot * (2 + kIterSlots + kRingSlots);
 constexpr double kFloor64 = 1e-14;   // residual floor relative to ||A_M E|| (FP64)
@@ -74,19 +75,28 @@ struct Dims {
     long Ns = 0;            // state entries per component
     long Mtot = 0;          // |M|
     int nc_max = 1;
+    int nshift = 1;         // material fields: 2^d shifted grids for the reduced Ga, else 1
 };
 
-// gani: the transforms run on the grid of the approximation order N itself
-// (Def. GaNi, Algorithm 1), which must then be 3,5,7-smooth.
-bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, bool gani = false) {
+// Plan schemes: the Ga on the double grid, GaNi on the grid of the order N,
+// and the reduced Ga (Lemma reduce_grid) with 2^d shifted transforms of size N.
+enum Scheme { kSchemeGa = 0, kSchemeGani = 1, kSchemeReduced = 2 };
+
+// GaNi: the transforms run on the grid of the approximation order N itself
+// (Def. GaNi, Algorithm 1), which must then be 3,5,7-smooth.  Reduced Ga: the
+// material series keeps its support Z_{2N-1}, the transforms run on the
+// N-grid (2^d shifted copies), which must then be 3,5,7-smooth.
+bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = kSchemeGa) {
     if (d != 2 && d != 3 || N == nullptr) return false;
+    const bool gani = scheme == kSchemeGani, red = scheme == kSchemeReduced;
     o->d = d;
     for (int a = 0; a < d; ++a) {
         if (N[a] < 1 || N[a] % 2 == 0 || N[a] > 100000) return false;
         if (gani && !is_smooth_odd(N[a])) return false;
+        if (red && !is_smooth_odd(N[a])) return false;
         o->N[a] = N[a];
         o->L[a] = gani ? N[a] : 2 * N[a] - 1;
-        o->M[a] = gani ? N[a] : smooth_odd(2 * N[a] - 1);
+        o->M[a] = (gani || red) ? N[a] : smooth_odd(2 * N[a] - 1);
         o->P[a] = P ? std::max<int>(P[a], o->M[a]) : o->M[a];
         if (P && !is_smooth_odd(P[a])) return false;
     }
@@ -96,6 +106,7 @@ bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, bool gani = f
     o->Mtot = 1;
     for (int a = 0; a < d; ++a) o->Mtot *= o->M[a];
     o->nc_max = std::max(1, d - 1);
+    o->nshift = red ? 1 << d : 1;
     return true;
 }
 
@@ -169,10 +180,10 @@ Layout make_layout(const Dims &D, int precision) {
     L.q = take(vec);
     L.xsol = take((size_t)2 * d * vec);  // [kind][alpha][nc][Ns]
     L.xsol64 = take(precision == FFTGAL_FP32_ITER ? (size_t)d * vec : 0);
-    L.gA64 = take((size_t)D.Mtot * 8);
-    L.gB64 = take((size_t)D.Mtot * 8);
-    L.gA32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.Mtot * 4 : 0);
-    L.gB32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.Mtot * 4 : 0);
+    L.gA64 = take((size_t)D.nshift * D.Mtot * 8);
+    L.gB64 = take((size_t)D.nshift * D.Mtot * 8);
+    L.gA32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.nshift * D.Mtot * 4 : 0);
+    L.gB32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.nshift * D.Mtot * 4 : 0);
     // partial sums: the largest work-group count of any reducing launch
     // (worst case: one pencil / one row pair per work-group)
     long nwg = update_blocks(2L * D.Ns);  // CG update of at most two coefficient components
@@ -251,7 +262,8 @@ struct fftgal_plan {
     bool hist_on = false;  // per-iteration (rr, alpha) history; only when maxit <= kMaxHist
     int cur_alpha = 0;
     double btol = 0.0;  // bound tolerance of the stopping test (fftgal_set_bound_tol)
-    bool gani = false;  // material sampled at the grid points of the order-N grid
+    bool gani = false;     // material sampled at the grid points of the order-N grid
+    bool reduced = false;  // reduced Ga: 2^d shifted transforms of size N (Lemma reduce_grid)
     // kernel timing (fftgal_set_timing): classes recorded
     unsigned timing_mask = 0;
     struct Ev {
@@ -435,15 +447,24 @@ int run_row(Plan *pl, RowArgs &r, bool fp64, int cls) {
     return FFTGAL_OK;
 }
 
+// Shift s (bit d-1-a of s is s_a) of the reduced Ga on an EXPAND or PROJECT pass.
+void set_shift(Plan *pl, PencilArgs &a, int shift) {
+    for (int x = 0; x < 3; ++x) {
+        a.shift[x] = x < pl->D.d ? (shift >> (pl->D.d - 1 - x)) & 1 : 0;
+        a.Nfull[x] = pl->D.N[x];
+    }
+}
+
 // The inverse half of the operator: CG state (n_c components per solution)
 // -> d spatial components per solution on the M-grid, stored as half-spectrum
 // rows along the last axis (T1 in 2D, T2 in 3D).
 int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss, int nsol,
-                   bool update_p, const CgStatus *st, void **rows_out, int cls_expand, int cls_inv) {
+                   bool update_p, const CgStatus *st, void **rows_out, int cls_expand, int cls_inv, int shift = 0) {
     const Dims &D = pl->D;
     const int d = D.d;
     const int ncomp_total = nsol * d;
     PencilArgs a = base_pencil(pl, pl->fM[0], fp64);
+    set_shift(pl, a, shift);
     a.pro = PRO_EXPAND;
     a.epi = EPI_PLAIN;
     a.kind = kind;
@@ -507,7 +528,8 @@ int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss,
 // The forward half: half-spectrum rows -> projected CG vector q (scaled),
 // plus partial sums of (dot, q) (or (q, q) when dot == nullptr).
 int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const void *dot, double scale,
-                   const CgStatus *st, double *partial, int *nparts, int cls_fwd, int cls_proj) {
+                   const CgStatus *st, double *partial, int *nparts, int cls_fwd, int cls_proj, int shift = 0,
+                   bool accumulate = false) {
     const Dims &D = pl->D;
     const int d = D.d;
     void *src = rows;
@@ -534,6 +556,8 @@ int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const voi
         src = pl->ws + pl->Lo.T1;
     }
     PencilArgs a = base_pencil(pl, pl->fM[0], fp64);
+    set_shift(pl, a, shift);
+    a.accumulate = accumulate ? 1 : 0;
     a.pro = PRO_PLAIN;
     a.epi = EPI_PROJECT;
     a.kind = kind;
@@ -566,7 +590,7 @@ int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const voi
     return FFTGAL_OK;
 }
 
-RowArgs base_row(Plan *pl, bool fp64, int mode, void *rows, int kind) {
+RowArgs base_row(Plan *pl, bool fp64, int mode, void *rows, int kind, int shift = 0) {
     const Dims &D = pl->D;
     RowArgs r{};
     r.data = rows;
@@ -581,9 +605,9 @@ RowArgs base_row(Plan *pl, bool fp64, int mode, void *rows, int kind) {
     r.scale = 1.0;
     const bool gsep = pl->separate_gB && kind == KIND_J;
     if (fp64)
-        r.g = pl->ws + (gsep ? pl->Lo.gB64 : pl->Lo.gA64);
+        r.g = pl->ws + (gsep ? pl->Lo.gB64 : pl->Lo.gA64) + (size_t)shift * D.Mtot * 8;
     else
-        r.g = pl->ws + (gsep ? pl->Lo.gB32 : pl->Lo.gA32);
+        r.g = pl->ws + (gsep ? pl->Lo.gB32 : pl->Lo.gA32) + (size_t)shift * D.Mtot * 4;
     const double *c0 = kind == KIND_E ? pl->A0 : pl->B0;
     const double *c1 = kind == KIND_E ? pl->DA : pl->DB;
     for (int i = 0; i < 9; ++i) {
@@ -602,11 +626,13 @@ RowArgs base_row(Plan *pl, bool fp64, int mode, void *rows, int kind) {
 
 // ---- material setup --------------------------------------------------------
 
-// Inverse transforms of a Fourier half-grid on Z_{2N-1} (stored wrapped,
-// layout [n1][n2][n3 >= 0]) into a real field on the M-grid (eq. MBA_GA).
-int series_to_field(Plan *pl, void *coef, double *field) {
+// Inverse transforms of a Fourier half-grid (stored wrapped, layout
+// [n1][n2][n3 >= 0]; extents Li[0], Li[1] and Lhi along the last axis; by
+// default Z_{2N-1}) into a real field on the M-grid (eq. MBA_GA).
+int series_to_field(Plan *pl, void *coef, double *field, const int *Li = nullptr, int Lhi = 0) {
     const Dims &D = pl->D;
     const int d = D.d;
+    const int L0 = Li ? Li[0] : D.L[0], L1 = Li ? Li[1] : D.L[1], Lh = Li ? Lhi : D.Lh;
     void *U = pl->ws + pl->Lo.T2;
     void *W = pl->ws + pl->Lo.T1;
     void *cur = coef;
@@ -615,17 +641,17 @@ int series_to_field(Plan *pl, void *coef, double *field) {
     a.epi = EPI_PLAIN;
     a.ncomp = 1;
     a.sgn = +1;
-    a.L_in = D.L[0];
+    a.L_in = L0;
     a.L_out = D.M[0];
     a.in = cur;
     void *dst1 = (cur == U) ? W : U;
     a.out = dst1;
     if (d == 3) {
-        a.nb = D.L[1] * D.Lh;
-        a.in_ls = a.out_ls = (long)D.L[1] * D.Lh;
+        a.nb = L1 * Lh;
+        a.in_ls = a.out_ls = (long)L1 * Lh;
     } else {
-        a.nb = D.Lh;
-        a.in_ls = a.out_ls = D.Lh;
+        a.nb = Lh;
+        a.in_ls = a.out_ls = Lh;
     }
     int rc = run_pencil(pl, a, 1, true, 8, FFTGAL_K_SETUP);
     if (rc) return rc;
@@ -636,16 +662,16 @@ int series_to_field(Plan *pl, void *coef, double *field) {
         b.epi = EPI_PLAIN;
         b.ncomp = 1;
         b.sgn = +1;
-        b.L_in = D.L[1];
+        b.L_in = L1;
         b.L_out = D.M[1];
         b.in = cur;
         void *dst2 = (cur == U) ? W : U;
         b.out = dst2;
-        b.nb = D.Lh;
-        b.in_os = (long)D.L[1] * D.Lh;
-        b.in_ls = D.Lh;
-        b.out_os = (long)D.M[1] * D.Lh;
-        b.out_ls = D.Lh;
+        b.nb = Lh;
+        b.in_os = (long)L1 * Lh;
+        b.in_ls = Lh;
+        b.out_os = (long)D.M[1] * Lh;
+        b.out_ls = Lh;
         rc = run_pencil(pl, b, D.M[0], true, 8, FFTGAL_K_SETUP);
         if (rc) return rc;
         cur = dst2;
@@ -653,7 +679,7 @@ int series_to_field(Plan *pl, void *coef, double *field) {
     RowArgs r{};
     r.data = cur;
     r.nrows = (d == 3) ? D.M[0] * D.M[1] : D.M[0];
-    r.Nh_row = D.Lh;
+    r.Nh_row = Lh;
     r.cs = 0;
     r.f = pl->fM[d - 1];
     r.tw = pl->ws + pl->Lo.tw64;
@@ -664,6 +690,33 @@ int series_to_field(Plan *pl, void *coef, double *field) {
     r.real_stride = D.M[d - 1];
     r.scale = 1.0;
     return run_row(pl, r, true, FFTGAL_K_SETUP);
+}
+
+// Reduced Ga (Lemma reduce_grid): the double-grid field at the points
+// (2r - s) / (2N) of each shift s is the size-N inverse DFT of the series
+// folded onto Z_N with the phase of s.  The series is parked in the solution
+// region (free while the material is set), each fold goes to W and is
+// transformed into field + s |N|.
+int series_to_shifted_fields(Plan *pl, void *coef, double *field) {
+    const Dims &D = pl->D;
+    const int d = D.d;
+    const size_t nser = (size_t)(d == 3 ? (long)D.L[0] * D.L[1] : (long)D.L[0]) * D.Lh * 16;
+    if (nser > (size_t)2 * d * pl->vec_bytes()) return fail(pl, FFTGAL_EINVAL, "series scratch too small");
+    void *ser = pl->ws + pl->Lo.xsol;
+    void *W = pl->ws + pl->Lo.T1;
+    HIPCHECK(pl, hipMemcpyAsync(ser, coef, nser, hipMemcpyDeviceToDevice, pl->stream));
+    const int Ni[2] = {D.N[0], D.N[1]};
+    for (int s = 0; s < D.nshift; ++s) {
+        int sh[3];
+        for (int a = 0; a < 3; ++a) sh[a] = a < d ? (s >> (d - 1 - a)) & 1 : 0;
+        {
+            Timed t(pl, FFTGAL_K_SETUP);
+            HIPCHECK(pl, launch_fold_series(W, ser, d, D.N, D.L, D.Lh, sh, pl->stream));
+        }
+        const int rc = series_to_field(pl, W, field + (size_t)s * D.Mtot, Ni, D.Nh);
+        if (rc) return rc;
+    }
+    return FFTGAL_OK;
 }
 
 // Voxel image (host, P^d doubles, row-major) -> truncated/extended Fourier
@@ -843,15 +896,22 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
     pl->capture = &cfg->passes;
     void *rows = nullptr;
     int npq = 0;
-    int rc = inverse_passes(pl, fp64, kind, nullptr, 0, 1, true, st, &rows, FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV);
-    if (!rc) {
-        RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind);
-        r.status = st;
-        rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
+    int rc = FFTGAL_OK;
+    // reduced Ga: q = sum_s 2^{-d} S*(s) F A(s) F^{-1} S(s) p over the shifted
+    // grids (Algorithm 3); the first shift also forms p = r + beta p
+    for (int s = 0; s < D.nshift && !rc; ++s) {
+        rc = inverse_passes(pl, fp64, kind, s == 0 ? nullptr : pl->ws + pl->Lo.p, 0, 1, s == 0, st, &rows,
+                            FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV, s);
+        if (!rc) {
+            RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind, s);
+            r.status = st;
+            rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
+        }
+        if (!rc)
+            rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.q, pl->ws + pl->Lo.p,
+                                1.0 / ((double)D.nshift * D.Mtot), st, pl->at<double>(pl->Lo.part_a), &npq,
+                                FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT, s, s > 0);
     }
-    if (!rc)
-        rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.q, pl->ws + pl->Lo.p, 1.0 / (double)D.Mtot, st,
-                            pl->at<double>(pl->Lo.part_a), &npq, FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT);
     pl->capture = nullptr;
     if (rc) return rc;
     const int nc = pl->nc(kind);
@@ -883,7 +943,7 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
 
 // Upload a captured iteration into the plan's iteration argument slots.
 int upload_iteration(Plan *pl, const IterCfg &cfg) {
-    if (cfg.passes.size() > 5) return fail(pl, FFTGAL_EINVAL, "too many passes");
+    if (cfg.passes.size() > (size_t)kMaxPasses) return fail(pl, FFTGAL_EINVAL, "too many passes");
     for (size_t i = 0; i < cfg.passes.size(); ++i) {
         const PassRec &r = cfg.passes[i];
         const bool fast = r.type == 0 ? r.pa.fast : r.ra.fast;
@@ -892,10 +952,12 @@ int upload_iteration(Plan *pl, const IterCfg &cfg) {
         std::memcpy(pl->iter_host[i], r.type == 0 ? (const void *)&r.pa : (const void *)&r.ra, sz);
         HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot((int)i), pl->iter_host[i], sz, hipMemcpyHostToDevice, pl->stream));
     }
-    std::memcpy(pl->iter_host[6], &cfg.upd, sizeof(UpdArgs));
-    std::memcpy(pl->iter_host[7], &cfg.item, sizeof(CgItem));
-    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(6), pl->iter_host[6], sizeof(UpdArgs), hipMemcpyHostToDevice, pl->stream));
-    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(7), pl->iter_host[7], sizeof(CgItem), hipMemcpyHostToDevice, pl->stream));
+    std::memcpy(pl->iter_host[kMaxPasses], &cfg.upd, sizeof(UpdArgs));
+    std::memcpy(pl->iter_host[kMaxPasses + 1], &cfg.item, sizeof(CgItem));
+    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(kMaxPasses), pl->iter_host[kMaxPasses], sizeof(UpdArgs),
+                                hipMemcpyHostToDevice, pl->stream));
+    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(kMaxPasses + 1), pl->iter_host[kMaxPasses + 1], sizeof(CgItem),
+                                hipMemcpyHostToDevice, pl->stream));
     return FFTGAL_OK;
 }
 
@@ -925,8 +987,8 @@ int enqueue_iteration(Plan *pl, const IterCfg &cfg) {
         const int rc = launch_pass(pl, cfg.passes[i], pl->iter_slot((int)i));
         if (rc) return rc;
     }
-    const CgItem *item = reinterpret_cast<const CgItem *>(pl->iter_slot(7));
-    const UpdArgs *upd = reinterpret_cast<const UpdArgs *>(pl->iter_slot(6));
+    const CgItem *item = reinterpret_cast<const CgItem *>(pl->iter_slot(kMaxPasses + 1));
+    const UpdArgs *upd = reinterpret_cast<const UpdArgs *>(pl->iter_slot(kMaxPasses));
     const int *woff0 = reinterpret_cast<const int *>(pl->arg_slot(0));
     {
         Timed t(pl, FFTGAL_K_CG_SCALAR);
@@ -954,24 +1016,32 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     const size_t es = fp64 ? 16 : 8;
     const size_t vbytes = (size_t)pl->nc(kind) * D.Ns * es;
     void *rows = pl->ws + (D.d == 3 ? pl->Lo.T2 : pl->Lo.T1);
-    RowArgs r = base_row(pl, fp64, ROW_RHS, rows, kind);
-    for (int a = 0; a < 3; ++a) r.E[a] = (a == alpha) ? 1.0 : 0.0;
-    r.partial = pl->at<double>(pl->Lo.part_b);
-    r.partial2 = pl->at<double>(pl->Lo.part_c);
-    int rc = run_row(pl, r, fp64, FFTGAL_K_RHS);
-    if (rc) return rc;
-    const int nload = row_grid(r);
-    int nrr = 0;
-    rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.r, nullptr, -1.0 / (double)D.Mtot, nullptr,
-                        pl->at<double>(pl->Lo.part_a), &nrr, FFTGAL_K_RHS, FFTGAL_K_RHS);
-    if (rc) return rc;
+    // one pass per shifted grid (reduced Ga; one grid otherwise), the load
+    // partials of shift s at offset s * nload, the projected loads summed in r
+    const double npts = (double)D.nshift * D.Mtot;
+    int nload = 0, nrr = 0, rc = FFTGAL_OK;
+    for (int s = 0; s < D.nshift; ++s) {
+        RowArgs r = base_row(pl, fp64, ROW_RHS, rows, kind, s);
+        for (int a = 0; a < 3; ++a) r.E[a] = (a == alpha) ? 1.0 : 0.0;
+        configure_row(r, fp64);  // the work-group count fixes the partial offsets
+        nload = row_grid(r);
+        if ((size_t)D.nshift * nload > pl->Lo.part_len) return fail(pl, FFTGAL_EINVAL, "partial buffers too small");
+        r.partial = pl->at<double>(pl->Lo.part_b) + (size_t)s * nload;
+        r.partial2 = pl->at<double>(pl->Lo.part_c) + (size_t)s * nload;
+        rc = run_row(pl, r, fp64, FFTGAL_K_RHS);
+        if (rc) return rc;
+        rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.r, nullptr, -1.0 / npts, nullptr,
+                            pl->at<double>(pl->Lo.part_a), &nrr, FFTGAL_K_RHS, FFTGAL_K_RHS, s, s > 0);
+        if (rc) return rc;
+    }
+    nload *= D.nshift;
     // The load sums |A_M E|^2 over grid points; (., .)_{R^{d x M}} divides by |M|.
-    const double floor_rel = (fp64 ? kFloor64 : kFloor32) / std::sqrt((double)D.Mtot);
+    const double floor_rel = (fp64 ? kFloor64 : kFloor32) / std::sqrt(npts);
     if (!pl->warm[kind][alpha]) {
         Timed t(pl, FFTGAL_K_CG_SCALAR);
         HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload,
-                                    pl->at<double>(pl->Lo.part_c), 1.0 / (double)D.Mtot, rtol, floor_rel, maxit,
-                                    pl->btol, pl->hist(kind, alpha), pl->stream));
+                                    pl->at<double>(pl->Lo.part_c), 1.0 / npts, rtol, floor_rel, maxit, pl->btol,
+                                    pl->hist(kind, alpha), pl->stream));
         HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
         HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
         return FFTGAL_OK;
@@ -979,6 +1049,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     // Warm start from the iterate x0 already in x: keep (b, b), |A_M E|^2 and
     // (A_M E).E as scalars, apply the operator to x0, then r_0 = b - K x0.
     pl->warm[kind][alpha] = false;
+    if (pl->reduced) return fail(pl, FFTGAL_EINVAL, "warm starts are not supported by reduced plans");
     double *scal = pl->at<double>(pl->Lo.gram) + 32;
     {
         Timed t(pl, FFTGAL_K_CG_SCALAR);
@@ -1171,14 +1242,14 @@ void sym_extremes(const double *A, int d, double *hi, double *lo) {
 
 namespace {
 
-size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P, bool gani) {
+size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P, int scheme) {
     Dims D;
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
-    if (!make_dims(d, N, nullptr, &D, gani)) return 0;
+    if (!make_dims(d, N, nullptr, &D, scheme)) return 0;
     const size_t base = make_layout(D, precision).total;
     if (P == nullptr) return base;
     Dims DP;
-    if (!make_dims(d, N, P, &DP, gani)) return 0;
+    if (!make_dims(d, N, P, &DP, scheme)) return 0;
     // a plan lays out its regions without P: an image that does not fit them
     // uses a tail of twiddles, U and W regions after the layout
     int Pv[3] = {1, 1, 1};
@@ -1193,16 +1264,17 @@ size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P,
 }
 
 int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace, size_t bytes,
-              void *hip_stream, bool gani) {
+              void *hip_stream, int scheme) {
     if (out == nullptr) return fail(nullptr, FFTGAL_EINVAL, "out is NULL");
     *out = nullptr;
     Dims D;
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
         return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
-    if (!make_dims(d, N, nullptr, &D, gani))
+    if (!make_dims(d, N, nullptr, &D, scheme))
         return fail(nullptr, FFTGAL_EINVAL,
-                    gani ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
-                         : "d must be 2 or 3 and every N odd and >= 1");
+                    scheme == kSchemeGani      ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
+                    : scheme == kSchemeReduced ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
+                                               : "d must be 2 or 3 and every N odd and >= 1");
     if (dev_workspace == nullptr || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))
         return fail(nullptr, FFTGAL_EINVAL, "workspace must be a 256-byte aligned device pointer");
     Layout Lo = make_layout(D, precision);
@@ -1212,7 +1284,8 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     auto *pl = new Plan();
     pl->D = D;
     pl->Lo = Lo;
-    pl->gani = gani;
+    pl->gani = scheme == kSchemeGani;
+    pl->reduced = scheme == kSchemeReduced;
     pl->precision = precision;
     pl->stream = reinterpret_cast<hipStream_t>(hip_stream);
     pl->ws = reinterpret_cast<char *>(dev_workspace);
@@ -1243,11 +1316,15 @@ extern "C" {
 
 
 size_t fftgal_workspace_bytes_p(int d, const int32_t *N, int precision, const int32_t *P) {
-    return workspace_bytes(d, N, precision, P, false);
+    return workspace_bytes(d, N, precision, P, kSchemeGa);
 }
 
 size_t fftgal_workspace_bytes_gani(int d, const int32_t *N, int precision, const int32_t *P) {
-    return workspace_bytes(d, N, precision, P, true);
+    return workspace_bytes(d, N, precision, P, kSchemeGani);
+}
+
+size_t fftgal_workspace_bytes_reduced(int d, const int32_t *N, int precision, const int32_t *P) {
+    return workspace_bytes(d, N, precision, P, kSchemeReduced);
 }
 
 size_t fftgal_workspace_bytes(int d, const int32_t *N, int precision) {
@@ -1256,12 +1333,17 @@ size_t fftgal_workspace_bytes(int d, const int32_t *N, int precision) {
 
 int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace, size_t bytes,
                 void *hip_stream) {
-    return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, false);
+    return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, kSchemeGa);
 }
 
 int fftgal_plan_gani(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace,
                      size_t bytes, void *hip_stream) {
-    return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, true);
+    return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, kSchemeGani);
+}
+
+int fftgal_plan_reduced(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace,
+                        size_t bytes, void *hip_stream) {
+    return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, kSchemeReduced);
 }
 
 
@@ -1346,7 +1428,8 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
                     HIPCHECK(pl, launch_incl_coeff(U, d, D.L[0], D.L[1], D.Lh, inc_dev, n, pass == 0 ? wA0 : wB0,
                                                    pl->stream));
                 }
-                rc = series_to_field(pl, U, pass == 0 ? gA : gB);
+                rc = pl->reduced ? series_to_shifted_fields(pl, U, pass == 0 ? gA : gB)
+                                 : series_to_field(pl, U, pass == 0 ? gA : gB);
                 if (rc) return rc;
             }
             HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // host table reused
@@ -1461,7 +1544,8 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
             void *coef = nullptr;
             rc = voxel_series(pl, img, map, vmax, &coef);
             if (rc) return rc;
-            rc = series_to_field(pl, coef, pass == 0 ? gA : gB);
+            rc = pl->reduced ? series_to_shifted_fields(pl, coef, pass == 0 ? gA : gB)
+                             : series_to_field(pl, coef, pass == 0 ? gA : gB);
             if (rc) return rc;
         }
     } else {
@@ -1469,9 +1553,9 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
     }
     if (!pl->fp64_iter()) {
         Timed t(pl, FFTGAL_K_SETUP);
-        HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gA32), gA, D.Mtot, pl->stream));
+        HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gA32), gA, (size_t)D.nshift * D.Mtot, pl->stream));
         if (pl->separate_gB)
-            HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gB32), gB, D.Mtot, pl->stream));
+            HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gB32), gB, (size_t)D.nshift * D.Mtot, pl->stream));
     }
     HIPCHECK(pl, hipStreamSynchronize(pl->stream));
     pl->have_mat = true;
@@ -1510,22 +1594,30 @@ int fftgal_bounds(struct fftgal_plan *pl, double *upper, double *lower, double *
         } else {
             st_ss = (long)(pl->vec_bytes() / 16);
         }
-        void *rows = nullptr;
-        int rc = inverse_passes(pl, true, kind, xs, st_ss, d, false, nullptr, &rows, FFTGAL_K_BOUNDS,
-                                FFTGAL_K_BOUNDS);
-        if (rc) return rc;
-        RowArgs r = base_row(pl, true, ROW_GRAM, rows, kind);
-        r.ncomp = d * d;
-        r.partial = pl->at<double>(pl->Lo.part_b);
-        rc = run_row(pl, r, true, FFTGAL_K_BOUNDS);
-        if (rc) return rc;
-        Timed t(pl, FFTGAL_K_BOUNDS);
-        HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->Lo.part_b), row_grid(r),
-                                         d * d, pl->stream));
-        HIPCHECK(pl, hipMemcpyAsync(gram[kind], pl->at<double>(pl->Lo.gram), d * d * 8, hipMemcpyDeviceToHost,
-                                    pl->stream));
-        HIPCHECK(pl, hipStreamSynchronize(pl->stream));
-        for (int i = 0; i < d * d; ++i) gram[kind][i] /= (double)D.Mtot;
+        // the energy quadrature on every shifted grid (reduced Ga: the
+        // quadratic form of Lemma reduce_grid), the d^2 sums of shift s in
+        // gram + 16 s, added on the host in shift order
+        for (int i = 0; i < d * d; ++i) gram[kind][i] = 0.0;
+        for (int s = 0; s < D.nshift; ++s) {
+            void *rows = nullptr;
+            int rc = inverse_passes(pl, true, kind, xs, st_ss, d, false, nullptr, &rows, FFTGAL_K_BOUNDS,
+                                    FFTGAL_K_BOUNDS, s);
+            if (rc) return rc;
+            RowArgs r = base_row(pl, true, ROW_GRAM, rows, kind, s);
+            r.ncomp = d * d;
+            r.partial = pl->at<double>(pl->Lo.part_b);
+            rc = run_row(pl, r, true, FFTGAL_K_BOUNDS);
+            if (rc) return rc;
+            Timed t(pl, FFTGAL_K_BOUNDS);
+            HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->Lo.part_b), row_grid(r),
+                                             d * d, pl->stream));
+            double gs[9];
+            HIPCHECK(pl, hipMemcpyAsync(gs, pl->at<double>(pl->Lo.gram), d * d * 8, hipMemcpyDeviceToHost,
+                                        pl->stream));
+            HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+            for (int i = 0; i < d * d; ++i) gram[kind][i] += gs[i];
+        }
+        for (int i = 0; i < d * d; ++i) gram[kind][i] /= (double)D.nshift * D.Mtot;
     }
     double up[9], bh[9], lo[9];
     for (int i = 0; i < d; ++i)
@@ -1592,6 +1684,7 @@ int fftgal_warm_start(struct fftgal_plan *fine, struct fftgal_plan *coarse) {
     if (!coarse || coarse == fine) return fail(fine, FFTGAL_EINVAL, "coarse plan is NULL or the fine plan itself");
     if (!fine->have_mat) return fail(fine, FFTGAL_ESTATE, "no material set on the fine plan");
     if (fine->busy || coarse->busy) return fail(fine, FFTGAL_ESTATE, "a plan has a solve in a batch");
+    if (fine->reduced) return fail(fine, FFTGAL_EINVAL, "warm starts are not supported by reduced plans");
     const int d = fine->D.d;
     if (coarse->D.d != d) return fail(fine, FFTGAL_EINVAL, "plans of different dimension");
     int n = 0;
@@ -1649,6 +1742,7 @@ int fftgal_bounds_of(struct fftgal_plan *pl, struct fftgal_plan *src, double *up
     if (!src || src == pl) return fail(pl, FFTGAL_EINVAL, "source plan is NULL or the plan itself");
     if (!pl->have_mat) return fail(pl, FFTGAL_ESTATE, "no material set");
     if (pl->busy || src->busy) return fail(pl, FFTGAL_ESTATE, "a plan has a solve in a batch");
+    if (pl->reduced || src->reduced) return fail(pl, FFTGAL_EINVAL, "a-posteriori bounds take Ga and GaNi plans");
     const int d = pl->D.d;
     if (src->D.d != d) return fail(pl, FFTGAL_EINVAL, "plans of different dimension");
     for (int k = 0; k < 2; ++k)
@@ -1898,6 +1992,7 @@ int fftgal_batch_add(struct fftgal_batch *b, struct fftgal_plan *pl, int kind, i
     if (!(rtol >= 0.0) || maxit < 0) return bfail(b, FFTGAL_EINVAL, "rtol must be >= 0 and maxit >= 0");
     if (!pl->have_mat) return bfail(b, FFTGAL_ESTATE, "plan has no material");
     if (pl->busy) return bfail(b, FFTGAL_ESTATE, "plan already has a solve in a batch");
+    if (pl->reduced) return bfail(b, FFTGAL_EINVAL, "reduced plans do not join batches");
     if ((int)b->members.size() >= b->cap) return bfail(b, FFTGAL_ENOMEM, "batch is full");
     int rc = start_solve(pl, kind, alpha, rtol, maxit);
     if (rc) return bfail(b, rc, "start of solve failed: %s", pl->err.c_str());

@@ -109,6 +109,12 @@ struct PencilArgs {
     // WINDOW: sinc window of a P-voxel image, times 1/|P|
     int Pw[3];
     double winscale;
+    // reduced Ga (Lemma reduce_grid): EXPAND multiplies frequency k by
+    // exp(-i pi sum_a shift_a k_a / Nfull_a) (S(s)), PROJECT by its conjugate
+    // (S*(s)) and, with accumulate, adds to the vector already in out
+    int shift[3];
+    int Nfull[3];
+    int accumulate;
 };
 
 // Batched real transforms along the last (contiguous, half-spectrum) axis,
@@ -236,6 +242,11 @@ hipError_t launch_convert_d2f(float *dst, const double *src, size_t n, hipStream
 hipError_t launch_sum_partials(double *out, const double *part, int nparts, int nvals,
                                hipStream_t s);
 hipError_t launch_image_stats(const double *img, long n, double *part, double *out, hipStream_t s);
+// Reduced Ga material (Lemma reduce_grid): fold a Fourier half-grid on
+// Z_{2N-1} (layout [L0][L1][Lh], wrapped) onto Z_N (layout [N0][N1][Nh]) with
+// the phase of the shift s: b(j) = sum_{k = j mod N} c(k) exp(-i pi s.k / N).
+hipError_t launch_fold_series(void *out, const void *coef, int d, const int *N, const int *L, int Lh,
+                              const int *shift, hipStream_t s);
 hipError_t launch_incl_coeff(void *out, int d, int L1, int L2, int Lh, const InclDev *incl, int n_incl,
                              double w0, hipStream_t s);
 

@@ -379,6 +379,15 @@ __device__ __forceinline__ int basis(int d, int kind, int k1, int k2, int k3, T 
     return nn == T(0) ? 0 : (primal || two) ? 1 : 2;
 }
 
+// exp(-i pi sum_a s_a k_a / N_a) of the shift s (S(s) of Lemma reduce_grid);
+// 1 when no shift is set.
+__device__ __forceinline__ void shift_phase(const PencilArgs &a, int k1, int k2, int k3, double *c, double *s) {
+    const double x = (a.shift[0] ? (double)k1 / a.Nfull[0] : 0.0) + (a.shift[1] ? (double)k2 / a.Nfull[1] : 0.0) +
+                     (a.shift[2] ? (double)k3 / a.Nfull[2] : 0.0);
+    sincospi(-x, s, c);
+}
+__device__ __forceinline__ bool has_shift(const PencilArgs &a) { return (a.shift[0] | a.shift[1] | a.shift[2]) != 0; }
+
 __device__ __forceinline__ double sinc_pi(double x) {
     return x == 0.0 ? 1.0 : sinpi(x) / (M_PI * x);
 }
@@ -459,6 +468,13 @@ __global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
                         const V cv = acc[(c * a.L_in + l) * B + bb];
                         ex -= t[c][al] * cv.y;  // i * t * c
                         ey += t[c][al] * cv.x;
+                    }
+                    if (has_shift(a)) {
+                        double pc, ps;
+                        shift_phase(a, k1, k2, k3, &pc, &ps);
+                        const T nx = ex * T(pc) - ey * T(ps);
+                        ey = ex * T(ps) + ey * T(pc);
+                        ex = nx;
                     }
                     bufA[posmod(k1, n) * B + bb] = mk<T>(ex, ey);
                 }
@@ -550,8 +566,22 @@ __global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
             const int l = (idx / B) % a.L_out;
             const int c = idx / (B * a.L_out);
             if (bb >= nbw) continue;
-            const V v = acc[idx];
+            V v = acc[idx];
             const long off = (long)c * a.out_cs + (long)l * a.out_ls + b0 + bb;
+            if (has_shift(a)) {  // S*(s): the conjugate phase
+                int k1, k2, k3;
+                freq(l, a.L_out, b0 + bb, &k1, &k2, &k3);
+                double pc, ps;
+                shift_phase(a, k1, k2, k3, &pc, &ps);
+                const T nx = v.x * T(pc) + v.y * T(ps);
+                v.y = v.y * T(pc) - v.x * T(ps);
+                v.x = nx;
+            }
+            if (a.accumulate) {
+                const V old = q[off];
+                v.x += old.x;
+                v.y += old.y;
+            }
             q[off] = v;
             const int klast = (b0 + bb) % a.Nh;
             const double w = klast == 0 ? 1.0 : 2.0;
@@ -670,6 +700,51 @@ __global__ __launch_bounds__(kThreads) void envelope_kernel(double *up, double *
         }
         up[idx] = hi;
         lo[idx] = lw;
+    }
+}
+
+// Reduced Ga material: fold the series on Z_{2N-1} onto Z_N with the phase of
+// shift s (one output frequency per thread; at most two sources per axis).
+// Index 2 is always the last axis; index 1 is used in 3D only.
+__global__ __launch_bounds__(kThreads) void fold_series_kernel(double2 *out, const double2 *coef, int d, int n0,
+                                                               int n1, int n2, int l0, int l1, int lh, int s0, int s1,
+                                                               int s2) {
+    const int nh = (n2 + 1) / 2;  // stored output entries along the last axis
+    const long total = (d == 3 ? (long)n0 * n1 : (long)n0) * nh;
+    const int nn[3] = {n0, n1, n2};
+    const int sh[3] = {s0, d == 3 ? s1 : 0, s2};
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)gridDim.x * kThreads) {
+        const int m2 = (int)(idx % nh);
+        const long r = idx / nh;
+        const int m1 = d == 3 ? (int)(r % n1) : 0;
+        const int m0 = d == 3 ? (int)(r / n1) : (int)r;
+        const int jj[3] = {wrapi(m0, n0), d == 3 ? wrapi(m1, n1) : 0, m2};
+        // sources k_a = j_a and j_a -/+ N_a (for j_a != 0): |k_a| <= N_a - 1
+        int ka[3][2], na[3];
+        for (int a = 0; a < 3; ++a) {
+            ka[a][0] = jj[a];
+            ka[a][1] = jj[a] > 0 ? jj[a] - nn[a] : jj[a] + nn[a];
+            na[a] = (jj[a] != 0 && (a != 1 || d == 3)) ? 2 : 1;
+        }
+        double re = 0.0, im = 0.0;
+        for (int i0 = 0; i0 < na[0]; ++i0)
+            for (int i1 = 0; i1 < na[1]; ++i1)
+                for (int i2 = 0; i2 < na[2]; ++i2) {
+                    const int k0 = ka[0][i0], k1 = ka[1][i1], k2 = ka[2][i2];
+                    // stored entries have k_last >= 0; the others by conjugate symmetry
+                    const bool cj = k2 < 0;
+                    const int q0 = cj ? -k0 : k0, q1 = cj ? -k1 : k1, q2 = cj ? -k2 : k2;
+                    double2 v = d == 3 ? coef[((long)posmod(q0, l0) * l1 + posmod(q1, l1)) * lh + q2]
+                                       : coef[(long)posmod(q0, l0) * lh + q2];
+                    if (cj) v.y = -v.y;
+                    const double x = (sh[0] ? (double)k0 / nn[0] : 0.0) + (sh[1] ? (double)k1 / nn[1] : 0.0) +
+                                     (sh[2] ? (double)k2 / nn[2] : 0.0);
+                    double ps, pc;
+                    sincospi(-x, &ps, &pc);
+                    re += v.x * pc - v.y * ps;
+                    im += v.x * ps + v.y * pc;
+                }
+        out[idx] = make_double2(re, im);
     }
 }
 
@@ -1332,6 +1407,8 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                 }
             }
             const int pos = posmod(k1, N);
+            double pc = 1.0, ps = 0.0;
+            if (has_shift(a)) shift_phase(a, k1, k2, k3, &pc, &ps);
 #pragma unroll
             for (int al = 0; al < D; ++al) {
                 T ex = T(0), ey = T(0);
@@ -1341,6 +1418,11 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                         ex -= tb[c][al] * v[c].y;
                         ey += tb[c][al] * v[c].x;
                     }
+                }
+                if (has_shift(a)) {
+                    const T nx = ex * T(pc) - ey * T(ps);
+                    ey = ex * T(ps) + ey * T(pc);
+                    ex = nx;
                 }
                 X[pos * NB + al * B + bb] = mk<T>(ex, ey);
             }
@@ -1426,6 +1508,8 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
 #pragma unroll
             for (int al = 0; al < D; ++al) y[al] = X[pos * NB + al * B + bb];
             const double w = (D == 3 ? k3 : k2) == 0 ? 1.0 : 2.0;  // half spectrum: k_d > 0 counts twice
+            double pc = 1.0, ps = 0.0;
+            if (has_shift(a)) shift_phase(a, k1, k2, k3, &pc, &ps);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (c < a.nc) {
@@ -1439,6 +1523,16 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                         }
                     }
                     const long off = c * a.out_cs + (long)l * a.out_ls + b0 + bb;
+                    if (has_shift(a)) {  // S*(s): the conjugate phase
+                        const T nx = qx * T(pc) + qy * T(ps);
+                        qy = qy * T(pc) - qx * T(ps);
+                        qx = nx;
+                    }
+                    if (a.accumulate) {
+                        const V old = gld(out + off);
+                        qx += old.x;
+                        qy += old.y;
+                    }
                     gst(out + off, mk<T>(qx, qy));
                     if (a.st_dot != nullptr) {
                         part += w * ((double)dx[t][c] * (double)qx + (double)dy[t][c] * (double)qy);
@@ -2916,6 +3010,17 @@ hipError_t launch_envelope(double *upper, double *lower, int d, const int *P, co
     const long total = (long)p0 * p1 * p2;
     const int blocks = (int)std::max<long>(1, std::min<long>(2048, (total + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(envelope_kernel, dim3(blocks), dim3(kThreads), 0, s, upper, lower, d, p0, p1, p2, inc, n, ext);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_series(void *out, const void *coef, int d, const int *N, const int *L, int Lh,
+                              const int *shift, hipStream_t s) {
+    const int n0 = N[0], n1 = d == 3 ? N[1] : 1, n2 = N[d - 1];
+    const long total = (d == 3 ? (long)n0 * n1 : (long)n0) * ((n2 + 1) / 2);
+    const int blocks = (int)std::max<long>(1, std::min<long>(4096, (total + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(fold_series_kernel, dim3(blocks), dim3(kThreads), 0, s, reinterpret_cast<double2 *>(out),
+                       reinterpret_cast<const double2 *>(coef), d, n0, n1, n2, L[0], d == 3 ? L[1] : 1, Lh, shift[0],
+                       d == 3 ? shift[1] : 0, shift[d - 1]);
     return hipGetLastError();
 }
 

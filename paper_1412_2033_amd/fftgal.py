@@ -29,6 +29,7 @@ EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", 
            "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
            "fftgal_warm_start", "fftgal_history", "fftgal_set_timing_classes", "fftgal_set_bound_tol",
            "fftgal_workspace_bytes_gani", "fftgal_plan_gani", "fftgal_bounds_of", "fftgal_envelope_images",
+           "fftgal_workspace_bytes_reduced", "fftgal_plan_reduced",
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
@@ -117,6 +118,11 @@ def load_library(path=LIB_PATH):
     lib.fftgal_workspace_bytes_gani.restype = ctypes.c_size_t
     lib.fftgal_plan_gani.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32p, ctypes.c_int, vp, ctypes.c_size_t, vp]
     lib.fftgal_plan_gani.restype = ctypes.c_int
+    lib.fftgal_workspace_bytes_reduced.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p]
+    lib.fftgal_workspace_bytes_reduced.restype = ctypes.c_size_t
+    lib.fftgal_plan_reduced.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32p, ctypes.c_int, vp, ctypes.c_size_t,
+                                        vp]
+    lib.fftgal_plan_reduced.restype = ctypes.c_int
     lib.fftgal_bounds_of.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.fftgal_bounds_of.restype = ctypes.c_int
@@ -164,6 +170,8 @@ def fftgal_workspace_bytes(d, N, precision=FP64, P=None, scheme="ga"):
     lib = load_library()
     if scheme == "gani":
         return int(lib.fftgal_workspace_bytes_gani(d, _i32(N), precision, None if P is None else _i32(P)))
+    if scheme == "reduced":
+        return int(lib.fftgal_workspace_bytes_reduced(d, _i32(N), precision, None if P is None else _i32(P)))
     if P is None:
         return int(lib.fftgal_workspace_bytes(d, _i32(N), precision))
     return int(lib.fftgal_workspace_bytes_p(d, _i32(N), precision, _i32(P)))
@@ -172,7 +180,7 @@ def fftgal_workspace_bytes(d, N, precision=FP64, P=None, scheme="ga"):
 def fftgal_plan(d, N, precision, workspace_ptr, nbytes, stream_ptr, scheme="ga"):
     lib = load_library()
     h = ctypes.c_void_p()
-    fn = lib.fftgal_plan_gani if scheme == "gani" else lib.fftgal_plan
+    fn = {"gani": lib.fftgal_plan_gani, "reduced": lib.fftgal_plan_reduced}.get(scheme, lib.fftgal_plan)
     _check(fn(ctypes.byref(h), d, _i32(N), precision, ctypes.c_void_p(workspace_ptr), nbytes,
               ctypes.c_void_p(stream_ptr)), None)
     return h

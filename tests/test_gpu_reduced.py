@@ -1,0 +1,151 @@
+"""GPU parity of the reduced Ga plans (Lemma reduce_grid, Algorithm 3).
+
+* fftgal_plan_reduced: bounds within 1e-10 of the oracle's reduced Ga (FP64;
+  1e-6 for the FP32-iteration form), which the oracle pins to the Ga bounds;
+  2D/3D, inclusions and voxels, non-cubic grids, generic and specialised
+  transform lengths;
+* a homogeneous material needs no iteration and is exact; the monitored
+  energy starts at the Voigt entry;
+* the reduced plan and the double-grid plan of the same N give the same bounds
+  on the device (3D, N = 81: specialised reduced kernels against the generic
+  length-175 double grid);
+* unsupported uses raise: a non-smooth N, warm starts, batches.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import material, reduced
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_2033_amd import fftgal
+    fftgal.load_library()
+    return fftgal
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+CASES = {
+    "circle2d_N9": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0, center=(0.05, -0.1)), (9, 9)),
+    "square2d_N15x25": (lambda: synth.square_inclusion(2, 0.6, 1.0, 10.0, center=(0.1, 0.2)), (15, 25)),
+    "twophase_iso_N15": (lambda: {"d": 2, "kind": "inclusions", "A0": np.eye(2), "shapes": ["rect", "circ"],
+                                  "centers": np.array([[0.1, -0.2], [-0.25, 0.2]]),
+                                  "sizes": np.array([[0.35, 0.2], [0.12, 0.0]]),
+                                  "A_in": np.array([12 * np.eye(2), 0.2 * np.eye(2)])}, (15, 15)),
+    "aniso3d_N5": (lambda: synth.cube_inclusion_aniso(0.5, 3), (5, 5, 5)),
+    "voxel2d_P15_N9": (lambda: synth.grf_voxels(11, (15, 15), d=2, corr_len=0.15), (9, 9)),
+    "voxel3d_P9_N5x7x3": (lambda: synth.grf_voxels(12, (9, 9, 9), d=3, corr_len=0.15), (5, 7, 3)),
+    # specialised transform lengths
+    "circle2d_N81": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0), (81, 81)),
+    "circle2d_N225x125": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 30.0, center=(0.2, 0.1)), (225, 125)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_reduced_matches_oracle(fg, name):
+    make, N = CASES[name]
+    micro = make()
+    d = len(N)
+    print("reduced %s N=%s" % (name, N), flush=True)
+    plan = fg.Plan(d, N, "fp64", P=micro.get("P"), scheme="reduced")
+    try:
+        res = plan.run(micro, rtol=1e-11)
+    finally:
+        plan.close()
+    ref = reduced.reduced_bounds(material.make_material(micro), N, tol=1e-11)
+    assert _rel(res["upper"], ref["upper"]) <= 1e-10
+    assert _rel(res["lower"], ref["lower"]) <= 1e-10
+
+
+def test_reduced_fp32_iterations(fg):
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0)
+    N = (81, 81)
+    print("reduced fp32 N=81", flush=True)
+    plan = fg.Plan(2, N, "fp32", scheme="reduced")
+    try:
+        res = plan.run(micro, rtol=1e-5)
+    finally:
+        plan.close()
+    ref = reduced.reduced_bounds(material.make_material(micro), N, tol=1e-11)
+    assert _rel(res["upper"], ref["upper"]) <= 1e-6
+    assert _rel(res["lower"], ref["lower"]) <= 1e-6
+
+
+@pytest.mark.parametrize("kind", ["inclusions", "voxels"])
+def test_reduced_equals_double_grid_3d(fg, kind):
+    N = (81, 81, 81)
+    micro = synth.cube_inclusion_aniso(0.45, 5) if kind == "inclusions" else \
+        synth.grf_voxels(5, (81, 81, 81), d=3, corr_len=0.05)
+    print("reduced vs double grid 3D N=81 %s" % kind, flush=True)
+    red = fg.Plan(3, N, "fp64", P=micro.get("P"), scheme="reduced")
+    try:
+        r = red.run(micro, rtol=1e-11)
+    finally:
+        red.close()
+    ga = fg.Plan(3, N, "fp64", P=micro.get("P"))
+    try:
+        g = ga.run(micro, rtol=1e-11)
+    finally:
+        ga.close()
+    assert _rel(r["upper"], g["upper"]) <= 1e-10
+    assert _rel(r["lower"], g["lower"]) <= 1e-10
+
+
+def test_reduced_homogeneous_and_history(fg):
+    # a homogeneous material has a zero right-hand side (no iteration, exact
+    # A); the first monitored energy of a non-trivial solve is the Voigt entry
+    from oracle import ga
+    A = synth.random_spd(7, 3)
+    micro = synth.cube_inclusion_aniso(0.5, 7)
+    micro["A0"] = A
+    micro["A_in"] = A.reshape(1, 3, 3).copy()
+    plan = fg.Plan(3, (5, 7, 5), "fp64", scheme="reduced")
+    try:
+        res = plan.run(micro, rtol=1e-12)
+    finally:
+        plan.close()
+    np.testing.assert_allclose(res["upper"], A, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    np.testing.assert_allclose(res["lower"], A, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    assert all(i["iters"] == 0 for i in res["info_primal"] + res["info_dual"])
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0)
+    plan = fg.Plan(2, (15, 15), "fp64", scheme="reduced")
+    try:
+        plan.run(micro, rtol=1e-10)
+        h0 = [plan.history(0, a)[0] for a in range(2)]
+    finally:
+        plan.close()
+    voigt, _ = ga.voigt_reuss(material.make_material(micro), 2)
+    for a in range(2):
+        assert abs(h0[a] - voigt[a, a]) <= 1e-12 * voigt[a, a]
+
+
+def test_reduced_errors(fg):
+    with pytest.raises(fg.FftgalError):
+        fg.Plan(2, (11, 11), "fp64", scheme="reduced")  # 11 is not 3,5,7-smooth
+    micro = synth.square_inclusion(2, 0.6, 1.0, 10.0)
+    a = fg.Plan(2, (5, 5), "fp64")
+    b = fg.Plan(2, (9, 9), "fp64", scheme="reduced")
+    try:
+        a.run(micro, rtol=1e-10)
+        b.set_material(micro)
+        with pytest.raises(fg.FftgalError):
+            b.warm_start(a)
+        batch = fg.Batch(capacity=2, stream=b.stream)
+        try:
+            with pytest.raises(fg.FftgalError):
+                batch.add(b, 0, 0)
+        finally:
+            batch.close()
+    finally:
+        a.close()
+        b.close()
