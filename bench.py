@@ -128,6 +128,8 @@ def main():
                     help="grid of the GaNi section (the paper compares GaNi of order 2N-1; 0: skip)")
     ap.add_argument("--warm-coarse", type=int, default=41,
                     help="coarse N of the warm-start / bound-monitoring section (0: skip)")
+    ap.add_argument("--reduced", type=int, default=81,
+                    help="N of the reduced-Ga section (3D, on the benchmark image; 0: skip)")
     ap.add_argument("--envelope", type=int, default=1,
                     help="upper-upper / lower-lower bounds section on an anisotropic cube inclusion (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -278,6 +280,8 @@ def main():
         out["warm_start"] = warm_start_bench(fftgal, micro_dev, d, N, M, args.warm_coarse, rtol64, dev)
     if args.gani > 0:
         out["gani"] = gani_bench(fftgal, micro_dev, d, M, args.gani, rtol64, last, dev)
+    if args.reduced > 0:
+        out["reduced"] = reduced_bench(fftgal, micro_dev, d, M, args.reduced, rtol64, dev)
     if args.envelope:
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.serve > 0:
@@ -389,6 +393,39 @@ def gani_bench(fftgal, micro_dev, d, P, Ng, rtol, ga_last, dev):
             "apost_upper_diag": diag(up), "apost_lower_diag": diag(lo), "apost_gap": round(gap, 6),
             "ga_N113_upper_diag": diag(ga_last["upper"]), "ga_N113_lower_diag": diag(ga_last["lower"]),
             "ga_N113_gap": round(float(ga_last["gap"]), 6)}
+
+
+def reduced_bench(fftgal, micro_dev, d, P, Nr, rtol, dev):
+    """Reduced Ga (Lemma reduce_grid, Algorithm 3) against the double-grid Ga
+    of the same order Nr on the benchmark image: time to bounds, CG
+    iterations, workspace bytes and the difference of the bounds (FP64)."""
+    import numpy as np
+    import torch
+    print("bench: reduced Ga N=%d" % Nr, file=sys.stderr, flush=True)
+    Nt = (Nr,) * d
+    out = {"N": Nr, "rtol": rtol}
+    res = {}
+    for scheme in ("reduced", "ga"):
+        plan = fftgal.Plan(d, Nt, "fp64", device=dev, P=P, scheme=scheme)
+        try:
+            plan.run(micro_dev, rtol=rtol)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = plan.run(micro_dev, rtol=rtol)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            grid = list(plan.M)
+        finally:
+            plan.close()
+        res[scheme] = r
+        out[scheme] = {"time_to_bounds_s": round(el, 4), "workspace_bytes": plan.nbytes, "transform_grid": grid,
+                       "cg_iterations": {"primal": [i["iters"] for i in r["info_primal"]],
+                                         "dual": [i["iters"] for i in r["info_dual"]]},
+                       "upper_diag": [round(float(v), 8) for v in np.diag(r["upper"])]}
+    out["bound_rel_diff"] = max(
+        float(np.linalg.norm(res["reduced"][k] - res["ga"][k]) / np.linalg.norm(res["ga"][k]))
+        for k in ("upper", "lower"))
+    return out
 
 
 def envelope_bench(fftgal, d, N, M, rtol, dev):
