@@ -927,11 +927,11 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
     u.nblocks = update_blocks((long)nc * D.Ns);
     u.st = st;
     u.partial = pl->at<double>(pl->Lo.part_c);
+    u.pq_part = pl->at<double>(pl->Lo.part_a);
+    u.npq = npq;
     cfg->upd = u;
     CgItem it{};
     it.st = st;
-    it.pq_part = pl->at<double>(pl->Lo.part_a);
-    it.npq = npq;
     it.rr_part = pl->at<double>(pl->Lo.part_c);
     it.nrr = u.nblocks;
     it.hist = pl->hist_on ? pl->hist(kind, alpha) : nullptr;
@@ -990,10 +990,6 @@ int enqueue_iteration(Plan *pl, const IterCfg &cfg) {
     const CgItem *item = reinterpret_cast<const CgItem *>(pl->iter_slot(kMaxPasses + 1));
     const UpdArgs *upd = reinterpret_cast<const UpdArgs *>(pl->iter_slot(kMaxPasses));
     const int *woff0 = reinterpret_cast<const int *>(pl->arg_slot(0));
-    {
-        Timed t(pl, FFTGAL_K_CG_SCALAR);
-        HIPCHECK(pl, launch_cg_alpha_multi(item, 1, pl->stream));
-    }
     {
         Timed t(pl, FFTGAL_K_CG_UPDATE);
         HIPCHECK(pl, launch_cg_update_multi(upd, woff0, 1, cfg.upd.nblocks, cfg.fp64, pl->stream));
@@ -2046,7 +2042,6 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
                     BHIPCHECK(b, launch_row(r.ra, r.fp64, b->stream));
             }
         }
-        BHIPCHECK(b, launch_cg_alpha_multi(items, nm, b->stream));
         for (const auto &u : b->ugroups)
             BHIPCHECK(b, launch_cg_update_multi(reinterpret_cast<const UpdArgs *>(base + u.args_off),
                                                 reinterpret_cast<const int *>(base + u.woff_off), u.np, u.total,

@@ -160,14 +160,14 @@ struct UpdArgs {
     int nc;
     int Nh;
     int nblocks;  // work-groups of this problem (fixes the reduction order)
-    const CgStatus *st;
+    CgStatus *st;
     double *partial;
+    const double *pq_part;  // partials of (p, K p) from the projection pass, or nullptr
+    int npq;
 };
 
 struct CgItem {
     CgStatus *st;
-    const double *pq_part;
-    int npq;
     const double *rr_part;
     int nrr;
     double *hist;      // (rr, alpha) per iteration, or nullptr
@@ -216,7 +216,6 @@ hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, 
                                int total, bool fp64, hipStream_t s);
 hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int *woff, int np, int total,
                             bool fp64, hipStream_t s);
-hipError_t launch_cg_alpha_multi(const CgItem *items, int np, hipStream_t s);
 hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t s);
 hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, int total, bool fp64,
                                   hipStream_t s);

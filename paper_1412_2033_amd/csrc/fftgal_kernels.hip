@@ -956,9 +956,22 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
 // ---------------------------------------------------------------------------
 // CG scalar and vector kernels (Remark CG; Saad Alg. 6.18).
 // ---------------------------------------------------------------------------
+// Sum of n partials in a fixed order: thread t adds entries t, t + blockDim,
+// t + 2 blockDim, ... in turn, then block_sum; the loads of eight such steps
+// are issued together (an entry past n adds an exact zero).
 __device__ double sum_fixed(const double *part, int n) {
+    constexpr int G = 8;
     double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    for (int i0 = threadIdx.x; i0 < n; i0 += G * blockDim.x) {
+        double t[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int i = i0 + j * (int)blockDim.x;
+            t[j] = i < n ? part[i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) v += t[j];
+    }
     return block_sum(v);
 }
 
@@ -1256,11 +1269,24 @@ __device__ __forceinline__ const Vt<T> *twiddles_to_lds(Vt<T> *dst, const Vt<T> 
     }
 }
 
-// pencils (or row pairs) per work-group so that one batch of all d
-// components stays within 24 KB of LDS (the passes are latency-bound:
-// smaller work-groups put more of them on a CU)
+// row pairs per work-group of the specialised anisotropic row pass so that
+// one batch of all d components stays within 24 KB of LDS (the passes are
+// latency-bound: smaller work-groups put more of them on a CU)
 constexpr int fast_batch(int n, int es, int d) {
     const int cap = 24 * 1024;
+    int b = 16;
+    while (b > 1 && d * b * n * es > cap) b /= 2;
+    return b;
+}
+
+// pencils per work-group of the specialised strided-axis pass: one batch of
+// all d components within 24 KB of LDS, or 48 KB for 3D FP64 transforms of
+// 225 points or more.  There the larger batch keeps more of the work-group
+// busy in the butterfly stages and lengthens the contiguous runs of the
+// strided operands; elsewhere (FP32, 2D, shorter 3D transforms) the smaller
+// work-groups, more of them per CU, measured faster.
+constexpr int pencil_batch(int n, int es, int d) {
+    const int cap = (es >= 16 && d == 3 && n >= 225) ? 48 * 1024 : 24 * 1024;
     int b = 16;
     while (b > 1 && d * b * n * es > cap) b /= 2;
     return b;
@@ -1298,7 +1324,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                                                         const int *__restrict__ woff, int np) {
     using V = Vt<T>;
     constexpr int N = kFastSched[FI].n;
-    constexpr int B = fast_batch(N, sizeof(V), D);
+    constexpr int B = pencil_batch(N, sizeof(V), D);
     constexpr int NB = D * B;  // LDS layout [pos][component][batch]
     constexpr int LPI = kThreads / NB;  // positions per step of the plain prologue / epilogue
     int lb;
@@ -2356,7 +2382,7 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
 template <typename T, int FI, int D>
 void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
     constexpr int N = kFastSched[FI].n;
-    constexpr int B = fast_batch(N, sizeof(Vt<T>), D);
+    constexpr int B = pencil_batch(N, sizeof(Vt<T>), D);
     const size_t lds = sizeof(Vt<T>) * ((size_t)N * D * B + tw_lds_entries(N, sizeof(Vt<T>)));
     hipLaunchKernelGGL((pencil_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
@@ -2589,23 +2615,7 @@ void launch_gram_fast(int fi, int d, const RowArgs *args, const int *woff, int n
     }
 }
 
-// ---- multi-problem CG kernels (one problem per work-group for the scalar ones) ----
-__global__ __launch_bounds__(kThreads) void cg_alpha_multi_kernel(const CgItem *__restrict__ items) {
-    const CgItem &it = items[blockIdx.x];
-    CgStatus *st = it.st;
-    if (st->done) return;
-    const double pq = sum_fixed(it.pq_part, it.npq);
-    if (threadIdx.x == 0) {
-        st->pq = pq;
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            st->breakdown = 1;
-            st->done = 1;
-        } else {
-            st->alpha = st->rr / pq;
-        }
-    }
-}
-
+// ---- multi-problem CG kernels (one problem per work-group for the scalar one) ----
 __global__ __launch_bounds__(kThreads) void cg_check_multi_kernel(const CgItem *__restrict__ items) {
     const CgItem &it = items[blockIdx.x];
     CgStatus *st = it.st;
@@ -2650,20 +2660,25 @@ __global__ __launch_bounds__(kThreads) void cg_check_multi_kernel(const CgItem *
 }
 
 // CG update: kUpdPer elements per thread in one pass (the grid, and with it
-// the reduction order, depends only on the problem size)
+// the reduction order, depends only on the problem size).  Every work-group
+// sums the (p, K p) partials of the projection pass itself, in one fixed
+// order, while its vector loads are in flight, and forms alpha = (r, r) /
+// (p, K p); work-group 0 records pq and alpha (or a breakdown) in the status.
 constexpr int kUpdPer = 2;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs *__restrict__ ua,
                                                                    const int *__restrict__ woff, int np) {
     constexpr int U = kUpdPer;
+    __shared__ double bcast;
     int lb;
     const UpdArgs &a = ua[find_problem(woff, np, &lb)];
-    if (a.st->done) return;
+    CgStatus *st = a.st;
+    if (st->done) return;
+    const double rr = st->rr;
     auto *x = gbl(reinterpret_cast<Vt<T> *>(a.x));
     auto *r = gbl(reinterpret_cast<Vt<T> *>(a.r));
     const auto *p = gbl(reinterpret_cast<const Vt<T> *>(a.p));
     const auto *q = gbl(reinterpret_cast<const Vt<T> *>(a.q));
-    const T alpha = T(a.st->alpha);
     const int npc = (int)a.n_per_comp;
     const int total = npc * a.nc;
     // all loads of the thread's U elements in flight together
@@ -2687,6 +2702,23 @@ __global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs
         qx[j] = qv.x;
         qy[j] = qv.y;
     }
+    const double pq = sum_fixed(a.pq_part, a.npq);
+    if (threadIdx.x == 0) bcast = pq;
+    __syncthreads();
+    const double pqa = bcast;
+    const bool bad = !(pqa > 0.0) || !isfinite(pqa);
+    const double alpha_d = bad ? 0.0 : rr / pqa;
+    if (lb == 0 && threadIdx.x == 0) {
+        st->pq = pqa;
+        if (bad) {
+            st->breakdown = 1;
+            st->done = 1;
+        } else {
+            st->alpha = alpha_d;
+        }
+    }
+    if (bad) return;
+    const T alpha = T(alpha_d);
     double part = 0.0;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
@@ -2816,7 +2848,7 @@ void configure_pencil(PencilArgs &a, bool fp64) {
     for (int s = 0; ok && s < a.f.nst; ++s) ok = a.f.radix[s] == kFastSched[fi].r[s];
     if (ok) {
         a.fast = 1;
-        a.B = fast_batch(a.f.n, fp64 ? 16 : 8, a.d);
+        a.B = pencil_batch(a.f.n, fp64 ? 16 : 8, a.d);
         return;
     }
     a.fast = 0;
@@ -2937,11 +2969,6 @@ hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int
         launch_row_fast<double>(fi, proto.d, args, woff, np, total, s);
     else
         launch_row_fast<float>(fi, proto.d, args, woff, np, total, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_alpha_multi(const CgItem *items, int np, hipStream_t s) {
-    hipLaunchKernelGGL(cg_alpha_multi_kernel, dim3(np), dim3(kThreads), 0, s, items);
     return hipGetLastError();
 }
 
