@@ -353,9 +353,12 @@ template <typename T>
 __device__ __forceinline__ int basis(int d, int kind, int k1, int k2, int k3, T t[2][3]) {
     // straight-line code (selects, no branches): written per branch, the
     // compiler keeps the partially written rows of t on the stack
+    // |k|^2 and |k x e_j|^2 are exact integers; rsqrt (reciprocal square
+    // root, within a few ulp) replaces a square root and a division, and the
+    // second one is only formed for the 3D dual (kind is uniform per launch)
     const T a = T(k1), b = T(k2), c = T(d == 3 ? k3 : 0);
     const T nn = a * a + b * b + c * c;
-    const T inv = nn == T(0) ? T(0) : T(1) / sqrt(nn);
+    const T inv = nn == T(0) ? T(0) : rsqrt(nn);
     const T h1 = a * inv, h2 = b * inv, h3 = c * inv;
     const int ab1 = k1 < 0 ? -k1 : k1, ab2 = k2 < 0 ? -k2 : k2, ab3 = k3 < 0 ? -k3 : k3;
     const bool x1 = ab1 <= ab2 && ab1 <= ab3;  // k x e_1
@@ -363,13 +366,16 @@ __device__ __forceinline__ int basis(int d, int kind, int k1, int k2, int k3, T 
     T u1 = x1 ? T(0) : x2 ? -c : b;
     T u2 = x1 ? c : x2 ? T(0) : -a;
     T u3 = x1 ? -b : x2 ? a : T(0);
-    const T uu = u1 * u1 + u2 * u2 + u3 * u3;
-    const T un = uu == T(0) ? T(0) : T(1) / sqrt(uu);
+    const bool primal = kind == KIND_E, two = d == 2;
+    T un = T(0);
+    if (!primal && !two) {
+        const T uu = u1 * u1 + u2 * u2 + u3 * u3;
+        un = uu == T(0) ? T(0) : rsqrt(uu);
+    }
     u1 *= un;
     u2 *= un;
     u3 *= un;
     const T s = (k1 != 0) ? (k1 > 0 ? T(1) : T(-1)) : (k2 != 0) ? (k2 > 0 ? T(1) : T(-1)) : (k3 > 0 ? T(1) : T(-1));
-    const bool primal = kind == KIND_E, two = d == 2;
     t[0][0] = primal ? h1 : two ? -h2 : u1;
     t[0][1] = primal ? h2 : two ? h1 : u2;
     t[0][2] = primal ? h3 : two ? T(0) : u3;

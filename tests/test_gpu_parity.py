@@ -106,7 +106,19 @@ def test_c1_full_size_against_golden(fg):
     assert _rel(res["lower"], gold["lower"]) < 1e-10
 
 
-@pytest.mark.parametrize("case", ["c2_365", "c3", "c2_1013"])
+def _golden_micro(case):
+    if case.startswith("c2"):
+        return synth.circle_inclusion_vf(0.3, 1.0, 100.0), None
+    if case == "c3":
+        return synth.cube_inclusion_aniso(0.5, 3), None
+    # the benchmark workload: 225^3 random-field voxels, image resident on the device
+    import torch
+    micro = synth.grf_voxels(5, (225, 225, 225), d=3, corr_len=0.05, vf=0.4, a_matrix=1.0, a_incl=100.0)
+    micro["image"] = torch.from_numpy(np.ascontiguousarray(micro["image"])).to("cuda:0")
+    return micro, (225, 225, 225)
+
+
+@pytest.mark.parametrize("case", ["c2_365", "c3", "c2_1013", "c5"])
 def test_full_size_against_golden(fg, case):
     path = os.path.join(HERE, "golden", case + ".json")
     if not os.path.exists(path):
@@ -114,10 +126,11 @@ def test_full_size_against_golden(fg, case):
     with open(path) as f:
         gold = json.load(f)
     N = tuple(gold["N"])
-    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0) if case.startswith("c2") else synth.cube_inclusion_aniso(0.5, 3)
-    res = _gpu(fg, micro, N, rtol=gold["tol"])
+    micro, P = _golden_micro(case)
+    res = _gpu(fg, micro, N, rtol=gold["tol"], P=P)
     assert _rel(res["upper"], gold["upper"]) < 1e-10
     assert _rel(res["lower"], gold["lower"]) < 1e-10
+    assert np.min(np.linalg.eigvalsh(np.asarray(res["upper"]) - np.asarray(res["lower"]))) > 0
 
 
 def test_homogeneous_zero_iterations(fg):
