@@ -462,65 +462,72 @@ int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss,
                    bool update_p, const CgStatus *st, void **rows_out, int cls_expand, int cls_inv, int shift = 0) {
     const Dims &D = pl->D;
     const int d = D.d;
-    const int ncomp_total = nsol * d;
-    PencilArgs a = base_pencil(pl, pl->fM[0], fp64);
-    set_shift(pl, a, shift);
-    a.pro = PRO_EXPAND;
-    a.epi = EPI_PLAIN;
-    a.kind = kind;
-    a.nc = pl->nc(kind);
-    a.ncomp = d;
-    a.nsol = nsol;
-    a.sgn = +1;
-    a.L_in = D.N[0];
-    a.L_out = D.M[0];
-    a.st_cs = D.Ns;
-    a.st_ss = st_ss;
-    a.update_p = update_p ? 1 : 0;
-    a.status = st;
-    if (update_p) {
-        a.st_r = pl->ws + pl->Lo.r;
-        a.st_p = pl->ws + pl->Lo.p;
-    } else {
-        a.st_x = state;
+    const size_t es = fp64 ? 16 : 8;
+    // several solutions (the energy quadrature): one launch per solution, so
+    // that each takes the specialised kernels; solution s fills the
+    // components s d .. s d + d - 1 of the intermediates
+    for (int s = 0; s < nsol; ++s) {
+        PencilArgs a = base_pencil(pl, pl->fM[0], fp64);
+        set_shift(pl, a, shift);
+        a.pro = PRO_EXPAND;
+        a.epi = EPI_PLAIN;
+        a.kind = kind;
+        a.nc = pl->nc(kind);
+        a.ncomp = d;
+        a.nsol = 1;
+        a.sgn = +1;
+        a.L_in = D.N[0];
+        a.L_out = D.M[0];
+        a.st_cs = D.Ns;
+        a.st_ss = st_ss;
+        a.update_p = update_p ? 1 : 0;
+        a.status = st;
+        if (update_p) {
+            a.st_r = pl->ws + pl->Lo.r;
+            a.st_p = pl->ws + pl->Lo.p;
+        } else {
+            a.st_x = state == nullptr ? nullptr : static_cast<const char *>(state) + (size_t)s * st_ss * es;
+        }
+        if (d == 3) {
+            a.nb = D.N[1] * D.Nh;
+            a.in_ls = (long)D.N[1] * D.Nh;
+            a.out_ls = (long)D.N[1] * D.Nh;
+            a.out_cs = (long)D.M[0] * D.N[1] * D.Nh;
+        } else {
+            a.nb = D.Nh;
+            a.in_ls = D.Nh;
+            a.out_ls = D.Nh;
+            a.out_cs = (long)D.M[0] * D.Nh;
+        }
+        a.out = pl->ws + pl->Lo.T1 + (size_t)s * d * a.out_cs * es;
+        int rc = run_pencil(pl, a, 1, fp64, fp64 ? 8 : 16, cls_expand);
+        if (rc) return rc;
     }
-    a.out = pl->ws + pl->Lo.T1;
-    if (d == 3) {
-        a.nb = D.N[1] * D.Nh;
-        a.in_ls = (long)D.N[1] * D.Nh;
-        a.out_ls = (long)D.N[1] * D.Nh;
-        a.out_cs = (long)D.M[0] * D.N[1] * D.Nh;
-    } else {
-        a.nb = D.Nh;
-        a.in_ls = D.Nh;
-        a.out_ls = D.Nh;
-        a.out_cs = (long)D.M[0] * D.Nh;
-    }
-    int rc = run_pencil(pl, a, 1, fp64, fp64 ? 8 : 16, cls_expand);
-    if (rc) return rc;
     if (d == 2) {
         *rows_out = pl->ws + pl->Lo.T1;
         return FFTGAL_OK;
     }
-    PencilArgs b = base_pencil(pl, pl->fM[1], fp64);
-    b.pro = PRO_PLAIN;
-    b.epi = EPI_PLAIN;
-    b.ncomp = ncomp_total;
-    b.sgn = +1;
-    b.L_in = D.N[1];
-    b.L_out = D.M[1];
-    b.status = st;
-    b.in = pl->ws + pl->Lo.T1;
-    b.out = pl->ws + pl->Lo.T2;
-    b.nb = D.Nh;
-    b.in_cs = (long)D.M[0] * D.N[1] * D.Nh;
-    b.in_os = (long)D.N[1] * D.Nh;
-    b.in_ls = D.Nh;
-    b.out_cs = (long)D.M[0] * D.M[1] * D.Nh;
-    b.out_os = (long)D.M[1] * D.Nh;
-    b.out_ls = D.Nh;
-    rc = run_pencil(pl, b, D.M[0], fp64, fp64 ? 8 : 16, cls_inv);
-    if (rc) return rc;
+    for (int s = 0; s < nsol; ++s) {
+        PencilArgs b = base_pencil(pl, pl->fM[1], fp64);
+        b.pro = PRO_PLAIN;
+        b.epi = EPI_PLAIN;
+        b.ncomp = d;
+        b.sgn = +1;
+        b.L_in = D.N[1];
+        b.L_out = D.M[1];
+        b.status = st;
+        b.nb = D.Nh;
+        b.in_cs = (long)D.M[0] * D.N[1] * D.Nh;
+        b.in_os = (long)D.N[1] * D.Nh;
+        b.in_ls = D.Nh;
+        b.out_cs = (long)D.M[0] * D.M[1] * D.Nh;
+        b.out_os = (long)D.M[1] * D.Nh;
+        b.out_ls = D.Nh;
+        b.in = pl->ws + pl->Lo.T1 + (size_t)s * d * b.in_cs * es;
+        b.out = pl->ws + pl->Lo.T2 + (size_t)s * d * b.out_cs * es;
+        const int rc = run_pencil(pl, b, D.M[0], fp64, fp64 ? 8 : 16, cls_inv);
+        if (rc) return rc;
+    }
     *rows_out = pl->ws + pl->Lo.T2;
     return FFTGAL_OK;
 }

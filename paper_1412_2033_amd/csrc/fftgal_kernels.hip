@@ -2494,9 +2494,12 @@ void launch_row_iso(int fi, const RowArgs *args, const int *woff, int np, int to
 // Energy Gram quadrature (ROW_GRAM) for the specialised lengths: all d^2
 // component fields of the d solutions are transformed to the grid in one
 // in-place batch, then (A_M (E_s + e_s), E_t + e_t) is summed over the rows.
+// Row pairs per work-group: one batch within 48 KB of LDS, so that several
+// work-groups share a CU (a single pair of 225-point rows of 9 fields takes
+// 32 KB in FP64: four work-groups per CU).
 constexpr int gram_batch(int n, int es, int d) {
     int b = 8;
-    while (b > 1 && d * d * b * n * es > 144 * 1024) b /= 2;
+    while (b > 1 && d * d * b * n * es > 48 * 1024) b /= 2;
     return b;
 }
 
