@@ -118,7 +118,7 @@ def _golden_micro(case):
     return micro, (225, 225, 225)
 
 
-@pytest.mark.parametrize("case", ["c2_365", "c3", "c2_1013", "c5"])
+@pytest.mark.parametrize("case", ["c2_41", "c2_365", "c3", "c2_1013", "c5"])
 def test_full_size_against_golden(fg, case):
     path = os.path.join(HERE, "golden", case + ".json")
     if not os.path.exists(path):
