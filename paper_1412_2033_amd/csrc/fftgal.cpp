@@ -312,6 +312,28 @@ hipEvent_t pool_event(Plan *pl) {
 
 // Brackets the launches issued during its lifetime with two events of class
 // `cls` when the plan's timing is on.
+// Timing of one specialised launch: the dispatch records the two events at
+// its own start and end (the kernel's duration, no marker packets).
+struct TimedLaunch {
+    Plan *pl;
+    int cls;
+    LaunchEv ev;
+    TimedLaunch(Plan *p, int c) : pl(p), cls(c) {
+        if ((pl->timing_mask >> cls) & 1u) {
+            ev.start = pool_event(pl);
+            ev.stop = ev.start ? pool_event(pl) : nullptr;
+            if (ev.start && !ev.stop) {
+                pl->pool.push_back(ev.start);
+                ev.start = nullptr;
+            }
+        }
+    }
+    ~TimedLaunch() {
+        if (ev.start) pl->evs.push_back({cls, ev.start, ev.stop});
+    }
+};
+
+// Timing of a span of stream work between two recorded events.
 struct Timed {
     Plan *pl;
     int cls;
@@ -405,10 +427,10 @@ int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int Bmax, int cls
         hipError_t e;
         void *dev = ring_upload(pl, a, &e);
         HIPCHECK(pl, e);
-        Timed t(pl, cls);
+        TimedLaunch t(pl, cls);
         HIPCHECK(pl, launch_pencil_multi(a, reinterpret_cast<const PencilArgs *>(dev),
                                          reinterpret_cast<const int *>(pl->arg_slot(0)), 1, pencil_grid(a, nouter),
-                                         fp64, pl->stream));
+                                         fp64, pl->stream, t.ev));
         return FFTGAL_OK;
     }
     Timed t(pl, cls);
@@ -436,10 +458,10 @@ int run_row(Plan *pl, RowArgs &r, bool fp64, int cls) {
         hipError_t e;
         void *dev = ring_upload(pl, r, &e);
         HIPCHECK(pl, e);
-        Timed t(pl, cls);
+        TimedLaunch t(pl, cls);
         HIPCHECK(pl, launch_row_multi(r, reinterpret_cast<const RowArgs *>(dev),
                                       reinterpret_cast<const int *>(pl->arg_slot(0)), 1, row_grid(r), fp64,
-                                      pl->stream));
+                                      pl->stream, t.ev));
         return FFTGAL_OK;
     }
     Timed t(pl, cls);
@@ -971,20 +993,25 @@ int upload_iteration(Plan *pl, const IterCfg &cfg) {
 // Launch one captured pass of a single plan (specialised passes read their
 // arguments from `dev_args`).
 int launch_pass(Plan *pl, const PassRec &r, const void *dev_args) {
-    Timed t(pl, r.cls);
     const int *woff0 = reinterpret_cast<const int *>(pl->arg_slot(0));
     if (r.type == 0) {
-        if (r.pa.fast)
+        if (r.pa.fast) {
+            TimedLaunch t(pl, r.cls);
             HIPCHECK(pl, launch_pencil_multi(r.pa, reinterpret_cast<const PencilArgs *>(dev_args), woff0, 1, r.grid,
-                                             r.fp64, pl->stream));
-        else
+                                             r.fp64, pl->stream, t.ev));
+        } else {
+            Timed t(pl, r.cls);
             HIPCHECK(pl, launch_pencil(r.pa, r.nouter, r.fp64, pl->stream));
+        }
     } else {
-        if (r.ra.fast)
+        if (r.ra.fast) {
+            TimedLaunch t(pl, r.cls);
             HIPCHECK(pl, launch_row_multi(r.ra, reinterpret_cast<const RowArgs *>(dev_args), woff0, 1, r.grid, r.fp64,
-                                          pl->stream));
-        else
+                                          pl->stream, t.ev));
+        } else {
+            Timed t(pl, r.cls);
             HIPCHECK(pl, launch_row(r.ra, r.fp64, pl->stream));
+        }
     }
     return FFTGAL_OK;
 }
@@ -998,11 +1025,11 @@ int enqueue_iteration(Plan *pl, const IterCfg &cfg) {
     const UpdArgs *upd = reinterpret_cast<const UpdArgs *>(pl->iter_slot(kMaxPasses));
     const int *woff0 = reinterpret_cast<const int *>(pl->arg_slot(0));
     {
-        Timed t(pl, FFTGAL_K_CG_UPDATE);
-        HIPCHECK(pl, launch_cg_update_multi(upd, woff0, 1, cfg.upd.nblocks, cfg.fp64, pl->stream));
+        TimedLaunch t(pl, FFTGAL_K_CG_UPDATE);
+        HIPCHECK(pl, launch_cg_update_multi(upd, woff0, 1, cfg.upd.nblocks, cfg.fp64, pl->stream, t.ev));
     }
-    Timed t(pl, FFTGAL_K_CG_SCALAR);
-    HIPCHECK(pl, launch_cg_check_multi(item, 1, pl->stream));
+    TimedLaunch t(pl, FFTGAL_K_CG_SCALAR);
+    HIPCHECK(pl, launch_cg_check_multi(item, 1, pl->stream, t.ev));
     return FFTGAL_OK;
 }
 

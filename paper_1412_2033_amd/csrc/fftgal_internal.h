@@ -212,13 +212,20 @@ hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const d
                           double btol, double *hist, hipStream_t s);
 // Multi-problem launches: `args` and `woff` are device arrays; problem i
 // owns work-groups [woff[i], woff[i + 1]) of a grid of `total` work-groups.
+// Optional pair of events that a dispatch records itself at its start and at
+// its end (hipExtLaunchKernel): the kernel's own duration, with no marker
+// packets between launches.  Both null: an ordinary launch.
+struct LaunchEv {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
 hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, const int *woff, int np,
-                               int total, bool fp64, hipStream_t s);
+                               int total, bool fp64, hipStream_t s, LaunchEv ev = LaunchEv{});
 hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int *woff, int np, int total,
-                            bool fp64, hipStream_t s);
-hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t s);
+                            bool fp64, hipStream_t s, LaunchEv ev = LaunchEv{});
+hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t s, LaunchEv ev = LaunchEv{});
 hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, int total, bool fp64,
-                                  hipStream_t s);
+                                  hipStream_t s, LaunchEv ev = LaunchEv{});
 int pencil_grid(const PencilArgs &a, int nouter);  // work-groups of one problem
 int update_blocks(long n);                         // work-groups of one CG update
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);

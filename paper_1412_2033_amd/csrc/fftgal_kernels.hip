@@ -9,6 +9,7 @@
 
 #include <type_traits>
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -2385,24 +2386,39 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     }
 }
 
+// Launch target of the specialised kernels: the stream and, for timing, the
+// events the dispatch records at its own start and end.
+struct Disp {
+    hipStream_t s;
+    LaunchEv ev;
+    Disp(hipStream_t st, LaunchEv e = LaunchEv{}) : s(st), ev(e) {}
+};
+template <typename... KArgs, typename... Args>
+void dispatch(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, const Disp &d, Args... args) {
+    if (d.ev.start != nullptr)
+        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, d.s, d.ev.start, d.ev.stop, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, d.s, args...);
+}
+
 template <typename T, int FI, int D>
-void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int total, const Disp &s) {
     constexpr int N = kFastSched[FI].n;
     constexpr int B = pencil_batch(N, sizeof(Vt<T>), D);
     const size_t lds = sizeof(Vt<T>) * ((size_t)N * D * B + tw_lds_entries(N, sizeof(Vt<T>)));
-    hipLaunchKernelGGL((pencil_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
+    dispatch((pencil_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
 
 template <typename T, int FI, int D>
-void launch_row_fast_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_row_fast_t(const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     constexpr int N = kFastSched[FI].n;
     constexpr int RP = fast_batch(N, sizeof(Vt<T>), D);
     const size_t lds = sizeof(Vt<T>) * ((size_t)N * D * RP + tw_lds_entries(N, sizeof(Vt<T>)));
-    hipLaunchKernelGGL((row_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
+    dispatch((row_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
 
 template <typename T, int FI>
-void launch_pencil_fast_d(int d, const PencilArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_pencil_fast_d(int d, const PencilArgs *args, const int *woff, int np, int total, const Disp &s) {
     if (d == 3)
         launch_pencil_fast_t<T, FI, 3>(args, woff, np, total, s);
     else
@@ -2410,7 +2426,7 @@ void launch_pencil_fast_d(int d, const PencilArgs *args, const int *woff, int np
 }
 
 template <typename T, int FI>
-void launch_row_fast_d(int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_row_fast_d(int d, const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     if (d == 3)
         launch_row_fast_t<T, FI, 3>(args, woff, np, total, s);
     else
@@ -2419,7 +2435,7 @@ void launch_row_fast_d(int d, const RowArgs *args, const int *woff, int np, int 
 
 template <typename T>
 void launch_pencil_fast(int fi, int d, const PencilArgs *args, const int *woff, int np, int total,
-                        hipStream_t s) {
+                        const Disp &s) {
     switch (fi) {
         case 0: launch_pencil_fast_d<T, 0>(d, args, woff, np, total, s); break;
         case 1: launch_pencil_fast_d<T, 1>(d, args, woff, np, total, s); break;
@@ -2431,7 +2447,7 @@ void launch_pencil_fast(int fi, int d, const PencilArgs *args, const int *woff, 
 }
 
 template <typename T>
-void launch_row_fast(int fi, int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_row_fast(int fi, int d, const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     switch (fi) {
         case 0: launch_row_fast_d<T, 0>(d, args, woff, np, total, s); break;
         case 1: launch_row_fast_d<T, 1>(d, args, woff, np, total, s); break;
@@ -2444,33 +2460,33 @@ void launch_row_fast(int fi, int d, const RowArgs *args, const int *woff, int np
 
 
 template <typename T, int FI>
-void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     if constexpr (palindromic(FI)) {
         constexpr int N = kFastSched[FI].n;
         if constexpr (kFastSched[FI].nst == 2) {
             const size_t lds = sizeof(T) * (size_t)split_tb(FI) * N + sizeof(Vt<T>) * N;
-            hipLaunchKernelGGL((row_iso_split<T, FI>), dim3(total), dim3(split_nt(FI)), lds, s, args, woff, np);
+            dispatch((row_iso_split<T, FI>), dim3(total), dim3(split_nt(FI)), lds, s, args, woff, np);
         } else {
             const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + N);
-            hipLaunchKernelGGL((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
+            dispatch((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
         }
     }
 }
 
 template <typename T, int FI>
-void launch_row_staged_t(int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_row_staged_t(int d, const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     if constexpr (palindromic(FI) && kFastSched[FI].nst == 2) {
         if (d == 3)
-            hipLaunchKernelGGL((row_iso_staged<T, FI, 3>), dim3(total), dim3(staged_nt(FI, 3)), staged_lds<T>(FI, 3),
+            dispatch((row_iso_staged<T, FI, 3>), dim3(total), dim3(staged_nt(FI, 3)), staged_lds<T>(FI, 3),
                                s, args, woff, np);
         else
-            hipLaunchKernelGGL((row_iso_staged<T, FI, 2>), dim3(total), dim3(staged_nt(FI, 2)), staged_lds<T>(FI, 2),
+            dispatch((row_iso_staged<T, FI, 2>), dim3(total), dim3(staged_nt(FI, 2)), staged_lds<T>(FI, 2),
                                s, args, woff, np);
     }
 }
 
 template <typename T>
-void launch_row_staged(int fi, int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_row_staged(int fi, int d, const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     switch (fi) {
         case 0: launch_row_staged_t<T, 0>(d, args, woff, np, total, s); break;
         case 2: launch_row_staged_t<T, 2>(d, args, woff, np, total, s); break;
@@ -2479,7 +2495,7 @@ void launch_row_staged(int fi, int d, const RowArgs *args, const int *woff, int 
 }
 
 template <typename T>
-void launch_row_iso(int fi, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_row_iso(int fi, const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     switch (fi) {
         case 0: launch_row_iso_t<T, 0>(args, woff, np, total, s); break;
         case 1: launch_row_iso_t<T, 1>(args, woff, np, total, s); break;
@@ -2598,22 +2614,22 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
 }
 
 template <int FI, int D>
-void launch_gram_fast_t(const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_gram_fast_t(const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     constexpr int N = kFastSched[FI].n;
     constexpr int RP = gram_batch(N, 16, D);
     const size_t lds = (size_t)16 * N * D * D * RP;
-    hipLaunchKernelGGL((row_gram_fast<double, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
+    dispatch((row_gram_fast<double, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
 }
 
 template <int FI>
-void launch_gram_fast_d(int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_gram_fast_d(int d, const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     if (d == 3)
         launch_gram_fast_t<FI, 3>(args, woff, np, total, s);
     else
         launch_gram_fast_t<FI, 2>(args, woff, np, total, s);
 }
 
-void launch_gram_fast(int fi, int d, const RowArgs *args, const int *woff, int np, int total, hipStream_t s) {
+void launch_gram_fast(int fi, int d, const RowArgs *args, const int *woff, int np, int total, const Disp &s) {
     switch (fi) {
         case 0: launch_gram_fast_d<0>(d, args, woff, np, total, s); break;
         case 1: launch_gram_fast_d<1>(d, args, woff, np, total, s); break;
@@ -2939,9 +2955,10 @@ int pencil_grid(const PencilArgs &a, int nouter) { return pencil_grid_x(a) * nou
 int update_blocks(long n) { return (int)std::max<long>(1, (n + (long)kThreads * kUpdPer - 1) / ((long)kThreads * kUpdPer)); }
 
 hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, const int *woff, int np, int total,
-                               bool fp64, hipStream_t s) {
+                               bool fp64, hipStream_t st, LaunchEv ev) {
     const int fi = fast_index(proto.f.n);
     if (!proto.fast || fi < 0 || np < 1 || total < 1) return hipErrorInvalidValue;
+    const Disp s(st, ev);
     if (fp64)
         launch_pencil_fast<double>(fi, proto.d, args, woff, np, total, s);
     else
@@ -2950,9 +2967,10 @@ hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, 
 }
 
 hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int *woff, int np, int total, bool fp64,
-                            hipStream_t s) {
+                            hipStream_t st, LaunchEv ev) {
     const int fi = fast_index(proto.f.n);
     if (!proto.fast || fi < 0 || np < 1 || total < 1) return hipErrorInvalidValue;
+    const Disp s(st, ev);
     if (proto.mode == ROW_GRAM) {
         if (!fp64) return hipErrorInvalidValue;
         launch_gram_fast(fi, proto.d, args, woff, np, total, s);
@@ -2981,16 +2999,18 @@ hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int
     return hipGetLastError();
 }
 
-hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t s) {
-    hipLaunchKernelGGL(cg_check_multi_kernel, dim3(np), dim3(kThreads), 0, s, items);
+hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t st, LaunchEv ev) {
+    dispatch(cg_check_multi_kernel, dim3(np), dim3(kThreads), 0, Disp(st, ev), items);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, int total, bool fp64, hipStream_t s) {
+hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, int total, bool fp64, hipStream_t st,
+                                  LaunchEv ev) {
+    const Disp s(st, ev);
     if (fp64)
-        hipLaunchKernelGGL(cg_update_multi_kernel<double>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
+        dispatch(cg_update_multi_kernel<double>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
     else
-        hipLaunchKernelGGL(cg_update_multi_kernel<float>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
+        dispatch(cg_update_multi_kernel<float>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
     return hipGetLastError();
 }
 
