@@ -338,6 +338,28 @@ __device__ double block_sum(double v) {
     return s;
 }
 
+// K work-group sums at once, each in the order of block_sum (a shuffle tree
+// per wave, then the waves in turn), written to out[0 .. K-1] by the first K
+// threads: one barrier for all K instead of three per sum.
+template <int K>
+__device__ void block_sum_many(const double (&v)[K], double *out) {
+    __shared__ double red[K][kThreads / 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) red[k][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[threadIdx.x][w];
+        out[threadIdx.x] = s;
+    }
+}
+
 __device__ __forceinline__ int wrapi(int i, int L) { return i < (L + 1) / 2 ? i : i - L; }
 __device__ __forceinline__ int posmod(int k, int n) {
     int r = k % n;
@@ -2606,11 +2628,7 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
             }
         }
     }
-#pragma unroll
-    for (int i = 0; i < D * D; ++i) {
-        const double sum = block_sum(gs[i]);
-        if (threadIdx.x == 0) a.partial[(long)lb * D * D + i] = sum;
-    }
+    block_sum_many<D * D>(gs, a.partial + (long)lb * D * D);
 }
 
 template <int FI, int D>
