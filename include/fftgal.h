@@ -299,11 +299,13 @@ int fftgal_grid_size(const struct fftgal_plan *plan, int axis);
 
 /*
  * Kernel timing (tracing).  While enabled, every kernel launch of the plan is
- * bracketed by a pair of HIP events on the plan's stream, tagged with one of
- * the classes below.  fftgal_read_timing() waits for the stream, writes the
- * summed milliseconds and the launch counts per class (arrays of
- * FFTGAL_K_COUNT entries; either may be NULL) since the previous read, and
- * resets them.  Enabling adds two event records per launch.
+ * timed by a pair of HIP events tagged with one of the classes below: the
+ * specialised kernels and the CG kernels are dispatched so that the dispatch
+ * itself records the events at the kernel's start and end; other launches are
+ * bracketed by two event records on the plan's stream.  fftgal_read_timing()
+ * waits for the stream, writes the summed milliseconds and the launch counts
+ * per class (arrays of FFTGAL_K_COUNT entries; either may be NULL) since the
+ * previous read, and resets them.
  */
 enum fftgal_kernel_class {
     FFTGAL_K_EXPAND = 0,      /* CG state -> d components, inverse DFT along axis 1 */
@@ -311,8 +313,8 @@ enum fftgal_kernel_class {
     FFTGAL_K_ROW = 2,         /* C2R along axis d, material multiply, R2C           */
     FFTGAL_K_PENCIL_FWD = 3,  /* forward DFT along axis 2 (d = 3)                   */
     FFTGAL_K_PROJECT = 4,     /* forward DFT along axis 1, projection, (p, Kp)      */
-    FFTGAL_K_CG_UPDATE = 5,   /* x += alpha p, r -= alpha q, (r, r)                 */
-    FFTGAL_K_CG_SCALAR = 6,   /* alpha / beta / stopping test, vector clears        */
+    FFTGAL_K_CG_UPDATE = 5,   /* alpha, x += alpha p, r -= alpha q, (r, r)          */
+    FFTGAL_K_CG_SCALAR = 6,   /* beta / stopping test, initial state, clears        */
     FFTGAL_K_RHS = 7,         /* right-hand side -G A_M E                           */
     FFTGAL_K_BOUNDS = 8,      /* FP64 fields and energy Gram quadrature             */
     FFTGAL_K_SETUP = 9,       /* material fields A_M, B_M                           */
