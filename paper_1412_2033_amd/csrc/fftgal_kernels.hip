@@ -428,7 +428,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
     using V = Vt<T>;
     if (a.status != nullptr && a.status->done) return;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     const int n = a.f.n;
     const int B = a.B;
     V *bufA = reinterpret_cast<V *>(smem_raw);
@@ -784,7 +784,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     using V = Vt<T>;
     if (a.status != nullptr && a.status->done) return;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     const int n = a.f.n;
     const int RP = a.RP;
     const int nh = a.Nh_row;
@@ -1359,7 +1359,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     int lb;
     const PencilArgs &a = pa[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     V *X = reinterpret_cast<V *>(smem_raw);
     const int gx = (a.nb + B - 1) / B;
     const int o = lb / gx;
@@ -1629,7 +1629,7 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
     int lb;
     const RowArgs &a = ra[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     V *X = reinterpret_cast<V *>(smem_raw);
     const int nh = a.Nh_row;
     const V *tw = twiddles_to_lds<T, N>(X + N * NB, reinterpret_cast<const V *>(a.tw) + a.f.twoff[0]);
@@ -1853,7 +1853,7 @@ __global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__rest
     int lb;
     const RowArgs &a = ra[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     V *X = reinterpret_cast<V *>(smem_raw);  // [transform][pos]
     V *tws = X + TB * N;
     const V *twg = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
@@ -2005,7 +2005,7 @@ __global__ __launch_bounds__(split_nt(FI)) void row_iso_split(const RowArgs *__r
     int lb;
     const RowArgs &a = ra[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     T *Bf = reinterpret_cast<T *>(smem_raw);            // [transform][pos], one part at a time
     V *tws = reinterpret_cast<V *>(Bf + TB * N);        // last-stage twiddles
     const V *twg = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
@@ -2229,7 +2229,7 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     int lb;
     const RowArgs &a = ra[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     T *Gs = reinterpret_cast<T *>(smem_raw);                                           // [2 PW][N] material
     V *tp = reinterpret_cast<V *>(smem_raw + (sizeof(T) * PW * 2 * N + 15) / 16 * 16);  // [NTP] stage twiddles
     V *St = tp + NTP;                      // [TB][2][SR] staged half-spectrum rows ...
@@ -2551,7 +2551,7 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
     constexpr int NB = NC * RP;  // LDS layout [component][row pair][pos]
     int lb;
     const RowArgs &a = ra[find_problem(woff, np, &lb)];
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     V *X = reinterpret_cast<V *>(smem_raw);
     const int nh = a.Nh_row;
     const V *tw = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
