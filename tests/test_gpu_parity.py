@@ -144,6 +144,28 @@ def test_homogeneous_zero_iterations(fg):
     assert all(i["iters"] == 0 for i in res["info_primal"] + res["info_dual"])
 
 
+@pytest.mark.parametrize("d, N", [(2, (9, 7)), (3, (5, 3, 7))])
+def test_no_inclusions(fg, d, N):
+    # an empty inclusion list: the matrix alone (anisotropic), A_H = A0 exactly
+    A = synth.random_spd(11 + d, d)
+    micro = {"d": d, "kind": "inclusions", "A0": A, "shapes": [], "centers": np.zeros((0, d)),
+             "sizes": np.zeros((0, d)), "A_in": np.zeros((0, d, d))}
+    res = _gpu(fg, micro, N)
+    np.testing.assert_allclose(res["upper"], A, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    np.testing.assert_allclose(res["lower"], A, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    assert all(i["iters"] == 0 for i in res["info_primal"] + res["info_dual"])
+
+
+@pytest.mark.parametrize("d, N, P", [(2, (7, 9), (15, 21)), (3, (5, 5, 3), (9, 9, 5))])
+def test_constant_voxel_image(fg, d, N, P):
+    # a voxel image of one value c: A_H = c I exactly, with no iteration
+    micro = {"d": d, "kind": "voxels", "P": P, "image": np.full(P, 3.25)}
+    res = _gpu(fg, micro, N, P=P)
+    np.testing.assert_allclose(res["upper"], 3.25 * np.eye(d), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(res["lower"], 3.25 * np.eye(d), rtol=1e-13, atol=1e-13)
+    assert all(i["iters"] == 0 for i in res["info_primal"] + res["info_dual"])
+
+
 def test_laminate_exact_entries(fg):
     micro = synth.square_inclusion(2, 1.0, 1.0, 10.0)
     micro["sizes"] = np.array([[0.4, 1.0]])
