@@ -87,7 +87,7 @@ enum Scheme { kSchemeGa = 0, kSchemeGani = 1, kSchemeReduced = 2 };
 // material series keeps its support Z_{2N-1}, the transforms run on the
 // N-grid (2^d shifted copies), which must then be 3,5,7-smooth.
 bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = kSchemeGa) {
-    if (d != 2 && d != 3 || N == nullptr) return false;
+    if ((d != 2 && d != 3) || N == nullptr) return false;
     const bool gani = scheme == kSchemeGani, red = scheme == kSchemeReduced;
     o->d = d;
     for (int a = 0; a < d; ++a) {
@@ -407,8 +407,7 @@ void *ring_upload(Plan *pl, const A &a, hipError_t *err) {
     return pl->ring_slot(i);
 }
 
-int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int Bmax, int cls) {
-    (void)Bmax;
+int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int cls) {
     configure_pencil(a, fp64);
     if (pencil_lds_bytes(a, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "transform length %d too large for one work-group", a.f.n);
@@ -522,7 +521,7 @@ int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss,
             a.out_cs = (long)D.M[0] * D.Nh;
         }
         a.out = pl->ws + pl->Lo.T1 + (size_t)s * d * a.out_cs * es;
-        int rc = run_pencil(pl, a, 1, fp64, fp64 ? 8 : 16, cls_expand);
+        int rc = run_pencil(pl, a, 1, fp64, cls_expand);
         if (rc) return rc;
     }
     if (d == 2) {
@@ -547,7 +546,7 @@ int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss,
         b.out_ls = D.Nh;
         b.in = pl->ws + pl->Lo.T1 + (size_t)s * d * b.in_cs * es;
         b.out = pl->ws + pl->Lo.T2 + (size_t)s * d * b.out_cs * es;
-        const int rc = run_pencil(pl, b, D.M[0], fp64, fp64 ? 8 : 16, cls_inv);
+        const int rc = run_pencil(pl, b, D.M[0], fp64, cls_inv);
         if (rc) return rc;
     }
     *rows_out = pl->ws + pl->Lo.T2;
@@ -580,7 +579,7 @@ int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const voi
         b.out_cs = (long)D.M[0] * D.N[1] * D.Nh;
         b.out_os = (long)D.N[1] * D.Nh;
         b.out_ls = D.Nh;
-        int rc = run_pencil(pl, b, D.M[0], fp64, fp64 ? 8 : 16, cls_fwd);
+        int rc = run_pencil(pl, b, D.M[0], fp64, cls_fwd);
         if (rc) return rc;
         src = pl->ws + pl->Lo.T1;
     }
@@ -613,7 +612,7 @@ int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const voi
         a.out_ls = D.Nh;
     }
     a.out_cs = D.Ns;
-    int rc = run_pencil(pl, a, 1, fp64, fp64 ? 8 : 16, cls_proj);
+    int rc = run_pencil(pl, a, 1, fp64, cls_proj);
     if (rc) return rc;
     *nparts = pencil_grid_x(a);
     return FFTGAL_OK;
@@ -682,7 +681,7 @@ int series_to_field(Plan *pl, void *coef, double *field, const int *Li = nullptr
         a.nb = Lh;
         a.in_ls = a.out_ls = Lh;
     }
-    int rc = run_pencil(pl, a, 1, true, 8, FFTGAL_K_SETUP);
+    int rc = run_pencil(pl, a, 1, true, FFTGAL_K_SETUP);
     if (rc) return rc;
     cur = dst1;
     if (d == 3) {
@@ -701,7 +700,7 @@ int series_to_field(Plan *pl, void *coef, double *field, const int *Li = nullptr
         b.in_ls = Lh;
         b.out_os = (long)D.M[1] * Lh;
         b.out_ls = Lh;
-        rc = run_pencil(pl, b, D.M[0], true, 8, FFTGAL_K_SETUP);
+        rc = run_pencil(pl, b, D.M[0], true, FFTGAL_K_SETUP);
         if (rc) return rc;
         cur = dst2;
     }
@@ -793,7 +792,7 @@ int voxel_series(Plan *pl, const double *img_dev, int imgmap, double vmax, void 
         b.in_ls = D.Lh;
         b.out_os = (long)D.L[1] * D.Lh;
         b.out_ls = D.Lh;
-        rc = run_pencil(pl, b, P[0], true, 8, FFTGAL_K_SETUP);
+        rc = run_pencil(pl, b, P[0], true, FFTGAL_K_SETUP);
         if (rc) return rc;
         cur = U;
     }
@@ -820,7 +819,7 @@ int voxel_series(Plan *pl, const double *img_dev, int imgmap, double vmax, void 
         a.nb = D.Lh;
         a.in_ls = a.out_ls = D.Lh;
     }
-    rc = run_pencil(pl, a, 1, true, 8, FFTGAL_K_SETUP);
+    rc = run_pencil(pl, a, 1, true, FFTGAL_K_SETUP);
     if (rc) return rc;
     *coef_out = dst;
     return FFTGAL_OK;

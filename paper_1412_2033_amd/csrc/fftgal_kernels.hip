@@ -668,8 +668,8 @@ __global__ __launch_bounds__(kThreads) void sample_incl_kernel(double *g, int d,
     }
 }
 
-__global__ __launch_bounds__(kThreads) void sample_voxel_kernel(double *g, const double *img, int d, int p0, int p1,
-                                                                int p2, int m0, int m1, int m2, int map, double vmax) {
+__global__ __launch_bounds__(kThreads) void sample_voxel_kernel(double *g, const double *img, int p0, int p1, int p2,
+                                                                int m0, int m1, int m2, int map, double vmax) {
     const long total = (long)m0 * m1 * m2;
     for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)gridDim.x * kThreads) {
         const int j2 = (int)(idx % m2);
@@ -3073,7 +3073,7 @@ hipError_t launch_sample_voxel(double *g, const double *img, int d, const int *P
     const int p0 = P[0], p1 = P[1], p2 = d == 3 ? P[2] : 1;
     const long total = (long)m0 * m1 * m2;
     const int blocks = (int)std::max<long>(1, std::min<long>(2048, (total + kThreads - 1) / kThreads));
-    hipLaunchKernelGGL(sample_voxel_kernel, dim3(blocks), dim3(kThreads), 0, s, g, img, d, p0, p1, p2, m0, m1, m2, map,
+    hipLaunchKernelGGL(sample_voxel_kernel, dim3(blocks), dim3(kThreads), 0, s, g, img, p0, p1, p2, m0, m1, m2, map,
                        vmax);
     return hipGetLastError();
 }
