@@ -17,7 +17,9 @@ that the bounds stay within 1e-6 of the FP64 path), and a sample of the 2D
 serving mix (random circles, contrast 10..1e4, N in {41, 63, 123, 365}) is
 run twice: sequentially through the plain FP64 path, and through the
 continuous-batching loop in the FP32-iteration form with Poisson arrivals at
-0.8x its measured capacity (p50/p99 latency, throughput).
+0.8x its measured capacity (p50/p99 latency, throughput).  A sample of 3D
+random-field requests (N in {41, 63, 113}) is served the same way under an
+HBM budget that admits about two N = 113 plans at once.
 
     python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--serve 32]
 """
@@ -122,6 +124,10 @@ def main():
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--rtol32", type=float, default=5e-6, help="CG tolerance of the FP32-iteration form")
     ap.add_argument("--serve", type=int, default=32, help="serving-mix requests (0: skip)")
+    ap.add_argument("--serve3d", type=int, default=8,
+                    help="3D random-field requests (N in {41, 63, 113}) served under an HBM budget (0: skip)")
+    ap.add_argument("--serve3d-budget-gib", type=float, default=2.5,
+                    help="HBM budget of the 3D serving sample (GiB of plan workspaces)")
     ap.add_argument("--N", type=int, default=113)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gani", type=int, default=225,
@@ -286,6 +292,8 @@ def main():
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.serve > 0:
         out["serving"] = serving_bench(args.serve, args.rtol32)
+    if args.serve3d > 0:
+        out["serving_3d"] = serving3d_bench(args.serve3d, args.rtol32, args.serve3d_budget_gib)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(micro, N, d)
@@ -508,6 +516,53 @@ def serving_bench(n, rtol, seed=4):
                                      "p50_s": round(serve.percentile(lat, 50), 4),
                                      "p99_s": round(serve.percentile(lat, 99), 4),
                                      "Mpoint_iter_per_s": round(st["Mpoint_iter_per_s"], 1)},
+            "throughput_speedup_vs_sequential_fp64": round(capacity / (n / t_seq), 2),
+            "max_bound_rel_diff_vs_fp64": err, "solves_not_converged": bad}
+
+
+def serving3d_bench(n, rtol, budget_gib, seed=9):
+    """3D random-field requests (N in {41, 63, 113}, the benchmark's material
+    recipe) served under an HBM budget that admits about two N = 113 plans at
+    once: sequential plain FP64 vs continuous-batched FP32 iterations, same
+    tolerance."""
+    import numpy as np
+    import synth
+    from paper_1412_2033_amd import serve
+    print("bench: 3D serving sample of %d requests: building images" % n, file=sys.stderr, flush=True)
+    base = synth.serving_requests_3d(seed, n, rate_per_s=1.0)
+    print("bench: 3D serving: sequential FP64", file=sys.stderr, flush=True)
+    seq, t_seq = serve.sequential(base, precision="fp64", rtol=rtol)
+    by = {r["id"]: r for r in seq}
+    budget = int(budget_gib * (1 << 30))
+    srv = serve.Server(precision="fp32", rtol=rtol, hbm_budget=budget, capacity=16)
+    print("bench: 3D serving: batched FP32, all requests at t=0", file=sys.stderr, flush=True)
+    rec0, st0 = srv.run(synth.with_arrivals(base, seed, 1e9))
+    capacity = n / st0["wall_s"]
+    rate = 0.8 * capacity
+    print("bench: 3D serving: Poisson arrivals at %.1f req/s" % rate, file=sys.stderr, flush=True)
+    rec, st = srv.run(synth.with_arrivals(base, seed + 1, rate))
+    srv.close()
+    lat = [r["latency_s"] for r in rec]
+    seq_t = [r["seconds"] for r in seq]
+    err = max(float(np.linalg.norm(r[k] - by[r["id"]][k]) / np.linalg.norm(by[r["id"]][k]))
+              for r in rec for k in ("upper", "lower"))
+    bad = sum(1 for r in rec for s in r["status"] if s != 0)
+    return {"requests": n, "N": [r["N"] for r in base],
+            "mix": "3D Gaussian random-field voxels on (2N-1)^3, correlation length 0.05, vf 0.4, contrast 100, "
+                   "N in {41,63,113}",
+            "rtol": rtol, "hbm_budget_bytes": budget,
+            "sequential_fp64": {"wall_s": round(t_seq, 3), "req_per_s": round(n / t_seq, 2),
+                                "p50_s": round(serve.percentile(seq_t, 50), 4),
+                                "p99_s": round(serve.percentile(seq_t, 99), 4)},
+            "batched_fp32_capacity": {"wall_s": round(st0["wall_s"], 3), "req_per_s": round(capacity, 2),
+                                      "Mpoint_iter_per_s": round(st0["Mpoint_iter_per_s"], 1),
+                                      "peak_hbm_bytes": st0["peak_hbm_bytes"],
+                                      "deferred_requests": st0["deferred_requests"]},
+            "batched_fp32_poisson": {"rate_req_per_s": round(rate, 2), "wall_s": round(st["wall_s"], 3),
+                                     "p50_s": round(serve.percentile(lat, 50), 4),
+                                     "p99_s": round(serve.percentile(lat, 99), 4),
+                                     "peak_hbm_bytes": st["peak_hbm_bytes"],
+                                     "deferred_requests": st["deferred_requests"]},
             "throughput_speedup_vs_sequential_fp64": round(capacity / (n / t_seq), 2),
             "max_bound_rel_diff_vs_fp64": err, "solves_not_converged": bad}
 

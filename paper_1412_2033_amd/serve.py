@@ -42,6 +42,7 @@ class Server:
         self.capacity = capacity
         self.pool = collections.defaultdict(list)
         self.used_bytes = 0
+        self.peak_bytes = 0
         self.plans_created = 0
 
     def _plan(self, d, N):
@@ -49,6 +50,9 @@ class Server:
         if self.pool[key]:
             return self.pool[key].pop()
         need = fftgal.fftgal_workspace_bytes(d, N, fftgal.PRECISIONS[self.precision])
+        if need > self.hbm_budget:
+            raise ValueError("a plan of d = %d, N = %s needs %d bytes, more than the HBM budget %d"
+                             % (d, N, need, self.hbm_budget))
         # release idle plans of other shapes until the new one fits
         for k in list(self.pool):
             while self.used_bytes + need > self.hbm_budget and self.pool[k]:
@@ -59,6 +63,7 @@ class Server:
         if self.used_bytes + need > self.hbm_budget:
             return None
         self.used_bytes += need
+        self.peak_bytes = max(self.peak_bytes, self.used_bytes)
         self.plans_created += 1
         return fftgal.Plan(d, N, self.precision, device=self.device, stream=self.batch.stream)
 
@@ -70,6 +75,7 @@ class Server:
         by_sid = {}
         records = []
         iter_points = 0.0
+        deferred = set()  # requests that waited for memory with a slot free
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else None
         sim_now = 0.0
@@ -83,6 +89,7 @@ class Server:
                 N = (int(req["N"]),) * d
                 plan = self._plan(d, N)
                 if plan is None:
+                    deferred.add(req["id"])
                     break  # wait until a plan's memory is released
                 waiting.popleft()
                 plan.set_material(req["micro"])
@@ -120,7 +127,8 @@ class Server:
                     sim_now = pending[0]["arrival_s"]
         wall = time.perf_counter() - t0
         return records, {"wall_s": wall, "Mpoint_iter_per_s": iter_points / wall / 1e6,
-                         "plans_created": self.plans_created, "hbm_bytes": self.used_bytes}
+                         "plans_created": self.plans_created, "hbm_bytes": self.used_bytes,
+                         "peak_hbm_bytes": self.peak_bytes, "deferred_requests": len(deferred)}
 
     def close(self):
         for plans in self.pool.values():

@@ -15,5 +15,8 @@ from .microstructures import (  # noqa: F401
     random_spd,
     grf_voxels,
     serving_requests,
+    serving_requests_3d,
+    poisson_arrivals,
+    with_arrivals,
     grf_request,
 )

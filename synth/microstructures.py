@@ -180,3 +180,38 @@ def serving_requests(seed, n, rate_per_s, N_choices=(41, 63, 123, 365)):
         out.append({"id": i, "arrival_s": float(t[i]), "N": N,
                     "micro": random_circles(micro_seed)})
     return out
+
+
+def poisson_arrivals(seed, n, rate_per_s):
+    """n Poisson arrival times (the first at t = 0) at ``rate_per_s``."""
+    rng = _rng(seed)
+    gaps = rng.exponential(1.0 / rate_per_s, size=n)
+    return np.cumsum(gaps) - gaps[0]
+
+
+def serving_requests_3d(seed, n, rate_per_s, N_choices=(41, 63, 113), corr_len=0.05, vf=0.4, contrast=100.0):
+    """A stream of 3D random-field requests with Poisson arrivals.
+
+    Each request is a two-phase voxel image on the doubled grid (2N - 1)^3 of
+    its own order N (drawn from ``N_choices``): a Gaussian random field of
+    correlation length ``corr_len`` thresholded at volume fraction ``vf``,
+    phases 1 and ``contrast``.  Returns dicts ``{"id", "arrival_s", "N",
+    "micro"}`` like :func:`serving_requests`.
+    """
+    ss = np.random.SeedSequence(seed)
+    subs = ss.spawn(n + 1)
+    t = poisson_arrivals(int(subs[0].generate_state(1)[0]), n, rate_per_s)
+    out = []
+    for i in range(n):
+        r = np.random.Generator(np.random.PCG64(subs[i + 1]))
+        N = int(N_choices[int(r.integers(0, len(N_choices)))])
+        micro = grf_voxels(int(r.integers(0, 2**62)), (2 * N - 1,) * 3, d=3, corr_len=corr_len, vf=vf,
+                           a_matrix=1.0, a_incl=contrast)
+        out.append({"id": i, "arrival_s": float(t[i]), "N": N, "micro": micro})
+    return out
+
+
+def with_arrivals(requests, seed, rate_per_s):
+    """The same requests (shared microstructures) with new Poisson arrival times."""
+    t = poisson_arrivals(seed, len(requests), rate_per_s)
+    return [dict(r, arrival_s=float(t[i])) for i, r in enumerate(requests)]

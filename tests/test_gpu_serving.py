@@ -95,3 +95,33 @@ def test_server_mix_matches_fp64(fg):
         assert np.min(np.linalg.eigvalsh(rec["upper"] - rec["lower"])) > -1e-12
     print("worst FP32-served vs FP64 bound error %.2e" % worst)
     assert worst < 1e-6
+
+
+def test_server_3d_mix_under_hbm_budget(fg):
+    # 3D random-field requests of three orders arriving at once, with an HBM
+    # budget that holds one plan of each order: the second N = 23 request must
+    # wait for memory; every result matches the plain FP64 path within 1e-6
+    from paper_1412_2033_amd import serve
+    reqs = [dict(r, arrival_s=0.0) for r in synth.serving_requests_3d(4, 10, rate_per_s=1.0, N_choices=(5, 13, 23))]
+    need = {N: fg.fftgal_workspace_bytes(3, (N,) * 3, fg.PRECISIONS["fp32"]) for N in (5, 13, 23)}
+    budget = sum(need.values()) + need[5] // 2
+    srv = serve.Server(precision="fp32", rtol=5e-6, capacity=8, iters_per_step=6, hbm_budget=budget)
+    records, stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert len(records) == len(reqs)
+    assert all(st == 0 for rec in records for st in rec["status"])
+    assert stats["peak_hbm_bytes"] <= budget
+    assert stats["deferred_requests"] >= 1
+    seq, _ = serve.sequential(reqs, precision="fp64", rtol=1e-10)
+    by = {r["id"]: r for r in seq}
+    for rec in records:
+        ref = by[rec["id"]]
+        for key in ("upper", "lower"):
+            assert np.linalg.norm(rec[key] - ref[key]) / np.linalg.norm(ref[key]) < 1e-6
+        assert np.min(np.linalg.eigvalsh(rec["upper"] - rec["lower"])) > -1e-12
+    with pytest.raises(ValueError):
+        small = serve.Server(precision="fp32", hbm_budget=need[5] // 2)
+        try:
+            small.run(reqs[:1], realtime=False)
+        finally:
+            small.close()
