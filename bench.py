@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--rtol32", type=float, default=5e-6, help="CG tolerance of the FP32-iteration form")
     ap.add_argument("--serve", type=int, default=32, help="serving-mix requests (0: skip)")
+    ap.add_argument("--aniso", type=int, default=63,
+                    help="N of the anisotropic-cube comparison of the FP32-iteration form with FP64 (0: skip)")
     ap.add_argument("--serve3d", type=int, default=8,
                     help="3D random-field requests (N in {41, 63, 113}) served under an HBM budget (0: skip)")
     ap.add_argument("--serve3d-budget-gib", type=float, default=2.5,
@@ -290,6 +292,8 @@ def main():
         out["reduced"] = reduced_bench(fftgal, micro_dev, d, M, args.reduced, rtol64, dev)
     if args.envelope:
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
+    if args.aniso:
+        out["aniso_fp32"] = aniso_bench(fftgal, args.aniso, rtol64, args.rtol32, dev)
     if args.serve > 0:
         out["serving"] = serving_bench(args.serve, args.rtol32)
     if args.serve3d > 0:
@@ -518,6 +522,40 @@ def serving_bench(n, rtol, seed=4):
                                      "Mpoint_iter_per_s": round(st["Mpoint_iter_per_s"], 1)},
             "throughput_speedup_vs_sequential_fp64": round(capacity / (n / t_seq), 2),
             "max_bound_rel_diff_vs_fp64": err, "solves_not_converged": bad}
+
+
+def aniso_bench(fftgal, n, rtol64, rtol32, dev):
+    """Centred cube of side 0.5 with an anisotropic SPD inclusion (eigenvalues
+    log-uniform in [10, 1000], random rotation, seed 3) in an isotropic matrix
+    of 1, d = 3, order n: time to bounds of the plain FP64 path and of the
+    FP32-iteration form (the anisotropic row pass), and the bound error of the
+    latter against the former."""
+    import numpy as np
+    import synth
+    import torch
+    micro = synth.cube_inclusion_aniso(0.5, 3)
+    N = (n,) * 3
+    out = {"microstructure": "cube side 0.5, anisotropic SPD inclusion (seed 3), matrix 1", "N": n}
+    res = {}
+    for prec, rtol in (("fp64", rtol64), ("fp32", rtol32)):
+        plan = fftgal.Plan(3, N, prec, device=dev)
+        plan.run(micro, rtol=rtol)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = plan.run(micro, rtol=rtol)
+        torch.cuda.synchronize()
+        res[prec] = r
+        out[prec] = {"rtol": rtol, "time_to_bounds_s": round(time.perf_counter() - t, 4),
+                     "cg_iterations": {"primal": [i["iters"] for i in r["info_primal"]],
+                                       "dual": [i["iters"] for i in r["info_dual"]]},
+                     "upper_diag": [round(float(v), 8) for v in np.diag(r["upper"])],
+                     "lower_diag": [round(float(v), 8) for v in np.diag(r["lower"])]}
+        plan.close()
+    out["fp32_bound_rel_err_vs_fp64"] = max(
+        float(np.linalg.norm(res["fp32"][k] - res["fp64"][k]) / np.linalg.norm(res["fp64"][k]))
+        for k in ("upper", "lower"))
+    out["speedup_fp32_vs_fp64"] = round(out["fp64"]["time_to_bounds_s"] / out["fp32"]["time_to_bounds_s"], 3)
+    return out
 
 
 def serving3d_bench(n, rtol, budget_gib, seed=9):

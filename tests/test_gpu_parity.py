@@ -133,6 +133,23 @@ def test_full_size_against_golden(fg, case):
     assert np.min(np.linalg.eigvalsh(np.asarray(res["upper"]) - np.asarray(res["lower"]))) > 0
 
 
+@pytest.mark.parametrize("case", ["c3", "c5"])
+def test_fp32_full_size_against_golden(fg, case):
+    # the FP32-iteration form at full size (C3: anisotropic cube, N = 63, the
+    # anisotropic row pass; C5: the benchmark workload) within 1e-6 of the
+    # oracle's FP64 bounds, lower <= upper
+    path = os.path.join(HERE, "golden", case + ".json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    with open(path) as f:
+        gold = json.load(f)
+    micro, P = _golden_micro(case)
+    res = _gpu(fg, micro, tuple(gold["N"]), "fp32", rtol=5e-6, P=P)
+    assert _rel(res["upper"], gold["upper"]) < 1e-6
+    assert _rel(res["lower"], gold["lower"]) < 1e-6
+    assert np.min(np.linalg.eigvalsh(np.asarray(res["upper"]) - np.asarray(res["lower"]))) > 0
+
+
 def test_homogeneous_zero_iterations(fg):
     A = synth.random_spd(7, 3)
     micro = synth.cube_inclusion_aniso(0.5, 7)
