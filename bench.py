@@ -19,7 +19,10 @@ run twice: sequentially through the plain FP64 path, and through the
 continuous-batching loop in the FP32-iteration form with Poisson arrivals at
 0.8x its measured capacity (p50/p99 latency, throughput).  A sample of 3D
 random-field requests (N in {41, 63, 113}) is served the same way under an
-HBM budget that admits about two N = 113 plans at once.
+HBM budget that admits about two N = 113 plans at once.  Further sections:
+the FP32-iteration form on the anisotropic cube (N = 63), the 2D disc at
+N = 41, 365, 1013 (bounds vs N), warm start, GaNi, reduced Ga and envelope
+bounds; --main-only times the main workload alone.
 
     python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--serve 32]
 """
@@ -126,6 +129,10 @@ def main():
     ap.add_argument("--serve", type=int, default=32, help="serving-mix requests (0: skip)")
     ap.add_argument("--aniso", type=int, default=63,
                     help="N of the anisotropic-cube comparison of the FP32-iteration form with FP64 (0: skip)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time the main workload only (every other section off; used for profiling)")
+    ap.add_argument("--sweep2d", type=int, default=1,
+                    help="2D disc (vf 0.3, contrast 100) bounds at N = 41, 365, 1013, FP64 rtol 1e-10 (0: skip)")
     ap.add_argument("--serve3d", type=int, default=8,
                     help="3D random-field requests (N in {41, 63, 113}) served under an HBM budget (0: skip)")
     ap.add_argument("--serve3d-budget-gib", type=float, default=2.5,
@@ -143,6 +150,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (profiler counter scale)")
     args = ap.parse_args()
+    if args.main_only:
+        args.serve = args.serve3d = args.gani = args.warm_coarse = args.reduced = 0
+        args.envelope = args.aniso = args.sweep2d = 0
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards by independent solves/requests; "
               "see the design notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -294,6 +304,8 @@ def main():
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.aniso:
         out["aniso_fp32"] = aniso_bench(fftgal, args.aniso, rtol64, args.rtol32, dev)
+    if args.sweep2d:
+        out["sweep_2d"] = sweep2d_bench(fftgal, dev)
     if args.serve > 0:
         out["serving"] = serving_bench(args.serve, args.rtol32)
     if args.serve3d > 0:
@@ -555,6 +567,33 @@ def aniso_bench(fftgal, n, rtol64, rtol32, dev):
         float(np.linalg.norm(res["fp32"][k] - res["fp64"][k]) / np.linalg.norm(res["fp64"][k]))
         for k in ("upper", "lower"))
     out["speedup_fp32_vs_fp64"] = round(out["fp64"]["time_to_bounds_s"] / out["fp32"]["time_to_bounds_s"], 3)
+    return out
+
+
+def sweep2d_bench(fftgal, dev, Ns=(41, 365, 1013)):
+    """Centred disc of volume fraction 0.3, phases 1 and 100, d = 2: plain FP64
+    bounds to relative residual 1e-10 at each order N (doubled grids 81^2,
+    729^2, 2025^2), with time to bounds and the trace gap."""
+    import numpy as np
+    import synth
+    import torch
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0)
+    out = {"microstructure": "centred disc, vf 0.3, contrast 100", "rtol": 1e-10, "orders": []}
+    for n in Ns:
+        plan = fftgal.Plan(2, (n, n), "fp64", device=dev)
+        plan.run(micro, rtol=1e-10)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = plan.run(micro, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        plan.close()
+        out["orders"].append({"N": n, "M": 2 * n - 1, "time_to_bounds_s": round(dt, 4),
+                              "cg_iterations": {"primal": [i["iters"] for i in r["info_primal"]],
+                                                "dual": [i["iters"] for i in r["info_dual"]]},
+                              "upper_diag": [round(float(v), 10) for v in np.diag(r["upper"])],
+                              "lower_diag": [round(float(v), 10) for v in np.diag(r["lower"])],
+                              "gap": round(float(r["gap"]), 10)})
     return out
 
 
