@@ -154,8 +154,8 @@ def main():
         args.serve = args.serve3d = args.gani = args.warm_coarse = args.reduced = 0
         args.envelope = args.aniso = args.sweep2d = 0
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the path shards by independent solves/requests; "
-              "see the design notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU (independent solves and requests shard across GPUs "
+              "by problem); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
