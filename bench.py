@@ -163,7 +163,7 @@ def main():
 
     if args.copy_calibration:
         # a plain device copy: the profiler's counter scale, and the streaming
-        # rate this machine reaches (read + write bytes over event time)
+        # rate this GPU reaches (read + write bytes over event time)
         src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         e0 = torch.cuda.Event(enable_timing=True)
