@@ -13,11 +13,12 @@ timed region starts.
 The metric is Mpoint-CG-iter/s: (2N-1)^3 grid points times the CG iterations
 of all six solves, divided by the step time, for the plain FP64 path.  The
 same steps are then timed in the FP32-iteration form (tolerance calibrated so
-that the bounds stay within 1e-6 of the FP64 path), and a sample of the 2D
-serving mix (random circles, contrast 10..1e4, N in {41, 63, 123, 365}) is
-run twice: sequentially through the plain FP64 path, and through the
-continuous-batching loop in the FP32-iteration form with Poisson arrivals at
-0.8x its measured capacity (p50/p99 latency, throughput).  A sample of 3D
+that the bounds stay within 1e-6 of the FP64 path), and the 2D serving mix
+(512 requests of random circles, contrast 10..1e4, N in {41, 63, 123, 365})
+is run sequentially through the plain FP64 path and through the
+continuous-batching loop in the FP32-iteration form: all at once (capacity),
+then with Poisson arrivals at 0.5, 0.8, 1.0 and 1.2x that capacity (p50/p99
+latency, throughput).  A sample of 3D
 random-field requests (N in {41, 63, 113}) is served the same way under an
 HBM budget that admits about two N = 113 plans at once.  Further sections:
 the FP32-iteration form on the anisotropic cube (N = 63), the 2D disc at
@@ -126,7 +127,7 @@ def main():
                     help="form whose rate is the headline value (default: the plain FP64 path)")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--rtol32", type=float, default=5e-6, help="CG tolerance of the FP32-iteration form")
-    ap.add_argument("--serve", type=int, default=32, help="serving-mix requests (0: skip)")
+    ap.add_argument("--serve", type=int, default=512, help="serving-mix requests (0: skip)")
     ap.add_argument("--aniso", type=int, default=63,
                     help="N of the anisotropic-cube comparison of the FP32-iteration form with FP64 (0: skip)")
     ap.add_argument("--main-only", action="store_true",
@@ -510,10 +511,20 @@ def serving_bench(n, rtol, seed=4):
     print("bench: serving: batched FP32, all requests at t=0", file=sys.stderr, flush=True)
     rec0, st0 = srv.run(at_once)
     capacity = n / st0["wall_s"]
-    rate = 0.8 * capacity
-    reqs = synth.serving_requests(seed, n, rate_per_s=rate)
-    print("bench: serving: Poisson arrivals at %.1f req/s" % rate, file=sys.stderr, flush=True)
-    rec, st = srv.run(reqs)
+    # Poisson arrivals at 0.8x the batched capacity, and a sweep of the load
+    sweep = []
+    rec = st = None
+    for factor in (0.5, 0.8, 1.0, 1.2):
+        r_f = factor * capacity
+        reqs = synth.serving_requests(seed, n, rate_per_s=r_f)
+        print("bench: serving: Poisson arrivals at %.1f req/s (%.1fx capacity)" % (r_f, factor), file=sys.stderr,
+              flush=True)
+        rec_f, st_f = srv.run(reqs)
+        lat_f = [r["latency_s"] for r in rec_f]
+        sweep.append({"load": factor, "rate_req_per_s": round(r_f, 2), "wall_s": round(st_f["wall_s"], 3),
+                      "p50_s": round(serve.percentile(lat_f, 50), 4), "p99_s": round(serve.percentile(lat_f, 99), 4)})
+        if factor == 0.8:
+            rec, st, rate = rec_f, st_f, r_f
     srv.close()
     lat = [r["latency_s"] for r in rec]
     seq_t = [r["seconds"] for r in seq]
@@ -532,6 +543,7 @@ def serving_bench(n, rtol, seed=4):
                                      "p50_s": round(serve.percentile(lat, 50), 4),
                                      "p99_s": round(serve.percentile(lat, 99), 4),
                                      "Mpoint_iter_per_s": round(st["Mpoint_iter_per_s"], 1)},
+            "load_sweep": sweep,
             "throughput_speedup_vs_sequential_fp64": round(capacity / (n / t_seq), 2),
             "max_bound_rel_diff_vs_fp64": err, "solves_not_converged": bad}
 
