@@ -65,6 +65,14 @@ enum fftgal_precision {
                              bound quadrature in FP64                            */
 };
 
+/* Layout flag of the reduced Ga (or-ed into `precision` of
+ * fftgal_workspace_bytes_reduced and fftgal_plan_reduced): one set of transform
+ * intermediates, the 2^d shifts of every operator pass run one after another
+ * (smallest workspace).  Without it every shift has intermediates and a
+ * projected vector of its own and the shifts of a pass share one launch
+ * (faster, larger workspace).  EINVAL with the other plan kinds. */
+#define FFTGAL_REDUCED_LEAN 0x100
+
 enum fftgal_material_kind {
     FFTGAL_INCLUSIONS = 0, /* eq. inclcomp: matrix phase plus inclusions          */
     FFTGAL_VOXELS = 1      /* eq. gridcomp: piecewise-constant voxel image        */
@@ -264,7 +272,11 @@ int fftgal_bounds_of(struct fftgal_plan *plan, struct fftgal_plan *src, double *
  * the bound tolerance work as for fftgal_plan; warm starts, a-posteriori
  * bounds and batches are not available (EINVAL).  The workspace holds 2^d
  * material fields of |N| values and transform intermediates of the N-grid:
- * fftgal_workspace_bytes_reduced (P as in fftgal_workspace_bytes_p).
+ * fftgal_workspace_bytes_reduced (P as in fftgal_workspace_bytes_p).  With the
+ * default layout and specialised transform lengths the shifts of each operator
+ * pass run in one launch, each on intermediates and a projected vector of its
+ * own, summed by the CG update in shift order; with FFTGAL_REDUCED_LEAN in
+ * `precision` (both calls) one set of intermediates serves the shifts in turn.
  */
 size_t fftgal_workspace_bytes_reduced(int d, const int32_t *N, int precision, const int32_t *P);
 int fftgal_plan_reduced(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace,

@@ -126,12 +126,21 @@ void voxel_scratch(const Dims &D, const int *P, size_t *need_u, size_t *need_w) 
 
 struct Layout {
     size_t tw64, tw32, twP64, twP32, T1, T2, r, p, q, xsol, xsol64, gA64, gB64, gA32, gB32, part_a, part_b,
-        part_c, gram, args, status, hist, total;
+        part_c, gram, args, margs, status, hist, total;
     size_t tw_len, twP_len;  // complex entries per table region
     size_t part_len;         // doubles per partial region
+    // reduced Ga: the intermediates of one shift (d components, complex
+    // entries) in T1 / T2, so that the 2^d shifts of an operator pass can run
+    // in one launch, each on its own slot
+    size_t t1_slot, t2_slot;
 };
 
-Layout make_layout(const Dims &D, int precision) {
+constexpr size_t kMultiArgsBytes = 64 * 1024;  // argument tables of multi-shift passes
+
+// grouped: reduced Ga with one intermediate slot and one projected vector per
+// shift (the shifts of a pass share a launch); otherwise one of each.
+Layout make_layout(const Dims &D, int precision, bool grouped = true) {
+    const bool slots = grouped && D.nshift > 1;
     Layout L{};
     const int d = D.d;
     const size_t c16 = 16;
@@ -163,6 +172,8 @@ Layout make_layout(const Dims &D, int precision) {
                                      (size_t)D.L[0] * D.L[1] * Lh, (size_t)D.M[0] * D.M[1] * Lh});
         t2 = std::max(t2, s_u);
         t1 = std::max(t1, s_w + 4096);
+        L.t1_slot = (size_t)d * D.M[0] * D.N[1] * D.Nh;
+        L.t2_slot = (size_t)d * D.M[0] * D.M[1] * D.Nh;
     } else {
         t1 = (size_t)d2 * D.M[0] * D.Nh;
         t2 = 0;
@@ -171,13 +182,19 @@ Layout make_layout(const Dims &D, int precision) {
         const size_t s_w = std::max({(size_t)D.P[0] * Lh, (size_t)D.M[0] * Lh});
         t2 = s_u;
         t1 = std::max(t1, s_w + 4096);
+        L.t1_slot = (size_t)d * D.M[0] * D.Nh;
+        L.t2_slot = 0;
+    }
+    if (slots) {
+        t1 = std::max(t1, (size_t)D.nshift * L.t1_slot);
+        t2 = std::max(t2, (size_t)D.nshift * L.t2_slot);
     }
     L.T1 = take(t1 * c16);
     L.T2 = take(t2 * c16);
     const size_t vec = (size_t)D.nc_max * D.Ns * c16;
     L.r = take(vec);
     L.p = take(vec);
-    L.q = take(vec);
+    L.q = take(vec * (slots ? D.nshift : 1));  // grouped reduced Ga: one projected vector per shift
     L.xsol = take((size_t)2 * d * vec);  // [kind][alpha][nc][Ns]
     L.xsol64 = take(precision == FFTGAL_FP32_ITER ? (size_t)d * vec : 0);
     L.gA64 = take((size_t)D.nshift * D.Mtot * 8);
@@ -197,6 +214,7 @@ Layout make_layout(const Dims &D, int precision) {
     L.part_c = take(L.part_len * 8);
     L.gram = take(64 * 8);
     L.args = take(kArgsBytes);
+    L.margs = take(slots ? kMultiArgsBytes : 0);
     L.status = take(6 * sizeof(CgStatus));
     L.hist = take((size_t)6 * 2 * (kMaxHist + 1) * 8);
     L.total = align256(off);
@@ -236,6 +254,14 @@ struct PassRec {
     bool fp64;
     PencilArgs pa;
     RowArgs ra;
+    // a pass over several problems (the shifts of the reduced Ga) in one
+    // launch: np argument sets and their work-group offsets, uploaded to the
+    // multi-argument region at table_off / woff_off (bytes)
+    int np = 1;
+    std::vector<PencilArgs> pas;
+    std::vector<RowArgs> ras;
+    std::vector<int> woff;
+    size_t table_off = 0, woff_off = 0;
 };
 
 struct fftgal_plan {
@@ -276,6 +302,13 @@ struct fftgal_plan {
     int32_t t_cnt[FFTGAL_K_COUNT] = {0};
     // pass capture: while non-null, pass launches are recorded instead of run
     std::vector<PassRec> *capture = nullptr;
+    // intermediate slot of the operator passes being built (reduced Ga: one
+    // per shift, so that the shifts of a pass can share a launch)
+    int islot = 0;
+    bool grouped = false;  // reduced Ga laid out with one slot per shift
+    char *T1s() { return ws + Lo.T1 + (size_t)islot * Lo.t1_slot * 16; }
+    char *T2s() { return ws + Lo.T2 + (size_t)islot * Lo.t2_slot * 16; }
+    std::vector<unsigned char> margs_host;  // staging of the multi-shift argument tables
     int ring = 0;
     unsigned char ring_host[kRingSlots][kArgSlot];
     unsigned char iter_host[kIterSlots][kArgSlot];
@@ -520,12 +553,12 @@ int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss,
             a.out_ls = D.Nh;
             a.out_cs = (long)D.M[0] * D.Nh;
         }
-        a.out = pl->ws + pl->Lo.T1 + (size_t)s * d * a.out_cs * es;
+        a.out = pl->T1s() + (size_t)s * d * a.out_cs * es;
         int rc = run_pencil(pl, a, 1, fp64, cls_expand);
         if (rc) return rc;
     }
     if (d == 2) {
-        *rows_out = pl->ws + pl->Lo.T1;
+        *rows_out = pl->T1s();
         return FFTGAL_OK;
     }
     for (int s = 0; s < nsol; ++s) {
@@ -544,12 +577,12 @@ int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss,
         b.out_cs = (long)D.M[0] * D.M[1] * D.Nh;
         b.out_os = (long)D.M[1] * D.Nh;
         b.out_ls = D.Nh;
-        b.in = pl->ws + pl->Lo.T1 + (size_t)s * d * b.in_cs * es;
-        b.out = pl->ws + pl->Lo.T2 + (size_t)s * d * b.out_cs * es;
+        b.in = pl->T1s() + (size_t)s * d * b.in_cs * es;
+        b.out = pl->T2s() + (size_t)s * d * b.out_cs * es;
         const int rc = run_pencil(pl, b, D.M[0], fp64, cls_inv);
         if (rc) return rc;
     }
-    *rows_out = pl->ws + pl->Lo.T2;
+    *rows_out = pl->T2s();
     return FFTGAL_OK;
 }
 
@@ -571,7 +604,7 @@ int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const voi
         b.L_out = D.N[1];
         b.status = st;
         b.in = rows;
-        b.out = pl->ws + pl->Lo.T1;
+        b.out = pl->T1s();
         b.nb = D.Nh;
         b.in_cs = (long)D.M[0] * D.M[1] * D.Nh;
         b.in_os = (long)D.M[1] * D.Nh;
@@ -581,7 +614,7 @@ int forward_passes(Plan *pl, bool fp64, int kind, void *rows, void *q, const voi
         b.out_ls = D.Nh;
         int rc = run_pencil(pl, b, D.M[0], fp64, cls_fwd);
         if (rc) return rc;
-        src = pl->ws + pl->Lo.T1;
+        src = pl->T1s();
     }
     PencilArgs a = base_pencil(pl, pl->fM[0], fp64);
     set_shift(pl, a, shift);
@@ -915,32 +948,94 @@ struct IterCfg {
     bool fp64 = true;
 };
 
+// Group the per-shift passes of a reduced-Ga iteration (k passes per shift,
+// shift-major) into passes over all shifts: the EXPAND of shift 0 alone (it
+// forms p, which the other shifts read), the EXPAND of the other shifts
+// together, then each later pass of all shifts together, every shift on its
+// own intermediate slot.  False (and no change) unless every pass runs a
+// specialised kernel and the argument tables fit their region.
+bool group_shifts(std::vector<PassRec> &ps, int nshift) {
+    if (nshift < 2 || ps.empty() || ps.size() % nshift) return false;
+    for (const auto &r : ps)
+        if (!(r.type == 0 ? r.pa.fast : r.ra.fast)) return false;
+    const size_t k = ps.size() / nshift;
+    std::vector<PassRec> out;
+    out.push_back(ps[0]);
+    size_t off = 0;
+    auto group = [&](size_t j, int s0) {
+        PassRec g = ps[s0 * k + j];
+        g.np = nshift - s0;
+        int tot = 0;
+        for (int sh = s0; sh < nshift; ++sh) {
+            const PassRec &m = ps[sh * k + j];
+            g.woff.push_back(tot);
+            tot += m.grid;
+            if (m.type == 0)
+                g.pas.push_back(m.pa);
+            else
+                g.ras.push_back(m.ra);
+        }
+        g.grid = tot;
+        g.table_off = off;
+        off += ((size_t)g.np * (g.type == 0 ? sizeof(PencilArgs) : sizeof(RowArgs)) + 255) / 256 * 256;
+        g.woff_off = off;
+        off += ((size_t)g.np * sizeof(int) + 255) / 256 * 256;
+        out.push_back(std::move(g));
+    };
+    group(0, 1);
+    for (size_t j = 1; j < k; ++j) group(j, 0);
+    if (off > kMultiArgsBytes) return false;
+    ps.swap(out);
+    return true;
+}
+
 int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
     const Dims &D = pl->D;
     CgStatus *st = pl->status(kind, alpha);
     void *x = pl->xsol(kind, alpha);
-    cfg->passes.clear();
     cfg->fp64 = fp64;
-    pl->capture = &cfg->passes;
-    void *rows = nullptr;
-    int npq = 0;
-    int rc = FFTGAL_OK;
     // reduced Ga: q = sum_s 2^{-d} S*(s) F A(s) F^{-1} S(s) p over the shifted
-    // grids (Algorithm 3); the first shift also forms p = r + beta p
-    for (int s = 0; s < D.nshift && !rc; ++s) {
-        rc = inverse_passes(pl, fp64, kind, s == 0 ? nullptr : pl->ws + pl->Lo.p, 0, 1, s == 0, st, &rows,
-                            FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV, s);
-        if (!rc) {
-            RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind, s);
-            r.status = st;
-            rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
+    // grids (Algorithm 3); the first shift also forms p = r + beta p.  With
+    // specialised kernels every shift gets its own intermediates and its own
+    // projected vector q_s (summed by the update pass in shift order), so that
+    // the shifts of each pass share a launch; otherwise the shifts run one
+    // after another, accumulating into q.
+    const bool multi = pl->grouped;
+    int npq = 0, npq_shift = 0;
+    auto build = [&](bool grouped) -> int {
+        cfg->passes.clear();
+        pl->capture = &cfg->passes;
+        void *rows = nullptr;
+        int rc = FFTGAL_OK;
+        for (int s = 0; s < D.nshift && !rc; ++s) {
+            pl->islot = grouped ? s : 0;
+            rc = inverse_passes(pl, fp64, kind, s == 0 ? nullptr : pl->ws + pl->Lo.p, 0, 1, s == 0, st, &rows,
+                                FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV, s);
+            if (!rc) {
+                RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind, s);
+                r.status = st;
+                rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
+            }
+            if (!rc) {
+                char *q = pl->ws + pl->Lo.q + (grouped ? (size_t)s * pl->vec_bytes() : 0);
+                double *part = pl->at<double>(pl->Lo.part_a) + (grouped ? (size_t)s * npq_shift : 0);
+                rc = forward_passes(pl, fp64, kind, rows, q, pl->ws + pl->Lo.p, 1.0 / ((double)D.nshift * D.Mtot),
+                                    st, part, &npq, FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT, s, !grouped && s > 0);
+                if (s == 0) npq_shift = npq;
+            }
         }
-        if (!rc)
-            rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.q, pl->ws + pl->Lo.p,
-                                1.0 / ((double)D.nshift * D.Mtot), st, pl->at<double>(pl->Lo.part_a), &npq,
-                                FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT, s, s > 0);
+        pl->islot = 0;
+        pl->capture = nullptr;
+        return rc;
+    };
+    bool grouped = multi;
+    int rc = build(grouped);
+    if (!rc && grouped) {
+        if ((size_t)D.nshift * npq_shift > pl->Lo.part_len || !group_shifts(cfg->passes, D.nshift)) {
+            grouped = false;
+            rc = build(false);
+        }
     }
-    pl->capture = nullptr;
     if (rc) return rc;
     const int nc = pl->nc(kind);
     UpdArgs u{};
@@ -956,7 +1051,9 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
     u.st = st;
     u.partial = pl->at<double>(pl->Lo.part_c);
     u.pq_part = pl->at<double>(pl->Lo.part_a);
-    u.npq = npq;
+    u.npq = grouped ? D.nshift * npq_shift : npq;
+    u.nq = grouped ? D.nshift : 1;
+    u.q_ss = (long)(pl->vec_bytes() / (fp64 ? 16 : 8));
     cfg->upd = u;
     CgItem it{};
     it.st = st;
@@ -972,10 +1069,23 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
 // Upload a captured iteration into the plan's iteration argument slots.
 int upload_iteration(Plan *pl, const IterCfg &cfg) {
     if (cfg.passes.size() > (size_t)kMaxPasses) return fail(pl, FFTGAL_EINVAL, "too many passes");
+    size_t mused = 0;
+    for (const PassRec &r : cfg.passes) {
+        if (r.np < 2) continue;
+        if (pl->margs_host.size() < kMultiArgsBytes) pl->margs_host.assign(kMultiArgsBytes, 0);
+        const size_t tb = (size_t)r.np * (r.type == 0 ? sizeof(PencilArgs) : sizeof(RowArgs));
+        std::memcpy(pl->margs_host.data() + r.table_off, r.type == 0 ? (const void *)r.pas.data() : (const void *)r.ras.data(),
+                    tb);
+        std::memcpy(pl->margs_host.data() + r.woff_off, r.woff.data(), (size_t)r.np * sizeof(int));
+        mused = std::max(mused, r.woff_off + (size_t)r.np * sizeof(int));
+    }
+    if (mused > 0)
+        HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->Lo.margs, pl->margs_host.data(), mused, hipMemcpyHostToDevice,
+                                    pl->stream));
     for (size_t i = 0; i < cfg.passes.size(); ++i) {
         const PassRec &r = cfg.passes[i];
         const bool fast = r.type == 0 ? r.pa.fast : r.ra.fast;
-        if (!fast) continue;
+        if (!fast || r.np > 1) continue;
         const size_t sz = r.type == 0 ? sizeof(PencilArgs) : sizeof(RowArgs);
         std::memcpy(pl->iter_host[i], r.type == 0 ? (const void *)&r.pa : (const void *)&r.ra, sz);
         HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot((int)i), pl->iter_host[i], sz, hipMemcpyHostToDevice, pl->stream));
@@ -993,6 +1103,18 @@ int upload_iteration(Plan *pl, const IterCfg &cfg) {
 // arguments from `dev_args`).
 int launch_pass(Plan *pl, const PassRec &r, const void *dev_args) {
     const int *woff0 = reinterpret_cast<const int *>(pl->arg_slot(0));
+    if (r.np > 1) {  // several shifts in one launch: argument table and offsets
+        const char *tab = pl->ws + pl->Lo.margs + r.table_off;
+        const int *woff = reinterpret_cast<const int *>(pl->ws + pl->Lo.margs + r.woff_off);
+        TimedLaunch t(pl, r.cls);
+        if (r.type == 0)
+            HIPCHECK(pl, launch_pencil_multi(r.pa, reinterpret_cast<const PencilArgs *>(tab), woff, r.np, r.grid, r.fp64,
+                                             pl->stream, t.ev));
+        else
+            HIPCHECK(pl, launch_row_multi(r.ra, reinterpret_cast<const RowArgs *>(tab), woff, r.np, r.grid, r.fp64,
+                                          pl->stream, t.ev));
+        return FFTGAL_OK;
+    }
     if (r.type == 0) {
         if (r.pa.fast) {
             TimedLaunch t(pl, r.cls);
@@ -1273,9 +1395,12 @@ namespace {
 
 size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P, int scheme) {
     Dims D;
+    const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
+    precision &= ~FFTGAL_REDUCED_LEAN;
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
+    if (lean && scheme != kSchemeReduced) return 0;
     if (!make_dims(d, N, nullptr, &D, scheme)) return 0;
-    const size_t base = make_layout(D, precision).total;
+    const size_t base = make_layout(D, precision, !lean).total;
     if (P == nullptr) return base;
     Dims DP;
     if (!make_dims(d, N, P, &DP, scheme)) return 0;
@@ -1297,8 +1422,12 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     if (out == nullptr) return fail(nullptr, FFTGAL_EINVAL, "out is NULL");
     *out = nullptr;
     Dims D;
+    const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
+    precision &= ~FFTGAL_REDUCED_LEAN;
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
         return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
+    if (lean && scheme != kSchemeReduced)
+        return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_REDUCED_LEAN applies to reduced plans only");
     if (!make_dims(d, N, nullptr, &D, scheme))
         return fail(nullptr, FFTGAL_EINVAL,
                     scheme == kSchemeGani      ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
@@ -1306,7 +1435,7 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
                                                : "d must be 2 or 3 and every N odd and >= 1");
     if (dev_workspace == nullptr || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))
         return fail(nullptr, FFTGAL_EINVAL, "workspace must be a 256-byte aligned device pointer");
-    Layout Lo = make_layout(D, precision);
+    Layout Lo = make_layout(D, precision, !lean);
     if (bytes < Lo.total)
         return fail(nullptr, FFTGAL_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, Lo.total);
     // a larger workspace provisions voxel images up to the largest P that fits
@@ -1315,6 +1444,7 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     pl->Lo = Lo;
     pl->gani = scheme == kSchemeGani;
     pl->reduced = scheme == kSchemeReduced;
+    pl->grouped = !lean && D.nshift > 1;
     pl->precision = precision;
     pl->stream = reinterpret_cast<hipStream_t>(hip_stream);
     pl->ws = reinterpret_cast<char *>(dev_workspace);

@@ -164,6 +164,10 @@ struct UpdArgs {
     double *partial;
     const double *pq_part;  // partials of (p, K p) from the projection pass, or nullptr
     int npq;
+    // K p as the sum of nq vectors q, q + q_ss, ... (the shifts of the reduced
+    // Ga, added in that order); nq = 1 otherwise
+    int nq;
+    long q_ss;
 };
 
 struct CgItem {

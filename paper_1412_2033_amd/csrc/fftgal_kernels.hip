@@ -2745,6 +2745,16 @@ __global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs
         qx[j] = qv.x;
         qy[j] = qv.y;
     }
+    // the other shifts' contributions to K p, added in shift order
+    for (int sh = 1; sh < a.nq; ++sh) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const long o = off[j] < 0 ? 0L : off[j];
+            const Vt<T> qv = gld(q + sh * a.q_ss + o);
+            qx[j] += qv.x;
+            qy[j] += qv.y;
+        }
+    }
     const double pq = sum_fixed(a.pq_part, a.npq);
     if (threadIdx.x == 0) bcast = pq;
     __syncthreads();

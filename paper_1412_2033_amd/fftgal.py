@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libfftgal.so")
 
 FP64 = 0
 FP32_ITER = 1
+REDUCED_LEAN = 0x100  # reduced Ga laid out with one set of intermediates (shifts in turn)
 PRECISIONS = {"fp64": FP64, "fp32": FP32_ITER, "fp32_iter": FP32_ITER}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5: "ESTATE", -6: "EBREAKDOWN"}
@@ -328,7 +329,7 @@ def fftgal_history(plan, kind, alpha, cap=20001):
 class Plan:
     """A plan plus the torch device workspace it runs in."""
 
-    def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None, scheme="ga"):
+    def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None, scheme="ga", lean=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fftgal needs a HIP device")
@@ -336,13 +337,14 @@ class Plan:
         self.N = tuple(int(n) for n in N)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.scheme = scheme
-        self.nbytes = fftgal_workspace_bytes(self.d, self.N, self.precision, P, scheme)
+        flags = self.precision | (REDUCED_LEAN if lean else 0)
+        self.nbytes = fftgal_workspace_bytes(self.d, self.N, flags, P, scheme)
         if self.nbytes == 0:
             raise FftgalError(-1, "invalid plan arguments")
         dev = torch.device(device)
         self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
-        self.handle = fftgal_plan(self.d, self.N, self.precision, self.workspace.data_ptr(), self.nbytes,
+        self.handle = fftgal_plan(self.d, self.N, flags, self.workspace.data_ptr(), self.nbytes,
                                   self.stream.cuda_stream, scheme)
         self.M = tuple(fftgal_grid_size(self.handle, a) for a in range(self.d))
 

@@ -48,6 +48,13 @@ def test_workspace_bytes_validation(lib):
     assert fp32 > fp64  # FP32 form keeps FP64 fields for the bounds plus FP32 copies
     big = fftgal.fftgal_workspace_bytes(3, (113, 113, 113), 0)
     assert 0.5e9 < big < 4e9
+    # reduced Ga: the lean layout (one set of intermediates) is the smaller one;
+    # the flag is refused by the other plan kinds
+    grouped = fftgal.fftgal_workspace_bytes(3, (81, 81, 81), 0, scheme="reduced")
+    lean = fftgal.fftgal_workspace_bytes(3, (81, 81, 81), fftgal.REDUCED_LEAN, scheme="reduced")
+    assert 0 < lean < grouped
+    assert fftgal.fftgal_workspace_bytes(3, (81, 81, 81), fftgal.REDUCED_LEAN) == 0
+    assert fftgal.fftgal_workspace_bytes(3, (81, 81, 81), fftgal.REDUCED_LEAN, scheme="gani") == 0
 
 
 def test_plan_rejects_bad_arguments_without_device(lib):

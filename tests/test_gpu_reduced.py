@@ -8,7 +8,8 @@
   energy starts at the Voigt entry;
 * the reduced plan and the double-grid plan of the same N give the same bounds
   on the device (3D, N = 81: specialised reduced kernels against the generic
-  length-175 double grid);
+  length-175 double grid); the lean layout (shifts in turn) and the default
+  one (the shifts of a pass in one launch) agree;
 * unsupported uses raise: a non-smooth N, warm starts, batches.
 """
 
@@ -99,6 +100,27 @@ def test_reduced_equals_double_grid_3d(fg, kind):
         ga.close()
     assert _rel(r["upper"], g["upper"]) <= 1e-10
     assert _rel(r["lower"], g["lower"]) <= 1e-10
+
+
+@pytest.mark.parametrize("d, N", [(2, (81, 81)), (3, (81, 81, 81))])
+def test_reduced_lean_equals_grouped(fg, d, N):
+    # the lean layout (shifts in turn, one set of intermediates, q accumulated)
+    # and the default one (shifts of a pass in one launch, q summed by the
+    # update) give the same bounds; the lean workspace is the smaller
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0) if d == 2 else synth.cube_inclusion_aniso(0.45, 5)
+    print("reduced lean vs grouped d=%d N=%s" % (d, N), flush=True)
+    res = {}
+    nbytes = {}
+    for lean in (False, True):
+        plan = fg.Plan(d, N, "fp64", scheme="reduced", lean=lean)
+        try:
+            res[lean] = plan.run(micro, rtol=1e-11)
+            nbytes[lean] = plan.nbytes
+        finally:
+            plan.close()
+    assert nbytes[True] < nbytes[False]
+    assert _rel(res[True]["upper"], res[False]["upper"]) <= 1e-10
+    assert _rel(res[True]["lower"], res[False]["lower"]) <= 1e-10
 
 
 def test_reduced_homogeneous_and_history(fg):
