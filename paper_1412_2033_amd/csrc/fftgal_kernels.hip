@@ -1359,6 +1359,9 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     int lb;
     const PencilArgs &a = pa[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
+    // loads of a starting work-group before the stages of running ones (the
+    // priority drops again once the batch is in LDS)
+    __builtin_amdgcn_s_setprio(3);
     extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     V *X = reinterpret_cast<V *>(smem_raw);
     const int gx = (a.nb + B - 1) / B;
@@ -1523,6 +1526,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
             load(std::integral_constant<int, N>{});
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     fft_ip<T, FI, 0, 1, 0, NB, false>(X, tw, sg);
     auto *out = gbl(reinterpret_cast<V *>(a.out));
     if (a.epi == EPI_PROJECT) {
@@ -2239,7 +2243,10 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     const int pr0 = lb * PW;
     const int npr = min(PW, npairs - pr0);
     const int nrow_wg = min(2 * npr, a.nrows - 2 * pr0);  // rows of this work-group
-    // ---- all global loads in flight together, then parked in LDS
+    // ---- all global loads in flight together, then parked in LDS; the waves
+    // of a work-group issuing its loads take priority over those already in
+    // the transform arithmetic, so that a new work-group's loads leave early
+    __builtin_amdgcn_s_setprio(3);
     constexpr int GP = (PW * 2 * N + NT - 1) / NT;
     constexpr int SP = (TB * 2 * SR + NT - 1) / NT;
     constexpr int NW = (R - 1) * TQ;  // stage-1 twiddles
@@ -2292,6 +2299,7 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
         if (idx < NW) tp[idx] = mk<T>(wx[t], wy[t]);
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     // ---- packed Hermitian extension of the two rows of this thread's transform
     const int tr = threadIdx.x / LG;
     const int lane = threadIdx.x - tr * LG;
