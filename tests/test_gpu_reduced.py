@@ -82,6 +82,27 @@ def test_reduced_fp32_iterations(fg):
     assert _rel(res["lower"], ref["lower"]) <= 1e-6
 
 
+def test_reduced_fp32_3d_against_double_grid(fg):
+    # the FP32-iteration form of the reduced plan (shifts of a pass in one
+    # launch, 3D, N = 81) within 1e-6 of the FP64 double-grid bounds
+    N = (81, 81, 81)
+    micro = synth.cube_inclusion_aniso(0.45, 5)
+    print("reduced fp32 3D N=81", flush=True)
+    red = fg.Plan(3, N, "fp32", scheme="reduced")
+    try:
+        r = red.run(micro, rtol=5e-6)
+    finally:
+        red.close()
+    ga = fg.Plan(3, N, "fp64")
+    try:
+        g = ga.run(micro, rtol=1e-10)
+    finally:
+        ga.close()
+    assert _rel(r["upper"], g["upper"]) <= 1e-6
+    assert _rel(r["lower"], g["lower"]) <= 1e-6
+    assert np.min(np.linalg.eigvalsh(np.asarray(r["upper"]) - np.asarray(r["lower"]))) > 0
+
+
 @pytest.mark.parametrize("kind", ["inclusions", "voxels"])
 def test_reduced_equals_double_grid_3d(fg, kind):
     N = (81, 81, 81)
