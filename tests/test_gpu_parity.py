@@ -239,3 +239,33 @@ def test_error_paths(fg):
     infos, code = plan.solve_primal(0, 1e-12, 1)
     assert code == -4 and infos[0]["iters"] == 1 and not infos[0]["converged"]
     plan.close()
+
+
+@pytest.mark.parametrize("N", [(41, 41), (9, 7, 11), (113, 5, 9)])
+def test_kernel_timing_classes(fg, N):
+    # kernel timing (dispatch-recorded events for the specialised and CG
+    # launches, recorded events otherwise): one launch per operator pass and
+    # per CG kernel per iteration, positive times; a class mask times only the
+    # classes it names
+    d = len(N)
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0) if d == 2 else synth.cube_inclusion_aniso(0.45, 4)
+    plan = fg.Plan(d, N, "fp64")
+    try:
+        plan.set_material(micro)
+        plan.set_timing(True)
+        plan.read_timing()
+        infos, code = plan.solve_primal(0, 1e-30, 12)
+        t = plan.read_timing()
+        assert infos[0]["iters"] == 12
+        passes = ["expand", "row", "project", "cg_update", "cg_scalar"] + (["pencil_inv", "pencil_fwd"] if d == 3 else [])
+        for c in passes:
+            ms, n = t[c]
+            assert n >= 12 and ms > 0.0, (c, ms, n)
+        plan.set_timing(True, classes=("row",))
+        plan.read_timing()
+        plan.solve_primal(0, 1e-30, 5)
+        t = plan.read_timing()
+        assert t["row"][1] >= 5 and t["row"][0] > 0.0
+        assert all(t[c][1] == 0 for c in t if c != "row")
+    finally:
+        plan.close()
