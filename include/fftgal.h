@@ -50,8 +50,9 @@ enum fftgal_status {
     FFTGAL_EINVAL = -1,     /* invalid argument (message says which)            */
     FFTGAL_ENOMEM = -2,     /* workspace smaller than fftgal_workspace_bytes()   */
     FFTGAL_EDEVICE = -3,    /* a HIP call failed                                */
-    FFTGAL_ENOTCONV = -4,   /* CG stopped at maxit; the field is still admissible,
-                               so fftgal_bounds() still returns guaranteed bounds */
+    FFTGAL_ENOTCONV = -4,   /* CG stopped at maxit, or (FP32_ITER) stalled by
+                               rounding; the field kept is still admissible, so
+                               fftgal_bounds() still returns guaranteed bounds */
     FFTGAL_ESTATE = -5,     /* call out of order (e.g. bounds before solves)     */
     FFTGAL_EBREAKDOWN = -6  /* CG breakdown: (p, Kp) <= 0 or not finite (a
                                non-SPD or non-finite material)                   */
@@ -128,6 +129,9 @@ typedef struct fftgal_info {
     int32_t converged;  /* 1 if the stopping test was met within maxit          */
     double rel_res;     /* ||r_k|| / ||b|| at exit (0 if b = 0)                  */
     double res0;        /* ||b|| (= ||r_0|| from e_0 = 0), (.,.)_{R^{d x M}}    */
+    int32_t stagnated;  /* FP32_ITER only: 1 if the iteration stopped because
+                           FP32 rounding stalled it (see fftgal_solve_primal)   */
+    int32_t iterate;    /* the CG iteration whose field the plan keeps           */
 } fftgal_info;
 
 /*
@@ -168,6 +172,18 @@ int fftgal_set_material(struct fftgal_plan *plan, const fftgal_material *m);
  * rounding level of the load is treated as zero -- or at maxit.  `info` (may be
  * NULL; an array of d entries when alpha = -1) receives the outcome.  Returns
  * OK, ENOTCONV, EBREAKDOWN, ESTATE (no material) or EINVAL.
+ *
+ * Every CG iterate is admissible, so the energy of each is a guaranteed bound
+ * (Sec. 6.4).  With FP32_ITER, once FP32 rounding dominates (tolerances near
+ * or below the FP32 attainable accuracy, high contrast) the iterates drift and
+ * their exact energies rise again.  FP32_ITER solves therefore measure the
+ * exact energy of the iterate every 64 iterations (one more operator
+ * application) and keep a copy of the lowest one; they stop when that energy
+ * rises by more than 1e-5 of itself, when it stops falling while the residual
+ * has made no new minimum for 64 iterations, or when (p, K p) <= 0 after the
+ * first step.  The kept field is then restored and the call returns ENOTCONV
+ * with info.stagnated = 1 and info.iterate = the iteration of that field.  A
+ * solve that reaches maxit keeps the better of its last iterate and the copy.
  */
 int fftgal_solve_primal(struct fftgal_plan *plan, int alpha, double rtol, int maxit,
                         fftgal_info *info);
@@ -330,7 +346,8 @@ enum fftgal_kernel_class {
     FFTGAL_K_RHS = 7,         /* right-hand side -G A_M E                           */
     FFTGAL_K_BOUNDS = 8,      /* FP64 fields and energy Gram quadrature             */
     FFTGAL_K_SETUP = 9,       /* material fields A_M, B_M                           */
-    FFTGAL_K_COUNT = 10
+    FFTGAL_K_CHECKPOINT = 10, /* FP32 best-iterate checkpoints (exact energies)     */
+    FFTGAL_K_COUNT = 11
 };
 int fftgal_set_timing(struct fftgal_plan *plan, int enable);
 /* As fftgal_set_timing, for the classes whose bit (1 << class) is set only

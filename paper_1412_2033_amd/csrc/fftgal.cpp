@@ -33,6 +33,7 @@ constexpr int kRingSlots = 32;
 constexpr size_t kArgsBytes = kArgSlot * (2 + kIterSlots + kRingSlots);
 constexpr double kFloor64 = 1e-14;   // residual floor relative to ||A_M E|| (FP64)
 constexpr double kFloor32 = 1e-7;    // (FP32 iterations)
+constexpr int kCkptEvery = 64;       // FP32 iterations between best-iterate checkpoints
 
 int smooth_odd(int m) {
     for (int n = std::max(1, m);; ++n) {
@@ -125,8 +126,8 @@ void voxel_scratch(const Dims &D, const int *P, size_t *need_u, size_t *need_w) 
 }
 
 struct Layout {
-    size_t tw64, tw32, twP64, twP32, T1, T2, r, p, q, xsol, xsol64, gA64, gB64, gA32, gB32, part_a, part_b,
-        part_c, gram, args, margs, status, hist, total;
+    size_t tw64, tw32, twP64, twP32, T1, T2, r, p, q, xsol, xsol64, bvec, xbest, gA64, gB64, gA32, gB32, part_a,
+        part_b, part_c, gram, args, margs, status, hist, total;
     size_t tw_len, twP_len;  // complex entries per table region
     size_t part_len;         // doubles per partial region
     // reduced Ga: the intermediates of one shift (d components, complex
@@ -197,6 +198,9 @@ Layout make_layout(const Dims &D, int precision, bool grouped = true) {
     L.q = take(vec * (slots ? D.nshift : 1));  // grouped reduced Ga: one projected vector per shift
     L.xsol = take((size_t)2 * d * vec);  // [kind][alpha][nc][Ns]
     L.xsol64 = take(precision == FFTGAL_FP32_ITER ? (size_t)d * vec : 0);
+    // FP32 iterations: the right-hand side and the best iterate so far
+    L.bvec = take(precision == FFTGAL_FP32_ITER ? vec : 0);
+    L.xbest = take(precision == FFTGAL_FP32_ITER ? vec : 0);
     L.gA64 = take((size_t)D.nshift * D.Mtot * 8);
     L.gB64 = take((size_t)D.nshift * D.Mtot * 8);
     L.gA32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.nshift * D.Mtot * 4 : 0);
@@ -1154,6 +1158,54 @@ int enqueue_iteration(Plan *pl, const IterCfg &cfg) {
     return FFTGAL_OK;
 }
 
+// Update-grid arguments of a solve's vectors (CG update geometry).
+UpdArgs solve_vectors(Plan *pl, int kind, int alpha) {
+    UpdArgs u{};
+    u.x = pl->xsol(kind, alpha);
+    u.r = pl->ws + pl->Lo.r;
+    u.p = pl->ws + pl->Lo.p;
+    u.q = pl->ws + pl->Lo.q;
+    u.n_per_comp = pl->D.Ns;
+    u.cs = pl->D.Ns;
+    u.nc = pl->nc(kind);
+    u.Nh = pl->D.Nh;
+    u.nblocks = update_blocks((long)u.nc * pl->D.Ns);
+    u.st = pl->status(kind, alpha);
+    return u;
+}
+
+// Best-iterate checkpoint of an FP32 solve: K x with the partials of (x, K x)
+// (the operator passes of an iteration, reading the iterate instead of
+// forming p), then the energy test (see launch_cg_checkpoint).  Periodic
+// checkpoints are skipped on the device once the solve is done; the final
+// one runs after a solve that did not converge.
+int checkpoint(Plan *pl, int kind, int alpha, bool final) {
+    const Dims &D = pl->D;
+    CgStatus *st = pl->status(kind, alpha);
+    void *x = pl->xsol(kind, alpha);
+    const CgStatus *gate = final ? nullptr : st;
+    const int cls = FFTGAL_K_CHECKPOINT;
+    int nq = 0;
+    for (int s = 0; s < D.nshift; ++s) {  // reduced Ga: the shifts in turn, summed into q
+        void *rows = nullptr;
+        int rc = inverse_passes(pl, false, kind, x, 0, 1, false, gate, &rows, cls, cls, s);
+        if (rc) return rc;
+        RowArgs r = base_row(pl, false, ROW_OPER, rows, kind, s);
+        r.status = gate;
+        rc = run_row(pl, r, false, cls);
+        if (rc) return rc;
+        rc = forward_passes(pl, false, kind, rows, pl->ws + pl->Lo.q, x, 1.0 / ((double)D.nshift * D.Mtot), gate,
+                            pl->at<double>(pl->Lo.part_a), &nq, cls, cls, s, s > 0);
+        if (rc) return rc;
+    }
+    const UpdArgs u = solve_vectors(pl, kind, alpha);
+    Timed t(pl, cls);
+    HIPCHECK(pl, launch_cg_checkpoint(u, pl->ws + pl->Lo.bvec, pl->ws + pl->Lo.xbest, pl->at<double>(pl->Lo.part_a),
+                                      nq, pl->at<double>(pl->Lo.part_b), kCkptEvery, final ? 1 : 0, false,
+                                      pl->stream));
+    return FFTGAL_OK;
+}
+
 // Right-hand side r_0 = -P^* F_M (A_M E), ||A_M E||, status initialisation,
 // x = p = 0 (stream ordered; no host synchronisation).
 int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
@@ -1186,6 +1238,8 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
         if (rc) return rc;
     }
     nload *= D.nshift;
+    // FP32 iterations keep b for the exact energies of the checkpoints
+    if (!fp64) HIPCHECK(pl, launch_copy_vec(pl->ws + pl->Lo.bvec, pl->ws + pl->Lo.r, vbytes, pl->stream));
     // The load sums |A_M E|^2 over grid points; (., .)_{R^{d x M}} divides by |M|.
     const double floor_rel = (fp64 ? kFloor64 : kFloor32) / std::sqrt(npts);
     if (!pl->warm[kind][alpha]) {
@@ -1195,6 +1249,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
                                     pl->hist(kind, alpha), pl->stream));
         HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
         HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
+        if (!fp64) HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.xbest, vbytes, pl->stream));
         return FFTGAL_OK;
     }
     // Warm start from the iterate x0 already in x: keep (b, b), |A_M E|^2 and
@@ -1235,6 +1290,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
                                      pl->at<double>(pl->Lo.part_c), u.nblocks, scal, (double)D.Mtot, rtol, floor_rel,
                                      maxit, pl->btol, pl->hist(kind, alpha), pl->stream));
     HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
+    if (!fp64) HIPCHECK(pl, launch_copy_vec(pl->ws + pl->Lo.xbest, x, vbytes, pl->stream));
     return FFTGAL_OK;
 }
 
@@ -1244,11 +1300,28 @@ int finish_solve(Plan *pl, int kind, int alpha, const CgStatus &h, fftgal_info *
     inf.converged = h.converged;
     inf.res0 = std::sqrt(std::max(0.0, h.rr0));
     inf.rel_res = h.rr0 > 0 ? std::sqrt(std::max(0.0, h.rr) / h.rr0) : 0.0;
+    inf.stagnated = h.stagnated;
+    inf.iterate = h.ck_restore ? h.best_it : h.iter;
     pl->last_info[kind][alpha] = inf;
     if (info) *info = inf;
     pl->solved[kind][alpha] = true;
     if (h.breakdown) return fail(pl, FFTGAL_EBREAKDOWN, "CG breakdown (non-SPD or non-finite material)");
+    if (h.stagnated)
+        return fail(pl, FFTGAL_ENOTCONV, "FP32 iterations stalled after %d iterations; the field of iteration %d "
+                    "(lowest exact energy) is kept", h.iter, inf.iterate);
     if (!h.converged) return fail(pl, FFTGAL_ENOTCONV, "CG did not converge in %d iterations", h.maxit);
+    return FFTGAL_OK;
+}
+
+// After an FP32 solve that stopped without converging (at maxit or on a stall
+// not already handled by a checkpoint): keep the better of the last iterate
+// and the kept copy, then read the status again.
+int final_checkpoint(Plan *pl, int kind, int alpha, CgStatus *h) {
+    if (pl->fp64_iter() || h->converged || h->breakdown || (h->stagnated && h->ck_restore)) return FFTGAL_OK;
+    const int rc = checkpoint(pl, kind, alpha, true);
+    if (rc) return rc;
+    HIPCHECK(pl, hipMemcpyAsync(h, pl->status(kind, alpha), sizeof *h, hipMemcpyDeviceToHost, pl->stream));
+    HIPCHECK(pl, hipStreamSynchronize(pl->stream));
     return FFTGAL_OK;
 }
 
@@ -1276,8 +1349,9 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
         for (int i = 0; i < todo; ++i) {
             rc = enqueue_iteration(pl, cfg);
             if (rc) return rc;
+            ++enq;
+            if (!fp64 && enq % kCkptEvery == 0 && (rc = checkpoint(pl, kind, alpha, false))) return rc;
         }
-        enq += todo;
         HIPCHECK(pl, hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, pl->stream));
         HIPCHECK(pl, hipStreamSynchronize(pl->stream));
         if (h.done || enq >= maxit) break;
@@ -1292,6 +1366,7 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
         it_prev = h.iter;
         rr_prev = h.rr;
     }
+    if ((rc = final_checkpoint(pl, kind, alpha, &h))) return rc;
     return finish_solve(pl, kind, alpha, h, info);
 }
 
@@ -1977,6 +2052,7 @@ struct fftgal_batch {
         Plan *pl;
         int kind, alpha, id;
         IterCfg cfg;
+        int enq = 0;  // iterations enqueued (FP32 checkpoints every kCkptEvery)
     };
     std::vector<Member> members;
     struct Done {
@@ -2210,6 +2286,14 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
                                                 reinterpret_cast<const int *>(base + u.woff_off), u.np, u.total,
                                                 u.fp64, b->stream));
         BHIPCHECK(b, launch_cg_check_multi(items, nm, b->stream));
+        // FP32 members: best-iterate checkpoints at the same iteration counts
+        // as when solved alone
+        for (auto &m : b->members) {
+            ++m.enq;
+            if (m.cfg.fp64 || m.enq % kCkptEvery) continue;
+            const int rc = checkpoint(m.pl, m.kind, m.alpha, false);
+            if (rc) return bfail(b, rc, "checkpoint failed: %s", m.pl->err.c_str());
+        }
     }
     b->mirror_host.resize(nm);
     BHIPCHECK(b, hipMemcpyAsync(b->mirror_host.data(), b->ws, nm * sizeof(CgStatus), hipMemcpyDeviceToHost,
@@ -2226,7 +2310,10 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
         }
         Batch::Done d;
         d.id = mem.id;
-        d.status = finish_solve(mem.pl, mem.kind, mem.alpha, h, &d.info);
+        CgStatus hf = h;
+        const int rc = final_checkpoint(mem.pl, mem.kind, mem.alpha, &hf);
+        if (rc) return bfail(b, rc, "checkpoint failed: %s", mem.pl->err.c_str());
+        d.status = finish_solve(mem.pl, mem.kind, mem.alpha, hf, &d.info);
         mem.pl->busy = false;
         b->done.push_back(d);
         b->dirty = true;

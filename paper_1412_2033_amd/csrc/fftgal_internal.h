@@ -59,6 +59,16 @@ struct CgStatus {
     double energy;   // energy of the current iterate (CG recurrence)
     double dprev;    // energy decrease of the previous step
     double btol;     // bound tolerance (0: residual test only)
+    // best-iterate guard of the FP32-iteration form: exact energies of the
+    // iterate at checkpoints, the lowest one kept in a copy of the field
+    double eAE;      // (A_M E, E): the energy of e = 0
+    double ebest;    // lowest checkpoint energy (the initial iterate's at start)
+    double rrmin;    // smallest (r_k, r_k) so far
+    int32_t rrmin_it;  // iteration of rrmin
+    int32_t best_it;   // iteration of the kept copy
+    int32_t stagnated; // stopped because FP32 rounding stalled the iteration
+    int32_t ck_copy;   // set by a checkpoint: copy the iterate into the best copy
+    int32_t ck_restore;  // set by a checkpoint: restore the iterate from the best copy
     int32_t iter;
     int32_t maxit;
     int32_t done;
@@ -211,6 +221,18 @@ hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s);
 int row_grid(const RowArgs &a);
 int pencil_grid_x(const PencilArgs &a);
 
+// Best-iterate checkpoint of an FP32 solve (between iterations, after the
+// operator was applied to the iterate x with partials of (x, K x) in
+// part_xkx): partials of (b, x) per update work-group, then the exact energy
+// (A_M E, E) - 2 (b, x) + (x, K x) compared with the best one: a lower energy
+// is copied into xbest; a clear rise, or no gain while the residual has not
+// reached a new minimum for `window` iterations, stops the solve and restores
+// x from xbest.  final = 1 (after the last iteration of a solve that did not
+// converge) only restores x when the kept copy is better.  Every kernel does
+// nothing when the solve is done, except in the final checkpoint.
+hipError_t launch_cg_checkpoint(const UpdArgs &u, const void *b, void *xbest, const double *part_xkx, int n_xkx,
+                                double *part_bx, int window, int final, bool fp64, hipStream_t s);
+hipError_t launch_copy_vec(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part, int n_load,
                           const double *work_part, double inv_mtot, double tol, double floor_rel, int maxit,
                           double btol, double *hist, hipStream_t s);

@@ -1027,6 +1027,14 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgStatus *st, const d
         st->energy = work * inv_mtot;
         st->dprev = 0.0;
         st->btol = btol;
+        st->eAE = st->energy;
+        st->ebest = st->energy;  // e_0 = 0: the kept copy starts as zero
+        st->rrmin = rr;
+        st->rrmin_it = 0;
+        st->best_it = 0;
+        st->stagnated = 0;
+        st->ck_copy = 0;
+        st->ck_restore = 0;
         st->breakdown = !isfinite(rr) || !isfinite(load);
         st->converged = (rr == 0.0 || rr <= st->floor2) && !st->breakdown;
         st->done = st->converged || st->breakdown || maxit <= 0;
@@ -1099,6 +1107,14 @@ __global__ __launch_bounds__(kThreads) void cg_init_warm_kernel(CgStatus *st, co
         st->energy = scal[2] / mtot - bx - rx;
         st->dprev = 0.0;
         st->btol = btol;
+        st->eAE = scal[2] / mtot;
+        st->ebest = st->energy;  // the kept copy starts as the initial iterate
+        st->rrmin = rr;
+        st->rrmin_it = 0;
+        st->best_it = 0;
+        st->stagnated = 0;
+        st->ck_copy = 0;
+        st->ck_restore = 0;
         st->breakdown = !isfinite(rr) || !isfinite(load) || !isfinite(bb);
         st->converged = (rr == 0.0 || rr <= st->tol2 * bb || rr <= st->floor2) && !st->breakdown;
         st->done = st->converged || st->breakdown || maxit <= 0;
@@ -2689,6 +2705,10 @@ __global__ __launch_bounds__(kThreads) void cg_check_multi_kernel(const CgItem *
                 st->energy -= dstep;
                 st->beta = rr / st->rr;
                 st->rr = rr;
+                if (rr < st->rrmin) {
+                    st->rrmin = rr;
+                    st->rrmin_it = iter;
+                }
                 if (rr <= st->tol2 * st->rr0 || rr <= st->floor2) {
                     st->converged = 1;
                     st->done = 1;
@@ -2772,7 +2792,14 @@ __global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs
     if (lb == 0 && threadIdx.x == 0) {
         st->pq = pqa;
         if (bad) {
-            st->breakdown = 1;
+            // the material is SPD (validated when it is set), so with FP32
+            // iterates a finite (p, K p) <= 0 after the first step is rounding
+            // that has overtaken the iteration: a stall, and the best iterate
+            // is kept; in FP64, or at the first step, the operator is at fault
+            if (sizeof(T) == 4 && isfinite(pqa) && st->iter > 0)
+                st->stagnated = 1;
+            else
+                st->breakdown = 1;
             st->done = 1;
         } else {
             st->alpha = alpha_d;
@@ -2793,6 +2820,98 @@ __global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs
     }
     const double s = block_sum(part);
     if (threadIdx.x == 0) a.partial[lb] = s;
+}
+
+// ---- best-iterate checkpoints of the FP32-iteration form ----
+// Every CG iterate is admissible, so its exact energy is a guaranteed bound
+// (Sec. 6.4); with FP32 iterates the recursively updated residual and the
+// iterate drift apart once rounding dominates, and the energy of later
+// iterates rises again.  A checkpoint measures the exact energy of the
+// current iterate x: with b = -G A_M E the right-hand side and K the operator,
+// (A_M (E + x), E + x) = (A_M E, E) - 2 (b, x) + (K x, x).
+
+// Partials of (b, x) over the update grid (half-spectrum weights).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void ckpt_dot_kernel(UpdArgs a, const Vt<T> *b, double *part, int final) {
+    const CgStatus *st = a.st;
+    if (st->done && !final) return;
+    const Vt<T> *x = reinterpret_cast<const Vt<T> *>(a.x);
+    double acc = 0.0;
+    const long total = a.n_per_comp * a.nc;
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)a.nblocks * kThreads) {
+        const long c = idx / a.n_per_comp;
+        const long i = idx - c * a.n_per_comp;
+        const long off = c * a.cs + i;
+        const Vt<T> bv = b[off], xv = x[off];
+        const double w = (i % a.Nh) == 0 ? 1.0 : 2.0;
+        acc += w * ((double)bv.x * xv.x + (double)bv.y * xv.y);
+    }
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// The energy of x against the best one; sets the copy / restore flags.
+__global__ __launch_bounds__(kThreads) void ckpt_decide_kernel(CgStatus *st, const double *part_xkx, int n_xkx,
+                                                               const double *part_bx, int n_bx, int window,
+                                                               int final) {
+    const bool skip = final ? (st->converged || st->breakdown) : st->done;
+    if (skip) {
+        if (threadIdx.x == 0) {
+            st->ck_copy = 0;
+            st->ck_restore = 0;
+        }
+        return;
+    }
+    const double xkx = sum_fixed(part_xkx, n_xkx);
+    const double bx = sum_fixed(part_bx, n_bx);
+    if (threadIdx.x != 0) return;
+    const double e = st->eAE - 2.0 * bx + xkx;
+    st->ck_copy = 0;
+    st->ck_restore = 0;
+    if (final) {
+        // keep the current iterate unless the kept copy is better
+        if (!(e <= st->ebest)) st->ck_restore = 1;
+        return;
+    }
+    if (isfinite(e) && e < st->ebest) {
+        st->ebest = e;
+        st->best_it = st->iter;
+        st->ck_copy = 1;
+        return;
+    }
+    // a rise far beyond the rounding of the FP32 operator (~1e-7 of the
+    // energy), or no gain while the residual has made no new minimum for a
+    // whole window: the iteration has stalled
+    const bool rise = !isfinite(e) || e > st->ebest + 1e-5 * fabs(st->ebest);
+    const bool stall = st->iter - st->rrmin_it >= window;
+    if (rise || stall) {
+        st->stagnated = 1;
+        st->done = 1;
+        st->ck_restore = 1;
+    }
+}
+
+// Copy x into xbest or back, as the checkpoint decided.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void ckpt_copy_kernel(UpdArgs a, Vt<T> *xbest) {
+    const CgStatus *st = a.st;
+    const int cp = st->ck_copy, rs = st->ck_restore;
+    if (!cp && !rs) return;
+    Vt<T> *x = reinterpret_cast<Vt<T> *>(a.x);
+    const long total = a.n_per_comp * a.nc;
+    for (long idx = blockIdx.x * (long)kThreads + threadIdx.x; idx < total; idx += (long)a.nblocks * kThreads) {
+        const long c = idx / a.n_per_comp;
+        const long off = c * a.cs + (idx - c * a.n_per_comp);
+        if (cp)
+            xbest[off] = x[off];
+        else
+            x[off] = xbest[off];
+    }
+}
+
+__global__ void copy_words_kernel(unsigned int *dst, const unsigned int *src, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // Device-side validation of a voxel image: per work-group min, max and the
@@ -3047,6 +3166,35 @@ hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, in
         dispatch(cg_update_multi_kernel<double>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
     else
         dispatch(cg_update_multi_kernel<float>, dim3(total), dim3(kThreads), 0, s, ua, woff, np);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_checkpoint(const UpdArgs &u, const void *b, void *xbest, const double *part_xkx, int n_xkx,
+                                double *part_bx, int window, int final, bool fp64, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(ckpt_dot_kernel<double>, dim3(u.nblocks), dim3(kThreads), 0, s, u,
+                           reinterpret_cast<const double2 *>(b), part_bx, final);
+    else
+        hipLaunchKernelGGL(ckpt_dot_kernel<float>, dim3(u.nblocks), dim3(kThreads), 0, s, u,
+                           reinterpret_cast<const float2 *>(b), part_bx, final);
+    hipLaunchKernelGGL(ckpt_decide_kernel, dim3(1), dim3(kThreads), 0, s, u.st, part_xkx, n_xkx, part_bx, u.nblocks,
+                       window, final);
+    if (fp64)
+        hipLaunchKernelGGL(ckpt_copy_kernel<double>, dim3(u.nblocks), dim3(kThreads), 0, s, u,
+                           reinterpret_cast<double2 *>(xbest));
+    else
+        hipLaunchKernelGGL(ckpt_copy_kernel<float>, dim3(u.nblocks), dim3(kThreads), 0, s, u,
+                           reinterpret_cast<float2 *>(xbest));
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_vec(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes % 4) return hipErrorInvalidValue;
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(copy_words_kernel, dim3(blocks), dim3(kThreads), 0, s, reinterpret_cast<unsigned int *>(dst),
+                       reinterpret_cast<const unsigned int *>(src), n);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", 
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
-                  "bounds", "setup")
+                  "bounds", "setup", "checkpoint")
 
 
 class FftgalError(RuntimeError):
@@ -61,11 +61,13 @@ class Material(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("rel_res", ctypes.c_double), ("res0", ctypes.c_double)]
+                ("rel_res", ctypes.c_double), ("res0", ctypes.c_double),
+                ("stagnated", ctypes.c_int32), ("iterate", ctypes.c_int32)]
 
     def as_dict(self):
         return {"iters": int(self.iters), "converged": bool(self.converged),
-                "rel_res": float(self.rel_res), "res0": float(self.res0)}
+                "rel_res": float(self.rel_res), "res0": float(self.res0),
+                "stagnated": bool(self.stagnated), "iterate": int(self.iterate)}
 
 
 _LIB = None

@@ -13,6 +13,13 @@ Cases (unit cell, inputs from ``synth``):
 * c5      -- 3D, N = 113, 225^3-voxel Gaussian random field (seed 5,
              correlation length 0.05) thresholded at volume fraction 0.4,
              phases 1 / 100, tol 1e-10 (the benchmark workload)
+* serve_mix -- the eight requests of synth.serving_requests(21, 8, ...) with
+             N drawn from {21, 41, 123}: random non-overlapping discs, contrast
+             log-uniform in [10, 1e4], tol 1e-10 (one list of results)
+* stall     -- requests 11, 64 and 469 of synth.serving_requests(4, 512, ...)
+             (random discs at contrast ~9.6e3, N = 41, 63, 41), tol 1e-10: the
+             FP32-iteration form stalls on them below a relative residual of
+             ~1e-7 (one list of results)
 """
 
 import json
@@ -41,8 +48,55 @@ def case(name):
     raise ValueError(name)
 
 
+SERVE_MIX = dict(seed=21, n=8, N_choices=(21, 41, 123))
+
+
+def serve_mix():
+    reqs = synth.serving_requests(SERVE_MIX["seed"], SERVE_MIX["n"], rate_per_s=1e6,
+                                  N_choices=SERVE_MIX["N_choices"])
+    t0 = time.time()
+    rows = []
+    for r in reqs:
+        N = (int(r["N"]),) * 2
+        res = ga.ga_bounds(material.make_material(r["micro"]), N, tol=1e-10, maxit=20000)
+        rows.append({"id": r["id"], "N": list(N), "upper": res["upper"].tolist(), "lower": res["lower"].tolist(),
+                     "iters_primal": res["iters_primal"], "iters_dual": res["iters_dual"]})
+    out = {"case": "serve_mix", "requests": SERVE_MIX["seed"], "n": SERVE_MIX["n"],
+           "N_choices": list(SERVE_MIX["N_choices"]), "tol": 1e-10, "results": rows,
+           "oracle_seconds": time.time() - t0}
+    with open(os.path.join(HERE, "serve_mix.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("serve_mix done in %.1f s" % out["oracle_seconds"], flush=True)
+
+
+STALL = dict(seed=4, n=512, ids=(11, 64, 469))
+
+
+def stall():
+    reqs = synth.serving_requests(STALL["seed"], STALL["n"], rate_per_s=1.0)
+    t0 = time.time()
+    rows = []
+    for rid in STALL["ids"]:
+        r = reqs[rid]
+        N = (int(r["N"]),) * 2
+        res = ga.ga_bounds(material.make_material(r["micro"]), N, tol=1e-10, maxit=20000)
+        rows.append({"id": rid, "N": list(N), "upper": res["upper"].tolist(), "lower": res["lower"].tolist(),
+                     "iters_primal": res["iters_primal"], "iters_dual": res["iters_dual"]})
+    out = {"case": "stall", "requests": STALL["seed"], "n": STALL["n"], "tol": 1e-10, "results": rows,
+           "oracle_seconds": time.time() - t0}
+    with open(os.path.join(HERE, "stall.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("stall done in %.1f s" % out["oracle_seconds"], flush=True)
+
+
 def main(names):
     for name in names:
+        if name == "serve_mix":
+            serve_mix()
+            continue
+        if name == "stall":
+            stall()
+            continue
         micro, N, tol = case(name)
         t0 = time.time()
         res = ga.ga_bounds(material.make_material(micro), N, tol=tol, maxit=20000)

@@ -87,7 +87,7 @@ def test_fp64_matches_oracle(fg, name):
 
 
 @pytest.mark.parametrize("name", ["square2d_N9", "circle2d_N15", "aniso3d_N5", "voxel3d_N5", "circle2d_N113",
-                                  "aniso3d_N41x5x63"])
+                                  "aniso3d_N41x5x63", "circle2d_N123", "voxel3d_N113x5x5", "aniso3d_N5x113x9"])
 def test_fp32_iteration_form(fg, name):
     make, N = CASES[name]
     micro = make()
@@ -133,9 +133,10 @@ def test_full_size_against_golden(fg, case):
     assert np.min(np.linalg.eigvalsh(np.asarray(res["upper"]) - np.asarray(res["lower"]))) > 0
 
 
-@pytest.mark.parametrize("case", ["c3", "c5"])
+@pytest.mark.parametrize("case", ["c2_41", "c2_365", "c2_1013", "c3", "c5"])
 def test_fp32_full_size_against_golden(fg, case):
-    # the FP32-iteration form at full size (C3: anisotropic cube, N = 63, the
+    # the FP32-iteration form at full size (C2: 2D disc, contrast 100, on the
+    # double grids 81^2, 729^2 and 2025^2; C3: anisotropic cube, N = 63, the
     # anisotropic row pass; C5: the benchmark workload) within 1e-6 of the
     # oracle's FP64 bounds, lower <= upper
     path = os.path.join(HERE, "golden", case + ".json")

@@ -125,3 +125,76 @@ def test_server_3d_mix_under_hbm_budget(fg):
             small.run(reqs[:1], realtime=False)
         finally:
             small.close()
+
+
+def _golden_serve_mix():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "serve_mix.json")
+    with open(path) as f:
+        gold = json.load(f)
+    reqs = synth.serving_requests(gold["requests"], gold["n"], rate_per_s=1e6, N_choices=tuple(gold["N_choices"]))
+    return reqs, {r["id"]: r for r in gold["results"]}
+
+
+@pytest.mark.parametrize("precision, rtol, tol", [("fp64", 1e-10, 1e-10), ("fp32", 5e-6, 1e-6)])
+def test_served_requests_match_oracle(fg, precision, rtol, tol):
+    # eight random-disc requests (N in {21, 41, 123}: double grids 41^2, 81^2
+    # and 245^2; contrast 10..1e4) served together in one batch; every entry of
+    # every served bound against the oracle's bounds (golden file written by
+    # tests/golden/make_golden.py serve_mix, which calls only the oracle)
+    from paper_1412_2033_amd import serve
+    reqs, gold = _golden_serve_mix()
+    srv = serve.Server(precision=precision, rtol=rtol, capacity=8, iters_per_step=6)
+    records, stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert len(records) == len(reqs)
+    worst = 0.0
+    for rec in records:
+        ref = gold[rec["id"]]
+        assert all(st == 0 for st in rec["status"]), rec["status"]
+        for key in ("upper", "lower"):
+            b = np.asarray(ref[key])
+            err = np.max(np.abs(np.asarray(rec[key]) - b)) / np.linalg.norm(b)
+            worst = max(worst, err)
+            assert err < tol, (rec["id"], rec["N"], key, err)
+        assert np.min(np.linalg.eigvalsh(rec["upper"] - rec["lower"])) > -1e-12
+    print("%s served vs oracle: worst entry error %.2e" % (precision, worst))
+
+
+def test_batch_alone_equals_mix_long_lengths(fg):
+    # the batched launches at the serving mix's longer double grids (245 and
+    # 729, specialised kernels) beside a short one, FP32 and FP64: bitwise the
+    # same bounds as each problem solved alone
+    cases = [(synth.random_circles(31, contrast=300.0), (123, 123), "fp32"),
+             (synth.random_circles(32, contrast=50.0), (365, 365), "fp32"),
+             (synth.random_circles(33, contrast=300.0), (123, 123), "fp64"),
+             (synth.random_circles(34, contrast=20.0), (41, 41), "fp32")]
+    rtol = 5e-6
+    alone = [_alone(fg, m, N, p, rtol) for m, N, p in cases]
+    print("alone done", flush=True)
+    batch = fg.Batch(capacity=16)
+    plans = []
+    owner = {}
+    seqs = []
+    k = []
+    for i, (m, N, p) in enumerate(cases):
+        pl = fg.Plan(len(N), N, p, stream=batch.stream)
+        pl.set_material(m)
+        plans.append(pl)
+        seqs.append([(0, 0), (0, 1), (1, 0), (1, 1)])
+        k.append(0)
+        owner[batch.add(pl, 0, 0, rtol=rtol)] = i
+    while owner:
+        batch.step(7)
+        for sid, info, st in batch.poll():
+            j = owner.pop(sid)
+            k[j] += 1
+            if k[j] < len(seqs[j]):
+                owner[batch.add(plans[j], *seqs[j][k[j]], rtol=rtol)] = j
+    for i, pl in enumerate(plans):
+        up, lo, gap = pl.bounds()
+        assert np.array_equal(up, alone[i]["upper"]), i
+        assert np.array_equal(lo, alone[i]["lower"]), i
+        pl.close()
+    batch.close()
