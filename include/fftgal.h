@@ -155,6 +155,24 @@ int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision
                 void *dev_workspace, size_t bytes, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * allocation): fftgal_plan on a workspace the library owns, a static device
+ * array of fftgal_static_workspace_bytes() = 64 MiB that each GPU the library
+ * runs on holds until the process ends (it fits 2D plans up to N = 365 and 3D
+ * plans up to N = 41 in either precision).  Allocates no device memory.  The
+ * plan works like one from fftgal_plan on the current device and `hip_stream`.
+ * All calls on one GPU share that GPU's array, so only one plan at a time may
+ * hold it: a second fftgal_plan_static on the same device while the first is
+ * alive returns ESTATE (the array is not cleared between plans; a plan
+ * initialises what it reads, as with a caller's workspace).  fftgal_destroy
+ * waits for the plan's stream and releases the array.  ENOMEM if the plan
+ * needs more than the array holds; EINVAL as fftgal_plan.
+ */
+int fftgal_plan_static(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *hip_stream);
+size_t fftgal_static_workspace_bytes(void);
+
+/*
  * Build the double-grid material fields A_M and B_M (eq. MBA_GA; Lemma
  * integ_eval_VM) on the device from closed-form Fourier coefficients
  * (Remark anal_Fourier) or from the voxel image (Lemma grid_compos), for both

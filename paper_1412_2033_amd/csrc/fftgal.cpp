@@ -12,6 +12,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -320,6 +321,7 @@ struct fftgal_plan {
     char *iter_slot(int i) { return arg_slot(2 + i); }
     char *ring_slot(int i) { return arg_slot(2 + kIterSlots + i); }
     std::string err = "no error";
+    int static_dev = -1;  // device whose static workspace this plan holds, or -1
 
     template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
     bool fp64_iter() const { return precision == FFTGAL_FP64; }
@@ -1546,6 +1548,24 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
 
 }  // namespace
 
+// ---- the library's static workspace (fftgal_plan_static) -------------------
+//
+// A file-scope device array that every GPU the library runs on holds until
+// the process ends.  Its name is a host-side stand-in in host code: the
+// device address is taken once per device with hipGetSymbolAddress and only
+// that address is used.  One plan at a time may hold a device's array.
+constexpr size_t kStaticBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+struct StaticSlot {
+    void *ptr = nullptr;           // device address of `scratch` on this device
+    const Plan *owner = nullptr;   // the live plan holding it
+};
+std::mutex g_static_mu;
+std::map<int, StaticSlot> g_static;
+}  // namespace
+
 extern "C" {
 
 
@@ -1569,6 +1589,37 @@ int fftgal_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision
                 void *hip_stream) {
     return make_plan(out, d, N, precision, dev_workspace, bytes, hip_stream, kSchemeGa);
 }
+
+int fftgal_plan_static(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *hip_stream) {
+    if (out == nullptr) return fail(nullptr, FFTGAL_EINVAL, "out is NULL");
+    *out = nullptr;
+    const size_t need = fftgal_workspace_bytes(d, N, precision);
+    if (need == 0) return fail(nullptr, FFTGAL_EINVAL, "d must be 2 or 3, every N odd and >= 1, precision known");
+    if (need > kStaticBytes)
+        return fail(nullptr, FFTGAL_ENOMEM, "the plan needs %zu bytes; the static workspace holds %zu", need,
+                    kStaticBytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, FFTGAL_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticSlot &slot = g_static[dev];
+    if (slot.owner != nullptr)
+        return fail(nullptr, FFTGAL_ESTATE, "the static workspace of device %d is held by another plan", dev);
+    if (slot.ptr == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(nullptr, FFTGAL_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        slot.ptr = p;
+    }
+    const int rc = make_plan(out, d, N, precision, slot.ptr, kStaticBytes, hip_stream, kSchemeGa);
+    if (rc != FFTGAL_OK) return rc;
+    (*out)->static_dev = dev;
+    slot.owner = *out;
+    return FFTGAL_OK;
+}
+
+size_t fftgal_static_workspace_bytes(void) { return kStaticBytes; }
 
 int fftgal_plan_gani(struct fftgal_plan **out, int d, const int32_t *N, int precision, void *dev_workspace,
                      size_t bytes, void *hip_stream) {
@@ -2026,6 +2077,13 @@ int fftgal_destroy(struct fftgal_plan *pl) {
         (void)hipEventDestroy(e.b);
     }
     for (hipEvent_t e : pl->pool) (void)hipEventDestroy(e);
+    if (pl->static_dev >= 0) {
+        // the static workspace is free for the next plan once this plan's work is done
+        (void)hipStreamSynchronize(pl->stream);
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        StaticSlot &slot = g_static[pl->static_dev];
+        if (slot.owner == pl) slot.owner = nullptr;
+    }
     delete pl;
     return FFTGAL_OK;
 }

@@ -30,7 +30,8 @@ EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", 
            "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
            "fftgal_warm_start", "fftgal_history", "fftgal_set_timing_classes", "fftgal_set_bound_tol",
            "fftgal_workspace_bytes_gani", "fftgal_plan_gani", "fftgal_bounds_of", "fftgal_envelope_images",
-           "fftgal_workspace_bytes_reduced", "fftgal_plan_reduced",
+           "fftgal_workspace_bytes_reduced", "fftgal_plan_reduced", "fftgal_plan_static",
+           "fftgal_static_workspace_bytes",
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
 KERNEL_CLASSES = ("expand", "pencil_inv", "row", "pencil_fwd", "project", "cg_update", "cg_scalar", "rhs",
@@ -119,6 +120,10 @@ def load_library(path=LIB_PATH):
     lib.fftgal_set_bound_tol.restype = ctypes.c_int
     lib.fftgal_workspace_bytes_gani.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p]
     lib.fftgal_workspace_bytes_gani.restype = ctypes.c_size_t
+    lib.fftgal_plan_static.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32p, ctypes.c_int, vp]
+    lib.fftgal_plan_static.restype = ctypes.c_int
+    lib.fftgal_static_workspace_bytes.argtypes = []
+    lib.fftgal_static_workspace_bytes.restype = ctypes.c_size_t
     lib.fftgal_plan_gani.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32p, ctypes.c_int, vp, ctypes.c_size_t, vp]
     lib.fftgal_plan_gani.restype = ctypes.c_int
     lib.fftgal_workspace_bytes_reduced.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p]
@@ -187,6 +192,18 @@ def fftgal_plan(d, N, precision, workspace_ptr, nbytes, stream_ptr, scheme="ga")
     _check(fn(ctypes.byref(h), d, _i32(N), precision, ctypes.c_void_p(workspace_ptr), nbytes,
               ctypes.c_void_p(stream_ptr)), None)
     return h
+
+
+def fftgal_plan_static(d, N, precision, stream_ptr):
+    """A plan on the library's static device workspace (no device allocation)."""
+    h = ctypes.c_void_p()
+    _check(load_library().fftgal_plan_static(ctypes.byref(h), d, _i32(N), precision, ctypes.c_void_p(stream_ptr)),
+           None)
+    return h
+
+
+def fftgal_static_workspace_bytes():
+    return int(load_library().fftgal_static_workspace_bytes())
 
 
 def fftgal_bounds_of(plan, src, d):
