@@ -75,7 +75,7 @@ def energy(AM, E, e):
     return inner(material.apply_pointwise(AM, f), f)
 
 
-def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0, x0=None, btol=0.0, energy0=None):
+def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0, x0=None):
     """Conjugate gradients (Remark CG; Saad Alg. 6.18) from x_0 = 0, or from an
     initial approximation x0 in the minimisation space (Sec. 6.4).
 
@@ -84,12 +84,6 @@ def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0, x0=None, btol=0.0, ener
     "res_history", "alphas", "rr"}: alphas[k] is the step of iteration k + 1 and
     rr[k] = (r_k, r_k); ``monitor`` is called with the iterate after every step
     (and with x_0 before the first).
-
-    With btol > 0 (and the energy of x_0, ``energy0``) CG also stops on the
-    bound: one step lowers the energy by d_k = alpha_k (r_{k-1}, r_{k-1}); from
-    the second step on it stops once d_k <= btol |energy_k| (1 - q), q =
-    d_k / d_{k-1} clipped to [0, 0.99] -- the remaining decrease, estimated as
-    d_k q / (1 - q), is then below btol times the energy.
     """
     if x0 is None:
         x = np.zeros_like(b)
@@ -107,8 +101,6 @@ def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0, x0=None, btol=0.0, ener
         return x, {"iters": 0, "rel_res": hist[0], "res_history": hist, "alphas": alphas, "rr": rrs}
     p = r.copy()
     it = 0
-    en = energy0
-    dprev = 0.0
     while it < maxit and np.sqrt(rr / rr0) > tol and np.sqrt(rr) > abs_stop:
         q = apply(p)
         alpha = rr / inner(p, q)
@@ -117,7 +109,6 @@ def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0, x0=None, btol=0.0, ener
         rr_new = inner(r, r)
         beta = rr_new / rr
         p = r + beta * p
-        dk = alpha * rr
         rr = rr_new
         it += 1
         alphas.append(float(alpha))
@@ -125,14 +116,6 @@ def cg(apply, b, tol, maxit, monitor=None, abs_stop=0.0, x0=None, btol=0.0, ener
         hist.append(float(np.sqrt(rr / rr0)))
         if monitor is not None:
             monitor(x)
-        if btol > 0 and en is not None:
-            en -= dk
-            if it >= 2 and dprev > 0 and np.sqrt(rr / rr0) > tol and np.sqrt(rr) > abs_stop:
-                qk = min(max(dk / dprev, 0.0), 0.99)
-                if dk <= btol * abs(en) * (1.0 - qk):
-                    dprev = dk
-                    break
-            dprev = dk
     return x, {"iters": it, "rel_res": float(np.sqrt(rr / rr0)), "res_history": hist, "alphas": alphas, "rr": rrs}
 
 
@@ -157,7 +140,7 @@ def prolong(e, N_coarse, M):
 RESIDUAL_FLOOR = 1e-14
 
 
-def solve(AM, N, E, kind, tol=1e-10, maxit=10_000, track_energy=False, x0=None, btol=0.0):
+def solve(AM, N, E, kind, tol=1e-10, maxit=10_000, track_energy=False, x0=None):
     """Minimiser of Def. Ga for one macroscopic E (primal, kind 'E') or J (dual, 'J').
 
     Solves G A_M e = -G A_M E by CG (Cor. Ga_linsys) from 0 or from the
@@ -171,9 +154,7 @@ def solve(AM, N, E, kind, tol=1e-10, maxit=10_000, track_energy=False, x0=None, 
     floor = RESIDUAL_FLOOR * np.sqrt(inner(load, load))
     energies = []
     mon = (lambda x: energies.append(energy(AM, E, x))) if track_energy else None
-    e0 = energy(AM, E, np.zeros_like(b) if x0 is None else x0) if btol > 0 else None
-    e, info = cg(lambda p: matvec(AM, p, N, kind), b, tol, maxit, mon, abs_stop=floor, x0=x0, btol=btol,
-                 energy0=e0)
+    e, info = cg(lambda p: matvec(AM, p, N, kind), b, tol, maxit, mon, abs_stop=floor, x0=x0)
     e = project(e, N, kind)
     info["energies"] = energies
     return e, info
@@ -194,15 +175,14 @@ def gram(AM, fields):
     return out
 
 
-def ga_bounds(mat, N, M=None, tol=1e-10, maxit=10_000, track_energy=False, warm=None, btol=0.0):
+def ga_bounds(mat, N, M=None, tol=1e-10, maxit=10_000, track_energy=False, warm=None):
     """Guaranteed bounds of Prop. struct_bounds from the Ga scheme (Def. Ga).
 
     Returns a dict with ``upper`` = A_{H,N}, ``lower`` = B_{H,N}^{-1}, the
     unsymmetrised Gram matrices, the CG iteration counts, the fields, the CG
     scalars and (optionally) the per-iteration energies of each primal/dual
     solve.  ``warm`` (the result of a coarser ga_bounds) starts every solve
-    from the prolongation of the coarse field (Sec. 6.4); ``btol`` adds the
-    bound test of ``cg``.
+    from the prolongation of the coarse field (Sec. 6.4).
     """
     N = tuple(int(n) for n in N)
     d = len(N)
@@ -220,7 +200,7 @@ def ga_bounds(mat, N, M=None, tol=1e-10, maxit=10_000, track_energy=False, warm=
             x0 = None
             if warm is not None:
                 x0 = prolong(warm["fields_" + key][a], warm["N"], M)
-            e, info = solve(AM, N, E, kind, tol, maxit, track_energy, x0=x0, btol=btol)
+            e, info = solve(AM, N, E, kind, tol, maxit, track_energy, x0=x0)
             fields.append(e)
             out["iters_" + key].append(info["iters"])
             out["energies_" + key].append(info["energies"])

@@ -148,15 +148,20 @@ def test_bound_tolerance_matches_oracle(fg, btol):
         res = plan.run(micro, rtol=1e-12)
     finally:
         plan.close()
+    from bound_rule import first_stop
     mat = material.make_material(micro)
     ref = ga.ga_bounds(mat, N, tol=1e-12, track_energy=True)
-    ob = ga.ga_bounds(mat, N, tol=1e-12, btol=btol)
     gB = np.linalg.inv(res["lower"])
     for a in range(2):
         kp = res["info_primal"][a]["iters"]
         kd = res["info_dual"][a]["iters"]
-        assert kp < ref["iters_primal"][a] and abs(kp - ob["iters_primal"][a]) <= 1
-        assert kd < ref["iters_dual"][a] and abs(kd - ob["iters_dual"][a]) <= 1
+        # the stopping iteration is where the documented rule first holds on the
+        # oracle's exact energies (the device applies it to the CG recurrence,
+        # equal up to rounding, so a decision at the threshold may move by one)
+        op = first_stop(ref["energies_primal"][a], btol)
+        od = first_stop(ref["energies_dual"][a], btol)
+        assert kp < ref["iters_primal"][a] and abs(kp - op) <= 1
+        assert kd < ref["iters_dual"][a] and abs(kd - od) <= 1
         assert abs(res["upper"][a, a] - ref["energies_primal"][a][kp]) <= 1e-9 * res["upper"][a, a]
         assert abs(gB[a, a] - ref["energies_dual"][a][kd]) <= 1e-9 * gB[a, a]
         assert res["upper"][a, a] >= ref["upper"][a, a] * (1 - 1e-12)

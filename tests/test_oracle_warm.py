@@ -122,17 +122,21 @@ def test_cold_start_energy_is_voigt():
 
 
 @pytest.mark.parametrize("btol", [1e-4, 1e-6, 1e-8])
-def test_bound_tolerance_stop(btol):
-    # the bound test stops CG early; the bounds stay guaranteed (upper above,
-    # lower below the converged Ga bounds, Prop. struct_bounds) and within a
-    # small multiple of btol of them
+def test_bound_tolerance_rule_on_exact_energies(btol):
+    # the library's bound-based stopping rule (tests/bound_rule.py) applied to
+    # the oracle's exact energies of the CG iterates: it stops before
+    # convergence, and the energy where it stops is on the guaranteed side of
+    # the converged Ga energy (every iterate is admissible, Sec. 6.4) and
+    # within a small multiple of btol of it
+    from bound_rule import first_stop
     mat = _circle(200.0)
     N = (21, 21)
-    ref = ga.ga_bounds(mat, N, tol=1e-12)
-    res = ga.ga_bounds(mat, N, tol=1e-12, btol=btol)
-    assert sum(res["iters_primal"]) < sum(ref["iters_primal"])
-    for a in range(2):
-        up, lo = res["upper"][a, a], res["lower"][a, a]
-        assert up >= ref["upper"][a, a] * (1 - 1e-13) and lo <= ref["lower"][a, a] * (1 + 1e-13)
-        assert (up - ref["upper"][a, a]) / ref["upper"][a, a] <= 20 * btol
-        assert (ref["lower"][a, a] - lo) / ref["lower"][a, a] <= 20 * btol
+    ref = ga.ga_bounds(mat, N, tol=1e-12, track_energy=True)
+    for key, gram in (("primal", ref["gram_A"]), ("dual", ref["gram_B"])):
+        for a in range(2):
+            en = ref["energies_" + key][a]
+            k = first_stop(en, btol)
+            assert k is not None and k < ref["iters_" + key][a]
+            conv = gram[a, a]
+            assert en[k] >= conv * (1 - 1e-13)
+            assert (en[k] - conv) / conv <= 20 * btol
