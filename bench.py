@@ -88,10 +88,49 @@ def algorithmic_bytes(cls, d, N, M, es, gs, nc):
     return 0
 
 
-def cpu_baseline(micro, N, d):
-    """The oracle, as it stands, on a bounded sample: one CG iteration at full size."""
+def host_workers():
+    """Host threads the oracle's FFTs may use: the cores this process may run
+    on, capped by OMP_NUM_THREADS when set (the host's share per GPU)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(micro, N, d, gpu_iters, gpu_small):
+    """The oracle, as it stands (scipy.fft with every host thread it may use),
+    on a bounded sample: full time to bounds of the two 2D N = 41 workloads
+    (square of side 0.6 at contrast 10; disc of volume fraction 0.3 at
+    contrast 100; FP64, rtol 1e-10), and one CG iteration of the 3D benchmark
+    workload at full size, whose time times the GPU's CG iteration count
+    estimates the oracle's time to bounds there (labelled as an estimate)."""
     import numpy as np
-    from oracle import ga, material
+    import synth
+    from oracle import ga, grids, material
+    workers = host_workers()
+    grids.set_workers(workers)
+    full = {}
+    for key, m in (("c1_square_N41", synth.square_inclusion(2, 0.6, 1.0, 10.0)),
+                   ("c2_disc_N41", synth.circle_inclusion_vf(0.3, 1.0, 100.0))):
+        t0 = time.perf_counter()
+        res = ga.ga_bounds(material.make_material(m), (41, 41), tol=1e-10)
+        dt = time.perf_counter() - t0
+        its = sum(res["iters_primal"]) + sum(res["iters_dual"])
+        full[key] = {"time_to_bounds_s": round(dt, 3), "cg_iterations": its,
+                     "Mpoint_iter_per_s": round(81 * 81 * its / dt / 1e6, 3),
+                     "gpu_time_to_bounds_s": gpu_small.get(key)}
     t0 = time.perf_counter()
     mat = material.make_material(micro)
     AM = material.double_grid_matrix(mat, N, tuple(2 * n - 1 for n in N), "A")
@@ -113,9 +152,17 @@ def cpu_baseline(micro, N, d):
     pts = 1
     for m in M:
         pts *= m
-    return {"value": pts / it_s / 1e6, "unit": "Mpoint*CG-iter/s", "cores": 1, "kind": "oracle",
-            "sample": "1 oracle CG iteration (Algorithm 2 matvec, FP64, numpy.fft single-threaded, "
-                      "primal, d=3, M=225) after building A_M (%.1f s); %.2f s per iteration" % (setup_s, it_s)}
+    grids.set_workers(1)
+    est = 2 * setup_s + it_s * gpu_iters
+    return {"value": round(pts / it_s / 1e6, 3), "unit": "Mpoint*CG-iter/s", "cores": workers, "kind": "oracle",
+            "sample": "1 oracle CG iteration of the benchmark workload (Algorithm 2 matvec, FP64, d=3, M=225, "
+                      "scipy.fft with %d threads) after building A_M (%.1f s): %.3f s per iteration; plus the full "
+                      "oracle runs of the two 2D N=41 workloads" % (workers, setup_s, it_s),
+            "host": {"os_cpu_count": os.cpu_count(), "threads_used": workers, "cpu_model": cpu_model()},
+            "full_runs": full,
+            "benchmark_time_to_bounds_estimate_s": round(est, 1),
+            "estimate_note": "ESTIMATE, not a run: the measured oracle iteration time x the %d CG iterations the "
+                             "GPU takes on this workload, plus twice the A_M setup (A and its inverse)" % gpu_iters}
 
 
 def main():
@@ -312,9 +359,34 @@ def main():
     if args.serve3d > 0:
         out["serving_3d"] = serving3d_bench(args.serve3d, args.rtol32, args.serve3d_budget_gib)
     if not args.no_cpu_baseline:
+        gpu_small = small_2d_times(fftgal, dev)
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(micro, N, d)
+        gpu_iters = sum(f64["iters"]["primal"]) + sum(f64["iters"]["dual"])
+        out["cpu_baseline"] = cpu_baseline(micro, N, d, gpu_iters, gpu_small)
     print(json.dumps(out), flush=True)
+
+
+def small_2d_times(fftgal, dev):
+    """GPU time to bounds of the two 2D N = 41 workloads the CPU baseline runs
+    in full (FP64, rtol 1e-10; best of three after one warm-up)."""
+    import synth
+    import torch
+    out = {}
+    for key, m in (("c1_square_N41", synth.square_inclusion(2, 0.6, 1.0, 10.0)),
+                   ("c2_disc_N41", synth.circle_inclusion_vf(0.3, 1.0, 100.0))):
+        plan = fftgal.Plan(2, (41, 41), "fp64", device=dev)
+        plan.run(m, rtol=1e-10)
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.run(m, rtol=1e-10)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        plan.close()
+        out[key] = round(best, 5)
+    return out
 
 
 BOUND_TOL = 1e-6  # bound tolerance of the monitoring section (the FP32-iteration form's stated accuracy)

@@ -10,6 +10,16 @@ point set as the centred Z_M of eq. grid_points.  A Fourier array of shape
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft
+
+# threads of the library FFT (scipy.fft workers); set_workers changes it
+_WORKERS = 1
+
+
+def set_workers(n):
+    """Threads the FFT steps may use (the arithmetic is the same for any n)."""
+    global _WORKERS
+    _WORKERS = max(1, int(n))
 
 
 def wrapped_freqs(M):
@@ -43,14 +53,14 @@ def dft(u, axes=None):
     """F_M of eq. DFT: (1/|M|) sum_m omega_M^{-mk} u(m), over the given axes."""
     axes = tuple(range(u.ndim)) if axes is None else tuple(axes)
     size = np.prod([u.shape[a] for a in axes])
-    return np.fft.fftn(u, axes=axes) / size
+    return scipy.fft.fftn(u, axes=axes, workers=_WORKERS) / size
 
 
 def idft(uh, axes=None):
     """F_M^{-1} of eq. DFT: sum_k omega_M^{mk} uh(k), over the given axes."""
     axes = tuple(range(uh.ndim)) if axes is None else tuple(axes)
     size = np.prod([uh.shape[a] for a in axes])
-    return np.fft.ifftn(uh, axes=axes) * size
+    return scipy.fft.ifftn(uh, axes=axes, workers=_WORKERS) * size
 
 
 def naive_dft(u, sign):
