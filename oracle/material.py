@@ -72,8 +72,10 @@ class GridComposite:
     Chat(m) = (1/|P|) sum_p omega_P^{-mp} C^p, which is P-periodic in m, so it is
     read at m mod P whether P is larger or smaller than 2N-1 (Remark
     eval_with_FFT).  With psihat(m) = prod_a (1/P_a) sinc(m_a/P_a) the factors of
-    |P| cancel.  The image holds isotropic scalar conductivities; the dual uses
-    the voxel-wise inverse 1/C^p.
+    |P| cancel.  The image holds either scalar conductivities (shape P: C^p = c^p I)
+    or symmetric positive definite matrices (shape P + (d, d): eq. gridcomp with
+    C^p in R^{d x d}, one DFT per matrix entry); the dual uses the voxel-wise
+    inverse (C^p)^{-1}.
     """
 
     def __init__(self, micro):
@@ -84,16 +86,28 @@ class GridComposite:
         # primal uses an upper approximation of A, the dual a lower one)
         dual = micro.get("image_dual")
         self.image_dual = self.image if dual is None else np.asarray(dual, float)
-        self._chat_A = grids.dft(self.image)
-        self._chat_B = grids.dft(1.0 / self.image_dual)
+        self.tensor = self.image.ndim == self.d + 2
+        if self.tensor:
+            if self.image.shape != self.P + (self.d, self.d) or self.image_dual.shape != self.image.shape:
+                raise ValueError("a tensor image has shape P + (d, d)")
+            axes = tuple(range(self.d))
+            self._chat_A = grids.dft(self.image, axes=axes)
+            self._chat_B = grids.dft(np.linalg.inv(self.image_dual), axes=axes)
+        else:
+            self._chat_A = grids.dft(self.image)
+            self._chat_B = grids.dft(1.0 / self.image_dual)
 
     def _coeff(self, k, chat):
         idx = tuple(np.mod(k[a], self.P[a]) for a in range(self.d))
-        val = chat[idx]
+        win = np.ones(k.shape[1:])
         for a in range(self.d):
-            val = val * fourier.sinc(k[a] / self.P[a])
+            win = win * fourier.sinc(k[a] / self.P[a])
+        if self.tensor:
+            # chat[idx] has shape k.shape[1:] + (d, d): entries to the front
+            val = np.moveaxis(np.moveaxis(chat[idx], -1, 0), -1, 0)
+            return val * win
         eye = np.eye(self.d)[(...,) + (None,) * (k.ndim - 1)]
-        return eye * val
+        return eye * (chat[idx] * win)
 
     def coeff_A(self, k):
         return self._coeff(k, self._chat_A)

@@ -19,4 +19,6 @@ from .microstructures import (  # noqa: F401
     poisson_arrivals,
     with_arrivals,
     grf_request,
+    polycrystal,
+    multiphase_aniso,
 )

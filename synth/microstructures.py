@@ -12,7 +12,8 @@ the GPU binding:
 
 ``{"d": d, "kind": "voxels", "P": (P_1..P_d), "image": array of shape P}``
     Piecewise-constant isotropic image: voxel ``p`` (stored at index ``p mod P``)
-    is centred at ``p / P`` and has scalar conductivity ``image[p]``.
+    is centred at ``p / P`` and has scalar conductivity ``image[p]``; an image of
+    shape ``P + (d, d)`` holds a symmetric positive definite matrix per voxel.
 
 All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
 """
@@ -82,6 +83,54 @@ def cube_inclusion_aniso(side, seed, d=3):
         "sizes": np.full((1, d), float(side)),
         "A_in": a_in.reshape(1, d, d),
     }
+
+
+def polycrystal(seed, P, d=3, n_grains=12, log10_lo=0.0, log10_hi=2.0):
+    """Voxel image of anisotropic grains: a periodic Voronoi tessellation.
+
+    ``n_grains`` seed points uniform in the cell; voxel p (centre p / P) belongs
+    to the seed nearest under the periodic minimum image (ties to the lower
+    seed index).  Each grain has its own conductivity Q diag(lambda) Q^T
+    (``random_spd`` with sub-seeds: eigenvalues 10**U(lo, hi), Q Haar).
+    Returns a voxel descriptor whose image has shape P + (d, d).
+    """
+    P = tuple(int(p) for p in (P if np.iterable(P) else (P,) * d))
+    ss = np.random.SeedSequence(seed)
+    subs = ss.spawn(n_grains + 1)
+    rng = np.random.Generator(np.random.PCG64(subs[0]))
+    seeds = rng.uniform(-0.5, 0.5, size=(n_grains, d))
+    mats = np.array([random_spd(int(subs[g + 1].generate_state(1)[0]), d, log10_lo, log10_hi)
+                     for g in range(n_grains)])
+    axes = [np.where(np.arange(p) < (p + 1) // 2, np.arange(p), np.arange(p) - p) / p for p in P]
+    x = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)  # voxel centres, shape P + (d,)
+    best = np.full(P, np.inf)
+    grain = np.zeros(P, dtype=int)
+    for g in range(n_grains):
+        dd = x - seeds[g]
+        dd -= np.round(dd)
+        dist = np.sum(dd * dd, axis=-1)
+        closer = dist < best
+        best = np.where(closer, dist, best)
+        grain = np.where(closer, g, grain)
+    return {"d": d, "kind": "voxels", "P": P, "image": mats[grain]}
+
+
+def multiphase_aniso(seed, d=3, n=3, log10_lo=0.0, log10_hi=2.0):
+    """Non-overlapping boxes (placed on a lattice of cell positions), each with
+    its own anisotropic SPD conductivity, in an anisotropic SPD matrix phase:
+    eq. inclcomp with a different A_i per inclusion."""
+    ss = np.random.SeedSequence(seed)
+    subs = ss.spawn(n + 2)
+    rng = np.random.Generator(np.random.PCG64(subs[0]))
+    # n boxes of side 0.3 in distinct cells of a 3^d lattice of spacing 1/3
+    cells = rng.permutation(3 ** d)[:n]
+    centers = np.array([[((c // 3 ** a) % 3) / 3.0 - 1.0 / 3.0 for a in range(d)] for c in cells])
+    centers += rng.uniform(-0.01, 0.01, size=centers.shape)
+    sizes = rng.uniform(0.2, 0.3, size=(n, d))
+    A0 = random_spd(int(subs[1].generate_state(1)[0]), d, 0.0, 0.5)
+    A_in = np.array([random_spd(int(subs[i + 2].generate_state(1)[0]), d, log10_lo, log10_hi) for i in range(n)])
+    return {"d": d, "kind": "inclusions", "A0": A0, "shapes": ["rect"] * n, "centers": centers, "sizes": sizes,
+            "A_in": A_in}
 
 
 def _min_image_dist(a, b):
