@@ -74,6 +74,16 @@ enum fftgal_precision {
  * (faster, larger workspace).  EINVAL with the other plan kinds. */
 #define FFTGAL_REDUCED_LEAN 0x100
 
+/* Flag or-ed into `precision` of fftgal_workspace_bytes* and fftgal_plan /
+ * fftgal_plan_static: the plan stores the material as d (d + 1) / 2 fields per
+ * side (the entries of the symmetric A_M and B_M of eq. MBA_GA) instead of one
+ * scalar field with constant matrices.  Materials without that scalar form
+ * need it: matrix voxel images (image_tensor) and inclusion sets whose phases
+ * differ and are not all isotropic (eq. inclcomp with one SPD A_i per
+ * inclusion).  Ga plans only (EINVAL with GaNi and reduced plans); the
+ * workspace grows by (d (d + 1) / 2 - 1) material fields per side. */
+#define FFTGAL_TENSOR 0x200
+
 enum fftgal_material_kind {
     FFTGAL_INCLUSIONS = 0, /* eq. inclcomp: matrix phase plus inclusions          */
     FFTGAL_VOXELS = 1      /* eq. gridcomp: piecewise-constant voxel image        */
@@ -94,16 +104,23 @@ enum fftgal_shape {
  *   and ABSOLUTE conductivity A_in[i*d*d ..] (SPD; not the increment
  *   A_i = A_in - A0 of eq. inclcomp, because the dual needs A_in^{-1}).
  *   Inclusions must not overlap (periodic minimum image); the dual material
- *   is then A^{-1} = A0^{-1} + sum_i f_i [A_in^{-1} - A0^{-1}].  Supported:
- *   all A_in equal (two-phase, any SPD matrices), or A0 and every A_in
- *   isotropic (multiples of I).
+ *   is then A^{-1} = A0^{-1} + sum_i f_i [A_in^{-1} - A0^{-1}].  Any plan
+ *   takes all A_in equal (two-phase, any SPD matrices) or A0 and every A_in
+ *   isotropic (multiples of I); a plan made with FFTGAL_TENSOR takes any SPD
+ *   A0 and A_in (one per inclusion).
  * FFTGAL_VOXELS (eq. gridcomp with psi = rect_{1/P}, Lemma grid_compos,
  *   Remark eval_with_FFT): image holds P[0]*...*P[d-1] positive scalar
  *   conductivities, row-major, voxel p centred at x = p/P; the dual uses
- *   1/image.  Each P[a] must be an odd 3,5,7-smooth integer.  If
- *   image_device is non-zero, image is a device pointer that is read
- *   (stream-ordered, on the plan's stream) during fftgal_set_material only and
- *   validated on the device; otherwise it is host memory.
+ *   1/image.  With image_tensor non-zero (plans made with FFTGAL_TENSOR) it
+ *   holds instead one symmetric positive definite d x d matrix C^p per voxel
+ *   (P[0]*...*P[d-1]*d*d doubles, voxel-major, each matrix row-major), and
+ *   the dual uses the voxel-wise inverse (C^p)^{-1}.  Each P[a] must be an
+ *   odd 3,5,7-smooth integer.  If image_device is non-zero, image is a device
+ *   pointer that is read (stream-ordered, on the plan's stream) during
+ *   fftgal_set_material only and validated on the device; otherwise it is
+ *   host memory (a matrix image is then copied in chunks through the plan's
+ *   scratch).  Voxels that are not positive (scalars) or not finite,
+ *   symmetric and positive definite (matrices) give EINVAL.
  */
 typedef struct fftgal_material {
     int32_t kind;
@@ -121,6 +138,8 @@ typedef struct fftgal_material {
      * solves its voxel-wise inverse 1 / image_dual -- upper and lower
      * approximations of A for Lemma bounds_bounds */
     const double *image_dual;
+    /* non-zero: image (and image_dual) hold a d x d matrix per voxel */
+    int32_t image_tensor;
 } fftgal_material;
 
 /* Outcome of one CG solve (Remark CG). */

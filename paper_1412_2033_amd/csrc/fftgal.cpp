@@ -78,6 +78,7 @@ struct Dims {
     long Mtot = 0;          // |M|
     int nc_max = 1;
     int nshift = 1;         // material fields: 2^d shifted grids for the reduced Ga, else 1
+    int nfield = 1;         // fields per material side: d (d + 1) / 2 with FFTGAL_TENSOR, else 1
 };
 
 // Plan schemes: the Ga on the double grid, GaNi on the grid of the order N,
@@ -88,7 +89,7 @@ enum Scheme { kSchemeGa = 0, kSchemeGani = 1, kSchemeReduced = 2 };
 // (Def. GaNi, Algorithm 1), which must then be 3,5,7-smooth.  Reduced Ga: the
 // material series keeps its support Z_{2N-1}, the transforms run on the
 // N-grid (2^d shifted copies), which must then be 3,5,7-smooth.
-bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = kSchemeGa) {
+bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = kSchemeGa, bool tensor = false) {
     if ((d != 2 && d != 3) || N == nullptr) return false;
     const bool gani = scheme == kSchemeGani, red = scheme == kSchemeReduced;
     o->d = d;
@@ -109,6 +110,7 @@ bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = 
     for (int a = 0; a < d; ++a) o->Mtot *= o->M[a];
     o->nc_max = std::max(1, d - 1);
     o->nshift = red ? 1 << d : 1;
+    o->nfield = tensor ? d * (d + 1) / 2 : 1;
     return true;
 }
 
@@ -202,10 +204,11 @@ Layout make_layout(const Dims &D, int precision, bool grouped = true) {
     // FP32 iterations: the right-hand side and the best iterate so far
     L.bvec = take(precision == FFTGAL_FP32_ITER ? vec : 0);
     L.xbest = take(precision == FFTGAL_FP32_ITER ? vec : 0);
-    L.gA64 = take((size_t)D.nshift * D.Mtot * 8);
-    L.gB64 = take((size_t)D.nshift * D.Mtot * 8);
-    L.gA32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.nshift * D.Mtot * 4 : 0);
-    L.gB32 = take(precision == FFTGAL_FP32_ITER ? (size_t)D.nshift * D.Mtot * 4 : 0);
+    const size_t nfld = (size_t)D.nshift * D.nfield * D.Mtot;
+    L.gA64 = take(nfld * 8);
+    L.gB64 = take(nfld * 8);
+    L.gA32 = take(precision == FFTGAL_FP32_ITER ? nfld * 4 : 0);
+    L.gB32 = take(precision == FFTGAL_FP32_ITER ? nfld * 4 : 0);
     // partial sums: the largest work-group count of any reducing launch
     // (worst case: one pencil / one row pair per work-group)
     long nwg = update_blocks(2L * D.Ns);  // CG update of at most two coefficient components
@@ -281,6 +284,7 @@ struct fftgal_plan {
     int Pcur[3] = {0, 0, 0};
     bool have_mat = false;
     bool separate_gB = false;
+    bool gen = false;  // the material uses the d (d + 1) / 2 general fields
     double A0[9], DA[9], B0[9], DB[9];
     bool solved[2][3] = {{false, false, false}, {false, false, false}};
     bool warm[2][3] = {{false, false, false}, {false, false, false}};  // x holds an initial iterate
@@ -675,6 +679,14 @@ RowArgs base_row(Plan *pl, bool fp64, int mode, void *rows, int kind, int shift 
         r.g = pl->ws + (gsep ? pl->Lo.gB64 : pl->Lo.gA64) + (size_t)shift * D.Mtot * 8;
     else
         r.g = pl->ws + (gsep ? pl->Lo.gB32 : pl->Lo.gA32) + (size_t)shift * D.Mtot * 4;
+    r.nfield = 1;
+    r.gstride = D.Mtot;
+    if (pl->gen) {
+        r.nfield = D.nfield;
+        r.iso = 0;
+        for (int i = 0; i < 9; ++i) r.A0[i] = r.D[i] = 0.0;
+        return r;
+    }
     const double *c0 = kind == KIND_E ? pl->A0 : pl->B0;
     const double *c1 = kind == KIND_E ? pl->DA : pl->DB;
     for (int i = 0; i < 9; ++i) {
@@ -1470,17 +1482,220 @@ void sym_extremes(const double *A, int d, double *hi, double *lo) {
 
 namespace {
 
+// Field f of the general material (entries 11, 12, [13,] 22, [23,] 33).
+void field_entry(int f, int d, int *a, int *b) {
+    int k = 0;
+    for (int i = 0; i < d; ++i)
+        for (int j = i; j < d; ++j) {
+            if (k == f) {
+                *a = i;
+                *b = j;
+                return;
+            }
+            ++k;
+        }
+}
+
+// Inclusion composite with phases that need the general fields (eq.
+// inclcomp_formula per matrix entry): for each side (A, then A^{-1}, whose
+// inclusion values are the inverses of the phases because inclusions do not
+// overlap) and each entry (a, b), the series w0 delta_k0 + sum_i w_i chi_i(k)
+// with w0 = the matrix phase's entry and w_i = the entry of phase i minus it,
+// transformed to the M-grid (eq. MBA_GA).
+int general_inclusions(Plan *pl, const fftgal_material *m, std::vector<InclDev> &inc, InclDev *inc_dev) {
+    const Dims &D = pl->D;
+    const int d = D.d, n = (int)inc.size();
+    double A0inv[9];
+    if (!inv_small(m->A0, d, A0inv)) return fail(pl, FFTGAL_EINVAL, "A0 is singular");
+    std::vector<double> inv_in((size_t)n * d * d);
+    for (int i = 0; i < n; ++i)
+        if (!inv_small(m->A_in + (size_t)i * d * d, d, &inv_in[(size_t)i * d * d]))
+            return fail(pl, FFTGAL_EINVAL, "inclusion %d: A_in is singular", i);
+    void *U = pl->ws + pl->Lo.T2;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double *base = pass == 0 ? m->A0 : A0inv;
+        const double *ph = pass == 0 ? m->A_in : inv_in.data();
+        double *field = pl->at<double>(pass == 0 ? pl->Lo.gA64 : pl->Lo.gB64);
+        for (int f = 0; f < D.nfield; ++f) {
+            int a, b;
+            field_entry(f, d, &a, &b);
+            for (int i = 0; i < n; ++i) inc[i].w = ph[(size_t)i * d * d + a * d + b] - base[a * d + b];
+            if (n > 0)
+                HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
+                                            pl->stream));
+            {
+                Timed t(pl, FFTGAL_K_SETUP);
+                HIPCHECK(pl, launch_incl_coeff(U, d, D.L[0], D.L[1], D.Lh, inc_dev, n, base[a * d + b], pl->stream));
+            }
+            const int rc = series_to_field(pl, U, field + (size_t)f * D.Mtot);
+            if (rc) return rc;
+            HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // host table reused
+        }
+    }
+    pl->gen = true;
+    pl->separate_gB = true;
+    return FFTGAL_OK;
+}
+
+// Matrix voxel image (eq. gridcomp with C^p in R^{d x d}, Lemma grid_compos
+// per entry): validation, then for each side (the image; the voxel-wise
+// inverse of image_dual or of the image) and entry (a, b) the scalar image of
+// that entry through the voxel series (sinc window) to the M-grid field.  A
+// host image passes through the W scratch region in chunks.
+int tensor_voxels(Plan *pl, const fftgal_material *m, long Ptot, size_t wbytes) {
+    const Dims &D = pl->D;
+    const int d = D.d;
+    const size_t vb = (size_t)d * d * 8;  // bytes per voxel matrix
+    double *staging = pl->at<double>(pl->vox_u);
+    double *chunkbuf = pl->at<double>(pl->vox_w);
+    const long cap = (long)(wbytes / vb);
+    if (!m->image_device && cap < 1) return fail(pl, FFTGAL_ENOMEM, "no scratch for the matrix image");
+    // run `body(device_matrices, first_voxel, count)` over the image, chunked for host images
+    auto over = [&](const double *img, auto body) -> int {
+        if (m->image_device) return body(img, 0L, Ptot);
+        for (long v0 = 0; v0 < Ptot; v0 += cap) {
+            const long cnt = std::min(cap, Ptot - v0);
+            HIPCHECK(pl, hipMemcpyAsync(chunkbuf, img + (size_t)v0 * d * d, (size_t)cnt * vb, hipMemcpyHostToDevice,
+                                        pl->stream));
+            const int rc = body(chunkbuf, v0, cnt);
+            if (rc) return rc;
+            HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // the chunk buffer is reused
+        }
+        return FFTGAL_OK;
+    };
+    const bool dual = m->image_dual != nullptr;
+    for (int which = 0; which < (dual ? 2 : 1); ++which) {
+        const double *img = which == 1 ? m->image_dual : m->image;
+        double bad = 0.0;
+        int rc = over(img, [&](const double *src, long, long cnt) -> int {
+            int np = 0;
+            HIPCHECK(pl, launch_tensor_check(src, cnt, d, pl->at<double>(pl->Lo.part_a), &np, pl->stream));
+            HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->Lo.part_a), np, 1,
+                                             pl->stream));
+            double c = 0.0;
+            HIPCHECK(pl, hipMemcpyAsync(&c, pl->at<double>(pl->Lo.gram), 8, hipMemcpyDeviceToHost, pl->stream));
+            HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+            bad += c;
+            return FFTGAL_OK;
+        });
+        if (rc) return rc;
+        if (bad != 0.0)
+            return fail(pl, FFTGAL_EINVAL, "%.0f voxels %sare not finite symmetric positive definite matrices", bad,
+                        which == 1 ? "of the dual image " : "");
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const double *img = (pass == 1 && dual) ? m->image_dual : m->image;
+        double *field = pl->at<double>(pass == 0 ? pl->Lo.gA64 : pl->Lo.gB64);
+        for (int f = 0; f < D.nfield; ++f) {
+            int a, b;
+            field_entry(f, d, &a, &b);
+            int rc = over(img, [&](const double *src, long v0, long cnt) -> int {
+                Timed t(pl, FFTGAL_K_SETUP);
+                HIPCHECK(pl, launch_tensor_component(src, cnt, d, a, b, pass, staging + v0, pl->stream));
+                return FFTGAL_OK;
+            });
+            if (rc) return rc;
+            void *coef = nullptr;
+            if ((rc = voxel_series(pl, staging, 0, 0.0, &coef))) return rc;
+            if ((rc = series_to_field(pl, coef, field + (size_t)f * D.Mtot))) return rc;
+        }
+    }
+    pl->gen = true;
+    pl->separate_gB = true;
+    return FFTGAL_OK;
+}
+
+// Inclusion composite whose phases have the form A0 + g(x) D with one scalar
+// field per side: all phases equal (two-phase, any SPD matrices; g is the
+// indicator of the inclusions), or every phase isotropic (g is the conductivity
+// itself, and 1/conductivity for the dual).
+int scalar_inclusions(Plan *pl, const fftgal_material *m, std::vector<InclDev> &inc, bool same) {
+    const Dims &D = pl->D;
+    const int d = D.d, n = (int)inc.size();
+    double *gA = pl->at<double>(pl->Lo.gA64);
+    double *gB = pl->at<double>(pl->Lo.gB64);
+    int rc = FFTGAL_OK;
+    double A0inv[9];
+    inv_small(m->A0, d, A0inv);
+    double wA0 = 0.0, wB0 = 0.0;
+    std::vector<double> wA(n), wB(n);
+    if (same) {
+        pl->separate_gB = false;
+        std::memset(pl->DA, 0, sizeof pl->DA);
+        std::memset(pl->DB, 0, sizeof pl->DB);
+        for (int k = 0; k < d * d; ++k) {
+            pl->A0[k] = m->A0[k];
+            pl->B0[k] = A0inv[k];
+        }
+        if (n > 0) {
+            double Ainv[9];
+            inv_small(m->A_in, d, Ainv);
+            for (int k = 0; k < d * d; ++k) {
+                pl->DA[k] = m->A_in[k] - m->A0[k];
+                pl->DB[k] = Ainv[k] - A0inv[k];
+            }
+        }
+        for (int i = 0; i < n; ++i) wA[i] = wB[i] = 1.0;
+    } else {
+        double a0;
+        if (!is_iso(m->A0, d, &a0))
+            return fail(pl, FFTGAL_EINVAL, "different inclusion phases need isotropic A0 and A_in");
+        pl->separate_gB = true;
+        wA0 = a0;
+        wB0 = 1.0 / a0;
+        for (int i = 0; i < n; ++i) {
+            double ai;
+            if (!is_iso(m->A_in + (size_t)i * d * d, d, &ai))
+                return fail(pl, FFTGAL_EINVAL, "different inclusion phases need isotropic A0 and A_in");
+            wA[i] = ai - a0;
+            wB[i] = 1.0 / ai - 1.0 / a0;
+        }
+        for (int k = 0; k < 9; ++k) pl->A0[k] = pl->B0[k] = pl->DA[k] = pl->DB[k] = 0.0;
+        for (int a = 0; a < d; ++a) pl->DA[a * d + a] = pl->DB[a * d + a] = 1.0;
+    }
+    // device inclusion table lives at the end of the W scratch region
+    void *U = pl->ws + pl->Lo.T2;
+    const size_t inc_bytes = (size_t)std::max(n, 1) * sizeof(InclDev);
+    const size_t t1_bytes = pl->Lo.T2 - pl->Lo.T1;
+    if (inc_bytes + 4096 > t1_bytes / 2) return fail(pl, FFTGAL_EINVAL, "too many inclusions for this plan");
+    InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1 + (t1_bytes - inc_bytes - 256) / 256 * 256);
+    for (int pass = 0; pass < (pl->separate_gB ? 2 : 1); ++pass) {
+        for (int i = 0; i < n; ++i) inc[i].w = pass == 0 ? wA[i] : wB[i];
+        HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
+                                    pl->stream));
+        if (pl->gani) {
+            // Def. GaNi: the material at the grid points, not a Fourier series
+            Timed t(pl, FFTGAL_K_SETUP);
+            HIPCHECK(pl, launch_sample_incl(pass == 0 ? gA : gB, d, D.M, inc_dev, n, pass == 0 ? wA0 : wB0,
+                                            pl->stream));
+        } else {
+            {
+                Timed t(pl, FFTGAL_K_SETUP);
+                HIPCHECK(pl, launch_incl_coeff(U, d, D.L[0], D.L[1], D.Lh, inc_dev, n, pass == 0 ? wA0 : wB0,
+                                               pl->stream));
+            }
+            rc = pl->reduced ? series_to_shifted_fields(pl, U, pass == 0 ? gA : gB)
+                             : series_to_field(pl, U, pass == 0 ? gA : gB);
+            if (rc) return rc;
+        }
+        HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // host table reused
+    }
+    return FFTGAL_OK;
+}
+
 size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P, int scheme) {
     Dims D;
     const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
-    precision &= ~FFTGAL_REDUCED_LEAN;
+    const bool tensor = (precision & FFTGAL_TENSOR) != 0;
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
     if (lean && scheme != kSchemeReduced) return 0;
-    if (!make_dims(d, N, nullptr, &D, scheme)) return 0;
+    if (tensor && scheme != kSchemeGa) return 0;
+    if (!make_dims(d, N, nullptr, &D, scheme, tensor)) return 0;
     const size_t base = make_layout(D, precision, !lean).total;
     if (P == nullptr) return base;
     Dims DP;
-    if (!make_dims(d, N, P, &DP, scheme)) return 0;
+    if (!make_dims(d, N, P, &DP, scheme, tensor)) return 0;
     // a plan lays out its regions without P: an image that does not fit them
     // uses a tail of twiddles, U and W regions after the layout
     int Pv[3] = {1, 1, 1};
@@ -1500,12 +1715,15 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     *out = nullptr;
     Dims D;
     const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
-    precision &= ~FFTGAL_REDUCED_LEAN;
+    const bool tensor = (precision & FFTGAL_TENSOR) != 0;
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
         return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
     if (lean && scheme != kSchemeReduced)
         return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_REDUCED_LEAN applies to reduced plans only");
-    if (!make_dims(d, N, nullptr, &D, scheme))
+    if (tensor && scheme != kSchemeGa)
+        return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_TENSOR applies to Ga plans only");
+    if (!make_dims(d, N, nullptr, &D, scheme, tensor))
         return fail(nullptr, FFTGAL_EINVAL,
                     scheme == kSchemeGani      ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
                     : scheme == kSchemeReduced ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
@@ -1639,6 +1857,7 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
     const Dims &D = pl->D;
     const int d = D.d;
     pl->have_mat = false;
+    pl->gen = false;
     for (auto &row : pl->solved)
         for (bool &s : row) s = false;
     for (auto &row : pl->warm)
@@ -1654,70 +1873,22 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
         for (int i = 1; i < n && same; ++i)
             for (int k = 0; k < d * d; ++k)
                 if (m->A_in[(size_t)i * d * d + k] != m->A_in[k]) same = false;
-        double A0inv[9];
-        inv_small(m->A0, d, A0inv);
-        double wA0 = 0.0, wB0 = 0.0;
-        std::vector<double> wA(n), wB(n);
-        if (same) {
-            pl->separate_gB = false;
-            std::memset(pl->DA, 0, sizeof pl->DA);
-            std::memset(pl->DB, 0, sizeof pl->DB);
-            for (int k = 0; k < d * d; ++k) {
-                pl->A0[k] = m->A0[k];
-                pl->B0[k] = A0inv[k];
-            }
-            if (n > 0) {
-                double Ainv[9];
-                inv_small(m->A_in, d, Ainv);
-                for (int k = 0; k < d * d; ++k) {
-                    pl->DA[k] = m->A_in[k] - m->A0[k];
-                    pl->DB[k] = Ainv[k] - A0inv[k];
-                }
-            }
-            for (int i = 0; i < n; ++i) wA[i] = wB[i] = 1.0;
+        bool all_iso = true;
+        double tmp;
+        all_iso = is_iso(m->A0, d, &tmp);
+        for (int i = 0; i < n && all_iso; ++i) all_iso = is_iso(m->A_in + (size_t)i * d * d, d, &tmp);
+        if (!same && !all_iso) {
+            if (D.nfield < 2)
+                return fail(pl, FFTGAL_EINVAL, "inclusion phases that differ and are not all isotropic need a plan "
+                                               "made with FFTGAL_TENSOR");
+            const size_t inc_bytes = (size_t)std::max(n, 1) * sizeof(InclDev);
+            const size_t t1_bytes = pl->Lo.T2 - pl->Lo.T1;
+            if (inc_bytes + 4096 > t1_bytes / 2) return fail(pl, FFTGAL_EINVAL, "too many inclusions for this plan");
+            InclDev *inc_dev =
+                reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1 + (t1_bytes - inc_bytes - 256) / 256 * 256);
+            if ((rc = general_inclusions(pl, m, inc, inc_dev))) return rc;
         } else {
-            double a0;
-            if (!is_iso(m->A0, d, &a0))
-                return fail(pl, FFTGAL_EINVAL, "different inclusion phases need isotropic A0 and A_in");
-            pl->separate_gB = true;
-            wA0 = a0;
-            wB0 = 1.0 / a0;
-            for (int i = 0; i < n; ++i) {
-                double ai;
-                if (!is_iso(m->A_in + (size_t)i * d * d, d, &ai))
-                    return fail(pl, FFTGAL_EINVAL, "different inclusion phases need isotropic A0 and A_in");
-                wA[i] = ai - a0;
-                wB[i] = 1.0 / ai - 1.0 / a0;
-            }
-            for (int k = 0; k < 9; ++k) pl->A0[k] = pl->B0[k] = pl->DA[k] = pl->DB[k] = 0.0;
-            for (int a = 0; a < d; ++a) pl->DA[a * d + a] = pl->DB[a * d + a] = 1.0;
-        }
-        // device inclusion table lives at the end of the W scratch region
-        void *U = pl->ws + pl->Lo.T2;
-        const size_t inc_bytes = (size_t)std::max(n, 1) * sizeof(InclDev);
-        const size_t t1_bytes = pl->Lo.T2 - pl->Lo.T1;
-        if (inc_bytes + 4096 > t1_bytes / 2) return fail(pl, FFTGAL_EINVAL, "too many inclusions for this plan");
-        InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1 + (t1_bytes - inc_bytes - 256) / 256 * 256);
-        for (int pass = 0; pass < (pl->separate_gB ? 2 : 1); ++pass) {
-            for (int i = 0; i < n; ++i) inc[i].w = pass == 0 ? wA[i] : wB[i];
-            HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
-                                        pl->stream));
-            if (pl->gani) {
-                // Def. GaNi: the material at the grid points, not a Fourier series
-                Timed t(pl, FFTGAL_K_SETUP);
-                HIPCHECK(pl, launch_sample_incl(pass == 0 ? gA : gB, d, D.M, inc_dev, n, pass == 0 ? wA0 : wB0,
-                                                pl->stream));
-            } else {
-                {
-                    Timed t(pl, FFTGAL_K_SETUP);
-                    HIPCHECK(pl, launch_incl_coeff(U, d, D.L[0], D.L[1], D.Lh, inc_dev, n, pass == 0 ? wA0 : wB0,
-                                                   pl->stream));
-                }
-                rc = pl->reduced ? series_to_shifted_fields(pl, U, pass == 0 ? gA : gB)
-                                 : series_to_field(pl, U, pass == 0 ? gA : gB);
-                if (rc) return rc;
-            }
-            HIPCHECK(pl, hipStreamSynchronize(pl->stream));  // host table reused
+            if ((rc = scalar_inclusions(pl, m, inc, same))) return rc;
         }
     } else if (m->kind == FFTGAL_VOXELS) {
         long Ptot = 1;
@@ -1765,6 +1936,12 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
                                     pl->stream));
         HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->vox_tw32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice,
                                     pl->stream));
+        if (m->image_tensor) {
+            if (D.nfield < 2)
+                return fail(pl, FFTGAL_EINVAL, "matrix voxel images need a plan made with FFTGAL_TENSOR");
+            const size_t wb = pl->vox_w == pl->Lo.T1 ? wbytes : need_w;
+            if ((rc = tensor_voxels(pl, m, Ptot, wb))) return rc;
+        } else {
         // the image is read from the caller's device buffer, or from a staging
         // copy at the start of the U scratch region (re-uploaded per pass,
         // since the transforms overwrite U)
@@ -1833,14 +2010,15 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
                              : series_to_field(pl, coef, pass == 0 ? gA : gB);
             if (rc) return rc;
         }
+        }
     } else {
         return fail(pl, FFTGAL_EINVAL, "unknown material kind %d", m->kind);
     }
     if (!pl->fp64_iter()) {
         Timed t(pl, FFTGAL_K_SETUP);
-        HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gA32), gA, (size_t)D.nshift * D.Mtot, pl->stream));
-        if (pl->separate_gB)
-            HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gB32), gB, (size_t)D.nshift * D.Mtot, pl->stream));
+        const size_t nv = (size_t)D.nshift * (pl->gen ? D.nfield : 1) * D.Mtot;
+        HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gA32), gA, nv, pl->stream));
+        if (pl->separate_gB) HIPCHECK(pl, launch_convert_d2f(pl->at<float>(pl->Lo.gB32), gB, nv, pl->stream));
     }
     HIPCHECK(pl, hipStreamSynchronize(pl->stream));
     pl->have_mat = true;

@@ -147,6 +147,11 @@ struct RowArgs {
     const void *g;    // material field g (M^d, precision of the kernel)
     double A0[9];     // A(x) = A0 + g(x) D
     double D[9];
+    // nfield > 1: A(x) is the symmetric matrix whose entries 11, 12, [13,] 22,
+    // [23,] 33 are the fields g + f * gstride (f = 0 .. nfield - 1); A0 and D
+    // are unused
+    int nfield;
+    long gstride;
     double E[3];      // load for ROW_RHS
     void *real_out;   // ROW_C2R output rows (length n)
     const void *real_in;  // ROW_R2C input rows (length n)
@@ -233,6 +238,13 @@ int pencil_grid_x(const PencilArgs &a);
 hipError_t launch_cg_checkpoint(const UpdArgs &u, const void *b, void *xbest, const double *part_xkx, int n_xkx,
                                 double *part_bx, int window, int final, bool fp64, hipStream_t s);
 hipError_t launch_copy_vec(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Matrix voxel images (n voxels of d x d, row-major per voxel): per work-group
+// counts of voxels that are not finite, symmetric and positive definite into
+// part (one entry per work-group of the launch, nparts returned in *nparts).
+hipError_t launch_tensor_check(const double *img, long n, int d, double *part, int *nparts, hipStream_t s);
+// out[i] = entry (a, b) of voxel i's matrix, or of its inverse (invert = 1).
+hipError_t launch_tensor_component(const double *img, long n, int d, int a, int b, int invert, double *out,
+                                   hipStream_t s);
 hipError_t launch_cg_init(CgStatus *st, const double *rr_part, int n_rr, const double *load_part, int n_load,
                           const double *work_part, double inv_mtot, double tol, double floor_rel, int maxit,
                           double btol, double *hist, hipStream_t s);

@@ -777,6 +777,20 @@ __global__ __launch_bounds__(kThreads) void fold_series_kernel(double2 *out, con
     }
 }
 
+// Symmetric material matrix at linear grid point pt from d (d + 1) / 2 fields
+// (entries 11, 12, [13,] 22, [23,] 33; field f at g + f * stride).
+template <typename T>
+__device__ __forceinline__ void sym_load(const T *g, long stride, long pt, int d, T *m) {
+    int f = 0;
+    for (int i = 0; i < d; ++i)
+        for (int j = i; j < d; ++j) {
+            const T v = g[(long)f * stride + pt];
+            m[i * d + j] = v;
+            m[j * d + i] = v;
+            ++f;
+        }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass: real transforms along the last axis, two rows per complex DFT.
 // ---------------------------------------------------------------------------
@@ -867,8 +881,21 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             const int r1 = 2 * (pair0 + j);
             const int r2 = r1 + 1;
             const bool v2 = r2 < a.nrows;
-            const T g1 = g[(long)r1 * n + x];
-            const T g2 = v2 ? g[(long)r2 * n + x] : T(0);
+            T m1[9], m2[9];
+            if (a.nfield > 1) {
+                sym_load<T>(g, a.gstride, (long)r1 * n + x, d, m1);
+                if (v2)
+                    sym_load<T>(g, a.gstride, (long)r2 * n + x, d, m2);
+                else
+                    for (int i = 0; i < d * d; ++i) m2[i] = T(0);
+            } else {
+                const T g1 = g[(long)r1 * n + x];
+                const T g2 = v2 ? g[(long)r2 * n + x] : T(0);
+                for (int i = 0; i < d * d; ++i) {
+                    m1[i] = A0[i] + g1 * D[i];
+                    m2[i] = A0[i] + g2 * D[i];
+                }
+            }
             T e1[3], e2[3];
             for (int b = 0; b < d; ++b) {
                 if (a.mode == ROW_OPER) {
@@ -883,8 +910,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             for (int al = 0; al < d; ++al) {
                 T y1 = T(0), y2 = T(0);
                 for (int b = 0; b < d; ++b) {
-                    y1 += (A0[al * d + b] + g1 * D[al * d + b]) * e1[b];
-                    y2 += (A0[al * d + b] + g2 * D[al * d + b]) * e2[b];
+                    y1 += m1[al * d + b] * e1[b];
+                    y2 += m2[al * d + b] * e2[b];
                 }
                 zbuf(al)[idx] = mk<T>(y1, y2);
                 load += (double)y1 * y1 + (double)y2 * y2;
@@ -918,7 +945,13 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             for (int half = 0; half < 2; ++half) {
                 const int r = half ? r2 : r1;
                 if (r >= a.nrows) continue;
-                const T gg = g[(long)r * n + x];
+                T am[9];
+                if (a.nfield > 1) {
+                    sym_load<T>(g, a.gstride, (long)r * n + x, d, am);
+                } else {
+                    const T gg = g[(long)r * n + x];
+                    for (int i = 0; i < d * d; ++i) am[i] = A0[i] + gg * D[i];
+                }
                 T f[3][3];
                 for (int s = 0; s < d; ++s)
                     for (int b = 0; b < d; ++b) {
@@ -929,7 +962,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                     T af[3];
                     for (int al = 0; al < d; ++al) {
                         T y = T(0);
-                        for (int b = 0; b < d; ++b) y += (A0[al * d + b] + gg * D[al * d + b]) * f[t][b];
+                        for (int b = 0; b < d; ++b) y += am[al * d + b] * f[t][b];
                         af[al] = y;
                     }
                     for (int s = 0; s < d; ++s) {
@@ -1675,7 +1708,7 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
         const int x = idx - j * N;
         gv1[t] = T(0);
         gv2[t] = T(0);
-        if (idx < RP * N && j < nvp) {
+        if (idx < RP * N && j < nvp && a.nfield <= 1) {
             const int r1 = 2 * (pair0 + j);
             gv1[t] = g[(long)r1 * N + x];
             if (r1 + 1 < a.nrows) gv2[t] = g[(long)(r1 + 1) * N + x];
@@ -1733,18 +1766,34 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
             const int j = idx / N;
             const int x = idx - j * N;
             if (idx >= RP * N || j >= nvp) continue;
-            const T g1 = gv1[t];
-            const T g2 = gv2[t];
             V e[D];
 #pragma unroll
             for (int b = 0; b < D; ++b) e[b] = X[(b * RP + j) * N + x];
+            T m1[D * D], m2[D * D];
+            if (a.nfield > 1) {
+                const int r1 = 2 * (pair0 + j);
+                sym_load<T>(g, a.gstride, (long)r1 * N + x, D, m1);
+                if (r1 + 1 < a.nrows)
+                    sym_load<T>(g, a.gstride, (long)(r1 + 1) * N + x, D, m2);
+                else
+#pragma unroll
+                    for (int i = 0; i < D * D; ++i) m2[i] = T(0);
+            } else {
+                const T g1 = gv1[t];
+                const T g2 = gv2[t];
+#pragma unroll
+                for (int i = 0; i < D * D; ++i) {
+                    m1[i] = A0[i] + g1 * Dm[i];
+                    m2[i] = A0[i] + g2 * Dm[i];
+                }
+            }
 #pragma unroll
             for (int al = 0; al < D; ++al) {
                 T y1 = T(0), y2 = T(0);
 #pragma unroll
                 for (int b = 0; b < D; ++b) {
-                    y1 += (A0[al * D + b] + g1 * Dm[al * D + b]) * e[b].x;
-                    y2 += (A0[al * D + b] + g2 * Dm[al * D + b]) * e[b].y;
+                    y1 += m1[al * D + b] * e[b].x;
+                    y2 += m2[al * D + b] * e[b].y;
                 }
                 X[(al * RP + j) * N + x] = mk<T>(y1, y2);
             }
@@ -1764,15 +1813,30 @@ __global__ __launch_bounds__(kThreads) void row_fast(const RowArgs *__restrict__
                 const int r1 = 2 * (pair0 + j);
                 const int r2 = r1 + 1;
                 const bool v2 = r2 < a.nrows;
-                const T g1 = gv1[t];
-                const T g2 = gv2[t];
+                T m1[D * D], m2[D * D];
+                if (a.nfield > 1) {
+                    sym_load<T>(g, a.gstride, (long)r1 * N + x, D, m1);
+                    if (v2)
+                        sym_load<T>(g, a.gstride, (long)r2 * N + x, D, m2);
+                    else
+#pragma unroll
+                        for (int i = 0; i < D * D; ++i) m2[i] = T(0);
+                } else {
+                    const T g1 = gv1[t];
+                    const T g2 = gv2[t];
+#pragma unroll
+                    for (int i = 0; i < D * D; ++i) {
+                        m1[i] = A0[i] + g1 * Dm[i];
+                        m2[i] = A0[i] + g2 * Dm[i];
+                    }
+                }
 #pragma unroll
                 for (int al = 0; al < D; ++al) {
                     T y1 = T(0), y2 = T(0);
 #pragma unroll
                     for (int b = 0; b < D; ++b) {
-                        y1 += (A0[al * D + b] + g1 * Dm[al * D + b]) * T(a.E[b]);
-                        if (v2) y2 += (A0[al * D + b] + g2 * Dm[al * D + b]) * T(a.E[b]);
+                        y1 += m1[al * D + b] * T(a.E[b]);
+                        if (v2) y2 += m2[al * D + b] * T(a.E[b]);
                     }
                     y[al] = mk<T>(y1, y2);
                     load += (double)y1 * y1 + (double)y2 * y2;
@@ -2623,7 +2687,14 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
         for (int half = 0; half < 2; ++half) {
             const int r = r1 + half;
             if (r >= a.nrows) continue;
-            const T gg = g[(long)r * N + x];
+            T am[D * D];
+            if (a.nfield > 1) {
+                sym_load<T>(g, a.gstride, (long)r * N + x, D, am);
+            } else {
+                const T gg = g[(long)r * N + x];
+#pragma unroll
+                for (int i = 0; i < D * D; ++i) am[i] = A0[i] + gg * Dm[i];
+            }
             T f[D][D];
 #pragma unroll
             for (int sol = 0; sol < D; ++sol)
@@ -2639,7 +2710,7 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
                 for (int al = 0; al < D; ++al) {
                     T y = T(0);
 #pragma unroll
-                    for (int b = 0; b < D; ++b) y += (A0[al * D + b] + gg * Dm[al * D + b]) * f[t][b];
+                    for (int b = 0; b < D; ++b) y += am[al * D + b] * f[t][b];
                     af[al] = y;
                 }
 #pragma unroll
@@ -2914,6 +2985,75 @@ __global__ void copy_words_kernel(unsigned int *dst, const unsigned int *src, si
         dst[i] = src[i];
 }
 
+// ---- matrix voxel images (eq. gridcomp with C^p in R^{d x d}) ----
+// Determinant and inverse of a symmetric 2 x 2 or 3 x 3 matrix by cofactors.
+__device__ __forceinline__ double sym_det(const double *m, int d) {
+    if (d == 2) return m[0] * m[3] - m[1] * m[2];
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+           m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+__device__ __forceinline__ void sym_inverse(const double *m, int d, double *out) {
+    const double det = sym_det(m, d);
+    if (d == 2) {
+        out[0] = m[3] / det;
+        out[1] = -m[1] / det;
+        out[2] = -m[2] / det;
+        out[3] = m[0] / det;
+        return;
+    }
+    out[0] = (m[4] * m[8] - m[5] * m[7]) / det;
+    out[1] = (m[2] * m[7] - m[1] * m[8]) / det;
+    out[2] = (m[1] * m[5] - m[2] * m[4]) / det;
+    out[3] = (m[5] * m[6] - m[3] * m[8]) / det;
+    out[4] = (m[0] * m[8] - m[2] * m[6]) / det;
+    out[5] = (m[2] * m[3] - m[0] * m[5]) / det;
+    out[6] = (m[3] * m[7] - m[4] * m[6]) / det;
+    out[7] = (m[1] * m[6] - m[0] * m[7]) / det;
+    out[8] = (m[0] * m[4] - m[1] * m[3]) / det;
+}
+
+// A voxel matrix is accepted when finite, symmetric (to 1e-12 of its entries)
+// and positive definite (leading principal minors > 0, Sylvester).
+__global__ __launch_bounds__(kThreads) void tensor_check_kernel(const double *img, long n, int d, double *part) {
+    double bad = 0.0;
+    const int dd = d * d;
+    for (long i = blockIdx.x * (long)kThreads + threadIdx.x; i < n; i += (long)gridDim.x * kThreads) {
+        double m[9];
+        bool ok = true;
+        for (int k = 0; k < dd; ++k) {
+            m[k] = img[i * dd + k];
+            ok = ok && isfinite(m[k]);
+        }
+        for (int r = 0; r < d && ok; ++r)
+            for (int c = r + 1; c < d; ++c)
+                if (fabs(m[r * d + c] - m[c * d + r]) > 1e-12 * (fabs(m[r * d + c]) + fabs(m[c * d + r]))) ok = false;
+        if (ok) {
+            const double m1 = m[0];
+            const double m2 = m[0] * m[d + 1] - m[1] * m[d];
+            ok = m1 > 0.0 && m2 > 0.0 && (d == 2 || sym_det(m, d) > 0.0);
+        }
+        bad += ok ? 0.0 : 1.0;
+    }
+    const double s = block_sum(bad);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void tensor_component_kernel(const double *img, long n, int d, int a, int b,
+                                                                    int invert, double *out) {
+    const int dd = d * d;
+    for (long i = blockIdx.x * (long)kThreads + threadIdx.x; i < n; i += (long)gridDim.x * kThreads) {
+        if (!invert) {
+            out[i] = 0.5 * (img[i * dd + a * d + b] + img[i * dd + b * d + a]);
+            continue;
+        }
+        double m[9], inv[9];
+        for (int k = 0; k < dd; ++k) m[k] = img[i * dd + k];
+        sym_inverse(m, d, inv);
+        out[i] = 0.5 * (inv[a * d + b] + inv[b * d + a]);
+    }
+}
+
 // Device-side validation of a voxel image: per work-group min, max and the
 // number of entries that are not positive finite (part[3 b + 0..2]).
 __global__ __launch_bounds__(kThreads) void image_stats_kernel(const double *img, long n, double *part) {
@@ -3185,6 +3325,21 @@ hipError_t launch_cg_checkpoint(const UpdArgs &u, const void *b, void *xbest, co
     else
         hipLaunchKernelGGL(ckpt_copy_kernel<float>, dim3(u.nblocks), dim3(kThreads), 0, s, u,
                            reinterpret_cast<float2 *>(xbest));
+    return hipGetLastError();
+}
+
+hipError_t launch_tensor_check(const double *img, long n, int d, double *part, int *nparts, hipStream_t s) {
+    const int blocks = (int)std::max<long>(1, std::min<long>((n + kThreads - 1) / kThreads, 1024));
+    *nparts = blocks;
+    hipLaunchKernelGGL(tensor_check_kernel, dim3(blocks), dim3(kThreads), 0, s, img, n, d, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_tensor_component(const double *img, long n, int d, int a, int b, int invert, double *out,
+                                   hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>((n + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(tensor_component_kernel, dim3(blocks), dim3(kThreads), 0, s, img, n, d, a, b, invert, out);
     return hipGetLastError();
 }
 

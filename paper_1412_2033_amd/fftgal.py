@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libfftgal.so")
 FP64 = 0
 FP32_ITER = 1
 REDUCED_LEAN = 0x100  # reduced Ga laid out with one set of intermediates (shifts in turn)
+TENSOR = 0x200  # d(d+1)/2 material fields per side (matrix images, anisotropic multi-phase inclusions)
 PRECISIONS = {"fp64": FP64, "fp32": FP32_ITER, "fp32_iter": FP32_ITER}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5: "ESTATE", -6: "EBREAKDOWN"}
@@ -57,6 +58,7 @@ class Material(ctypes.Structure):
         ("image", ctypes.POINTER(ctypes.c_double)),
         ("image_device", ctypes.c_int32),
         ("image_dual", ctypes.POINTER(ctypes.c_double)),
+        ("image_tensor", ctypes.c_int32),
     ]
 
 
@@ -257,6 +259,8 @@ def material_struct(micro):
 
         m.image = ptr(img)
         m.image_device = 1 if on_device else 0
+        # a matrix per voxel: shape P + (d, d)
+        m.image_tensor = 1 if len(tuple(img.shape)) == d + 2 else 0
         if dual is not None:
             m.image_dual = ptr(dual)
     else:
@@ -348,7 +352,8 @@ def fftgal_history(plan, kind, alpha, cap=20001):
 class Plan:
     """A plan plus the torch device workspace it runs in."""
 
-    def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None, scheme="ga", lean=False):
+    def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None, scheme="ga", lean=False,
+                 tensor=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fftgal needs a HIP device")
@@ -356,7 +361,7 @@ class Plan:
         self.N = tuple(int(n) for n in N)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.scheme = scheme
-        flags = self.precision | (REDUCED_LEAN if lean else 0)
+        flags = self.precision | (REDUCED_LEAN if lean else 0) | (TENSOR if tensor else 0)
         self.nbytes = fftgal_workspace_bytes(self.d, self.N, flags, P, scheme)
         if self.nbytes == 0:
             raise FftgalError(-1, "invalid plan arguments")
