@@ -114,8 +114,9 @@ enum fftgal_shape {
  *   1/image.  With image_tensor non-zero (plans made with FFTGAL_TENSOR) it
  *   holds instead one symmetric positive definite d x d matrix C^p per voxel
  *   (P[0]*...*P[d-1]*d*d doubles, voxel-major, each matrix row-major), and
- *   the dual uses the voxel-wise inverse (C^p)^{-1}.  Each P[a] must be an
- *   odd 3,5,7-smooth integer.  If image_device is non-zero, image is a device
+ *   the dual uses the voxel-wise inverse (C^p)^{-1}.  Each P[a] must be odd
+ *   (lengths that are not 3,5,7-smooth are transformed by Bluestein's chirp
+ *   convolution, through the generic kernels).  If image_device is non-zero, image is a device
  *   pointer that is read (stream-ordered, on the plan's stream) during
  *   fftgal_set_material only and validated on the device; otherwise it is
  *   host memory (a matrix image is then copied in chunks through the plan's
@@ -289,8 +290,9 @@ int fftgal_set_bound_tol(struct fftgal_plan *plan, double btol);
  * GaNi plans (Def. GaNi, Algorithm 1): the material is sampled at the grid
  * points x = k / N of the grid of the approximation order N (a point on an
  * inclusion boundary counts as outside; a voxel p covers [p/P - 1/(2P),
- * p/P + 1/(2P))), and the transforms run on that grid, so every N_a must be
- * odd and 3,5,7-smooth.  The solve and bounds calls then return the GaNi
+ * p/P + 1/(2P))), and the transforms run on that grid: every N_a must be odd;
+ * a length that is not 3,5,7-smooth is transformed by Bluestein's chirp
+ * convolution of the smooth length L >= 2 N_a - 1 (generic kernels).  The solve and bounds calls then return the GaNi
  * minimisers and A~_{H,N} (upper) and B~_{H,N}^{-1} (lower) -- equal for odd
  * N (Remark duality_gani) and NOT guaranteed bounds; fftgal_bounds_of turns
  * the minimisers into guaranteed ones.  Workspace, arguments and errors as
@@ -320,8 +322,10 @@ int fftgal_bounds_of(struct fftgal_plan *plan, struct fftgal_plan *src, double *
  * (the series on Z_{2N-1} folded onto Z_N with the phase of s, then one
  * inverse DFT of size N), and every operator application runs the transform
  * passes once per shift with the phases S(s), S*(s) of the lemma, summing the
- * projected results.  Every N_a must be odd and 3,5,7-smooth (EINVAL
- * otherwise; 81, 125, 225, 245, 729 and 2025 run the specialised kernels).  Solves, bounds, history and
+ * projected results.  Every N_a must be odd; 81, 125, 225, 245, 729 and 2025
+ * run the specialised kernels, other 3,5,7-smooth lengths the generic ones,
+ * and the other lengths (the primes 41, 113, 1013 among them) Bluestein's chirp
+ * convolution of the smooth length L >= 2 N_a - 1 in the generic kernels.  Solves, bounds, history and
  * the bound tolerance work as for fftgal_plan; warm starts, a-posteriori
  * bounds and batches are not available (EINVAL).  The workspace holds 2^d
  * material fields of |N| values and transform intermediates of the N-grid:

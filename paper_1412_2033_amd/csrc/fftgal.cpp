@@ -48,6 +48,14 @@ int smooth_odd(int m) {
 
 bool is_smooth_odd(int n) { return n >= 1 && smooth_odd(n) == n; }
 
+// Complex table entries a transform of length n takes (stage twiddles of a
+// smooth n; for a Bluestein transform those of L plus the chirp and the filter).
+size_t fft_table_len(int n) {
+    if (is_smooth_odd(n)) return (size_t)n;
+    const int L = smooth_odd(2 * n - 1);
+    return (size_t)L + (size_t)n + (size_t)L;
+}
+
 std::vector<int> factor(int n) {
     std::vector<int> f;
     const int fi = fast_index(n);
@@ -86,22 +94,20 @@ struct Dims {
 enum Scheme { kSchemeGa = 0, kSchemeGani = 1, kSchemeReduced = 2 };
 
 // GaNi: the transforms run on the grid of the approximation order N itself
-// (Def. GaNi, Algorithm 1), which must then be 3,5,7-smooth.  Reduced Ga: the
-// material series keeps its support Z_{2N-1}, the transforms run on the
-// N-grid (2^d shifted copies), which must then be 3,5,7-smooth.
+// (Def. GaNi, Algorithm 1).  Reduced Ga: the material series keeps its support
+// Z_{2N-1}, the transforms run on the N-grid (2^d shifted copies).  Lengths
+// that are not 3,5,7-smooth are transformed by Bluestein's algorithm.
 bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = kSchemeGa, bool tensor = false) {
     if ((d != 2 && d != 3) || N == nullptr) return false;
     const bool gani = scheme == kSchemeGani, red = scheme == kSchemeReduced;
     o->d = d;
     for (int a = 0; a < d; ++a) {
         if (N[a] < 1 || N[a] % 2 == 0 || N[a] > 100000) return false;
-        if (gani && !is_smooth_odd(N[a])) return false;
-        if (red && !is_smooth_odd(N[a])) return false;
         o->N[a] = N[a];
         o->L[a] = gani ? N[a] : 2 * N[a] - 1;
         o->M[a] = (gani || red) ? N[a] : smooth_odd(2 * N[a] - 1);
         o->P[a] = P ? std::max<int>(P[a], o->M[a]) : o->M[a];
-        if (P && !is_smooth_odd(P[a])) return false;
+        if (P && (P[a] < 1 || P[a] % 2 == 0 || P[a] > 100000)) return false;
     }
     o->Nh = (o->N[d - 1] + 1) / 2;
     o->Lh = gani ? o->Nh : o->N[d - 1];
@@ -157,9 +163,9 @@ Layout make_layout(const Dims &D, int precision, bool grouped = true) {
     };
     // twiddle tables: one per axis length M_a (<= sum of lengths entries)
     L.tw_len = 0;
-    for (int a = 0; a < d; ++a) L.tw_len += D.M[a];
+    for (int a = 0; a < d; ++a) L.tw_len += fft_table_len(D.M[a]);
     L.twP_len = 0;
-    for (int a = 0; a < d; ++a) L.twP_len += D.P[a];
+    for (int a = 0; a < d; ++a) L.twP_len += fft_table_len(D.P[a]);
     L.tw64 = take(L.tw_len * c16);
     L.tw32 = take(L.tw_len * 8);
     L.twP64 = take(L.twP_len * c16);
@@ -229,26 +235,78 @@ Layout make_layout(const Dims &D, int precision, bool grouped = true) {
     return L;
 }
 
-void build_fft(int n, size_t tw_base_entry, std::vector<double> &tab, FftDesc *f) {
-    std::vector<int> rad = factor(n);
-    f->n = n;
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+
+// Stage twiddles of a smooth length m, appended at entry `pos` of tab.
+void stage_twiddles(int m, size_t &pos, std::vector<double> &tab, FftDesc *f) {
+    std::vector<int> rad = factor(m);
     f->nst = (int)rad.size();
     int p = 1;
-    size_t pos = tw_base_entry;
     for (int s = 0; s < f->nst; ++s) {
         const int r = rad[s];
         f->radix[s] = r;
         f->twoff[s] = (int)pos;
         for (int q = 1; q < r; ++q)
             for (int k = 0; k < p; ++k) {
-                const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)(q * k) /
-                                        (long double)(p * r);
+                const long double ang = -2.0L * kPiL * (long double)(q * k) / (long double)(p * r);
                 tab.push_back((double)cosl(ang));
                 tab.push_back((double)sinl(ang));
             }
         pos += (size_t)(r - 1) * p;
         p *= r;
     }
+}
+
+void build_fft(int n, size_t tw_base_entry, std::vector<double> &tab, FftDesc *f) {
+    size_t pos = tw_base_entry;
+    f->n = n;
+    f->L = n;
+    f->blue = 0;
+    f->choff = f->hoff = 0;
+    if (is_smooth_odd(n)) {
+        stage_twiddles(n, pos, tab, f);
+        return;
+    }
+    // Bluestein (see FftDesc): chirp c_m = exp(i pi m^2 / n), angles reduced
+    // exactly with m^2 mod 2n; H = DFT_L^-(v) / L with v_m = conj(c_m) at
+    // m mod L for |m| < n, evaluated directly in long double
+    const int L = smooth_odd(2 * n - 1);
+    f->L = L;
+    f->blue = 1;
+    stage_twiddles(L, pos, tab, f);
+    f->choff = (int)pos;
+    std::vector<long double> cr(n), ci(n);
+    for (int m = 0; m < n; ++m) {
+        const long long q = ((long long)m * m) % (2LL * n);
+        const long double ang = kPiL * (long double)q / (long double)n;
+        cr[m] = cosl(ang);
+        ci[m] = sinl(ang);
+        tab.push_back((double)cr[m]);
+        tab.push_back((double)ci[m]);
+    }
+    pos += (size_t)n;
+    f->hoff = (int)pos;
+    std::vector<long double> vr(L, 0.0L), vi(L, 0.0L);
+    for (int m = -(n - 1); m <= n - 1; ++m) {
+        const int am = m < 0 ? -m : m;
+        const int idx = ((m % L) + L) % L;
+        vr[idx] = cr[am];
+        vi[idx] = -ci[am];
+    }
+    for (int k = 0; k < L; ++k) {
+        long double hr = 0.0L, hi = 0.0L;
+        for (int m = 0; m < L; ++m) {
+            if (vr[m] == 0.0L && vi[m] == 0.0L) continue;
+            const long long q = ((long long)m * k) % L;
+            const long double ang = -2.0L * kPiL * (long double)q / (long double)L;
+            const long double c = cosl(ang), sn = sinl(ang);
+            hr += vr[m] * c - vi[m] * sn;
+            hi += vr[m] * sn + vi[m] * c;
+        }
+        tab.push_back((double)(hr / L));
+        tab.push_back((double)(hi / L));
+    }
+    pos += (size_t)L;
 }
 
 }  // namespace
@@ -1702,7 +1760,7 @@ size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P,
     size_t entry = 0;
     for (int a = 0; a < d; ++a) {
         Pv[a] = P[a];
-        entry += (size_t)P[a];
+        entry += fft_table_len(P[a]);
     }
     size_t need_u = 0, need_w = 0;
     voxel_scratch(D, Pv, &need_u, &need_w);
@@ -1725,9 +1783,7 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
         return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_TENSOR applies to Ga plans only");
     if (!make_dims(d, N, nullptr, &D, scheme, tensor))
         return fail(nullptr, FFTGAL_EINVAL,
-                    scheme == kSchemeGani      ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
-                    : scheme == kSchemeReduced ? "d must be 2 or 3 and every N odd, >= 1 and 3,5,7-smooth"
-                                               : "d must be 2 or 3 and every N odd and >= 1");
+                    "d must be 2 or 3 and every N odd and >= 1");
     if (dev_workspace == nullptr || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))
         return fail(nullptr, FFTGAL_EINVAL, "workspace must be a 256-byte aligned device pointer");
     Layout Lo = make_layout(D, precision, !lean);
@@ -1893,9 +1949,8 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
     } else if (m->kind == FFTGAL_VOXELS) {
         long Ptot = 1;
         for (int a = 0; a < d; ++a) {
-            if (!is_smooth_odd(m->P[a]))
-                return fail(pl, FFTGAL_EINVAL, "voxel resolution P[%d] = %d is not an odd 3,5,7-smooth integer", a,
-                            m->P[a]);
+            if (m->P[a] < 1 || m->P[a] % 2 == 0 || m->P[a] > 100000)
+                return fail(pl, FFTGAL_EINVAL, "voxel resolution P[%d] = %d is not an odd integer", a, m->P[a]);
             Ptot *= m->P[a];
         }
         if (!m->image) return fail(pl, FFTGAL_EINVAL, "image is NULL");

@@ -16,11 +16,21 @@ constexpr int kMaxStages = 16;  // radix-3/5/7 stages per FFT length
 // Stage s has radix radix[s] and twiddles w(q, k) = exp(-2 pi i q k / (p r)),
 // q = 1..r-1, k = 0..p-1 (p = product of the earlier radices), stored at
 // twoff[s] + (q - 1) * p + k in the plan's twiddle tables.
+// A length n that is not 3,5,7-smooth is transformed by Bluestein's chirp
+// convolution: with c_m = exp(sg i pi m^2 / n), sum_j x_j exp(sg 2 pi i j k / n)
+// = c_k sum_j (x_j c_j) conj(c_{k-j}), a circular convolution of length L >= 2n - 1
+// (3,5,7-smooth) done with two transforms of length L; the stages then describe
+// L, and the tables hold the chirp exp(i pi m^2 / n) (m < n) at choff and
+// H = DFT_L^-(conj chirp, placed at m mod L for |m| < n) / L at hoff.
 struct FftDesc {
     int n;
     int nst;
     int radix[kMaxStages];
     int twoff[kMaxStages];
+    int L;      // transform buffer length in LDS: n, or the Bluestein length
+    int blue;   // 1: Bluestein transform of length n through length L
+    int choff;
+    int hoff;
 };
 
 // Grid sizes with compile-time specialised kernels, and their radix
@@ -152,6 +162,10 @@ struct RowArgs {
     // are unused
     int nfield;
     long gstride;
+    // ROW_GRAM, generic kernel: 1 packs two components of one row per complex
+    // transform (RP rows per work-group) instead of two rows of one component
+    // (RP row pairs), halving the transform buffers for long rows
+    int gpack;
     double E[3];      // load for ROW_RHS
     void *real_out;   // ROW_C2R output rows (length n)
     const void *real_in;  // ROW_R2C input rows (length n)

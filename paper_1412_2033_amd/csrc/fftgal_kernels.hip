@@ -293,10 +293,10 @@ __device__ __forceinline__ void stage(const Vt<T> *X, Vt<T> *Y, int n, int p, in
     }
 }
 
-// Full transform in LDS, ping-ponging between A and Bf; returns the buffer
-// holding the result.  Must be called by every thread of the work-group.
+// The stages of a transform of length f.L in LDS, ping-ponging between A and
+// Bf; returns the buffer holding the result.
 template <typename T, bool ROWL>
-__device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
+__device__ Vt<T> *fft_stages(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
     Vt<T> *X = A;
     Vt<T> *Y = Bf;
     int p = 1;
@@ -304,12 +304,12 @@ __device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const V
         const int r = f.radix[s];
         const Vt<T> *t = tw + f.twoff[s];
         switch (r) {
-            case 3: stage<T, 3, ROWL>(X, Y, f.n, p, nb, t, sg); break;
-            case 5: stage<T, 5, ROWL>(X, Y, f.n, p, nb, t, sg); break;
-            case 7: stage<T, 7, ROWL>(X, Y, f.n, p, nb, t, sg); break;
-            case 9: stage<T, 9, ROWL>(X, Y, f.n, p, nb, t, sg); break;
-            case 15: stage<T, 15, ROWL>(X, Y, f.n, p, nb, t, sg); break;
-            default: stage<T, 25, ROWL>(X, Y, f.n, p, nb, t, sg); break;
+            case 3: stage<T, 3, ROWL>(X, Y, f.L, p, nb, t, sg); break;
+            case 5: stage<T, 5, ROWL>(X, Y, f.L, p, nb, t, sg); break;
+            case 7: stage<T, 7, ROWL>(X, Y, f.L, p, nb, t, sg); break;
+            case 9: stage<T, 9, ROWL>(X, Y, f.L, p, nb, t, sg); break;
+            case 15: stage<T, 15, ROWL>(X, Y, f.L, p, nb, t, sg); break;
+            default: stage<T, 25, ROWL>(X, Y, f.L, p, nb, t, sg); break;
         }
         __syncthreads();
         Vt<T> *tmp = X;
@@ -318,6 +318,49 @@ __device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const V
         p *= r;
     }
     return X;
+}
+
+// Full transform of nb sequences of length f.n in LDS (positions 0 .. n - 1 of
+// buffers of f.L positions; ROWL: element (pos, b) at b L + pos, else
+// pos nb + b); returns the buffer holding the result.  Must be called by
+// every thread of the work-group.
+template <typename T, bool ROWL>
+__device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
+    if (!f.blue) return fft_stages<T, ROWL>(A, Bf, f, nb, tw, sg);
+    // Bluestein: u_j = x_j c_j zero-padded to L, H (.) DFT^- u, DFT^+, times c_k
+    const int n = f.n, L = f.L;
+    const Vt<T> *chirp = tw + f.choff;
+    const Vt<T> *H = tw + f.hoff;
+    auto at = [&](Vt<T> *buf, int pos, int b) -> Vt<T> & { return ROWL ? buf[b * L + pos] : buf[pos * nb + b]; };
+    auto chirp_of = [&](int m) {  // c_m for the sign sg
+        Vt<T> c = chirp[m];
+        c.y *= sg;
+        return c;
+    };
+    for (int idx = threadIdx.x; idx < L * nb; idx += blockDim.x) {
+        const int b = idx / L, pos = idx - b * L;
+        Vt<T> &v = at(A, pos, b);
+        v = pos < n ? cmul(v, chirp_of(pos)) : mk<T>(T(0), T(0));
+    }
+    __syncthreads();
+    Vt<T> *X = fft_stages<T, ROWL>(A, Bf, f, nb, tw, T(-1));
+    for (int idx = threadIdx.x; idx < L * nb; idx += blockDim.x) {
+        const int b = idx / L, k = idx - b * L;
+        // H for the sign sg: H_k (sg = +1) or conj(H_{-k}) (sg = -1)
+        Vt<T> h = H[sg > T(0) ? k : (k == 0 ? 0 : L - k)];
+        if (sg < T(0)) h.y = -h.y;
+        Vt<T> &v = at(X, k, b);
+        v = cmul(v, h);
+    }
+    __syncthreads();
+    Vt<T> *Y = fft_stages<T, ROWL>(X, X == A ? Bf : A, f, nb, tw, T(1));
+    for (int idx = threadIdx.x; idx < n * nb; idx += blockDim.x) {
+        const int b = idx / n, pos = idx - b * n;
+        Vt<T> &v = at(Y, pos, b);
+        v = cmul(v, chirp_of(pos));
+    }
+    __syncthreads();
+    return Y;
 }
 
 // Deterministic work-group sum (fixed shuffle tree, then waves in order);
@@ -432,8 +475,8 @@ __global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
     const int n = a.f.n;
     const int B = a.B;
     V *bufA = reinterpret_cast<V *>(smem_raw);
-    V *bufB = bufA + (size_t)n * B;
-    V *acc = bufB + (size_t)n * B;
+    V *bufB = bufA + (size_t)a.f.L * B;
+    V *acc = bufB + (size_t)a.f.L * B;
     const int b0 = blockIdx.x * B;
     const int o = blockIdx.y;
     const int nbw = min(B, a.nb - b0);
@@ -800,10 +843,11 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     if (a.status != nullptr && a.status->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     const int n = a.f.n;
+    const int ln = a.f.L;  // buffer length per transform (n unless Bluestein)
     const int RP = a.RP;
     const int nh = a.Nh_row;
     V *S = reinterpret_cast<V *>(smem_raw);
-    V *Z = S + (size_t)RP * n;  // Z[c] = Z + c * RP * n
+    V *Z = S + (size_t)RP * ln;  // Z[c] = Z + c * RP * ln
     const V *tw = reinterpret_cast<const V *>(a.tw);
     V *data = reinterpret_cast<V *>(a.data);
     const T *g = reinterpret_cast<const T *>(a.g);
@@ -814,20 +858,95 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     const int d = a.d;
     const int nzc = (a.mode == ROW_RHS || a.mode == ROW_R2C) ? (a.mode == ROW_RHS ? d : 1) : a.ncomp;
 
-    auto zbuf = [&](int c) { return Z + (size_t)c * RP * n; };
+    auto zbuf = [&](int c) { return Z + (size_t)c * RP * ln; };
     auto fft_into = [&](int c, T sg) {
         V *res = fft_lds<T, true>(zbuf(c), S, a.f, RP, tw, sg);
         if (res != zbuf(c)) {
-            for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) zbuf(c)[idx] = res[idx];
+            for (int idx = threadIdx.x; idx < RP * ln; idx += blockDim.x) zbuf(c)[idx] = res[idx];
             __syncthreads();
         }
     };
+
+    if (a.mode == ROW_GRAM && a.gpack) {
+        // (A_M (E_s + e_s), E_t + e_t) with components 2 c2 and 2 c2 + 1 of one
+        // row packed per transform (z = u_{2 c2} + i u_{2 c2 + 1}); row r0 + j
+        const int r0 = blockIdx.x * RP;
+        const int nvr = min(RP, a.nrows - r0);
+        const int npk = (a.ncomp + 1) / 2;
+        for (int c2 = 0; c2 < npk; ++c2) {
+            V *zc = zbuf(c2);
+            for (int idx = threadIdx.x; idx < RP * ln; idx += blockDim.x) zc[idx] = zero;
+            __syncthreads();
+            const bool two = 2 * c2 + 1 < a.ncomp;
+            for (int idx = threadIdx.x; idx < RP * nh; idx += blockDim.x) {
+                const int j = idx / nh;
+                const int kx = idx - j * nh;
+                if (j >= nvr) continue;
+                const long row = (long)(r0 + j) * nh + kx;
+                const V u1 = data[(long)(2 * c2) * a.cs + row];
+                const V u2 = two ? data[(long)(2 * c2 + 1) * a.cs + row] : zero;
+                if (kx == 0) {
+                    zc[j * ln] = mk<T>(u1.x, u2.x);
+                } else {
+                    zc[j * ln + kx] = mk<T>(u1.x - u2.y, u1.y + u2.x);
+                    zc[j * ln + n - kx] = mk<T>(u1.x + u2.y, u2.x - u1.y);
+                }
+            }
+            __syncthreads();
+            fft_into(c2, T(1));
+        }
+        T A0[9], D[9];
+        for (int i = 0; i < d * d; ++i) {
+            A0[i] = T(a.A0[i]);
+            D[i] = T(a.D[i]);
+        }
+        double gs[9];
+        for (int i = 0; i < 9; ++i) gs[i] = 0.0;
+        for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) {
+            const int j = idx / n;
+            const int x = idx - j * n;
+            if (j >= nvr) continue;
+            const long r = r0 + j;
+            T am[9];
+            if (a.nfield > 1) {
+                sym_load<T>(g, a.gstride, r * n + x, d, am);
+            } else {
+                const T gg = g[r * n + x];
+                for (int i = 0; i < d * d; ++i) am[i] = A0[i] + gg * D[i];
+            }
+            T f[3][3];
+            for (int s2 = 0; s2 < d; ++s2)
+                for (int b = 0; b < d; ++b) {
+                    const int c = s2 * d + b;
+                    const V zv = zbuf(c / 2)[j * ln + x];
+                    f[s2][b] = ((c & 1) ? zv.y : zv.x) + (s2 == b ? T(1) : T(0));
+                }
+            for (int t = 0; t < d; ++t) {
+                T af[3];
+                for (int al = 0; al < d; ++al) {
+                    T y = T(0);
+                    for (int b = 0; b < d; ++b) y += am[al * d + b] * f[t][b];
+                    af[al] = y;
+                }
+                for (int s2 = 0; s2 < d; ++s2) {
+                    T dot = T(0);
+                    for (int al = 0; al < d; ++al) dot += f[s2][al] * af[al];
+                    gs[s2 * d + t] += dot;
+                }
+            }
+        }
+        for (int i = 0; i < d * d; ++i) {
+            const double sum = block_sum(gs[i]);
+            if (threadIdx.x == 0) a.partial[(long)blockIdx.x * d * d + i] = sum;
+        }
+        return;
+    }
 
     // ---- spatial values ----
     if (a.mode == ROW_OPER || a.mode == ROW_GRAM || a.mode == ROW_C2R) {
         for (int c = 0; c < a.ncomp; ++c) {
             V *zc = zbuf(c);
-            for (int idx = threadIdx.x; idx < RP * n; idx += blockDim.x) zc[idx] = zero;
+            for (int idx = threadIdx.x; idx < RP * ln; idx += blockDim.x) zc[idx] = zero;
             __syncthreads();
             for (int idx = threadIdx.x; idx < RP * nh; idx += blockDim.x) {
                 const int j = idx / nh;
@@ -838,10 +957,10 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                 const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
                 const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
                 if (kx == 0) {
-                    zc[j * n] = mk<T>(u1.x, u2.x);
+                    zc[j * ln] = mk<T>(u1.x, u2.x);
                 } else {
-                    zc[j * n + kx] = mk<T>(u1.x - u2.y, u1.y + u2.x);
-                    zc[j * n + n - kx] = mk<T>(u1.x + u2.y, u2.x - u1.y);
+                    zc[j * ln + kx] = mk<T>(u1.x - u2.y, u1.y + u2.x);
+                    zc[j * ln + n - kx] = mk<T>(u1.x + u2.y, u2.x - u1.y);
                 }
             }
             __syncthreads();
@@ -860,7 +979,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                 v.x = map_voxel<T>(rin[(long)r1 * a.real_stride + x], a.imgmap, a.vmax);
                 v.y = (r2 < a.nrows) ? map_voxel<T>(rin[(long)r2 * a.real_stride + x], a.imgmap, a.vmax) : T(0);
             }
-            zc[idx] = v;
+            zc[j * ln + x] = v;
         }
         __syncthreads();
     }
@@ -899,7 +1018,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             T e1[3], e2[3];
             for (int b = 0; b < d; ++b) {
                 if (a.mode == ROW_OPER) {
-                    const V zv = zbuf(b)[idx];
+                    const V zv = zbuf(b)[j * ln + x];
                     e1[b] = zv.x;
                     e2[b] = zv.y;
                 } else {
@@ -913,7 +1032,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                     y1 += m1[al * d + b] * e1[b];
                     y2 += m2[al * d + b] * e2[b];
                 }
-                zbuf(al)[idx] = mk<T>(y1, y2);
+                zbuf(al)[j * ln + x] = mk<T>(y1, y2);
                 load += (double)y1 * y1 + (double)y2 * y2;
                 if (a.mode == ROW_RHS) work += ((double)y1 + (double)y2) * a.E[al];
             }
@@ -955,7 +1074,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                 T f[3][3];
                 for (int s = 0; s < d; ++s)
                     for (int b = 0; b < d; ++b) {
-                        const V zv = zbuf(s * d + b)[idx];
+                        const V zv = zbuf(s * d + b)[j * ln + x];
                         f[s][b] = (half ? zv.y : zv.x) + (s == b ? T(1) : T(0));
                     }
                 for (int t = 0; t < d; ++t) {
@@ -987,7 +1106,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             if (j >= nvp) continue;
             const int r1 = 2 * (pair0 + j);
             const int r2 = r1 + 1;
-            const V zv = zbuf(0)[idx];
+            const V zv = zbuf(0)[j * ln + x];
             rout[(long)r1 * a.real_stride + x] = zv.x * scale;
             if (r2 < a.nrows) rout[(long)r2 * a.real_stride + x] = zv.y * scale;
         }
@@ -1005,8 +1124,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             if (j >= nvp) continue;
             const int r1 = 2 * (pair0 + j);
             const int r2 = r1 + 1;
-            const V w = zc[j * n + posmod(kx, n)];
-            const V wm = zc[j * n + posmod(-kx, n)];
+            const V w = zc[j * ln + posmod(kx, n)];
+            const V wm = zc[j * ln + posmod(-kx, n)];
             data[(long)c * a.cs + (long)r1 * nh + kx] = mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half);
             if (r2 < a.nrows)
                 data[(long)c * a.cs + (long)r2 * nh + kx] = mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half);
@@ -3127,7 +3246,7 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
     int lacc = 0;
     if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
     if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
-    return es * ((size_t)2 * a.f.n * a.B + (size_t)lacc * a.B);
+    return es * ((size_t)2 * a.f.L * a.B + (size_t)lacc * a.B);
 }
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
@@ -3148,12 +3267,14 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     int nz = a.ncomp;
     if (a.mode == ROW_RHS) nz = a.d;
     if (a.mode == ROW_R2C || a.mode == ROW_C2R) nz = 1;
-    return es * (size_t)(nz + 1) * a.RP * a.f.n;
+    if (a.mode == ROW_GRAM && a.gpack) nz = (a.ncomp + 1) / 2;
+    return es * (size_t)(nz + 1) * a.RP * a.f.L;
 }
 
 int pencil_grid_x(const PencilArgs &a) { return a.B > 0 ? (a.nb + a.B - 1) / a.B : 0; }
 int row_grid(const RowArgs &a) {
     if (a.RP < 1) return 0;
+    if (a.mode == ROW_GRAM && a.gpack && !a.fast) return (a.nrows + a.RP - 1) / a.RP;
     const int pairs = (a.nrows + 1) / 2;
     if (a.fast == 3) return (pairs + a.RP / a.d - 1) / (a.RP / a.d);
     return a.fast == 2 ? (a.d * pairs + a.RP - 1) / a.RP : (pairs + a.RP - 1) / a.RP;
@@ -3162,7 +3283,7 @@ int row_grid(const RowArgs &a) {
 static_assert(kNumFast == 6, "launch_*_fast switch covers six sizes");
 
 void configure_pencil(PencilArgs &a, bool fp64) {
-    const int fi = fast_index(a.f.n);
+    const int fi = a.f.blue ? -1 : fast_index(a.f.n);
     bool ok = fi >= 0 && a.nsol == 1 && a.ncomp == a.d && a.epi != EPI_WINDOW && (a.d == 2 || a.d == 3) &&
               a.f.nst == kFastSched[fi].nst && a.L_in <= a.f.n && a.L_out <= a.f.n;
     for (int s = 0; ok && s < a.f.nst; ++s) ok = a.f.radix[s] == kFastSched[fi].r[s];
@@ -3177,12 +3298,12 @@ void configure_pencil(PencilArgs &a, bool fp64) {
     if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
     const size_t es = fp64 ? 16 : 8;
     int B = fp64 ? 8 : 16;
-    while (B > 1 && es * ((size_t)2 * a.f.n * B + (size_t)lacc * B) > 80 * 1024) B /= 2;
+    while (B > 1 && es * ((size_t)2 * a.f.L * B + (size_t)lacc * B) > 80 * 1024) B /= 2;
     a.B = B;
 }
 
 void configure_row(RowArgs &r, bool fp64) {
-    const int fi = fast_index(r.f.n);
+    const int fi = r.f.blue ? -1 : fast_index(r.f.n);
     bool ok = fi >= 0 && (r.mode == ROW_OPER || r.mode == ROW_RHS) && r.ncomp == r.d && (r.d == 2 || r.d == 3) &&
               r.f.nst == kFastSched[fi].nst && r.Nh_row <= (r.f.n + 1) / 2;
     for (int s = 0; ok && s < r.f.nst; ++s) ok = r.f.radix[s] == kFastSched[fi].r[s];
@@ -3218,8 +3339,14 @@ void configure_row(RowArgs &r, bool fp64) {
     if (r.mode == ROW_RHS) nz = r.d;
     if (r.mode == ROW_R2C || r.mode == ROW_C2R) nz = 1;
     const size_t es = fp64 ? 16 : 8;
+    r.gpack = 0;
+    if (r.mode == ROW_GRAM && es * (size_t)(nz + 1) * r.f.L > 80 * 1024) {
+        // long rows: two components of one row per transform
+        r.gpack = 1;
+        nz = (r.ncomp + 1) / 2;
+    }
     int RP = 8;
-    while (RP > 1 && es * (size_t)(nz + 1) * RP * r.f.n > 80 * 1024) RP /= 2;
+    while (RP > 1 && es * (size_t)(nz + 1) * RP * r.f.L > 80 * 1024) RP /= 2;
     r.RP = RP;
 }
 

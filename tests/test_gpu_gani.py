@@ -46,6 +46,11 @@ CASES = {
     "circle2d_N81": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0), (81, 81)),
     "circle2d_N225x125": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 30.0, center=(0.2, 0.1)), (225, 125)),
     "voxel3d_N25x15x9": (lambda: synth.grf_voxels(13, (25, 15, 9), d=3, corr_len=0.15), (25, 15, 9)),
+    # orders that are not 3,5,7-smooth (Bluestein transforms): the paper's
+    # order 99 = 9 * 11, and an image whose resolution is not smooth either
+    "circle2d_N99": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0), (99, 99)),
+    "voxel3d_P99x11x13_N99x11x13": (lambda: synth.grf_voxels(15, (99, 11, 13), d=3, corr_len=0.1,
+                                                              a_matrix=0.029, a_incl=0.49), (99, 11, 13)),
 }
 
 
@@ -92,6 +97,6 @@ def test_gani_fp32_iterations(fg):
     assert _rel(res["lower"], np.linalg.inv(ref["B_gani"])) <= 1e-6
 
 
-def test_gani_rejects_non_smooth_grid(fg):
+def test_gani_rejects_even_grid(fg):
     with pytest.raises(fg.FftgalError):
-        fg.Plan(2, (11, 11), "fp64", scheme="gani")
+        fg.Plan(2, (10, 11), "fp64", scheme="gani")

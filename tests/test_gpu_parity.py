@@ -68,6 +68,9 @@ CASES = {
     "voxel3d_N113x5x5": (lambda: synth.grf_voxels(14, (225, 9, 9), d=3, corr_len=0.1), (113, 5, 5)),
     "voxel2d_multi_N9": (lambda: {"d": 2, "kind": "voxels", "P": (15, 15),
                                   "image": 1.0 + np.arange(225).reshape(15, 15) % 7}, (9, 9)),
+    # voxel resolutions that are not 3,5,7-smooth (Bluestein transforms of the image)
+    "voxel2d_P11x13_N5x7": (lambda: synth.grf_voxels(16, (11, 13), d=2, corr_len=0.15), (5, 7)),
+    "voxel3d_P99x9x11_N41x5x5": (lambda: synth.grf_voxels(17, (99, 9, 11), d=3, corr_len=0.1), (41, 5, 5)),
 }
 
 

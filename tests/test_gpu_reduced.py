@@ -10,7 +10,11 @@
   on the device (3D, N = 81: specialised reduced kernels against the generic
   length-175 double grid); the lean layout (shifts in turn) and the default
   one (the shifts of a pass in one launch) agree;
-* unsupported uses raise: a non-smooth N, warm starts, batches.
+* orders that are not 3,5,7-smooth (the primes 41, 113, 1013 of the
+  benchmark configurations) run Bluestein transforms: parity with the oracle
+  (converged and after 10 steps, entry by entry), and at N = 113 on the 225^3
+  benchmark image equality with the double grid;
+* unsupported uses raise: an even N, warm starts, batches.
 """
 
 import numpy as np
@@ -49,6 +53,14 @@ CASES = {
     # specialised transform lengths
     "circle2d_N81": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0), (81, 81)),
     "circle2d_N225x125": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 30.0, center=(0.2, 0.1)), (225, 125)),
+    # orders that are not 3,5,7-smooth (Bluestein transforms): the benchmark
+    # orders 41 and 113 and 1013 (on the row axis, where the energy Gram pass
+    # packs two components per transform), and short non-smooth lengths
+    "circle2d_N41": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0), (41, 41)),
+    "voxel3d_P225_N113x5x5": (lambda: synth.grf_voxels(14, (225, 9, 9), d=3, corr_len=0.1), (113, 5, 5)),
+    "circle2d_N5x1013": (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0, center=(0.1, 0.05)), (5, 1013)),
+    "square2d_N11x13": (lambda: synth.square_inclusion(2, 0.6, 1.0, 10.0, center=(0.1, 0.2)), (11, 13)),
+    "aniso3d_N7x11x13": (lambda: synth.cube_inclusion_aniso(0.45, 4), (7, 11, 13)),
 }
 
 
@@ -172,9 +184,50 @@ def test_reduced_homogeneous_and_history(fg):
         assert abs(h0[a] - voigt[a, a]) <= 1e-12 * voigt[a, a]
 
 
+@pytest.mark.parametrize("name", ["circle2d_N41", "voxel3d_P225_N113x5x5", "circle2d_N5x1013"])
+def test_reduced_truncated_entries_match_oracle(fg, name):
+    # first order in the operator (10 CG steps, rtol 0): each bound entry
+    # against the oracle's reduced Ga of the same iterates (Bluestein lengths)
+    make, N = CASES[name]
+    micro = make()
+    print("reduced truncated %s N=%s" % (name, N), flush=True)
+    plan = fg.Plan(len(N), N, "fp64", P=micro.get("P"), scheme="reduced")
+    try:
+        res = plan.run(micro, rtol=0.0, maxit=10)
+    finally:
+        plan.close()
+    ref = reduced.reduced_bounds(material.make_material(micro), N, tol=0.0, maxit=10)
+    for key in ("upper", "lower"):
+        b = np.asarray(ref[key])
+        assert np.max(np.abs(np.asarray(res[key]) - b)) / np.linalg.norm(b) < 1e-11, key
+
+
+def test_reduced_equals_double_grid_benchmark_order(fg):
+    # the benchmark workload's order N = 113 (a prime: transforms of length 113
+    # by Bluestein's convolution of length 225) on its 225^3 random-field
+    # image: the reduced plan gives the double-grid plan's bounds
+    import torch
+    N = (113, 113, 113)
+    micro = synth.grf_voxels(5, (225, 225, 225), d=3, corr_len=0.05, vf=0.4, a_matrix=1.0, a_incl=100.0)
+    micro["image"] = torch.from_numpy(np.ascontiguousarray(micro["image"])).to("cuda:0")
+    print("reduced vs double grid 3D N=113", flush=True)
+    red = fg.Plan(3, N, "fp64", P=micro["P"], scheme="reduced")
+    try:
+        r = red.run(micro, rtol=1e-11)
+    finally:
+        red.close()
+    ga = fg.Plan(3, N, "fp64", P=micro["P"])
+    try:
+        g = ga.run(micro, rtol=1e-11)
+    finally:
+        ga.close()
+    assert _rel(r["upper"], g["upper"]) <= 1e-10
+    assert _rel(r["lower"], g["lower"]) <= 1e-10
+
+
 def test_reduced_errors(fg):
     with pytest.raises(fg.FftgalError):
-        fg.Plan(2, (11, 11), "fp64", scheme="reduced")  # 11 is not 3,5,7-smooth
+        fg.Plan(2, (10, 11), "fp64", scheme="reduced")  # N must be odd
     micro = synth.square_inclusion(2, 0.6, 1.0, 10.0)
     a = fg.Plan(2, (5, 5), "fp64")
     b = fg.Plan(2, (9, 9), "fp64", scheme="reduced")
