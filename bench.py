@@ -193,13 +193,16 @@ def main():
                     help="coarse N of the warm-start / bound-monitoring section (0: skip)")
     ap.add_argument("--reduced", type=int, default=81,
                     help="N of the reduced-Ga section (3D, on the benchmark image; 0: skip)")
+    ap.add_argument("--reduced-prime", type=int, default=113,
+                    help="N of the reduced-Ga section at an order that is not 3,5,7-smooth (Bluestein "
+                         "transforms; default the benchmark order 113; 0: skip)")
     ap.add_argument("--envelope", type=int, default=1,
                     help="upper-upper / lower-lower bounds section on an anisotropic cube inclusion (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (profiler counter scale)")
     args = ap.parse_args()
     if args.main_only:
-        args.serve = args.serve3d = args.gani = args.warm_coarse = args.reduced = 0
+        args.serve = args.serve3d = args.gani = args.warm_coarse = args.reduced = args.reduced_prime = 0
         args.envelope = args.aniso = args.sweep2d = 0
     if args.gpus != 1:
         print("bench.py: the benchmark runs on one GPU (independent solves and requests shard across GPUs "
@@ -348,6 +351,9 @@ def main():
         out["gani"] = gani_bench(fftgal, micro_dev, d, M, args.gani, rtol64, last, dev)
     if args.reduced > 0:
         out["reduced"] = reduced_bench(fftgal, micro_dev, d, M, args.reduced, rtol64, dev)
+    if args.reduced_prime > 0:
+        out["reduced_bluestein"] = reduced_bench(fftgal, micro_dev, d, M, args.reduced_prime, rtol64, dev,
+                                                 variants=("reduced",))
     if args.envelope:
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.aniso:
@@ -492,7 +498,7 @@ def gani_bench(fftgal, micro_dev, d, P, Ng, rtol, ga_last, dev):
             "ga_N113_gap": round(float(ga_last["gap"]), 6)}
 
 
-def reduced_bench(fftgal, micro_dev, d, P, Nr, rtol, dev):
+def reduced_bench(fftgal, micro_dev, d, P, Nr, rtol, dev, variants=("reduced", "reduced_lean")):
     """Reduced Ga (Lemma reduce_grid, Algorithm 3) against the double-grid Ga
     of the same order Nr on the benchmark image: time to bounds, CG
     iterations, workspace bytes and the difference of the bounds (FP64)."""
@@ -504,7 +510,7 @@ def reduced_bench(fftgal, micro_dev, d, P, Nr, rtol, dev):
     res = {}
     # "reduced": the shifts of each pass in one launch; "reduced_lean": one set
     # of intermediates, shifts in turn (smallest workspace); "ga": double grid
-    for name in ("reduced", "reduced_lean", "ga"):
+    for name in tuple(variants) + ("ga",):
         scheme = "ga" if name == "ga" else "reduced"
         plan = fftgal.Plan(d, Nt, "fp64", device=dev, P=P, scheme=scheme, lean=name == "reduced_lean")
         try:
@@ -524,7 +530,7 @@ def reduced_bench(fftgal, micro_dev, d, P, Nr, rtol, dev):
                        "upper_diag": [round(float(v), 8) for v in np.diag(r["upper"])]}
     out["bound_rel_diff"] = max(
         float(np.linalg.norm(res[v][k] - res["ga"][k]) / np.linalg.norm(res["ga"][k]))
-        for v in ("reduced", "reduced_lean") for k in ("upper", "lower"))
+        for v in variants for k in ("upper", "lower"))
     return out
 
 

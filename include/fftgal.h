@@ -84,6 +84,15 @@ enum fftgal_precision {
  * workspace grows by (d (d + 1) / 2 - 1) material fields per side. */
 #define FFTGAL_TENSOR 0x200
 
+/* Flag or-ed into `precision` of fftgal_workspace_bytes* and fftgal_plan /
+ * fftgal_plan_gani: the plan keeps 2d copies of the per-solve buffers (transform
+ * intermediates, CG vectors, partial sums), so that all its d primal and d dual
+ * solves can run at once -- as members of a batch, or through
+ * fftgal_solve_all.  Without it a plan runs one solve at a time.  The
+ * workspace grows by 2d - 1 copies of that region plus the internal batch of
+ * fftgal_solve_all.  EINVAL with reduced plans. */
+#define FFTGAL_CONCURRENT 0x400
+
 enum fftgal_material_kind {
     FFTGAL_INCLUSIONS = 0, /* eq. inclcomp: matrix phase plus inclusions          */
     FFTGAL_VOXELS = 1      /* eq. gridcomp: piecewise-constant voxel image        */
@@ -229,6 +238,19 @@ int fftgal_solve_primal(struct fftgal_plan *plan, int alpha, double rtol, int ma
 /* The dual problem G^J B_M j = -G^J B_M J with J = e_alpha, as above. */
 int fftgal_solve_dual(struct fftgal_plan *plan, int alpha, double rtol, int maxit,
                       fftgal_info *info);
+
+/*
+ * All d primal and all d dual solves (Cor. Ga_linsys, Remark CG; the solves
+ * are independent), with the arguments and stopping tests of
+ * fftgal_solve_primal; `info` (may be NULL) receives 2d entries, primal
+ * alpha = 0..d-1 then dual.  A plan made with FFTGAL_CONCURRENT runs the 2d
+ * solves at once: every launch of an iteration covers all unfinished ones (a
+ * small grid fills the GPU that one solve leaves idle), each with its own
+ * reductions, so every result equals bitwise that of its solve alone.  Other
+ * plans run them one after another.  Returns the first non-OK outcome
+ * (ENOTCONV, EBREAKDOWN) after all solves ran, or ESTATE / EINVAL / EDEVICE.
+ */
+int fftgal_solve_all(struct fftgal_plan *plan, double rtol, int maxit, fftgal_info *info);
 
 /*
  * Guaranteed bounds from the d primal and d dual fields (Prop. struct_bounds):
@@ -409,8 +431,9 @@ int fftgal_read_timing(struct fftgal_plan *plan, double *ms, int32_t *count);
  * result is bitwise identical whether it runs alone, through
  * fftgal_solve_primal/dual, or in any mix.
  *
- * Every plan added must use the batch's stream, and a plan can have one solve
- * in a batch at a time (its CG vectors and transform buffers are per plan).
+ * Every plan added must use the batch's stream.  A plan can have one solve in
+ * batches at a time, or 2d (each of its solves once) when made with
+ * FFTGAL_CONCURRENT (its CG vectors and transform buffers are per solve slot).
  * The workspace is caller-owned device memory of
  * fftgal_batch_workspace_bytes(capacity) bytes.
  */
@@ -418,8 +441,9 @@ size_t fftgal_batch_workspace_bytes(int capacity);
 int fftgal_batch_create(struct fftgal_batch **out, int capacity, void *dev_workspace, size_t bytes,
                         void *hip_stream);
 /* Start solve (kind 0 = primal, 1 = dual; alpha in 0..d-1) of `plan`; writes
- * an identifier to *solve_id.  ESTATE if the plan has no material or already
- * has a solve in the batch; ENOMEM if the batch is full. */
+ * an identifier to *solve_id.  ESTATE if the plan has no material, if this
+ * solve of the plan is already in a batch or if all its solve slots are in
+ * use; ENOMEM if the batch is full. */
 int fftgal_batch_add(struct fftgal_batch *b, struct fftgal_plan *plan, int kind, int alpha, double rtol,
                      int maxit, int *solve_id);
 /* Enqueue `iterations` batched CG iterations, wait, and retire finished

@@ -143,13 +143,18 @@ struct Layout {
     // entries) in T1 / T2, so that the 2^d shifts of an operator pass can run
     // in one launch, each on its own slot
     size_t t1_slot, t2_slot;
+    // solve slots: the per-solve region [T1 .. part_c] repeated nslots times
+    int nslots;
+    size_t slot_bytes;
 };
 
 constexpr size_t kMultiArgsBytes = 64 * 1024;  // argument tables of multi-shift passes
 
 // grouped: reduced Ga with one intermediate slot and one projected vector per
 // shift (the shifts of a pass share a launch); otherwise one of each.
-Layout make_layout(const Dims &D, int precision, bool grouped = true) {
+// nsl: solve slots -- copies of the per-solve region (transform intermediates,
+// CG vectors, partial sums), so that nsl solves of the plan can run at once.
+Layout make_layout(const Dims &D, int precision, bool grouped = true, int nsl = 1) {
     const bool slots = grouped && D.nshift > 1;
     Layout L{};
     const int d = D.d;
@@ -199,33 +204,37 @@ Layout make_layout(const Dims &D, int precision, bool grouped = true) {
         t1 = std::max(t1, (size_t)D.nshift * L.t1_slot);
         t2 = std::max(t2, (size_t)D.nshift * L.t2_slot);
     }
+    // per-solve region (one copy per solve slot)
+    const size_t vec = (size_t)D.nc_max * D.Ns * c16;
     L.T1 = take(t1 * c16);
     L.T2 = take(t2 * c16);
-    const size_t vec = (size_t)D.nc_max * D.Ns * c16;
     L.r = take(vec);
     L.p = take(vec);
     L.q = take(vec * (slots ? D.nshift : 1));  // grouped reduced Ga: one projected vector per shift
-    L.xsol = take((size_t)2 * d * vec);  // [kind][alpha][nc][Ns]
-    L.xsol64 = take(precision == FFTGAL_FP32_ITER ? (size_t)d * vec : 0);
     // FP32 iterations: the right-hand side and the best iterate so far
     L.bvec = take(precision == FFTGAL_FP32_ITER ? vec : 0);
     L.xbest = take(precision == FFTGAL_FP32_ITER ? vec : 0);
+    // partial sums: the largest work-group count of any reducing launch
+    // (worst case: one pencil / one row per work-group)
+    long nwg = update_blocks(2L * D.Ns);  // CG update of at most two coefficient components
+    const long nbz = (d == 3) ? (long)D.N[1] * D.Nh : D.Nh;
+    const long nrows = (d == 3) ? (long)D.M[0] * D.M[1] : D.M[0];
+    nwg = std::max<long>(nwg, nbz);
+    nwg = std::max<long>(nwg, (nrows + 1) * d2);
+    L.part_len = (size_t)nwg + 64;
+    L.part_a = take(L.part_len * 8);
+    L.part_b = take(L.part_len * 8);
+    L.part_c = take(L.part_len * 8);
+    L.nslots = std::max(1, nsl);
+    L.slot_bytes = off - L.T1;
+    off += (size_t)(L.nslots - 1) * L.slot_bytes;
+    L.xsol = take((size_t)2 * d * vec);  // [kind][alpha][nc][Ns]
+    L.xsol64 = take(precision == FFTGAL_FP32_ITER ? (size_t)d * vec : 0);
     const size_t nfld = (size_t)D.nshift * D.nfield * D.Mtot;
     L.gA64 = take(nfld * 8);
     L.gB64 = take(nfld * 8);
     L.gA32 = take(precision == FFTGAL_FP32_ITER ? nfld * 4 : 0);
     L.gB32 = take(precision == FFTGAL_FP32_ITER ? nfld * 4 : 0);
-    // partial sums: the largest work-group count of any reducing launch
-    // (worst case: one pencil / one row pair per work-group)
-    long nwg = update_blocks(2L * D.Ns);  // CG update of at most two coefficient components
-    const long nbz = (d == 3) ? (long)D.N[1] * D.Nh : D.Nh;
-    const long nrows = (d == 3) ? (long)D.M[0] * D.M[1] : D.M[0];
-    nwg = std::max<long>(nwg, nbz);
-    nwg = std::max<long>(nwg, ((nrows + 1) / 2 + 1) * d2);
-    L.part_len = (size_t)nwg + 64;
-    L.part_a = take(L.part_len * 8);
-    L.part_b = take(L.part_len * 8);
-    L.part_c = take(L.part_len * 8);
     L.gram = take(64 * 8);
     L.args = take(kArgsBytes);
     L.margs = take(slots ? kMultiArgsBytes : 0);
@@ -351,7 +360,10 @@ struct fftgal_plan {
     // the layout when the image resolution exceeds what the layout provisions
     size_t vox_tw64 = 0, vox_tw32 = 0, vox_u = 0, vox_w = 0;
     fftgal_info last_info[2][3];
-    bool busy = false;     // a solve of this plan is a member of a batch
+    int busy = 0;          // solves of this plan that are members of a batch
+    size_t bws_off = 0, bws_len = 0;  // workspace of the internal batch (FFTGAL_CONCURRENT)
+    std::vector<char> slot_used;                               // solve slots held by batch members
+    bool in_batch[2][3] = {{false, false, false}, {false, false, false}};  // (kind, alpha) in a batch
     bool hist_on = false;  // per-iteration (rr, alpha) history; only when maxit <= kMaxHist
     int cur_alpha = 0;
     double btol = 0.0;  // bound tolerance of the stopping test (fftgal_set_bound_tol)
@@ -373,8 +385,11 @@ struct fftgal_plan {
     // per shift, so that the shifts of a pass can share a launch)
     int islot = 0;
     bool grouped = false;  // reduced Ga laid out with one slot per shift
-    char *T1s() { return ws + Lo.T1 + (size_t)islot * Lo.t1_slot * 16; }
-    char *T2s() { return ws + Lo.T2 + (size_t)islot * Lo.t2_slot * 16; }
+    char *T1s() { return ws + so(Lo.T1) + (size_t)islot * Lo.t1_slot * 16; }
+    char *T2s() { return ws + so(Lo.T2) + (size_t)islot * Lo.t2_slot * 16; }
+    // solve slot whose per-solve region the passes being built use
+    int slot = 0;
+    size_t so(size_t off) const { return off + (size_t)slot * Lo.slot_bytes; }
     std::vector<unsigned char> margs_host;  // staging of the multi-shift argument tables
     int ring = 0;
     unsigned char ring_host[kRingSlots][kArgSlot];
@@ -605,8 +620,8 @@ int inverse_passes(Plan *pl, bool fp64, int kind, const void *state, long st_ss,
         a.update_p = update_p ? 1 : 0;
         a.status = st;
         if (update_p) {
-            a.st_r = pl->ws + pl->Lo.r;
-            a.st_p = pl->ws + pl->Lo.p;
+            a.st_r = pl->ws + pl->so(pl->Lo.r);
+            a.st_p = pl->ws + pl->so(pl->Lo.p);
         } else {
             a.st_x = state == nullptr ? nullptr : static_cast<const char *>(state) + (size_t)s * st_ss * es;
         }
@@ -770,8 +785,8 @@ int series_to_field(Plan *pl, void *coef, double *field, const int *Li = nullptr
     const Dims &D = pl->D;
     const int d = D.d;
     const int L0 = Li ? Li[0] : D.L[0], L1 = Li ? Li[1] : D.L[1], Lh = Li ? Lhi : D.Lh;
-    void *U = pl->ws + pl->Lo.T2;
-    void *W = pl->ws + pl->Lo.T1;
+    void *U = pl->ws + pl->so(pl->Lo.T2);
+    void *W = pl->ws + pl->so(pl->Lo.T1);
     void *cur = coef;
     PencilArgs a = base_pencil(pl, pl->fM[0], true);
     a.pro = PRO_PLAIN;
@@ -840,7 +855,7 @@ int series_to_shifted_fields(Plan *pl, void *coef, double *field) {
     const size_t nser = (size_t)(d == 3 ? (long)D.L[0] * D.L[1] : (long)D.L[0]) * D.Lh * 16;
     if (nser > (size_t)2 * d * pl->vec_bytes()) return fail(pl, FFTGAL_EINVAL, "series scratch too small");
     void *ser = pl->ws + pl->Lo.xsol;
-    void *W = pl->ws + pl->Lo.T1;
+    void *W = pl->ws + pl->so(pl->Lo.T1);
     HIPCHECK(pl, hipMemcpyAsync(ser, coef, nser, hipMemcpyDeviceToDevice, pl->stream));
     const int Ni[2] = {D.N[0], D.N[1]};
     for (int s = 0; s < D.nshift; ++s) {
@@ -1085,7 +1100,7 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
         int rc = FFTGAL_OK;
         for (int s = 0; s < D.nshift && !rc; ++s) {
             pl->islot = grouped ? s : 0;
-            rc = inverse_passes(pl, fp64, kind, s == 0 ? nullptr : pl->ws + pl->Lo.p, 0, 1, s == 0, st, &rows,
+            rc = inverse_passes(pl, fp64, kind, s == 0 ? nullptr : pl->ws + pl->so(pl->Lo.p), 0, 1, s == 0, st, &rows,
                                 FFTGAL_K_EXPAND, FFTGAL_K_PENCIL_INV, s);
             if (!rc) {
                 RowArgs r = base_row(pl, fp64, ROW_OPER, rows, kind, s);
@@ -1093,9 +1108,9 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
                 rc = run_row(pl, r, fp64, FFTGAL_K_ROW);
             }
             if (!rc) {
-                char *q = pl->ws + pl->Lo.q + (grouped ? (size_t)s * pl->vec_bytes() : 0);
-                double *part = pl->at<double>(pl->Lo.part_a) + (grouped ? (size_t)s * npq_shift : 0);
-                rc = forward_passes(pl, fp64, kind, rows, q, pl->ws + pl->Lo.p, 1.0 / ((double)D.nshift * D.Mtot),
+                char *q = pl->ws + pl->so(pl->Lo.q) + (grouped ? (size_t)s * pl->vec_bytes() : 0);
+                double *part = pl->at<double>(pl->so(pl->Lo.part_a)) + (grouped ? (size_t)s * npq_shift : 0);
+                rc = forward_passes(pl, fp64, kind, rows, q, pl->ws + pl->so(pl->Lo.p), 1.0 / ((double)D.nshift * D.Mtot),
                                     st, part, &npq, FFTGAL_K_PENCIL_FWD, FFTGAL_K_PROJECT, s, !grouped && s > 0);
                 if (s == 0) npq_shift = npq;
             }
@@ -1116,24 +1131,24 @@ int capture_iteration(Plan *pl, int kind, int alpha, bool fp64, IterCfg *cfg) {
     const int nc = pl->nc(kind);
     UpdArgs u{};
     u.x = x;
-    u.r = pl->ws + pl->Lo.r;
-    u.p = pl->ws + pl->Lo.p;
-    u.q = pl->ws + pl->Lo.q;
+    u.r = pl->ws + pl->so(pl->Lo.r);
+    u.p = pl->ws + pl->so(pl->Lo.p);
+    u.q = pl->ws + pl->so(pl->Lo.q);
     u.n_per_comp = D.Ns;
     u.cs = D.Ns;
     u.nc = nc;
     u.Nh = D.Nh;
     u.nblocks = update_blocks((long)nc * D.Ns);
     u.st = st;
-    u.partial = pl->at<double>(pl->Lo.part_c);
-    u.pq_part = pl->at<double>(pl->Lo.part_a);
+    u.partial = pl->at<double>(pl->so(pl->Lo.part_c));
+    u.pq_part = pl->at<double>(pl->so(pl->Lo.part_a));
     u.npq = grouped ? D.nshift * npq_shift : npq;
     u.nq = grouped ? D.nshift : 1;
     u.q_ss = (long)(pl->vec_bytes() / (fp64 ? 16 : 8));
     cfg->upd = u;
     CgItem it{};
     it.st = st;
-    it.rr_part = pl->at<double>(pl->Lo.part_c);
+    it.rr_part = pl->at<double>(pl->so(pl->Lo.part_c));
     it.nrr = u.nblocks;
     it.hist = pl->hist_on ? pl->hist(kind, alpha) : nullptr;
     it.hist_cap = kMaxHist + 1;
@@ -1234,9 +1249,9 @@ int enqueue_iteration(Plan *pl, const IterCfg &cfg) {
 UpdArgs solve_vectors(Plan *pl, int kind, int alpha) {
     UpdArgs u{};
     u.x = pl->xsol(kind, alpha);
-    u.r = pl->ws + pl->Lo.r;
-    u.p = pl->ws + pl->Lo.p;
-    u.q = pl->ws + pl->Lo.q;
+    u.r = pl->ws + pl->so(pl->Lo.r);
+    u.p = pl->ws + pl->so(pl->Lo.p);
+    u.q = pl->ws + pl->so(pl->Lo.q);
     u.n_per_comp = pl->D.Ns;
     u.cs = pl->D.Ns;
     u.nc = pl->nc(kind);
@@ -1266,14 +1281,14 @@ int checkpoint(Plan *pl, int kind, int alpha, bool final) {
         r.status = gate;
         rc = run_row(pl, r, false, cls);
         if (rc) return rc;
-        rc = forward_passes(pl, false, kind, rows, pl->ws + pl->Lo.q, x, 1.0 / ((double)D.nshift * D.Mtot), gate,
-                            pl->at<double>(pl->Lo.part_a), &nq, cls, cls, s, s > 0);
+        rc = forward_passes(pl, false, kind, rows, pl->ws + pl->so(pl->Lo.q), x, 1.0 / ((double)D.nshift * D.Mtot), gate,
+                            pl->at<double>(pl->so(pl->Lo.part_a)), &nq, cls, cls, s, s > 0);
         if (rc) return rc;
     }
     const UpdArgs u = solve_vectors(pl, kind, alpha);
     Timed t(pl, cls);
-    HIPCHECK(pl, launch_cg_checkpoint(u, pl->ws + pl->Lo.bvec, pl->ws + pl->Lo.xbest, pl->at<double>(pl->Lo.part_a),
-                                      nq, pl->at<double>(pl->Lo.part_b), kCkptEvery, final ? 1 : 0, false,
+    HIPCHECK(pl, launch_cg_checkpoint(u, pl->ws + pl->so(pl->Lo.bvec), pl->ws + pl->so(pl->Lo.xbest), pl->at<double>(pl->so(pl->Lo.part_a)),
+                                      nq, pl->at<double>(pl->so(pl->Lo.part_b)), kCkptEvery, final ? 1 : 0, false,
                                       pl->stream));
     return FFTGAL_OK;
 }
@@ -1290,7 +1305,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     pl->cur_alpha = alpha;
     const size_t es = fp64 ? 16 : 8;
     const size_t vbytes = (size_t)pl->nc(kind) * D.Ns * es;
-    void *rows = pl->ws + (D.d == 3 ? pl->Lo.T2 : pl->Lo.T1);
+    void *rows = pl->ws + (D.d == 3 ? pl->so(pl->Lo.T2) : pl->so(pl->Lo.T1));
     // one pass per shifted grid (reduced Ga; one grid otherwise), the load
     // partials of shift s at offset s * nload, the projected loads summed in r
     const double npts = (double)D.nshift * D.Mtot;
@@ -1301,27 +1316,27 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
         configure_row(r, fp64);  // the work-group count fixes the partial offsets
         nload = row_grid(r);
         if ((size_t)D.nshift * nload > pl->Lo.part_len) return fail(pl, FFTGAL_EINVAL, "partial buffers too small");
-        r.partial = pl->at<double>(pl->Lo.part_b) + (size_t)s * nload;
-        r.partial2 = pl->at<double>(pl->Lo.part_c) + (size_t)s * nload;
+        r.partial = pl->at<double>(pl->so(pl->Lo.part_b)) + (size_t)s * nload;
+        r.partial2 = pl->at<double>(pl->so(pl->Lo.part_c)) + (size_t)s * nload;
         rc = run_row(pl, r, fp64, FFTGAL_K_RHS);
         if (rc) return rc;
-        rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->Lo.r, nullptr, -1.0 / npts, nullptr,
-                            pl->at<double>(pl->Lo.part_a), &nrr, FFTGAL_K_RHS, FFTGAL_K_RHS, s, s > 0);
+        rc = forward_passes(pl, fp64, kind, rows, pl->ws + pl->so(pl->Lo.r), nullptr, -1.0 / npts, nullptr,
+                            pl->at<double>(pl->so(pl->Lo.part_a)), &nrr, FFTGAL_K_RHS, FFTGAL_K_RHS, s, s > 0);
         if (rc) return rc;
     }
     nload *= D.nshift;
     // FP32 iterations keep b for the exact energies of the checkpoints
-    if (!fp64) HIPCHECK(pl, launch_copy_vec(pl->ws + pl->Lo.bvec, pl->ws + pl->Lo.r, vbytes, pl->stream));
+    if (!fp64) HIPCHECK(pl, launch_copy_vec(pl->ws + pl->so(pl->Lo.bvec), pl->ws + pl->so(pl->Lo.r), vbytes, pl->stream));
     // The load sums |A_M E|^2 over grid points; (., .)_{R^{d x M}} divides by |M|.
     const double floor_rel = (fp64 ? kFloor64 : kFloor32) / std::sqrt(npts);
     if (!pl->warm[kind][alpha]) {
         Timed t(pl, FFTGAL_K_CG_SCALAR);
-        HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->Lo.part_a), nrr, pl->at<double>(pl->Lo.part_b), nload,
-                                    pl->at<double>(pl->Lo.part_c), 1.0 / npts, rtol, floor_rel, maxit, pl->btol,
+        HIPCHECK(pl, launch_cg_init(st, pl->at<double>(pl->so(pl->Lo.part_a)), nrr, pl->at<double>(pl->so(pl->Lo.part_b)), nload,
+                                    pl->at<double>(pl->so(pl->Lo.part_c)), 1.0 / npts, rtol, floor_rel, maxit, pl->btol,
                                     pl->hist(kind, alpha), pl->stream));
         HIPCHECK(pl, launch_fill_zero(x, vbytes, pl->stream));
-        HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
-        if (!fp64) HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.xbest, vbytes, pl->stream));
+        HIPCHECK(pl, launch_fill_zero(pl->ws + pl->so(pl->Lo.p), vbytes, pl->stream));
+        if (!fp64) HIPCHECK(pl, launch_fill_zero(pl->ws + pl->so(pl->Lo.xbest), vbytes, pl->stream));
         return FFTGAL_OK;
     }
     // Warm start from the iterate x0 already in x: keep (b, b), |A_M E|^2 and
@@ -1331,9 +1346,9 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     double *scal = pl->at<double>(pl->Lo.gram) + 32;
     {
         Timed t(pl, FFTGAL_K_CG_SCALAR);
-        HIPCHECK(pl, launch_sum_partials(scal, pl->at<double>(pl->Lo.part_a), nrr, 1, pl->stream));
-        HIPCHECK(pl, launch_sum_partials(scal + 1, pl->at<double>(pl->Lo.part_b), nload, 1, pl->stream));
-        HIPCHECK(pl, launch_sum_partials(scal + 2, pl->at<double>(pl->Lo.part_c), nload, 1, pl->stream));
+        HIPCHECK(pl, launch_sum_partials(scal, pl->at<double>(pl->so(pl->Lo.part_a)), nrr, 1, pl->stream));
+        HIPCHECK(pl, launch_sum_partials(scal + 1, pl->at<double>(pl->so(pl->Lo.part_b)), nload, 1, pl->stream));
+        HIPCHECK(pl, launch_sum_partials(scal + 2, pl->at<double>(pl->so(pl->Lo.part_c)), nload, 1, pl->stream));
     }
     void *rows0 = nullptr;
     rc = inverse_passes(pl, fp64, kind, x, 0, 1, false, nullptr, &rows0, FFTGAL_K_RHS, FFTGAL_K_RHS);
@@ -1342,27 +1357,27 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     rc = run_row(pl, ro, fp64, FFTGAL_K_RHS);
     if (rc) return rc;
     int nq = 0;
-    rc = forward_passes(pl, fp64, kind, rows0, pl->ws + pl->Lo.q, nullptr, 1.0 / (double)D.Mtot, nullptr,
-                        pl->at<double>(pl->Lo.part_a), &nq, FFTGAL_K_RHS, FFTGAL_K_RHS);
+    rc = forward_passes(pl, fp64, kind, rows0, pl->ws + pl->so(pl->Lo.q), nullptr, 1.0 / (double)D.Mtot, nullptr,
+                        pl->at<double>(pl->so(pl->Lo.part_a)), &nq, FFTGAL_K_RHS, FFTGAL_K_RHS);
     if (rc) return rc;
     UpdArgs u{};
     u.x = x;
-    u.r = pl->ws + pl->Lo.r;
+    u.r = pl->ws + pl->so(pl->Lo.r);
     u.p = nullptr;
-    u.q = pl->ws + pl->Lo.q;
+    u.q = pl->ws + pl->so(pl->Lo.q);
     u.n_per_comp = D.Ns;
     u.cs = D.Ns;
     u.nc = pl->nc(kind);
     u.Nh = D.Nh;
     u.nblocks = update_blocks((long)u.nc * D.Ns);
     Timed t(pl, FFTGAL_K_CG_SCALAR);
-    HIPCHECK(pl, launch_warm_residual(u, pl->at<double>(pl->Lo.part_a), pl->at<double>(pl->Lo.part_b),
-                                      pl->at<double>(pl->Lo.part_c), fp64, pl->stream));
-    HIPCHECK(pl, launch_cg_init_warm(st, pl->at<double>(pl->Lo.part_a), pl->at<double>(pl->Lo.part_b),
-                                     pl->at<double>(pl->Lo.part_c), u.nblocks, scal, (double)D.Mtot, rtol, floor_rel,
+    HIPCHECK(pl, launch_warm_residual(u, pl->at<double>(pl->so(pl->Lo.part_a)), pl->at<double>(pl->so(pl->Lo.part_b)),
+                                      pl->at<double>(pl->so(pl->Lo.part_c)), fp64, pl->stream));
+    HIPCHECK(pl, launch_cg_init_warm(st, pl->at<double>(pl->so(pl->Lo.part_a)), pl->at<double>(pl->so(pl->Lo.part_b)),
+                                     pl->at<double>(pl->so(pl->Lo.part_c)), u.nblocks, scal, (double)D.Mtot, rtol, floor_rel,
                                      maxit, pl->btol, pl->hist(kind, alpha), pl->stream));
-    HIPCHECK(pl, launch_fill_zero(pl->ws + pl->Lo.p, vbytes, pl->stream));
-    if (!fp64) HIPCHECK(pl, launch_copy_vec(pl->ws + pl->Lo.xbest, x, vbytes, pl->stream));
+    HIPCHECK(pl, launch_fill_zero(pl->ws + pl->so(pl->Lo.p), vbytes, pl->stream));
+    if (!fp64) HIPCHECK(pl, launch_copy_vec(pl->ws + pl->so(pl->Lo.xbest), x, vbytes, pl->stream));
     return FFTGAL_OK;
 }
 
@@ -1540,6 +1555,10 @@ void sym_extremes(const double *A, int d, double *hi, double *lo) {
 
 namespace {
 
+// Device workspace of the internal batch that runs all 2d solves of a plan
+// made with FFTGAL_CONCURRENT at once.
+size_t bws_bytes(int d) { return align256(fftgal_batch_workspace_bytes(2 * d)); }
+
 // Field f of the general material (entries 11, 12, [13,] 22, [23,] 33).
 void field_entry(int f, int d, int *a, int *b) {
     int k = 0;
@@ -1569,7 +1588,7 @@ int general_inclusions(Plan *pl, const fftgal_material *m, std::vector<InclDev> 
     for (int i = 0; i < n; ++i)
         if (!inv_small(m->A_in + (size_t)i * d * d, d, &inv_in[(size_t)i * d * d]))
             return fail(pl, FFTGAL_EINVAL, "inclusion %d: A_in is singular", i);
-    void *U = pl->ws + pl->Lo.T2;
+    void *U = pl->ws + pl->so(pl->Lo.T2);
     for (int pass = 0; pass < 2; ++pass) {
         const double *base = pass == 0 ? m->A0 : A0inv;
         const double *ph = pass == 0 ? m->A_in : inv_in.data();
@@ -1627,8 +1646,8 @@ int tensor_voxels(Plan *pl, const fftgal_material *m, long Ptot, size_t wbytes) 
         double bad = 0.0;
         int rc = over(img, [&](const double *src, long, long cnt) -> int {
             int np = 0;
-            HIPCHECK(pl, launch_tensor_check(src, cnt, d, pl->at<double>(pl->Lo.part_a), &np, pl->stream));
-            HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->Lo.part_a), np, 1,
+            HIPCHECK(pl, launch_tensor_check(src, cnt, d, pl->at<double>(pl->so(pl->Lo.part_a)), &np, pl->stream));
+            HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->so(pl->Lo.part_a)), np, 1,
                                              pl->stream));
             double c = 0.0;
             HIPCHECK(pl, hipMemcpyAsync(&c, pl->at<double>(pl->Lo.gram), 8, hipMemcpyDeviceToHost, pl->stream));
@@ -1712,11 +1731,11 @@ int scalar_inclusions(Plan *pl, const fftgal_material *m, std::vector<InclDev> &
         for (int a = 0; a < d; ++a) pl->DA[a * d + a] = pl->DB[a * d + a] = 1.0;
     }
     // device inclusion table lives at the end of the W scratch region
-    void *U = pl->ws + pl->Lo.T2;
+    void *U = pl->ws + pl->so(pl->Lo.T2);
     const size_t inc_bytes = (size_t)std::max(n, 1) * sizeof(InclDev);
-    const size_t t1_bytes = pl->Lo.T2 - pl->Lo.T1;
+    const size_t t1_bytes = pl->so(pl->Lo.T2) - pl->so(pl->Lo.T1);
     if (inc_bytes + 4096 > t1_bytes / 2) return fail(pl, FFTGAL_EINVAL, "too many inclusions for this plan");
-    InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1 + (t1_bytes - inc_bytes - 256) / 256 * 256);
+    InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->so(pl->Lo.T1) + (t1_bytes - inc_bytes - 256) / 256 * 256);
     for (int pass = 0; pass < (pl->separate_gB ? 2 : 1); ++pass) {
         for (int i = 0; i < n; ++i) inc[i].w = pass == 0 ? wA[i] : wB[i];
         HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
@@ -1745,12 +1764,14 @@ size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P,
     Dims D;
     const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
     const bool tensor = (precision & FFTGAL_TENSOR) != 0;
-    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR);
+    const bool conc = (precision & FFTGAL_CONCURRENT) != 0;
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
     if (lean && scheme != kSchemeReduced) return 0;
     if (tensor && scheme != kSchemeGa) return 0;
+    if (conc && scheme == kSchemeReduced) return 0;
     if (!make_dims(d, N, nullptr, &D, scheme, tensor)) return 0;
-    const size_t base = make_layout(D, precision, !lean).total;
+    const size_t base = make_layout(D, precision, !lean, conc ? 2 * d : 1).total + (conc ? bws_bytes(d) : 0);
     if (P == nullptr) return base;
     Dims DP;
     if (!make_dims(d, N, P, &DP, scheme, tensor)) return 0;
@@ -1774,21 +1795,25 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     Dims D;
     const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
     const bool tensor = (precision & FFTGAL_TENSOR) != 0;
-    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR);
+    const bool conc = (precision & FFTGAL_CONCURRENT) != 0;
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
         return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
     if (lean && scheme != kSchemeReduced)
         return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_REDUCED_LEAN applies to reduced plans only");
     if (tensor && scheme != kSchemeGa)
         return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_TENSOR applies to Ga plans only");
+    if (conc && scheme == kSchemeReduced)
+        return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_CONCURRENT applies to Ga and GaNi plans");
     if (!make_dims(d, N, nullptr, &D, scheme, tensor))
         return fail(nullptr, FFTGAL_EINVAL,
                     "d must be 2 or 3 and every N odd and >= 1");
     if (dev_workspace == nullptr || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))
         return fail(nullptr, FFTGAL_EINVAL, "workspace must be a 256-byte aligned device pointer");
-    Layout Lo = make_layout(D, precision, !lean);
-    if (bytes < Lo.total)
-        return fail(nullptr, FFTGAL_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, Lo.total);
+    Layout Lo = make_layout(D, precision, !lean, conc ? 2 * d : 1);
+    const size_t bws = conc ? bws_bytes(d) : 0;  // the internal batch of fftgal_solve_all
+    if (bytes < Lo.total + bws)
+        return fail(nullptr, FFTGAL_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, Lo.total + bws);
     // a larger workspace provisions voxel images up to the largest P that fits
     auto *pl = new Plan();
     pl->D = D;
@@ -1797,6 +1822,9 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     pl->reduced = scheme == kSchemeReduced;
     pl->grouped = !lean && D.nshift > 1;
     pl->precision = precision;
+    pl->slot_used.assign(Lo.nslots, 0);
+    pl->bws_off = Lo.total;
+    pl->bws_len = bws;
     pl->stream = reinterpret_cast<hipStream_t>(hip_stream);
     pl->ws = reinterpret_cast<char *>(dev_workspace);
     pl->ws_bytes = bytes;
@@ -1938,10 +1966,10 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
                 return fail(pl, FFTGAL_EINVAL, "inclusion phases that differ and are not all isotropic need a plan "
                                                "made with FFTGAL_TENSOR");
             const size_t inc_bytes = (size_t)std::max(n, 1) * sizeof(InclDev);
-            const size_t t1_bytes = pl->Lo.T2 - pl->Lo.T1;
+            const size_t t1_bytes = pl->so(pl->Lo.T2) - pl->so(pl->Lo.T1);
             if (inc_bytes + 4096 > t1_bytes / 2) return fail(pl, FFTGAL_EINVAL, "too many inclusions for this plan");
             InclDev *inc_dev =
-                reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1 + (t1_bytes - inc_bytes - 256) / 256 * 256);
+                reinterpret_cast<InclDev *>(pl->ws + pl->so(pl->Lo.T1) + (t1_bytes - inc_bytes - 256) / 256 * 256);
             if ((rc = general_inclusions(pl, m, inc, inc_dev))) return rc;
         } else {
             if ((rc = scalar_inclusions(pl, m, inc, same))) return rc;
@@ -1965,13 +1993,13 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
             build_fft(m->P[a], entry, tab, &fP[a]);
             entry = tab.size() / 2;
         }
-        const size_t ubytes = pl->Lo.r - pl->Lo.T2;
-        const size_t wbytes = pl->Lo.T2 - pl->Lo.T1;
+        const size_t ubytes = pl->so(pl->Lo.r) - pl->so(pl->Lo.T2);
+        const size_t wbytes = pl->so(pl->Lo.T2) - pl->so(pl->Lo.T1);
         if (need_u <= ubytes && need_w <= wbytes && entry <= pl->Lo.twP_len) {
             pl->vox_tw64 = pl->Lo.twP64;
             pl->vox_tw32 = pl->Lo.twP32;
-            pl->vox_u = pl->Lo.T2;
-            pl->vox_w = pl->Lo.T1;
+            pl->vox_u = pl->so(pl->Lo.T2);
+            pl->vox_w = pl->so(pl->Lo.T1);
         } else {
             const size_t t0 = pl->Lo.total;
             pl->vox_tw64 = t0;
@@ -1994,7 +2022,7 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
         if (m->image_tensor) {
             if (D.nfield < 2)
                 return fail(pl, FFTGAL_EINVAL, "matrix voxel images need a plan made with FFTGAL_TENSOR");
-            const size_t wb = pl->vox_w == pl->Lo.T1 ? wbytes : need_w;
+            const size_t wb = pl->vox_w == pl->so(pl->Lo.T1) ? wbytes : need_w;
             if ((rc = tensor_voxels(pl, m, Ptot, wb))) return rc;
         } else {
         // the image is read from the caller's device buffer, or from a staging
@@ -2020,7 +2048,7 @@ int fftgal_set_material(struct fftgal_plan *pl, const fftgal_material *m) {
             if ((rc = upload(which))) return rc;
             {
                 Timed t(pl, FFTGAL_K_SETUP);
-                HIPCHECK(pl, launch_image_stats(img_of(which), Ptot, pl->at<double>(pl->Lo.part_a),
+                HIPCHECK(pl, launch_image_stats(img_of(which), Ptot, pl->at<double>(pl->so(pl->Lo.part_a)),
                                                 pl->at<double>(pl->Lo.gram), pl->stream));
             }
             HIPCHECK(pl, hipMemcpyAsync(stats, pl->at<double>(pl->Lo.gram), sizeof stats, hipMemcpyDeviceToHost,
@@ -2123,11 +2151,11 @@ int fftgal_bounds(struct fftgal_plan *pl, double *upper, double *lower, double *
             if (rc) return rc;
             RowArgs r = base_row(pl, true, ROW_GRAM, rows, kind, s);
             r.ncomp = d * d;
-            r.partial = pl->at<double>(pl->Lo.part_b);
+            r.partial = pl->at<double>(pl->so(pl->Lo.part_b));
             rc = run_row(pl, r, true, FFTGAL_K_BOUNDS);
             if (rc) return rc;
             Timed t(pl, FFTGAL_K_BOUNDS);
-            HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->Lo.part_b), row_grid(r),
+            HIPCHECK(pl, launch_sum_partials(pl->at<double>(pl->Lo.gram), pl->at<double>(pl->so(pl->Lo.part_b)), row_grid(r),
                                              d * d, pl->stream));
             double gs[9];
             HIPCHECK(pl, hipMemcpyAsync(gs, pl->at<double>(pl->Lo.gram), d * d * 8, hipMemcpyDeviceToHost,
@@ -2239,10 +2267,10 @@ int fftgal_envelope_images(struct fftgal_plan *pl, const fftgal_material *m, con
     sym_extremes(m->A0, d, &ext[0], &ext[1]);
     for (int i = 0; i < n; ++i) sym_extremes(m->A_in + (size_t)i * d * d, d, &ext[2 + 2 * i], &ext[3 + 2 * i]);
     const size_t inc_bytes = align256((size_t)std::max(n, 1) * sizeof(InclDev));
-    if (inc_bytes + ext.size() * 8 > pl->Lo.T2 - pl->Lo.T1)
+    if (inc_bytes + ext.size() * 8 > pl->so(pl->Lo.T2) - pl->so(pl->Lo.T1))
         return fail(pl, FFTGAL_ENOMEM, "too many inclusions for this plan's scratch");
-    InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->Lo.T1);
-    double *ext_dev = reinterpret_cast<double *>(pl->ws + pl->Lo.T1 + inc_bytes);
+    InclDev *inc_dev = reinterpret_cast<InclDev *>(pl->ws + pl->so(pl->Lo.T1));
+    double *ext_dev = reinterpret_cast<double *>(pl->ws + pl->so(pl->Lo.T1) + inc_bytes);
     if (n > 0)
         HIPCHECK(pl, hipMemcpyAsync(inc_dev, inc.data(), (size_t)n * sizeof(InclDev), hipMemcpyHostToDevice,
                                     pl->stream));
@@ -2344,6 +2372,7 @@ struct fftgal_batch {
         int kind, alpha, id;
         IterCfg cfg;
         int enq = 0;  // iterations enqueued (FP32 checkpoints every kCkptEvery)
+        int slot = 0;  // the plan's solve slot
     };
     std::vector<Member> members;
     struct Done {
@@ -2517,19 +2546,29 @@ int fftgal_batch_add(struct fftgal_batch *b, struct fftgal_plan *pl, int kind, i
     if (alpha < 0 || alpha >= pl->D.d) return bfail(b, FFTGAL_EINVAL, "alpha %d out of range", alpha);
     if (!(rtol >= 0.0) || maxit < 0) return bfail(b, FFTGAL_EINVAL, "rtol must be >= 0 and maxit >= 0");
     if (!pl->have_mat) return bfail(b, FFTGAL_ESTATE, "plan has no material");
-    if (pl->busy) return bfail(b, FFTGAL_ESTATE, "plan already has a solve in a batch");
     if (pl->reduced) return bfail(b, FFTGAL_EINVAL, "reduced plans do not join batches");
+    if (pl->in_batch[kind][alpha]) return bfail(b, FFTGAL_ESTATE, "this solve of the plan is already in a batch");
+    int slot = -1;
+    for (int k = 0; k < (int)pl->slot_used.size() && slot < 0; ++k)
+        if (!pl->slot_used[k]) slot = k;
+    if (slot < 0)
+        return bfail(b, FFTGAL_ESTATE, "the plan's %d solve slot(s) are in use (FFTGAL_CONCURRENT gives 2d)",
+                     (int)pl->slot_used.size());
     if ((int)b->members.size() >= b->cap) return bfail(b, FFTGAL_ENOMEM, "batch is full");
+    pl->slot = slot;
     int rc = start_solve(pl, kind, alpha, rtol, maxit);
-    if (rc) return bfail(b, rc, "start of solve failed: %s", pl->err.c_str());
     Batch::Member m;
     m.pl = pl;
     m.kind = kind;
     m.alpha = alpha;
+    m.slot = slot;
     m.id = b->next_id++;
-    rc = capture_iteration(pl, kind, alpha, pl->fp64_iter(), &m.cfg);
-    if (rc) return bfail(b, rc, "capture failed: %s", pl->err.c_str());
-    pl->busy = true;
+    if (!rc) rc = capture_iteration(pl, kind, alpha, pl->fp64_iter(), &m.cfg);
+    pl->slot = 0;
+    if (rc) return bfail(b, rc, "start of solve failed: %s", pl->err.c_str());
+    pl->busy += 1;
+    pl->slot_used[slot] = 1;
+    pl->in_batch[kind][alpha] = true;
     pl->solved[kind][alpha] = false;
     b->members.push_back(std::move(m));
     b->dirty = true;
@@ -2582,7 +2621,9 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
         for (auto &m : b->members) {
             ++m.enq;
             if (m.cfg.fp64 || m.enq % kCkptEvery) continue;
+            m.pl->slot = m.slot;
             const int rc = checkpoint(m.pl, m.kind, m.alpha, false);
+            m.pl->slot = 0;
             if (rc) return bfail(b, rc, "checkpoint failed: %s", m.pl->err.c_str());
         }
     }
@@ -2602,10 +2643,14 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
         Batch::Done d;
         d.id = mem.id;
         CgStatus hf = h;
+        mem.pl->slot = mem.slot;
         const int rc = final_checkpoint(mem.pl, mem.kind, mem.alpha, &hf);
+        mem.pl->slot = 0;
         if (rc) return bfail(b, rc, "checkpoint failed: %s", mem.pl->err.c_str());
         d.status = finish_solve(mem.pl, mem.kind, mem.alpha, hf, &d.info);
-        mem.pl->busy = false;
+        mem.pl->busy -= 1;
+        mem.pl->slot_used[mem.slot] = 0;
+        mem.pl->in_batch[mem.kind][mem.alpha] = false;
         b->done.push_back(d);
         b->dirty = true;
     }
@@ -2627,11 +2672,64 @@ int fftgal_batch_poll(struct fftgal_batch *b, int *solve_id, fftgal_info *info, 
 int fftgal_batch_destroy(struct fftgal_batch *b) {
     if (!b) return FFTGAL_OK;
     if (!b->members.empty()) (void)hipStreamSynchronize(b->stream);
-    for (auto &m : b->members) m.pl->busy = false;
+    for (auto &m : b->members) {
+        m.pl->busy -= 1;
+        m.pl->slot_used[m.slot] = 0;
+        m.pl->in_batch[m.kind][m.alpha] = false;
+    }
     delete b;
     return FFTGAL_OK;
 }
 
 const char *fftgal_batch_last_error(const struct fftgal_batch *b) { return b ? b->err.c_str() : "batch is NULL"; }
+
+int fftgal_solve_all(struct fftgal_plan *pl, double rtol, int maxit, fftgal_info *info) {
+    if (!pl) return FFTGAL_EINVAL;
+    if (!pl->have_mat) return fail(pl, FFTGAL_ESTATE, "no material set");
+    if (pl->busy) return fail(pl, FFTGAL_ESTATE, "the plan has a solve in a batch");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(pl, FFTGAL_EINVAL, "rtol must be >= 0 and maxit >= 0");
+    const int d = pl->D.d;
+    auto hard = [](int rc) { return rc == FFTGAL_EDEVICE || rc == FFTGAL_EINVAL || rc == FFTGAL_ESTATE; };
+    if ((int)pl->slot_used.size() < 2 * d || pl->bws_len == 0) {
+        // one solve slot: the d primal, then the d dual solves
+        const int r1 = solve_entry(pl, KIND_E, -1, rtol, maxit, info);
+        if (hard(r1)) return r1;
+        const int r2 = solve_entry(pl, KIND_J, -1, rtol, maxit, info ? info + d : nullptr);
+        if (hard(r2)) return r2;
+        return r1 != FFTGAL_OK ? r1 : r2;
+    }
+    // all 2d solves as members of one batch: every launch of an iteration
+    // covers all of them; each keeps its own reductions, so the results equal
+    // those of the solves run one after another
+    Batch *b = nullptr;
+    int rc = fftgal_batch_create(&b, 2 * d, pl->ws + pl->bws_off, pl->bws_len, pl->stream);
+    if (rc) return fail(pl, rc, "internal batch: %s", fftgal_last_error(nullptr));
+    int ids[6];
+    for (int k = 0; k < 2 && !rc; ++k)
+        for (int a = 0; a < d && !rc; ++a) {
+            rc = fftgal_batch_add(b, pl, k, a, rtol, maxit, &ids[k * d + a]);
+            if (rc) fail(pl, rc, "internal batch: %s", b->err.c_str());
+        }
+    int active = rc ? 0 : 2 * d;
+    while (!rc && active > 0) {
+        rc = fftgal_batch_step(b, 16, &active);
+        if (rc) fail(pl, rc, "internal batch: %s", b->err.c_str());
+    }
+    int worst = FFTGAL_OK;
+    int sid = 0, st = 0;
+    fftgal_info inf{};
+    while (fftgal_batch_poll(b, &sid, &inf, &st)) {
+        for (int j = 0; j < 2 * d; ++j)
+            if (ids[j] == sid) {
+                if (info) info[j] = inf;
+                if (st != FFTGAL_OK && worst == FFTGAL_OK) worst = st;
+            }
+    }
+    fftgal_batch_destroy(b);
+    if (rc) return rc;
+    if (worst == FFTGAL_EBREAKDOWN) return fail(pl, worst, "CG breakdown (non-SPD or non-finite material)");
+    if (worst == FFTGAL_ENOTCONV) return fail(pl, worst, "a solve did not converge (see info)");
+    return worst;
+}
 
 }  // extern "C"

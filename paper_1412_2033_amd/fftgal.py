@@ -23,6 +23,7 @@ FP64 = 0
 FP32_ITER = 1
 REDUCED_LEAN = 0x100  # reduced Ga laid out with one set of intermediates (shifts in turn)
 TENSOR = 0x200  # d(d+1)/2 material fields per side (matrix images, anisotropic multi-phase inclusions)
+CONCURRENT = 0x400  # per-solve buffers for all 2d solves: they may run at once
 PRECISIONS = {"fp64": FP64, "fp32": FP32_ITER, "fp32_iter": FP32_ITER}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5: "ESTATE", -6: "EBREAKDOWN"}
@@ -31,7 +32,7 @@ EXPORTS = ("fftgal_workspace_bytes", "fftgal_workspace_bytes_p", "fftgal_plan", 
            "fftgal_last_error", "fftgal_grid_size", "fftgal_set_timing", "fftgal_read_timing",
            "fftgal_warm_start", "fftgal_history", "fftgal_set_timing_classes", "fftgal_set_bound_tol",
            "fftgal_workspace_bytes_gani", "fftgal_plan_gani", "fftgal_bounds_of", "fftgal_envelope_images",
-           "fftgal_workspace_bytes_reduced", "fftgal_plan_reduced", "fftgal_plan_static",
+           "fftgal_workspace_bytes_reduced", "fftgal_plan_reduced", "fftgal_plan_static", "fftgal_solve_all",
            "fftgal_static_workspace_bytes",
            "fftgal_batch_workspace_bytes", "fftgal_batch_create", "fftgal_batch_add", "fftgal_batch_step",
            "fftgal_batch_poll", "fftgal_batch_destroy", "fftgal_batch_last_error")
@@ -99,6 +100,8 @@ def load_library(path=LIB_PATH):
     lib.fftgal_plan.restype = ctypes.c_int
     lib.fftgal_set_material.argtypes = [vp, ctypes.POINTER(Material)]
     lib.fftgal_set_material.restype = ctypes.c_int
+    lib.fftgal_solve_all.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]
+    lib.fftgal_solve_all.restype = ctypes.c_int
     for name in ("fftgal_solve_primal", "fftgal_solve_dual"):
         f = getattr(lib, name)
         f.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]
@@ -291,6 +294,16 @@ def fftgal_solve_dual(plan, d, alpha=-1, rtol=1e-10, maxit=20000):
     return _solve(load_library().fftgal_solve_dual, plan, d, alpha, rtol, maxit)
 
 
+def fftgal_solve_all(plan, d, rtol=1e-10, maxit=20000):
+    """All 2d solves: ([primal infos], [dual infos], status code)."""
+    infos = (Info * (2 * d))()
+    code = load_library().fftgal_solve_all(plan, rtol, maxit, infos)
+    if code not in (0, -4):
+        _check(code, plan)
+    out = [i.as_dict() for i in infos]
+    return out[:d], out[d:], code
+
+
 def fftgal_bounds(plan, d):
     up = (ctypes.c_double * (d * d))()
     lo = (ctypes.c_double * (d * d))()
@@ -353,7 +366,7 @@ class Plan:
     """A plan plus the torch device workspace it runs in."""
 
     def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None, scheme="ga", lean=False,
-                 tensor=False):
+                 tensor=False, concurrent=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fftgal needs a HIP device")
@@ -361,7 +374,9 @@ class Plan:
         self.N = tuple(int(n) for n in N)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.scheme = scheme
-        flags = self.precision | (REDUCED_LEAN if lean else 0) | (TENSOR if tensor else 0)
+        flags = self.precision | (REDUCED_LEAN if lean else 0) | (TENSOR if tensor else 0) | \
+            (CONCURRENT if concurrent else 0)
+        self.concurrent = bool(concurrent)
         self.nbytes = fftgal_workspace_bytes(self.d, self.N, flags, P, scheme)
         if self.nbytes == 0:
             raise FftgalError(-1, "invalid plan arguments")
@@ -427,8 +442,12 @@ class Plan:
         self.set_material(micro)
         if warm_from is not None:
             self.warm_start(warm_from)
-        ip, cp = self.solve_primal(-1, rtol, maxit)
-        idl, cd = self.solve_dual(-1, rtol, maxit)
+        if self.concurrent:
+            ip, idl, code = fftgal_solve_all(self.handle, self.d, rtol, maxit)
+            cp = cd = code
+        else:
+            ip, cp = self.solve_primal(-1, rtol, maxit)
+            idl, cd = self.solve_dual(-1, rtol, maxit)
         up, lo, gap = self.bounds()
         return {"upper": up, "lower": lo, "gap": gap, "info_primal": ip, "info_dual": idl,
                 "status_primal": cp, "status_dual": cd}

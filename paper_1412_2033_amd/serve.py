@@ -1,13 +1,16 @@
 """Continuous-batching request loop for guaranteed-bound requests.
 
 Requests (microstructures of any d and N) arrive over time.  A request is
-admitted when the batch has a free slot and its plan's workspace fits the HBM
-budget (plans are pooled per (d, N, precision) and kept on the device, so a
-later request of the same shape reuses one).  An admitted request's material
-fields are built at once; its 2d CG solves then run one after another as
-members of a shared batch (fftgal_batch_*), whose every launch advances all
-active solves of all requests together.  When a request's last solve retires,
-its bounds are evaluated (FP64 quadrature) and its latency recorded.
+admitted when the batch has free slots for its solves and its plan's workspace
+fits the HBM budget (plans are pooled per (d, N, precision) and kept on the
+device, so a later request of the same shape reuses one).  An admitted
+request's material fields are built at once; its 2d CG solves then join a
+shared batch (fftgal_batch_*) together -- plans are made with
+FFTGAL_CONCURRENT, one buffer set per solve -- and every launch of the batch
+advances all active solves of all requests.  (With concurrent=False a plan
+holds one buffer set and a request's solves run one after another.)  When a
+request's last solve retires, its bounds are evaluated (FP64 quadrature) and
+its latency recorded.
 
 All scheduling is host logic; every step of the computation runs in the HIP
 library.
@@ -29,7 +32,7 @@ def percentile(xs, q):
 
 class Server:
     def __init__(self, precision="fp32", rtol=5e-6, maxit=20000, capacity=256, hbm_budget=64 << 30,
-                 iters_per_step=8, device="cuda:0"):
+                 iters_per_step=8, device="cuda:0", concurrent=True):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -44,12 +47,14 @@ class Server:
         self.used_bytes = 0
         self.peak_bytes = 0
         self.plans_created = 0
+        self.concurrent = bool(concurrent)
+        self.flags = fftgal.PRECISIONS[precision] | (fftgal.CONCURRENT if self.concurrent else 0)
 
     def _plan(self, d, N):
         key = (d, N)
         if self.pool[key]:
             return self.pool[key].pop()
-        need = fftgal.fftgal_workspace_bytes(d, N, fftgal.PRECISIONS[self.precision])
+        need = fftgal.fftgal_workspace_bytes(d, N, self.flags)
         if need > self.hbm_budget:
             raise ValueError("a plan of d = %d, N = %s needs %d bytes, more than the HBM budget %d"
                              % (d, N, need, self.hbm_budget))
@@ -65,7 +70,8 @@ class Server:
         self.used_bytes += need
         self.peak_bytes = max(self.peak_bytes, self.used_bytes)
         self.plans_created += 1
-        return fftgal.Plan(d, N, self.precision, device=self.device, stream=self.batch.stream)
+        return fftgal.Plan(d, N, self.precision, device=self.device, stream=self.batch.stream,
+                           concurrent=self.concurrent)
 
     def run(self, requests, realtime=True):
         """Serve `requests` (dicts with id, arrival_s, N, micro); returns per-request records."""
@@ -73,6 +79,7 @@ class Server:
         waiting = collections.deque()
         active = {}
         by_sid = {}
+        n_solves = 0  # batch members
         records = []
         iter_points = 0.0
         deferred = set()  # requests that waited for memory with a slot free
@@ -83,9 +90,12 @@ class Server:
             now = clock() if realtime else sim_now
             while pending and pending[0]["arrival_s"] <= now:
                 waiting.append(pending.popleft())
-            while waiting and len(active) < self.capacity:
+            while waiting:
                 req = waiting[0]
                 d = int(req["micro"]["d"])
+                width = 2 * d if self.concurrent else 1  # solves the request adds at once
+                if n_solves + width > self.capacity:
+                    break
                 N = (int(req["N"]),) * d
                 plan = self._plan(d, N)
                 if plan is None:
@@ -94,21 +104,27 @@ class Server:
                 waiting.popleft()
                 plan.set_material(req["micro"])
                 seq = [(0, a) for a in range(d)] + [(1, a) for a in range(d)]
-                st = {"req": req, "plan": plan, "seq": seq, "k": 0, "t_admit": now, "iters": [], "status": [],
-                      "key": (d, N), "pts": float(np.prod([2 * n - 1 for n in N]))}
-                sid = self.batch.add(plan, *seq[0], self.rtol, self.maxit)
-                by_sid[sid] = st
+                st = {"req": req, "plan": plan, "seq": seq, "k": width, "left": len(seq), "t_admit": now,
+                      "iters": [], "status": [], "key": (d, N), "pts": float(np.prod([2 * n - 1 for n in N]))}
+                for j in range(width):
+                    by_sid[self.batch.add(plan, *seq[j], self.rtol, self.maxit)] = st
+                n_solves += width
                 active[id(plan)] = st
             if active:
                 self.batch.step(self.iters_per_step)
                 for sid, info, status in self.batch.poll():
                     st = by_sid.pop(sid)
+                    n_solves -= 1
                     st["iters"].append(info["iters"])
                     st["status"].append(status)
                     iter_points += info["iters"] * st["pts"]
-                    st["k"] += 1
-                    if st["k"] < len(st["seq"]):
+                    st["left"] -= 1
+                    if st["k"] < len(st["seq"]):  # one solve at a time: start the next
                         by_sid[self.batch.add(st["plan"], *st["seq"][st["k"]], self.rtol, self.maxit)] = st
+                        st["k"] += 1
+                        n_solves += 1
+                        continue
+                    if st["left"] > 0:
                         continue
                     up, lo, gap = st["plan"].bounds()
                     t_done = clock() if realtime else sim_now
@@ -139,7 +155,8 @@ class Server:
 
 
 def sequential(requests, precision="fp64", rtol=1e-10, maxit=20000, device="cuda:0"):
-    """The same requests solved one at a time with the plain (unbatched) path."""
+    """The same requests solved one at a time with the plain (unbatched) path:
+    one request after another, its solves one after another."""
     import torch
     out = []
     t0 = time.perf_counter()
