@@ -186,6 +186,8 @@ def main():
     ap.add_argument("--serve3d-budget-gib", type=float, default=2.5,
                     help="HBM budget of the 3D serving sample (GiB of plan workspaces)")
     ap.add_argument("--N", type=int, default=113)
+    ap.add_argument("--equal-accuracy", type=int, default=1,
+                    help="compare both forms at the same bound accuracy (1e-6) over a tolerance sweep (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gani", type=int, default=225,
                     help="grid of the GaNi section (the paper compares GaNi of order 2N-1; 0: skip)")
@@ -203,6 +205,7 @@ def main():
     args = ap.parse_args()
     if args.main_only:
         args.serve = args.serve3d = args.gani = args.warm_coarse = args.reduced = args.reduced_prime = 0
+        args.equal_accuracy = 0
         args.envelope = args.aniso = args.sweep2d = 0
     if args.gpus != 1:
         print("bench.py: the benchmark runs on one GPU (independent solves and requests shard across GPUs "
@@ -345,6 +348,8 @@ def main():
             "speedup_vs_fp64": round(f64["ms_per_step"] / f32["ms_per_step"], 3),
             "kernels": f32["kernels"], "roofline": f32["roofline"]},
     }
+    if args.equal_accuracy:
+        out["equal_accuracy"] = equal_accuracy_bench(fftgal, micro_dev, d, N, M, f64["last"], dev)
     if args.warm_coarse > 0:
         out["warm_start"] = warm_start_bench(fftgal, micro_dev, d, N, M, args.warm_coarse, rtol64, dev)
     if args.gani > 0:
@@ -588,9 +593,15 @@ def serving_bench(n, rtol, seed=4):
     seq, t_seq = serve.sequential(base, precision="fp64", rtol=rtol)
     by = {r["id"]: r for r in seq}
     at_once = [dict(r, arrival_s=0.0) for r in base]
+    print("bench: serving: batched FP32, one solve slot per plan, all requests at t=0", file=sys.stderr, flush=True)
+    srv1 = serve.Server(precision="fp32", rtol=rtol, concurrent=False)
+    rec1, st1 = srv1.run(at_once)
+    lat1 = [r["latency_s"] for r in rec1]
+    srv1.close()
     srv = serve.Server(precision="fp32", rtol=rtol)
     print("bench: serving: batched FP32, all requests at t=0", file=sys.stderr, flush=True)
     rec0, st0 = srv.run(at_once)
+    lat0 = [r["latency_s"] for r in rec0]
     capacity = n / st0["wall_s"]
     # Poisson arrivals at 0.8x the batched capacity, and a sweep of the load
     sweep = []
@@ -619,7 +630,14 @@ def serving_bench(n, rtol, seed=4):
                                 "p50_s": round(serve.percentile(seq_t, 50), 4),
                                 "p99_s": round(serve.percentile(seq_t, 99), 4)},
             "batched_fp32_capacity": {"wall_s": round(st0["wall_s"], 3), "req_per_s": round(capacity, 2),
-                                      "Mpoint_iter_per_s": round(st0["Mpoint_iter_per_s"], 1)},
+                                      "Mpoint_iter_per_s": round(st0["Mpoint_iter_per_s"], 1),
+                                      "solves_per_request_at_once": "all 2d (concurrent plans)",
+                                      "p50_s_all_at_t0": round(serve.percentile(lat0, 50), 4),
+                                      "p99_s_all_at_t0": round(serve.percentile(lat0, 99), 4)},
+            "batched_fp32_capacity_one_solve_at_a_time": {
+                "wall_s": round(st1["wall_s"], 3), "req_per_s": round(n / st1["wall_s"], 2),
+                "p50_s_all_at_t0": round(serve.percentile(lat1, 50), 4),
+                "p99_s_all_at_t0": round(serve.percentile(lat1, 99), 4)},
             "batched_fp32_poisson": {"rate_req_per_s": round(rate, 2), "wall_s": round(st["wall_s"], 3),
                                      "p50_s": round(serve.percentile(lat, 50), 4),
                                      "p99_s": round(serve.percentile(lat, 99), 4),
@@ -663,6 +681,36 @@ def aniso_bench(fftgal, n, rtol64, rtol32, dev):
     return out
 
 
+def equal_accuracy_bench(fftgal, micro_dev, d, N, M, ref, dev, target=1e-6):
+    """Time to bounds of both forms at the same stated bound accuracy: for each
+    form the loosest CG tolerance of a sweep whose bounds stay within `target`
+    (relative, Frobenius) of the FP64 bounds at rtol 1e-8 (`ref`)."""
+    import numpy as np
+    import torch
+    out = {"target_bound_rel_err": target, "reference": "FP64 path at rtol 1e-8", "forms": {}}
+    for prec in ("fp64", "fp32"):
+        plan = fftgal.Plan(d, N, prec, device=dev, P=M)
+        plan.run(micro_dev, rtol=1e-4)  # warm-up
+        rows = []
+        for rtol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 5e-6):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = plan.run(micro_dev, rtol=rtol)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            err = max(float(np.linalg.norm(r[k] - ref[k]) / np.linalg.norm(ref[k])) for k in ("upper", "lower"))
+            rows.append({"rtol": rtol, "time_to_bounds_s": round(el, 4), "bound_rel_err": err,
+                         "cg_iterations": sum(i["iters"] for i in r["info_primal"] + r["info_dual"])})
+            print("bench: equal accuracy %s rtol %g: %.4f s, err %.2e" % (prec, rtol, el, err), file=sys.stderr,
+                  flush=True)
+        plan.close()
+        ok = [row for row in rows if row["bound_rel_err"] <= target]
+        out["forms"][prec] = {"sweep": rows, "chosen": ok[0] if ok else None}
+    a, b = out["forms"]["fp64"]["chosen"], out["forms"]["fp32"]["chosen"]
+    out["fp32_speedup_at_equal_accuracy"] = round(a["time_to_bounds_s"] / b["time_to_bounds_s"], 3) if a and b else None
+    return out
+
+
 def sweep2d_bench(fftgal, dev, Ns=(41, 365, 1013)):
     """Centred disc of volume fraction 0.3, phases 1 and 100, d = 2: plain FP64
     bounds to relative residual 1e-10 at each order N (doubled grids 81^2,
@@ -673,15 +721,20 @@ def sweep2d_bench(fftgal, dev, Ns=(41, 365, 1013)):
     micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0)
     out = {"microstructure": "centred disc, vf 0.3, contrast 100", "rtol": 1e-10, "orders": []}
     for n in Ns:
-        plan = fftgal.Plan(2, (n, n), "fp64", device=dev)
-        plan.run(micro, rtol=1e-10)  # warm-up
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        r = plan.run(micro, rtol=1e-10)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        plan.close()
+        times = {}
+        for conc in (False, True):
+            # one solve after another, or all four in shared launches (fftgal_solve_all)
+            plan = fftgal.Plan(2, (n, n), "fp64", device=dev, concurrent=conc)
+            plan.run(micro, rtol=1e-10)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = plan.run(micro, rtol=1e-10)
+            torch.cuda.synchronize()
+            times[conc] = time.perf_counter() - t
+            plan.close()
+        dt = times[False]
         out["orders"].append({"N": n, "M": 2 * n - 1, "time_to_bounds_s": round(dt, 4),
+                              "time_to_bounds_concurrent_s": round(times[True], 4),
                               "cg_iterations": {"primal": [i["iters"] for i in r["info_primal"]],
                                                 "dual": [i["iters"] for i in r["info_dual"]]},
                               "upper_diag": [round(float(v), 10) for v in np.diag(r["upper"])],

@@ -5,12 +5,13 @@ admitted when the batch has free slots for its solves and its plan's workspace
 fits the HBM budget (plans are pooled per (d, N, precision) and kept on the
 device, so a later request of the same shape reuses one).  An admitted
 request's material fields are built at once; its 2d CG solves then join a
-shared batch (fftgal_batch_*) together -- plans are made with
-FFTGAL_CONCURRENT, one buffer set per solve -- and every launch of the batch
-advances all active solves of all requests.  (With concurrent=False a plan
-holds one buffer set and a request's solves run one after another.)  When a
-request's last solve retires, its bounds are evaluated (FP64 quadrature) and
-its latency recorded.
+shared batch (fftgal_batch_*) together -- plans of grids up to 2^20 points
+are made with FFTGAL_CONCURRENT, one buffer set per solve -- and every launch
+of the batch advances all active solves of all requests.  Larger grids, whose
+single solve already fills the GPU, keep one buffer set (a request's solves
+then run one after another), and so does every plan with concurrent=False.
+When a request's last solve retires, its bounds are evaluated (FP64
+quadrature) and its latency recorded.
 
 All scheduling is host logic; every step of the computation runs in the HIP
 library.
@@ -32,7 +33,7 @@ def percentile(xs, q):
 
 class Server:
     def __init__(self, precision="fp32", rtol=5e-6, maxit=20000, capacity=256, hbm_budget=64 << 30,
-                 iters_per_step=8, device="cuda:0", concurrent=True):
+                 iters_per_step=8, device="cuda:0", concurrent="auto"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -47,14 +48,22 @@ class Server:
         self.used_bytes = 0
         self.peak_bytes = 0
         self.plans_created = 0
-        self.concurrent = bool(concurrent)
-        self.flags = fftgal.PRECISIONS[precision] | (fftgal.CONCURRENT if self.concurrent else 0)
+        self.concurrent = concurrent
+
+    def concurrent_for(self, d, N):
+        """Whether plans of this shape hold one buffer set per solve."""
+        if self.concurrent == "auto":
+            return int(np.prod([2 * n - 1 for n in N])) <= (1 << 20)
+        return bool(self.concurrent)
+
+    def flags_for(self, d, N):
+        return fftgal.PRECISIONS[self.precision] | (fftgal.CONCURRENT if self.concurrent_for(d, N) else 0)
 
     def _plan(self, d, N):
         key = (d, N)
         if self.pool[key]:
             return self.pool[key].pop()
-        need = fftgal.fftgal_workspace_bytes(d, N, self.flags)
+        need = fftgal.fftgal_workspace_bytes(d, N, self.flags_for(d, N))
         if need > self.hbm_budget:
             raise ValueError("a plan of d = %d, N = %s needs %d bytes, more than the HBM budget %d"
                              % (d, N, need, self.hbm_budget))
@@ -71,7 +80,7 @@ class Server:
         self.peak_bytes = max(self.peak_bytes, self.used_bytes)
         self.plans_created += 1
         return fftgal.Plan(d, N, self.precision, device=self.device, stream=self.batch.stream,
-                           concurrent=self.concurrent)
+                           concurrent=self.concurrent_for(d, N))
 
     def run(self, requests, realtime=True):
         """Serve `requests` (dicts with id, arrival_s, N, micro); returns per-request records."""
@@ -93,10 +102,10 @@ class Server:
             while waiting:
                 req = waiting[0]
                 d = int(req["micro"]["d"])
-                width = 2 * d if self.concurrent else 1  # solves the request adds at once
+                N = (int(req["N"]),) * d
+                width = 2 * d if self.concurrent_for(d, N) else 1  # solves the request adds at once
                 if n_solves + width > self.capacity:
                     break
-                N = (int(req["N"]),) * d
                 plan = self._plan(d, N)
                 if plan is None:
                     deferred.add(req["id"])
