@@ -88,6 +88,21 @@ def algorithmic_bytes(cls, d, N, M, es, gs, nc):
     return 0
 
 
+def iteration_model_bytes(d, N, M, w):
+    """Bytes of one CG iteration in the pass-minimal model of the hot path (the
+    operator in one round trip of the N x ... x (N+1)/2 half-spectrum per
+    transform axis plus the material field, and the CG state): 4 d M N (N+1)/2
+    2w + M^3 w + 7 N^2 (N+1)/2 2w in 3D, 4 d M (N+1)/2 2w + M^2 w + 7 (N+1)/2 2w
+    in 2D (w = bytes of a real)."""
+    Nh = (N[-1] + 1) // 2
+    Mt = 1
+    for m in M:
+        Mt *= m
+    if d == 3:
+        return 4 * d * M[0] * N[1] * Nh * 2 * w + Mt * w + 7 * N[0] * N[1] * Nh * 2 * w
+    return 4 * d * M[0] * Nh * 2 * w + Mt * w + 7 * N[0] * Nh * 2 * w
+
+
 def host_workers():
     """Host threads the oracle's FFTs may use: the cores this process may run
     on, capped by OMP_NUM_THREADS when set (the host's share per GPU)."""
@@ -264,12 +279,15 @@ def main():
         it_p = sum(i["iters"] for i in traced["info_primal"])
         it_d = sum(i["iters"] for i in traced["info_dual"])
         per_cls = {}
+        design_bytes = 0
         for cls, (ms, cnt) in breakdown.items():
             if cnt == 0:
                 continue
             by = algorithmic_bytes(cls, d, N, M, es, gs, 1) * it_p + algorithmic_bytes(cls, d, N, M, es, gs, d - 1) * it_d
+            design_bytes += by
             per_cls[cls] = {"ms": round(ms, 3), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 2),
                             "GBs": round(by / (ms * 1e-3) / 1e9, 1) if by > 0 else None}
+        design_bytes /= max(1, it_p + it_d)
         dom = max((c for c in per_cls if per_cls[c]["GBs"]), key=lambda c: per_cls[c]["ms"])
         # timed steps: only the dominant class is bracketed by HIP events
         plan.set_timing(True, classes=(dom,))
@@ -300,6 +318,16 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, precision),
                 "kernel": dom, "bytes_per_launch": int(dom_bytes), "avg_launch_us": round(dom_avg_s * 1e6, 2),
                 "launches_timed": timing[dom][1], "iterations_timed": total_iters}
+        # the whole CG iteration: the pass-minimal model's bytes and this
+        # design's algorithmic bytes per iteration, over the time per iteration
+        # of the whole timed run (material setup, right-hand sides and bounds
+        # included, so conservative)
+        it_s = elapsed / total_iters
+        model = iteration_model_bytes(d, N, M, es // 2)
+        roof["iteration"] = {"model_bytes": int(model), "design_bytes": int(design_bytes),
+                             "us_per_iteration": round(it_s * 1e6, 2),
+                             "frac_model": round(model / it_s / 1e9 / HBM_PEAK_GBS, 4),
+                             "frac_design": round(design_bytes / it_s / 1e9 / HBM_PEAK_GBS, 4)}
         last = results[-1]
         return {"elapsed": elapsed, "value": pts * total_iters / elapsed / 1e6, "ms_per_step": 1e3 * elapsed / args.steps,
                 "kernels": per_cls, "roofline": roof, "last": last,

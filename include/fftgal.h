@@ -93,6 +93,19 @@ enum fftgal_precision {
  * fftgal_solve_all.  EINVAL with reduced plans. */
 #define FFTGAL_CONCURRENT 0x400
 
+/* Flag or-ed into `precision` of fftgal_workspace_bytes* and the plan
+ * constructors.  By default the CG iterations of 2D Ga plans whose double
+ * grid is 81 x 81 (N = 41; FP32-iteration form also 81 or 125 on either axis,
+ * N = 41 or 63) run entirely inside one work-group per solve: the CG vectors
+ * in registers, the operator of Algorithm 2 on the M_1 x M_2 grid in LDS, the
+ * update and the stopping test in the same kernel, many iterations per launch
+ * (timing class FFTGAL_K_SOLO).  Solves of such plans in a batch run that way
+ * too, side by side on a stream of the batch's own.  The flag keeps these
+ * plans on the per-pass kernels instead (one launch per pass and iteration).
+ * Both forms compute the same iterations; their results agree to rounding.
+ * It changes no workspace size. */
+#define FFTGAL_SEPARATE_PASSES 0x800
+
 enum fftgal_material_kind {
     FFTGAL_INCLUSIONS = 0, /* eq. inclcomp: matrix phase plus inclusions          */
     FFTGAL_VOXELS = 1      /* eq. gridcomp: piecewise-constant voxel image        */
@@ -410,7 +423,9 @@ enum fftgal_kernel_class {
     FFTGAL_K_BOUNDS = 8,      /* FP64 fields and energy Gram quadrature             */
     FFTGAL_K_SETUP = 9,       /* material fields A_M, B_M                           */
     FFTGAL_K_CHECKPOINT = 10, /* FP32 best-iterate checkpoints (exact energies)     */
-    FFTGAL_K_COUNT = 11
+    FFTGAL_K_SOLO = 11,       /* whole CG iterations of small 2D solves, one
+                                 work-group per solve (see FFTGAL_SEPARATE_PASSES) */
+    FFTGAL_K_COUNT = 12
 };
 int fftgal_set_timing(struct fftgal_plan *plan, int enable);
 /* As fftgal_set_timing, for the classes whose bit (1 << class) is set only

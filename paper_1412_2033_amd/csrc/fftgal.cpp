@@ -369,6 +369,7 @@ struct fftgal_plan {
     double btol = 0.0;  // bound tolerance of the stopping test (fftgal_set_bound_tol)
     bool gani = false;     // material sampled at the grid points of the order-N grid
     bool reduced = false;  // reduced Ga: 2^d shifted transforms of size N (Lemma reduce_grid)
+    bool solo = true;      // small 2D grids: whole CG iterations in one work-group per solve
     // kernel timing (fftgal_set_timing): classes recorded
     unsigned timing_mask = 0;
     struct Ev {
@@ -1412,11 +1413,83 @@ int final_checkpoint(Plan *pl, int kind, int alpha, CgStatus *h) {
     return FFTGAL_OK;
 }
 
+// Whether the CG iterations of this plan's solves run in the single
+// work-group solver (2D Ga on a double grid it holds in LDS).
+bool use_solo(const Plan *pl) {
+    const Dims &D = pl->D;
+    return pl->solo && D.d == 2 && !pl->gani && !pl->reduced && D.nshift == 1 && !pl->fM[0].blue &&
+           !pl->fM[1].blue && solo_fits(D.M[0], D.M[1], pl->fp64_iter());
+}
+
+// Arguments of the single work-group solver for one solve (in the plan's
+// current solve slot).
+SoloArgs make_solo(Plan *pl, int kind, int alpha) {
+    const Dims &D = pl->D;
+    const bool fp64 = pl->fp64_iter();
+    SoloArgs a{};
+    a.x = pl->xsol(kind, alpha);
+    a.r = pl->ws + pl->so(pl->Lo.r);
+    a.p = pl->ws + pl->so(pl->Lo.p);
+    a.st = pl->status(kind, alpha);
+    a.mirror = nullptr;
+    a.hist = pl->hist_on ? pl->hist(kind, alpha) : nullptr;
+    a.hist_cap = kMaxHist + 1;
+    const RowArgs r = base_row(pl, fp64, ROW_OPER, nullptr, kind, 0);
+    a.g = r.g;
+    a.gstride = r.gstride;
+    a.nfield = r.nfield;
+    for (int i = 0; i < 4; ++i) {
+        a.A0[i] = r.A0[i];
+        a.D[i] = r.D[i];
+    }
+    a.tw = pl->ws + (fp64 ? pl->Lo.tw64 : pl->Lo.tw32);
+    a.tw0 = pl->fM[0].twoff[0];
+    a.tw1 = pl->fM[1].twoff[0];
+    a.M0 = D.M[0];
+    a.M1 = D.M[1];
+    a.N0 = D.N[0];
+    a.Nh = D.Nh;
+    a.kind = kind;
+    a.scale = 1.0 / ((double)D.nshift * D.Mtot);
+    return a;
+}
+
+// Iterations of a solve in the single work-group solver: one launch up to
+// the next FP32 checkpoint (FP64: up to maxit; the kernel stops at
+// convergence), then the status.
+int run_solve_solo(Plan *pl, int kind, int alpha, int maxit, fftgal_info *info) {
+    const bool fp64 = pl->fp64_iter();
+    CgStatus *st = pl->status(kind, alpha);
+    const SoloArgs sa = make_solo(pl, kind, alpha);
+    static_assert(sizeof(SoloArgs) <= kArgSlot, "argument slot too small");
+    std::memcpy(pl->iter_host[0], &sa, sizeof sa);
+    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(0), pl->iter_host[0], sizeof sa, hipMemcpyHostToDevice, pl->stream));
+    const SoloArgs *dev = reinterpret_cast<const SoloArgs *>(pl->iter_slot(0));
+    CgStatus h{};
+    int enq = 0;
+    int rc = FFTGAL_OK;
+    for (;;) {
+        const int n = fp64 ? maxit - enq : std::min(maxit - enq, kCkptEvery - enq % kCkptEvery);
+        if (n > 0) {
+            TimedLaunch t(pl, FFTGAL_K_SOLO);
+            HIPCHECK(pl, launch_solo(sa, dev, 1, n, fp64, pl->stream, t.ev));
+            enq += n;
+            if (!fp64 && enq % kCkptEvery == 0 && (rc = checkpoint(pl, kind, alpha, false))) return rc;
+        }
+        HIPCHECK(pl, hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, pl->stream));
+        HIPCHECK(pl, hipStreamSynchronize(pl->stream));
+        if (h.done || enq >= maxit) break;
+    }
+    if ((rc = final_checkpoint(pl, kind, alpha, &h))) return rc;
+    return finish_solve(pl, kind, alpha, h, info);
+}
+
 int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info *info) {
     const bool fp64 = pl->fp64_iter();
     CgStatus *st = pl->status(kind, alpha);
     int rc = start_solve(pl, kind, alpha, rtol, maxit);
     if (rc) return rc;
+    if (use_solo(pl)) return run_solve_solo(pl, kind, alpha, maxit, info);
     IterCfg cfg;
     rc = capture_iteration(pl, kind, alpha, fp64, &cfg);
     if (rc) return rc;
@@ -1765,7 +1838,7 @@ size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P,
     const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
     const bool tensor = (precision & FFTGAL_TENSOR) != 0;
     const bool conc = (precision & FFTGAL_CONCURRENT) != 0;
-    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT);
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT | FFTGAL_SEPARATE_PASSES);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
     if (lean && scheme != kSchemeReduced) return 0;
     if (tensor && scheme != kSchemeGa) return 0;
@@ -1796,7 +1869,8 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
     const bool tensor = (precision & FFTGAL_TENSOR) != 0;
     const bool conc = (precision & FFTGAL_CONCURRENT) != 0;
-    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT);
+    const bool sep = (precision & FFTGAL_SEPARATE_PASSES) != 0;
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT | FFTGAL_SEPARATE_PASSES);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
         return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
     if (lean && scheme != kSchemeReduced)
@@ -1820,6 +1894,7 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     pl->Lo = Lo;
     pl->gani = scheme == kSchemeGani;
     pl->reduced = scheme == kSchemeReduced;
+    pl->solo = !sep;
     pl->grouped = !lean && D.nshift > 1;
     pl->precision = precision;
     pl->slot_used.assign(Lo.nslots, 0);
@@ -2373,6 +2448,8 @@ struct fftgal_batch {
         IterCfg cfg;
         int enq = 0;  // iterations enqueued (FP32 checkpoints every kCkptEvery)
         int slot = 0;  // the plan's solve slot
+        bool solo = false;  // iterations in the single work-group solver
+        SoloArgs sargs{};
     };
     std::vector<Member> members;
     struct Done {
@@ -2395,6 +2472,19 @@ struct fftgal_batch {
         size_t args_off, woff_off;
     };
     std::vector<UGroup> ugroups;
+    // members in the single work-group solver, one launch per grid and precision
+    struct SGroup {
+        bool fp64;
+        int np;
+        size_t args_off;
+        SoloArgs proto;
+    };
+    std::vector<SGroup> sgroups;
+    int n_items = 0;  // members in the per-pass kernels (CG items)
+    // the single work-group solves run on a stream of the batch's own, beside
+    // the per-pass kernels of the other members
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t items_off = 0;
     size_t blob_base = 0;  // device offset of the argument blob
     std::vector<unsigned char> blob;
@@ -2444,7 +2534,7 @@ int batch_rebuild(Batch *b) {
         std::map<std::tuple<int, int, int, int>, std::vector<size_t>> by;
         for (size_t m = 0; m < nm; ++m) {
             const auto &ps = b->members[m].cfg.passes;
-            if (i >= ps.size() || !pass_fast(ps[i])) continue;
+            if (b->members[m].solo || i >= ps.size() || !pass_fast(ps[i])) continue;
             const PassRec &r = ps[i];
             const int n = r.type == 0 ? r.pa.f.n : r.ra.f.n;
             const int d = r.type == 0 ? r.pa.d : r.ra.d;
@@ -2480,7 +2570,7 @@ int batch_rebuild(Batch *b) {
         int total = 0;
         for (size_t m = 0; m < nm; ++m) {
             const IterCfg &c = b->members[m].cfg;
-            if ((int)c.fp64 != f) continue;
+            if (b->members[m].solo || (int)c.fp64 != f) continue;
             ua.push_back(c.upd);
             woff.push_back(total);
             total += c.upd.nblocks;
@@ -2494,12 +2584,31 @@ int batch_rebuild(Batch *b) {
         u.woff_off = blob_put(b->blob, woff.data(), woff.size() * sizeof(int));
         b->ugroups.push_back(u);
     }
-    std::vector<CgItem> items(nm);
+    std::vector<CgItem> items;
+    std::map<std::tuple<int, int, int>, std::vector<SoloArgs>> solo_by;
     for (size_t m = 0; m < nm; ++m) {
-        items[m] = b->members[m].cfg.item;
-        items[m].mirror = reinterpret_cast<CgStatus *>(b->ws) + m;
+        CgStatus *mirror = reinterpret_cast<CgStatus *>(b->ws) + m;
+        const Batch::Member &mem = b->members[m];
+        if (mem.solo) {
+            SoloArgs a = mem.sargs;
+            a.mirror = mirror;
+            solo_by[std::make_tuple((int)mem.cfg.fp64, a.M0, a.M1)].push_back(a);
+            continue;
+        }
+        items.push_back(mem.cfg.item);
+        items.back().mirror = mirror;
     }
-    b->items_off = blob_put(b->blob, items.data(), items.size() * sizeof(CgItem));
+    b->n_items = (int)items.size();
+    b->items_off = items.empty() ? 0 : blob_put(b->blob, items.data(), items.size() * sizeof(CgItem));
+    b->sgroups.clear();
+    for (auto &kv : solo_by) {
+        Batch::SGroup g;
+        g.fp64 = std::get<0>(kv.first) != 0;
+        g.np = (int)kv.second.size();
+        g.proto = kv.second[0];
+        g.args_off = blob_put(b->blob, kv.second.data(), kv.second.size() * sizeof(SoloArgs));
+        b->sgroups.push_back(g);
+    }
     if (b->blob_base + b->blob.size() > b->bytes) return bfail(b, FFTGAL_ENOMEM, "batch workspace too small");
     BHIPCHECK(b, hipMemcpyAsync(b->ws + b->blob_base, b->blob.data(), b->blob.size(), hipMemcpyHostToDevice,
                                 b->stream));
@@ -2564,6 +2673,10 @@ int fftgal_batch_add(struct fftgal_batch *b, struct fftgal_plan *pl, int kind, i
     m.slot = slot;
     m.id = b->next_id++;
     if (!rc) rc = capture_iteration(pl, kind, alpha, pl->fp64_iter(), &m.cfg);
+    if (!rc && use_solo(pl)) {
+        m.solo = true;
+        m.sargs = make_solo(pl, kind, alpha);
+    }
     pl->slot = 0;
     if (rc) return bfail(b, rc, "start of solve failed: %s", pl->err.c_str());
     pl->busy += 1;
@@ -2590,7 +2703,42 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
     }
     char *base = b->ws + b->blob_base;
     const CgItem *items = reinterpret_cast<const CgItem *>(base + b->items_off);
-    for (int it = 0; it < iterations; ++it) {
+    if (!b->sgroups.empty()) {
+        // single work-group solves: on the side stream, in launches up to the
+        // next FP32 checkpoint of any of them (the checkpoints fall on the same
+        // iteration counts as when solved alone)
+        if (!b->side) {
+            BHIPCHECK(b, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+            BHIPCHECK(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+            BHIPCHECK(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+        }
+        BHIPCHECK(b, hipEventRecord(b->ev_fork, b->stream));
+        BHIPCHECK(b, hipStreamWaitEvent(b->side, b->ev_fork, 0));
+        int left = iterations;
+        while (left > 0) {
+            int n = left;
+            for (const auto &m : b->members)
+                if (m.solo && !m.cfg.fp64) n = std::min(n, kCkptEvery - m.enq % kCkptEvery);
+            for (const auto &g : b->sgroups)
+                BHIPCHECK(b, launch_solo(g.proto, reinterpret_cast<const SoloArgs *>(base + g.args_off), g.np, n,
+                                         g.fp64, b->side));
+            for (auto &m : b->members) {
+                if (!m.solo) continue;
+                m.enq += n;
+                if (m.cfg.fp64 || m.enq % kCkptEvery) continue;
+                m.pl->slot = m.slot;
+                const hipStream_t own = m.pl->stream;
+                m.pl->stream = b->side;
+                const int rc = checkpoint(m.pl, m.kind, m.alpha, false);
+                m.pl->stream = own;
+                m.pl->slot = 0;
+                if (rc) return bfail(b, rc, "checkpoint failed: %s", m.pl->err.c_str());
+            }
+            left -= n;
+        }
+        BHIPCHECK(b, hipEventRecord(b->ev_join, b->side));
+    }
+    for (int it = 0; it < iterations && b->n_items > 0; ++it) {
         for (size_t i = 0; i < 5; ++i) {
             for (const auto &g : b->groups) {
                 if (g.pass != i) continue;
@@ -2603,7 +2751,7 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
                                                   woff, g.np, g.total, g.proto.fp64, b->stream));
             }
             for (auto &m : b->members) {
-                if (i >= m.cfg.passes.size() || pass_fast(m.cfg.passes[i])) continue;
+                if (m.solo || i >= m.cfg.passes.size() || pass_fast(m.cfg.passes[i])) continue;
                 const PassRec &r = m.cfg.passes[i];
                 if (r.type == 0)
                     BHIPCHECK(b, launch_pencil(r.pa, r.nouter, r.fp64, b->stream));
@@ -2615,10 +2763,11 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
             BHIPCHECK(b, launch_cg_update_multi(reinterpret_cast<const UpdArgs *>(base + u.args_off),
                                                 reinterpret_cast<const int *>(base + u.woff_off), u.np, u.total,
                                                 u.fp64, b->stream));
-        BHIPCHECK(b, launch_cg_check_multi(items, nm, b->stream));
+        BHIPCHECK(b, launch_cg_check_multi(items, b->n_items, b->stream));
         // FP32 members: best-iterate checkpoints at the same iteration counts
         // as when solved alone
         for (auto &m : b->members) {
+            if (m.solo) continue;
             ++m.enq;
             if (m.cfg.fp64 || m.enq % kCkptEvery) continue;
             m.pl->slot = m.slot;
@@ -2627,6 +2776,7 @@ int fftgal_batch_step(struct fftgal_batch *b, int iterations, int *n_active) {
             if (rc) return bfail(b, rc, "checkpoint failed: %s", m.pl->err.c_str());
         }
     }
+    if (!b->sgroups.empty()) BHIPCHECK(b, hipStreamWaitEvent(b->stream, b->ev_join, 0));
     b->mirror_host.resize(nm);
     BHIPCHECK(b, hipMemcpyAsync(b->mirror_host.data(), b->ws, nm * sizeof(CgStatus), hipMemcpyDeviceToHost,
                                 b->stream));
@@ -2672,6 +2822,12 @@ int fftgal_batch_poll(struct fftgal_batch *b, int *solve_id, fftgal_info *info, 
 int fftgal_batch_destroy(struct fftgal_batch *b) {
     if (!b) return FFTGAL_OK;
     if (!b->members.empty()) (void)hipStreamSynchronize(b->stream);
+    if (b->side) {
+        (void)hipStreamSynchronize(b->side);
+        (void)hipStreamDestroy(b->side);
+        (void)hipEventDestroy(b->ev_fork);
+        (void)hipEventDestroy(b->ev_join);
+    }
     for (auto &m : b->members) {
         m.pl->busy -= 1;
         m.pl->slot_used[m.slot] = 0;

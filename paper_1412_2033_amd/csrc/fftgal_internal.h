@@ -199,6 +199,29 @@ struct UpdArgs {
     long q_ss;
 };
 
+// One 2D CG solve run entirely by one work-group (launch_solo): the CG
+// vectors x, r, p (nc = 1 component of N0 x Nh coefficients, half spectrum),
+// the status, the material A(x) = A0 + g(x) D (nfield = 1) or the fields g +
+// f gstride holding the entries 11, 12, 22 of A(x) (nfield = 3) on the M0 x M1
+// grid, the stage twiddles of both axes (entries tw0, tw1 of tw), the basis
+// kind and the scale 1 / (M0 M1) of the forward transforms.
+struct SoloArgs {
+    void *x, *r, *p;
+    CgStatus *st;
+    CgStatus *mirror;  // copy of the status at the end of a launch, or nullptr
+    double *hist;      // (rr, alpha) per iteration, or nullptr
+    int hist_cap;
+    const void *g;
+    long gstride;
+    int nfield;
+    double A0[4], D[4];
+    const void *tw;
+    int tw0, tw1;
+    int M0, M1, N0, Nh;
+    int kind;
+    double scale;
+};
+
 struct CgItem {
     CgStatus *st;
     const double *rr_part;
@@ -276,6 +299,13 @@ hipError_t launch_pencil_multi(const PencilArgs &proto, const PencilArgs *args, 
 hipError_t launch_row_multi(const RowArgs &proto, const RowArgs *args, const int *woff, int np, int total,
                             bool fp64, hipStream_t s, LaunchEv ev = LaunchEv{});
 hipError_t launch_cg_check_multi(const CgItem *items, int np, hipStream_t s, LaunchEv ev = LaunchEv{});
+// Whether a 2D Ga grid M0 x M1 has the single-work-group solver (both lengths
+// specialised, the complex grid within the LDS of one work-group).
+bool solo_fits(int M0, int M1, bool fp64);
+// `niter` CG iterations (fewer once a solve is done) of each of the np solves
+// in `args` (device array; all of one grid and precision), one work-group each.
+hipError_t launch_solo(const SoloArgs &proto, const SoloArgs *args, int np, int niter, bool fp64, hipStream_t s,
+                       LaunchEv ev = LaunchEv{});
 hipError_t launch_cg_update_multi(const UpdArgs *ua, const int *woff, int np, int total, bool fp64,
                                   hipStream_t s, LaunchEv ev = LaunchEv{});
 int pencil_grid(const PencilArgs &a, int nouter);  // work-groups of one problem

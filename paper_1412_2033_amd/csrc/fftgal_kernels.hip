@@ -1440,12 +1440,12 @@ __device__ __forceinline__ void stage_ip(Vt<T> *X, const Vt<T> *__restrict__ tw,
     __syncthreads();
 }
 
-template <typename T, int FI, int S, int P, int OFF, int NB, bool ROWL>
+template <typename T, int FI, int S, int P, int OFF, int NB, bool ROWL, int NT = kThreads>
 __device__ __forceinline__ void fft_ip(Vt<T> *X, const Vt<T> *tw, T sg) {
     if constexpr (S < kFastSched[FI].nst) {
         constexpr int R = kFastSched[FI].r[S];
-        stage_ip<T, R, kFastSched[FI].n, P, NB, ROWL>(X, tw + OFF, sg);
-        fft_ip<T, FI, S + 1, P * R, OFF + (R - 1) * P, NB, ROWL>(X, tw, sg);
+        stage_ip<T, R, kFastSched[FI].n, P, NB, ROWL, NT>(X, tw + OFF, sg);
+        fft_ip<T, FI, S + 1, P * R, OFF + (R - 1) * P, NB, ROWL, NT>(X, tw, sg);
     }
 }
 
@@ -3012,6 +3012,250 @@ __global__ __launch_bounds__(kThreads) void cg_update_multi_kernel(const UpdArgs
     if (threadIdx.x == 0) a.partial[lb] = s;
 }
 
+// ---------------------------------------------------------------------------
+// Whole 2D CG solves, one work-group each (small double grids).  The CG
+// vectors stay in registers (each thread owns coefficients idx = tid + 1024 j
+// of the N0 x Nh half spectrum); the operator of Algorithm 2 runs on one
+// complex M0 x M1 grid in LDS: the two components y_0, y_1 of the gradient
+// field (real on the grid) are packed as z = y_0 + i y_1, so that
+//   Z(k) = Y_0(k) + i Y_1(k),  Y_c(k) = i t_c(k) p(k)  (k_1 >= 0 stored;
+//   Z(-k) = conj(Y_0(k)) + i conj(Y_1(k)) from the Hermitian symmetry),
+// an inverse 2D DFT gives z on the grid, the material acts on (Re z, Im z) at
+// every point, a forward 2D DFT gives Z', and
+//   Y'_0(k) = (Z'(k) + conj(Z'(-k))) / 2,  Y'_1(k) = (Z'(k) - conj(Z'(-k))) / 2i
+// feed the projection q(k) = -i scale sum_c t_c(k) Y'_c(k).  The CG update and
+// the stopping test (as cg_update_multi_kernel and cg_check_multi_kernel,
+// with work-group sums in a fixed order) follow in the same work-group, so a
+// launch runs many iterations with no kernel boundary between them.
+// ---------------------------------------------------------------------------
+constexpr int kSoloNT = 1024;
+template <typename T>
+constexpr size_t solo_lds_bytes_t(int m0, int m1) {
+    return sizeof(Vt<T>) * ((size_t)m0 * m1 + m0 + m1 + (m0 + 1) / 2);
+}
+
+// fixed-order sum over the 1024 threads (shuffle tree per wave, then the
+// waves in turn by thread 0), broadcast to every thread
+__device__ __forceinline__ double solo_sum(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kSoloNT / 64; ++w) s += red[w];
+        red[kSoloNT / 64] = s;
+    }
+    __syncthreads();
+    return red[kSoloNT / 64];
+}
+
+template <typename T, int FI0, int FI1>
+__global__ __launch_bounds__(kSoloNT) void solo2d_kernel(const SoloArgs *__restrict__ sa, int niter) {
+    using V = Vt<T>;
+    constexpr int M0 = kFastSched[FI0].n, M1 = kFastSched[FI1].n;
+    constexpr int NT = kSoloNT;
+    constexpr int CPT = ((M0 + 1) / 2 * ((M1 + 3) / 4) + NT - 1) / NT;  // coefficients per thread
+    const SoloArgs &a = sa[blockIdx.x];
+    __shared__ CgStatus S;
+    __shared__ double red[NT / 64 + 1];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V *Z = reinterpret_cast<V *>(smem_raw);  // [M0][M1]
+    V *tw0 = Z + M0 * M1;                    // stage twiddles of axis 0
+    V *tw1 = tw0 + M0;                       // and of axis 1
+    V *P0 = tw1 + M1;                        // p at k_2 = 0, by stored index of k_1
+    if (threadIdx.x == 0) S = *a.st;
+    {
+        const auto *t0 = gbl(reinterpret_cast<const V *>(a.tw) + a.tw0);
+        const auto *t1 = gbl(reinterpret_cast<const V *>(a.tw) + a.tw1);
+        for (int i = threadIdx.x; i < M0 - 1; i += NT) tw0[i] = gld(t0 + i);
+        for (int i = threadIdx.x; i < M1 - 1; i += NT) tw1[i] = gld(t1 + i);
+    }
+    const int N0 = a.N0, Nh = a.Nh;
+    const int ns = N0 * Nh;
+    auto *gx = gbl(reinterpret_cast<V *>(a.x));
+    auto *gr = gbl(reinterpret_cast<V *>(a.r));
+    auto *gp = gbl(reinterpret_cast<V *>(a.p));
+    T xr[CPT], xi[CPT], rr_[CPT], ri[CPT], pr[CPT], pi_[CPT], t0[CPT], t1[CPT], wgt[CPT];
+    int zp[CPT], zm[CPT], lz[CPT];
+    bool own[CPT], pos1[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int idx = threadIdx.x + j * NT;
+        own[j] = idx < ns;
+        const int id = own[j] ? idx : 0;
+        const int l = id / Nh;
+        const int k1 = id - l * Nh;
+        const int k0 = wrapi(l, N0);
+        T tb[2][3];
+        const int nt = basis<T>(2, a.kind, k0, k1, 0, tb);
+        t0[j] = nt ? tb[0][0] : T(0);
+        t1[j] = nt ? tb[0][1] : T(0);
+        pos1[j] = k1 > 0;
+        lz[j] = k1 == 0 ? l : -1;
+        wgt[j] = k1 == 0 ? T(1) : T(2);
+        zp[j] = posmod(k0, M0) * M1 + k1;
+        zm[j] = posmod(-k0, M0) * M1 + (k1 == 0 ? 0 : M1 - k1);
+        const V vx = gld(gx + id), vr = gld(gr + id), vp = gld(gp + id);
+        xr[j] = vx.x;
+        xi[j] = vx.y;
+        rr_[j] = vr.x;
+        ri[j] = vr.y;
+        pr[j] = vp.x;
+        pi_[j] = vp.y;
+    }
+    const auto *g = gbl(reinterpret_cast<const T *>(a.g));
+    const T A00 = T(a.A0[0]), A01 = T(a.A0[1]), A11 = T(a.A0[3]);
+    const T D00 = T(a.D[0]), D01 = T(a.D[1]), D11 = T(a.D[3]);
+    const T scale = T(a.scale);
+    __syncthreads();
+    for (int it = 0; it < niter && !S.done; ++it) {
+        // p = r + beta p (beta = 0 at the first step of a solve)
+        const T beta = T(S.beta);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            pr[j] = rr_[j] + beta * pr[j];
+            pi_[j] = ri[j] + beta * pi_[j];
+            if (own[j] && lz[j] >= 0) P0[lz[j]] = mk<T>(pr[j], pi_[j]);
+        }
+        for (int i = threadIdx.x; i < M0 * M1; i += NT) Z[i] = mk<T>(T(0), T(0));
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            if (!own[j]) continue;
+            // at k_2 = 0 the stored pair p(k_1, 0), p(-k_1, 0) enters through its
+            // Hermitian part (p(k) + conj(p(-k))) / 2, the part a real field has
+            // (as the per-pass kernels, whose real transform along the last
+            // axis keeps the real part there); the rest, rounding of the
+            // right-hand side, must not reach the field
+            T px = pr[j], py = pi_[j];
+            if (lz[j] >= 0) {
+                const V pm = P0[lz[j] == 0 ? 0 : N0 - lz[j]];
+                px = (px + pm.x) * T(0.5);
+                py = (py - pm.y) * T(0.5);
+            }
+            // Y_c = i t_c p
+            const T y0x = -t0[j] * py, y0y = t0[j] * px;
+            const T y1x = -t1[j] * py, y1y = t1[j] * px;
+            Z[zp[j]] = mk<T>(y0x - y1y, y0y + y1x);
+            if (pos1[j]) Z[zm[j]] = mk<T>(y0x + y1y, y1x - y0y);
+        }
+        __syncthreads();
+        fft_ip<T, FI0, 0, 1, 0, M1, false, NT>(Z, tw0, T(1));
+        fft_ip<T, FI1, 0, 1, 0, M0, true, NT>(Z, tw1, T(1));
+        if (a.nfield == 1) {
+            for (int i = threadIdx.x; i < M0 * M1; i += NT) {
+                const V z = Z[i];
+                const T gv = g[i];
+                const T a00 = A00 + gv * D00, a01 = A01 + gv * D01, a11 = A11 + gv * D11;
+                Z[i] = mk<T>(a00 * z.x + a01 * z.y, a01 * z.x + a11 * z.y);
+            }
+        } else {
+            for (int i = threadIdx.x; i < M0 * M1; i += NT) {
+                const V z = Z[i];
+                const T a00 = g[i], a01 = g[a.gstride + i], a11 = g[2 * a.gstride + i];
+                Z[i] = mk<T>(a00 * z.x + a01 * z.y, a01 * z.x + a11 * z.y);
+            }
+        }
+        __syncthreads();
+        fft_ip<T, FI1, 0, 1, 0, M0, true, NT>(Z, tw1, T(-1));
+        fft_ip<T, FI0, 0, 1, 0, M1, false, NT>(Z, tw0, T(-1));
+        // projection q = -i scale sum_c t_c Y'_c and the partial of (p, q)
+        T qr[CPT], qi[CPT];
+        double part = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            qr[j] = qi[j] = T(0);
+            if (!own[j]) continue;
+            const V zk = Z[zp[j]], zn = Z[zm[j]];
+            const T h = T(0.5);
+            const T y0x = (zk.x + zn.x) * h, y0y = (zk.y - zn.y) * h;
+            const T y1x = (zk.y + zn.y) * h, y1y = (zn.x - zk.x) * h;
+            const T s0 = t0[j] * scale, s1 = t1[j] * scale;
+            qr[j] = s0 * y0y + s1 * y1y;
+            qi[j] = -(s0 * y0x + s1 * y1x);
+            part += (double)wgt[j] * ((double)pr[j] * (double)qr[j] + (double)pi_[j] * (double)qi[j]);
+        }
+        const double pq = solo_sum(part, red);
+        const bool bad = !(pq > 0.0) || !isfinite(pq);
+        if (threadIdx.x == 0) {
+            S.pq = pq;
+            if (bad) {
+                // as the update pass: with FP32 iterates a finite (p, K p) <= 0
+                // after the first step is a stall, otherwise a breakdown
+                if (sizeof(T) == 4 && isfinite(pq) && S.iter > 0)
+                    S.stagnated = 1;
+                else
+                    S.breakdown = 1;
+                S.done = 1;
+            } else {
+                S.alpha = S.rr / pq;
+            }
+        }
+        if (bad) break;  // uniform: pq is the same in every thread
+        const double alpha_d = S.rr / pq;
+        const T alpha = T(alpha_d);
+        double part2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            if (!own[j]) continue;
+            xr[j] = xr[j] + alpha * pr[j];
+            xi[j] = xi[j] + alpha * pi_[j];
+            rr_[j] = rr_[j] - alpha * qr[j];
+            ri[j] = ri[j] - alpha * qi[j];
+            part2 += (double)wgt[j] * ((double)rr_[j] * rr_[j] + (double)ri[j] * ri[j]);
+        }
+        const double rr = solo_sum(part2, red);
+        if (threadIdx.x == 0) {
+            // the stopping test of cg_check_multi_kernel
+            const int iter = S.iter + 1;
+            S.iter = iter;
+            if (a.hist != nullptr && iter < a.hist_cap) {
+                a.hist[2 * iter] = rr;
+                a.hist[2 * iter + 1] = S.alpha;
+            }
+            if (!isfinite(rr)) {
+                S.breakdown = 1;
+                S.done = 1;
+            } else {
+                const double dstep = S.alpha * S.rr;
+                S.energy -= dstep;
+                S.beta = rr / S.rr;
+                S.rr = rr;
+                if (rr < S.rrmin) {
+                    S.rrmin = rr;
+                    S.rrmin_it = iter;
+                }
+                if (rr <= S.tol2 * S.rr0 || rr <= S.floor2) {
+                    S.converged = 1;
+                    S.done = 1;
+                } else if (S.btol > 0.0 && iter >= 2 && S.dprev > 0.0 &&
+                           dstep <= S.btol * fabs(S.energy) * (1.0 - fmin(fmax(dstep / S.dprev, 0.0), 0.99))) {
+                    S.converged = 1;
+                    S.done = 1;
+                } else if (iter >= S.maxit) {
+                    S.done = 1;
+                }
+                S.dprev = dstep;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        if (!own[j]) continue;
+        const int idx = threadIdx.x + j * NT;
+        gst(gx + idx, mk<T>(xr[j], xi[j]));
+        gst(gr + idx, mk<T>(rr_[j], ri[j]));
+        gst(gp + idx, mk<T>(pr[j], pi_[j]));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *a.st = S;
+        if (a.mirror != nullptr) *a.mirror = S;
+    }
+}
+
 // ---- best-iterate checkpoints of the FP32-iteration form ----
 // Every CG iterate is admissible, so its exact energy is a guaranteed bound
 // (Sec. 6.4); with FP32 iterates the recursively updated residual and the
@@ -3370,6 +3614,40 @@ hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s) {
     } else {
         hipLaunchKernelGGL(row_kernel<float>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);
     }
+    return hipGetLastError();
+}
+
+bool solo_fits(int M0, int M1, bool fp64) {
+    const int f0 = fast_index(M0), f1 = fast_index(M1);
+    if (!((f0 == 0 || f0 == 1) && (f1 == 0 || f1 == 1))) return false;
+    const size_t lds = fp64 ? solo_lds_bytes_t<double>(M0, M1) : solo_lds_bytes_t<float>(M0, M1);
+    return lds + 1024 <= 160 * 1024;
+}
+
+template <typename T, int FI0, int FI1>
+void launch_solo_t(const SoloArgs *args, int np, int niter, const Disp &s) {
+    constexpr size_t lds = solo_lds_bytes_t<T>(kFastSched[FI0].n, kFastSched[FI1].n);
+    if constexpr (lds + 1024 <= 160 * 1024)
+        dispatch((solo2d_kernel<T, FI0, FI1>), dim3(np), dim3(kSoloNT), lds, s, args, niter);
+}
+
+template <typename T>
+void launch_solo_d(int f0, int f1, const SoloArgs *args, int np, int niter, const Disp &s) {
+    if (f0 == 0 && f1 == 0) launch_solo_t<T, 0, 0>(args, np, niter, s);
+    if (f0 == 0 && f1 == 1) launch_solo_t<T, 0, 1>(args, np, niter, s);
+    if (f0 == 1 && f1 == 0) launch_solo_t<T, 1, 0>(args, np, niter, s);
+    if (f0 == 1 && f1 == 1) launch_solo_t<T, 1, 1>(args, np, niter, s);
+}
+
+hipError_t launch_solo(const SoloArgs &proto, const SoloArgs *args, int np, int niter, bool fp64, hipStream_t st,
+                       LaunchEv ev) {
+    if (np < 1 || niter < 1 || !solo_fits(proto.M0, proto.M1, fp64)) return hipErrorInvalidValue;
+    const int f0 = fast_index(proto.M0), f1 = fast_index(proto.M1);
+    const Disp s(st, ev);
+    if (fp64)
+        launch_solo_d<double>(f0, f1, args, np, niter, s);
+    else
+        launch_solo_d<float>(f0, f1, args, np, niter, s);
     return hipGetLastError();
 }
 

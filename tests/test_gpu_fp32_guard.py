@@ -48,12 +48,17 @@ def _check(res, ref, tol):
     assert np.min(np.linalg.eigvalsh(np.asarray(res["upper"]) - np.asarray(res["lower"]))) > 0
 
 
+@pytest.mark.parametrize("separate", [True, False])
 @pytest.mark.parametrize("k", [0, 1, 2])
-def test_fp32_tight_tolerance_keeps_best_iterate(fg, k):
+def test_fp32_tight_tolerance_keeps_best_iterate(fg, k, separate):
+    # separate: the per-pass kernels; else the single work-group solver these
+    # small grids take by default (whose FP32 iterations reach rtol 1e-7 on
+    # some of these requests without stalling)
     req, ref = _stall_cases()[k]
     N = tuple(ref["N"])
-    print("request %d N=%s contrast %.0f" % (ref["id"], N, req["micro"]["A_in"][0][0, 0]), flush=True)
-    plan = fg.Plan(2, N, "fp32")
+    print("request %d N=%s contrast %.0f separate %s" % (ref["id"], N, req["micro"]["A_in"][0][0, 0], separate),
+          flush=True)
+    plan = fg.Plan(2, N, "fp32", separate_passes=separate)
     try:
         res = plan.run(req["micro"], rtol=1e-7, maxit=20000)
     finally:
@@ -62,7 +67,8 @@ def test_fp32_tight_tolerance_keeps_best_iterate(fg, k):
     print([(i["iters"], i["stagnated"], i["iterate"]) for i in infos], res["status_primal"], res["status_dual"])
     # at least one solve stalls (the unguarded iteration did), and every
     # stalled solve stopped long before maxit and kept an earlier field
-    assert any(i["stagnated"] for i in infos)
+    if separate:
+        assert any(i["stagnated"] for i in infos)
     for i in infos:
         if i["stagnated"]:
             assert i["iters"] < 3000 and not i["converged"]
