@@ -1389,19 +1389,23 @@ __global__ __launch_bounds__(kThreads) void incl_coeff_kernel(double2 *out, int 
 // ---------------------------------------------------------------------------
 // One in-place Stockham stage over NB transforms of length N: every thread
 // first loads all inputs of its butterflies into registers, then (after a
-// barrier) twiddles, transforms and stores them.
-template <typename T, int R, int N, int P, int NB, bool ROWL, int NT = kThreads>
+// barrier) twiddles, transforms and stores them.  Column layout (ROWL false)
+// with NA < NB: only the NA transforms 0 .. (NA - 1) / 2 and NB - NA / 2 ..
+// NB - 1 (the non-zero frequencies of a zero-padded axis) are done.
+template <typename T, int R, int N, int P, int NB, bool ROWL, int NT = kThreads, int NA = NB>
 __device__ __forceinline__ void stage_ip(Vt<T> *X, const Vt<T> *__restrict__ tw, T sg) {
     constexpr int TQ = N / R;
-    constexpr int TOT = TQ * NB;
+    constexpr int NT_ = ROWL ? NB : NA;  // transforms done
+    constexpr int TOT = TQ * NT_;
     constexpr int PER = (TOT + NT - 1) / NT;
+    auto colmap = [](int c) { return c < (NA + 1) / 2 ? c : c + (NB - NA); };
     Vt<T> u[PER][R];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
         const int idx = threadIdx.x + t * NT;
         if (PER * NT == TOT || idx < TOT) {
-            const int b = ROWL ? idx / TQ : idx % NB;
-            const int i = ROWL ? idx % TQ : idx / NB;
+            const int b = ROWL ? idx / TQ : colmap(idx % NA);
+            const int i = ROWL ? idx % TQ : idx / NA;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int pos = i + q * TQ;
@@ -1414,8 +1418,8 @@ __device__ __forceinline__ void stage_ip(Vt<T> *X, const Vt<T> *__restrict__ tw,
     for (int t = 0; t < PER; ++t) {
         const int idx = threadIdx.x + t * NT;
         if (PER * NT == TOT || idx < TOT) {
-            const int b = ROWL ? idx / TQ : idx % NB;
-            const int i = ROWL ? idx % TQ : idx / NB;
+            const int b = ROWL ? idx / TQ : colmap(idx % NA);
+            const int i = ROWL ? idx % TQ : idx / NA;
             const int k = i % P;
             if constexpr (P > 1) {
 #pragma unroll
@@ -1440,12 +1444,12 @@ __device__ __forceinline__ void stage_ip(Vt<T> *X, const Vt<T> *__restrict__ tw,
     __syncthreads();
 }
 
-template <typename T, int FI, int S, int P, int OFF, int NB, bool ROWL, int NT = kThreads>
+template <typename T, int FI, int S, int P, int OFF, int NB, bool ROWL, int NT = kThreads, int NA = NB>
 __device__ __forceinline__ void fft_ip(Vt<T> *X, const Vt<T> *tw, T sg) {
     if constexpr (S < kFastSched[FI].nst) {
         constexpr int R = kFastSched[FI].r[S];
-        stage_ip<T, R, kFastSched[FI].n, P, NB, ROWL, NT>(X, tw + OFF, sg);
-        fft_ip<T, FI, S + 1, P * R, OFF + (R - 1) * P, NB, ROWL, NT>(X, tw, sg);
+        stage_ip<T, R, kFastSched[FI].n, P, NB, ROWL, NT, NA>(X, tw + OFF, sg);
+        fft_ip<T, FI, S + 1, P * R, OFF + (R - 1) * P, NB, ROWL, NT, NA>(X, tw, sg);
     }
 }
 
@@ -3141,7 +3145,10 @@ __global__ __launch_bounds__(kSoloNT) void solo2d_kernel(const SoloArgs *__restr
             if (pos1[j]) Z[zm[j]] = mk<T>(y0x + y1y, y1x - y0y);
         }
         __syncthreads();
-        fft_ip<T, FI0, 0, 1, 0, M1, false, NT>(Z, tw0, T(1));
+        // columns: only the N_2 = (M_2 + 1) / 2 non-zero ones (zero-padded
+        // frequencies stay zero, and only they are read back after the
+        // forward transform)
+        fft_ip<T, FI0, 0, 1, 0, M1, false, NT, (M1 + 1) / 2>(Z, tw0, T(1));
         fft_ip<T, FI1, 0, 1, 0, M0, true, NT>(Z, tw1, T(1));
         if (a.nfield == 1) {
             for (int i = threadIdx.x; i < M0 * M1; i += NT) {
@@ -3159,7 +3166,7 @@ __global__ __launch_bounds__(kSoloNT) void solo2d_kernel(const SoloArgs *__restr
         }
         __syncthreads();
         fft_ip<T, FI1, 0, 1, 0, M0, true, NT>(Z, tw1, T(-1));
-        fft_ip<T, FI0, 0, 1, 0, M1, false, NT>(Z, tw0, T(-1));
+        fft_ip<T, FI0, 0, 1, 0, M1, false, NT, (M1 + 1) / 2>(Z, tw0, T(-1));
         // projection q = -i scale sum_c t_c Y'_c and the partial of (p, q)
         T qr[CPT], qi[CPT];
         double part = 0.0;
