@@ -2439,7 +2439,7 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     T *Gs = reinterpret_cast<T *>(smem_raw);                                           // [2 PW][N] material
     V *tp = reinterpret_cast<V *>(smem_raw + (sizeof(T) * PW * 2 * N + 15) / 16 * 16);  // [NTP] stage twiddles
-    V *St = tp + NTP;                      // [TB][2][SR] staged half-spectrum rows ...
+    V *St = tp + NTP;                      // [D][2 PW][SR] staged half-spectrum rows ...
     T *Bf = reinterpret_cast<T *>(St);     // ... later [TB][S], one part at a time
     const int nh = a.Nh_row;
     const int npairs = (a.nrows + 1) / 2;
@@ -2451,7 +2451,8 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     // the transform arithmetic, so that a new work-group's loads leave early
     __builtin_amdgcn_s_setprio(3);
     constexpr int GP = (PW * 2 * N + NT - 1) / NT;
-    constexpr int SP = (TB * 2 * SR + NT - 1) / NT;
+    constexpr int RS = 2 * PW * SR;  // staged slots of one component: its 2 PW rows
+    constexpr int SPC = (RS + NT - 1) / NT;
     constexpr int NW = (R - 1) * TQ;  // stage-1 twiddles
     constexpr int WP = (NW + NT - 1) / NT;
     const auto *gsrc = gbl(reinterpret_cast<const T *>(a.g) + (long)2 * pr0 * N);
@@ -2459,25 +2460,29 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     const auto *twg = gbl(reinterpret_cast<const V *>(a.tw) + a.f.twoff[0] + OFFL);
     const int gcnt = nrow_wg * N;
     T gv[GP];
-    T sx[SP], sy[SP];
+    T sx[D][SPC], sy[D][SPC];
     T wx[WP], wy[WP];
 #pragma unroll
     for (int t = 0; t < GP; ++t) {
         const int idx = threadIdx.x + t * NT;
         gv[t] = gsrc[idx < gcnt ? idx : 0];
     }
+    // the rows of a work-group are contiguous in each component: one flat
+    // copy per component into slots [c][row][SR] (slot k >= nh and rows past
+    // the last are zero), with the offsets of a component in 32 bits
 #pragma unroll
-    for (int t = 0; t < SP; ++t) {
-        const int idx = threadIdx.x + t * NT;
-        const int row = idx / SR;  // staged row: transform row / 2, second row of the pair row % 2
-        const int k = idx - row * SR;
-        const int tt = row >> 1;
-        const int lp = tt / D;
-        const bool ok = idx < TB * 2 * SR && k < nh && lp < npr && 2 * lp + (row & 1) < nrow_wg;
-        const long off = (long)(tt - lp * D) * a.cs + (long)(2 * (pr0 + lp) + (row & 1)) * nh + k;
-        const V v = gld(dsrc + (ok ? off : 0L));
-        sx[t] = ok ? v.x : T(0);
-        sy[t] = ok ? v.y : T(0);
+    for (int c = 0; c < D; ++c) {
+        const auto *dc = dsrc + (long)c * a.cs + (long)2 * pr0 * nh;
+#pragma unroll
+        for (int t = 0; t < SPC; ++t) {
+            const int f = threadIdx.x + t * NT;
+            const int row = f / SR;
+            const int k = f - row * SR;
+            const bool ok = f < RS && k < nh && row < nrow_wg;
+            const V v = gld(dc + (ok ? row * nh + k : 0));
+            sx[c][t] = ok ? v.x : T(0);
+            sy[c][t] = ok ? v.y : T(0);
+        }
     }
 #pragma unroll
     for (int t = 0; t < WP; ++t) {
@@ -2492,9 +2497,12 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
         if (idx < PW * 2 * N) Gs[idx] = idx < gcnt ? gv[t] : T(0);
     }
 #pragma unroll
-    for (int t = 0; t < SP; ++t) {
-        const int idx = threadIdx.x + t * NT;
-        if (idx < TB * 2 * SR) St[idx] = mk<T>(sx[t], sy[t]);
+    for (int c = 0; c < D; ++c) {
+#pragma unroll
+        for (int t = 0; t < SPC; ++t) {
+            const int f = threadIdx.x + t * NT;
+            if (f < RS) St[c * RS + f] = mk<T>(sx[c][t], sy[c][t]);
+        }
     }
 #pragma unroll
     for (int t = 0; t < WP; ++t) {
@@ -2518,7 +2526,7 @@ void row_iso_staged(const RowArgs *__restrict__ ra,
     auto zband = [](int q) { return q * TQ >= NHC && q * TQ + TQ - 1 <= N - NHC; };
     V u[R];
     {
-        const V *s1 = St + tl * 2 * SR;
+        const V *s1 = St + c * RS + 2 * lp * SR;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (zband(q)) {
