@@ -386,7 +386,7 @@ def main():
         out["reduced"] = reduced_bench(fftgal, micro_dev, d, M, args.reduced, rtol64, dev)
     if args.reduced_prime > 0:
         out["reduced_bluestein"] = reduced_bench(fftgal, micro_dev, d, M, args.reduced_prime, rtol64, dev,
-                                                 variants=("reduced",))
+                                                 variants=("reduced", "reduced_lean"))
     if args.envelope:
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.aniso:
