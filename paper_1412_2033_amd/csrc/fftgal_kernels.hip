@@ -1460,12 +1460,12 @@ __device__ __forceinline__ void fft_ip(Vt<T> *X, const Vt<T> *tw, T sg) {
 // cost more occupancy than its reads cost latency.
 constexpr bool tw_in_lds(int n, int es) { return n * es <= 12 * 1024; }
 constexpr size_t tw_lds_entries(int n, int es) { return tw_in_lds(n, es) ? (size_t)n : 0; }
-template <typename T, int N>
+template <typename T, int N, int NTH = kThreads>
 __device__ __forceinline__ const Vt<T> *twiddles_to_lds(Vt<T> *dst, const Vt<T> *__restrict__ src) {
     if constexpr (!tw_in_lds(N, sizeof(Vt<T>))) {
         return src;
     } else {
-        for (int i = threadIdx.x; i < N - 1; i += kThreads) dst[i] = src[i];
+        for (int i = threadIdx.x; i < N - 1; i += NTH) dst[i] = src[i];
         return dst;
     }
 }
@@ -2029,7 +2029,9 @@ constexpr int sched_off(int fi, int st) {
 // and last stages owns one butterfly of radix r[0]
 constexpr int iso_tb(int fi) {
     const int tq = kFastSched[fi].n / kFastSched[fi].r[0];
-    return tq <= 64 ? 128 / tq : (tq <= 128 ? 256 / tq : 320 / tq);
+    // transforms of more than 128 butterflies per stage (n = 2025): one per
+    // work-group, so that several share a CU
+    return tq <= 64 ? 128 / tq : (tq <= 128 ? 256 / tq : 1);
 }
 constexpr int iso_nt(int fi) {
     const int tq = kFastSched[fi].n / kFastSched[fi].r[0];
@@ -2046,7 +2048,8 @@ __device__ __forceinline__ void fft_mid(Vt<T> *X, const Vt<T> *tw, T sg) {
 }
 
 template <typename T, int FI>
-__global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__restrict__ ra,
+__global__ __launch_bounds__(iso_nt(FI)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1)))
+void row_iso_fast(const RowArgs *__restrict__ ra,
                                                            const int *__restrict__ woff, int np) {
     using V = Vt<T>;
     constexpr int N = kFastSched[FI].n;
@@ -2062,9 +2065,11 @@ __global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__rest
     if (a.status != nullptr && a.status->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     V *X = reinterpret_cast<V *>(smem_raw);  // [transform][pos]
-    V *tws = X + TB * N;
+    // stage twiddles staged in LDS when short; for the longest rows (2025
+    // points, 32 KB in FP64) the LDS goes to the transforms and the twiddles
+    // are read through the cache
     const V *twg = reinterpret_cast<const V *>(a.tw) + a.f.twoff[0];
-    for (int i = threadIdx.x; i < N - 1; i += NT) tws[i] = twg[i];
+    const V *tws = twiddles_to_lds<T, N, NT>(X + TB * N, twg);
     const V zero = mk<T>(T(0), T(0));
     const int nh = a.Nh_row;
     const int npairs = (a.nrows + 1) / 2;
@@ -2085,17 +2090,6 @@ __global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__rest
     const V *data = reinterpret_cast<const V *>(a.data);
     const V *row1 = data + (long)c * a.cs + (long)r1 * nh;
     const T *g = reinterpret_cast<const T *>(a.g);
-    T g1[R], g2[R];
-    {
-        // idle lanes read row r1 (in range); their products are never stored
-        const T *gr1 = g + (long)r1 * N + i;
-        const T *gr2 = v2 ? gr1 + N : gr1;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            g1[q] = gr1[q * TQ];
-            g2[q] = gr2[q * TQ];
-        }
-    }
     const T a0 = T(a.A0[0]);
     const T da = T(a.D[0]);
     V u[R];
@@ -2146,11 +2140,23 @@ __global__ __launch_bounds__(iso_nt(FI)) void row_iso_fast(const RowArgs *__rest
         u[q] = cmul(u[q], w);
     }
     dftn<T, R>(u, T(1));
-    // the two real rows at x = i + q TQ: multiply by a0 + g da
+    // the two real rows at x = i + q TQ: multiply by a0 + g da (the material
+    // values are loaded here, not held through the inverse stages; idle lanes
+    // read row r1, in range, and their products are never stored)
+    {
+        const T *gr1 = g + (long)r1 * N + i;
+        const T *gr2 = v2 ? gr1 + N : gr1;
+        T g1[R], g2[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        u[q].x *= a0 + g1[q] * da;
-        u[q].y *= a0 + g2[q] * da;
+        for (int q = 0; q < R; ++q) {
+            g1[q] = gr1[q * TQ];
+            g2[q] = gr2[q * TQ];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            u[q].x *= a0 + g1[q] * da;
+            u[q].y *= a0 + g2[q] * da;
+        }
     }
     // first forward stage on the same points
     dftn<T, R>(u, T(-1));
@@ -2708,7 +2714,7 @@ void launch_row_iso_t(const RowArgs *args, const int *woff, int np, int total, c
             const size_t lds = sizeof(T) * (size_t)split_tb(FI) * N + sizeof(Vt<T>) * N;
             dispatch((row_iso_split<T, FI>), dim3(total), dim3(split_nt(FI)), lds, s, args, woff, np);
         } else {
-            const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + N);
+            const size_t lds = sizeof(Vt<T>) * ((size_t)iso_tb(FI) * N + tw_lds_entries(N, sizeof(Vt<T>)));
             dispatch((row_iso_fast<T, FI>), dim3(total), dim3(iso_nt(FI)), lds, s, args, woff, np);
         }
     }
@@ -3518,7 +3524,7 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     if (a.fast == 2) {
         const int fi = fast_index(a.f.n);
         if (fi >= 0 && kFastSched[fi].nst == 2) return es / 2 * (size_t)a.RP * a.f.n + es * a.f.n;
-        return es * ((size_t)a.RP * a.f.n + a.f.n);
+        return es * ((size_t)a.RP * a.f.n + tw_lds_entries(a.f.n, (int)es));
     }
     if (a.fast)
         return es * ((size_t)a.f.n * (a.mode == ROW_GRAM ? a.d * a.d : a.d) * a.RP +
