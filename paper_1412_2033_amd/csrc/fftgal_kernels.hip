@@ -363,10 +363,11 @@ __device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const V
     return Y;
 }
 
-// Deterministic work-group sum (fixed shuffle tree, then waves in order);
-// the result is valid in thread 0.
-__device__ double block_sum(double v) {
-    __shared__ double red[kThreads / 64];
+// Deterministic work-group sum (fixed shuffle tree, then waves in order) over
+// a work-group of at most NT threads; the result is valid in thread 0.
+template <int NT>
+__device__ double block_sum_t(double v) {
+    __shared__ double red[NT / 64];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -380,6 +381,7 @@ __device__ double block_sum(double v) {
     __syncthreads();
     return s;
 }
+__device__ double block_sum(double v) { return block_sum_t<kThreads>(v); }
 
 // K work-group sums at once, each in the order of block_sum (a shuffle tree
 // per wave, then the waves in turn), written to out[0 .. K-1] by the first K
@@ -1520,14 +1522,20 @@ __device__ __forceinline__ int find_problem(const int *__restrict__ woff, int np
     return lo;
 }
 
+// threads of the specialised strided-axis pass: 512 for the 2D FP64 pencils
+// of 2025 points (one pencil of both components per work-group: each stage of
+// the transform then takes one round of the threads instead of two), else 256
+constexpr int pencil_nt(int n, int es, int d) { return (es >= 16 && d == 2 && n >= 2025) ? 512 : kThreads; }
+
 template <typename T, int FI, int D>
-__global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__restrict__ pa,
-                                                        const int *__restrict__ woff, int np) {
+__global__ __launch_bounds__(pencil_nt(kFastSched[FI].n, sizeof(Vt<T>), D))
+void pencil_fast(const PencilArgs *__restrict__ pa, const int *__restrict__ woff, int np) {
     using V = Vt<T>;
     constexpr int N = kFastSched[FI].n;
+    constexpr int NT = pencil_nt(N, sizeof(V), D);
     constexpr int B = pencil_batch(N, sizeof(V), D);
     constexpr int NB = D * B;  // LDS layout [pos][component][batch]
-    constexpr int LPI = kThreads / NB;  // positions per step of the plain prologue / epilogue
+    constexpr int LPI = NT / NB;  // positions per step of the plain prologue / epilogue
     int lb;
     const PencilArgs &a = pa[find_problem(woff, np, &lb)];
     if (a.status != nullptr && a.status->done) return;
@@ -1540,7 +1548,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     const int o = lb / gx;
     const int b0 = (lb - o * gx) * B;
     const int nbw = min(B, a.nb - b0);
-    const V *tw = twiddles_to_lds<T, N>(X + N * NB, reinterpret_cast<const V *>(a.tw) + a.f.twoff[0]);
+    const V *tw = twiddles_to_lds<T, N, NT>(X + N * NB, reinterpret_cast<const V *>(a.tw) + a.f.twoff[0]);
     const T sg = T(a.sgn);
     const T scale = T(a.scale);
     const V zero = mk<T>(T(0), T(0));
@@ -1582,7 +1590,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
       // the CG vectors hold at most (N + 1) / 2 frequencies per axis (Ga), or N
       // (GaNi, transforms on the grid of the approximation order itself)
       auto expand = [&](auto cap) {
-        constexpr int PE = (decltype(cap)::value * B + kThreads - 1) / kThreads;
+        constexpr int PE = (decltype(cap)::value * B + NT - 1) / NT;
         const auto *sr = gbl(reinterpret_cast<const V *>(a.st_r));
         auto *sp = gbl(reinterpret_cast<V *>(a.st_p));
         const auto *sx = gbl(reinterpret_cast<const V *>(a.st_x));
@@ -1590,7 +1598,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
         T ax[PE][2], ay[PE][2], bx[PE][2], by[PE][2];
 #pragma unroll
         for (int t = 0; t < PE; ++t) {
-            const int idx = threadIdx.x + t * kThreads;
+            const int idx = threadIdx.x + t * NT;
             const int bb = idx % B;
             const int l = idx / B;
             const bool ok = idx < a.L_in * B && bb < nbw;
@@ -1606,10 +1614,10 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
                 by[t][c] = vb.y;
             }
         }
-        for (int idx = threadIdx.x; idx < (N - a.L_in) * NB; idx += kThreads) X[khi * NB + idx] = zero;
+        for (int idx = threadIdx.x; idx < (N - a.L_in) * NB; idx += NT) X[khi * NB + idx] = zero;
 #pragma unroll
         for (int t = 0; t < PE; ++t) {
-            const int idx = threadIdx.x + t * kThreads;
+            const int idx = threadIdx.x + t * NT;
             const int bb = idx % B;
             const int l = idx / B;
             if (idx >= a.L_in * B) continue;
@@ -1699,18 +1707,18 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
-    fft_ip<T, FI, 0, 1, 0, NB, false>(X, tw, sg);
+    fft_ip<T, FI, 0, 1, 0, NB, false, NT>(X, tw, sg);
     auto *out = gbl(reinterpret_cast<V *>(a.out));
     if (a.epi == EPI_PROJECT) {
       // the projected vector holds at most (N + 1) / 2 frequencies per axis (Ga) or N (GaNi)
       auto project = [&](auto cap) -> double {
-        constexpr int PE = (decltype(cap)::value * B + kThreads - 1) / kThreads;
+        constexpr int PE = (decltype(cap)::value * B + NT - 1) / NT;
         const auto *dv = gbl(reinterpret_cast<const V *>(a.st_dot));
         T dx[PE][2], dy[PE][2];
         if (a.st_dot != nullptr) {
 #pragma unroll
             for (int t = 0; t < PE; ++t) {
-                const int idx = threadIdx.x + t * kThreads;
+                const int idx = threadIdx.x + t * NT;
                 const int bb = idx % B;
                 const int l = idx / B;
                 const bool ok = idx < a.L_out * B && bb < nbw;
@@ -1726,7 +1734,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
         double part = 0.0;
 #pragma unroll
         for (int t = 0; t < PE; ++t) {
-            const int idx = threadIdx.x + t * kThreads;
+            const int idx = threadIdx.x + t * NT;
             const int bb = idx % B;
             const int l = idx / B;
             if (idx >= a.L_out * B || bb >= nbw) continue;
@@ -1777,7 +1785,7 @@ __global__ __launch_bounds__(kThreads) void pencil_fast(const PencilArgs *__rest
       };
       const double part = (2 * a.L_out <= N + 1) ? project(std::integral_constant<int, (N + 1) / 2>{})
                                                  : project(std::integral_constant<int, N>{});
-        const double s = block_sum(part);
+        const double s = block_sum_t<NT>(part);
         if (threadIdx.x == 0) a.partial[lb] = s;
     } else {
         const int rr = threadIdx.x % NB;
@@ -2653,7 +2661,7 @@ void launch_pencil_fast_t(const PencilArgs *args, const int *woff, int np, int t
     constexpr int N = kFastSched[FI].n;
     constexpr int B = pencil_batch(N, sizeof(Vt<T>), D);
     const size_t lds = sizeof(Vt<T>) * ((size_t)N * D * B + tw_lds_entries(N, sizeof(Vt<T>)));
-    dispatch((pencil_fast<T, FI, D>), dim3(total), dim3(kThreads), lds, s, args, woff, np);
+    dispatch((pencil_fast<T, FI, D>), dim3(total), dim3(pencil_nt(N, sizeof(Vt<T>), D)), lds, s, args, woff, np);
 }
 
 template <typename T, int FI, int D>
