@@ -176,3 +176,32 @@ def test_solo_in_a_mixed_batch_equals_alone(fg):
             pl.close()
         b.close()
         torch.cuda.synchronize()
+
+
+def test_solo_history_and_bound_tolerance_match_separate_passes(fg):
+    # the energy history (fftgal_history) and the bound-tolerance stop run
+    # inside the solver: the same iterates' energies and stopping iterations
+    # as the per-pass kernels, to rounding
+    micro = synth.circle_inclusion_vf(0.3, 1.0, 200.0, center=(0.05, -0.1))
+    N = (41, 41)
+    out = {}
+    for sep in (False, True):
+        plan = fg.Plan(2, N, "fp64", separate_passes=sep)
+        try:
+            plan.run(micro, rtol=1e-10)
+            hist = [plan.history(k, a) for k in (0, 1) for a in range(2)]
+            plan.set_bound_tol(1e-6)
+            res = plan.run(micro, rtol=1e-12)
+            its = [i["iters"] for i in res["info_primal"] + res["info_dual"]]
+            out[sep] = (hist, its, res)
+        finally:
+            plan.close()
+    for h0, h1 in zip(out[False][0], out[True][0]):
+        assert len(h0) == len(h1)
+        np.testing.assert_allclose(h0, h1, rtol=1e-11)
+    assert all(abs(a - b) <= 1 for a, b in zip(out[False][1], out[True][1]))
+    ref = ga.ga_bounds(material.make_material(micro), N, tol=1e-12, track_energy=True)
+    up = np.asarray(out[False][2]["upper"])
+    for a in range(2):
+        k = out[False][2]["info_primal"][a]["iters"]
+        assert abs(up[a, a] - ref["energies_primal"][a][k]) <= 1e-9 * up[a, a]

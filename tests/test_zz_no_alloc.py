@@ -55,6 +55,9 @@ CALLS = [
     (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0, center=(0.1, 0.0)), (63, 63), "fp64", 1e-10),
     (lambda: synth.grf_voxels(3, (25, 25, 25), d=3, corr_len=0.1), (13, 13, 13), "fp32", 5e-6),
     (lambda: synth.square_inclusion(2, 0.6, 1.0, 10.0), (21, 21), "fp64", 1e-10),
+    # grids of the single work-group solver (its arguments in the plan's slots)
+    (lambda: synth.circle_inclusion_vf(0.3, 1.0, 100.0), (41, 41), "fp64", 1e-10),
+    (lambda: synth.square_inclusion(2, 0.5, 1.0, 10.0), (41, 63), "fp32", 5e-6),
 ]
 
 
