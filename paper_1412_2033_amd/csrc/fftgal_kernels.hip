@@ -1484,12 +1484,18 @@ constexpr int fast_batch(int n, int es, int d) {
 
 // pencils per work-group of the specialised strided-axis pass: one batch of
 // all d components within 24 KB of LDS, or 48 KB for 3D FP64 transforms of
-// 225 points or more.  There the larger batch keeps more of the work-group
-// busy in the butterfly stages and lengthens the contiguous runs of the
-// strided operands; elsewhere (FP32, 2D, shorter 3D transforms) the smaller
-// work-groups, more of them per CU, measured faster.
+// more than 225 points, where the larger batch keeps more of the work-group
+// busy in the butterfly stages; elsewhere (2D, shorter 3D transforms) the
+// smaller work-groups, more of them per CU, measured faster.  The 3D
+// transforms of 225 points (order 113) take tiles sized to the rounds of
+// resident work-groups, set by the axis-1 passes and their 113 x 57 pencils:
+// in FP32, 9 pencils (50 KB of LDS, three work-groups per CU) make 716
+// tiles, one round of the 768 work-groups that fit at once; in FP64 (twice
+// the bytes, more than all LDS of the chip holds) 7 pencils (79 KB, two per
+// CU) make 921 tiles, under two rounds of 512.
 constexpr int pencil_batch(int n, int es, int d) {
-    const int cap = (es >= 16 && d == 3 && n >= 225) ? 48 * 1024 : 24 * 1024;
+    if (d == 3 && n == 225) return es >= 16 ? 7 : 9;
+    const int cap = (es >= 16 && d == 3 && n > 225) ? 48 * 1024 : 24 * 1024;
     int b = 16;
     while (b > 1 && d * b * n * es > cap) b /= 2;
     return b;
@@ -1523,9 +1529,12 @@ __device__ __forceinline__ int find_problem(const int *__restrict__ woff, int np
 }
 
 // threads of the specialised strided-axis pass: 512 for the 2D FP64 pencils
-// of 2025 points (one pencil of both components per work-group: each stage of
-// the transform then takes one round of the threads instead of two), else 256
-constexpr int pencil_nt(int n, int es, int d) { return (es >= 16 && d == 2 && n >= 2025) ? 512 : kThreads; }
+// of 2025 points (one pencil of both components per work-group) and for the
+// 3D tiles of 225 points (315 or 405 transforms of 15 points per stage), so
+// that every stage of the transform takes one round of the threads; else 256
+constexpr int pencil_nt(int n, int es, int d) {
+    return ((es >= 16 && d == 2 && n >= 2025) || (d == 3 && n == 225)) ? 512 : kThreads;
+}
 
 template <typename T, int FI, int D>
 __global__ __launch_bounds__(pencil_nt(kFastSched[FI].n, sizeof(Vt<T>), D))
