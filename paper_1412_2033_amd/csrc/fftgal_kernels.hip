@@ -1331,15 +1331,14 @@ __global__ void d2f_kernel(float *dst, const double *src, size_t n) {
         dst[i] = (float)src[i];
 }
 
-// out[v] = sum_i part[i * nvals + v] in a fixed order (one work-group).
+// out[v] = sum_i part[i * nvals + v] in a fixed order (work-group v).
 __global__ __launch_bounds__(kThreads) void sum_partials_kernel(double *out, const double *part, int nparts,
                                                                 int nvals) {
-    for (int v = 0; v < nvals; ++v) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[(long)i * nvals + v];
-        s = block_sum(s);
-        if (threadIdx.x == 0) out[v] = s;
-    }
+    const int v = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[(long)i * nvals + v];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[v] = s;
 }
 
 // Fourier coefficients on the half grid of Z_{L} (L = 2N-1): entry
@@ -1492,9 +1491,13 @@ constexpr int fast_batch(int n, int es, int d) {
 // in FP32, 9 pencils (50 KB of LDS, three work-groups per CU) make 716
 // tiles, one round of the 768 work-groups that fit at once; in FP64 (twice
 // the bytes, more than all LDS of the chip holds) 7 pencils (79 KB, two per
-// CU) make 921 tiles, under two rounds of 512.
+// CU) make 921 tiles, under two rounds of 512.  The 2D FP32 transforms of 729
+// points (order 365) take 3 pencils with 512 threads (486 of the 2 x 3 x 81
+// radix-9 butterflies busy in one round, against two rounds for 2 pencils and
+// 256 threads): a batch of 16 such solves 7 % faster.
 constexpr int pencil_batch(int n, int es, int d) {
     if (d == 3 && n == 225) return es >= 16 ? 7 : 9;
+    if (es < 16 && d == 2 && n == 729) return 3;
     const int cap = (es >= 16 && d == 3 && n > 225) ? 48 * 1024 : 24 * 1024;
     int b = 16;
     while (b > 1 && d * b * n * es > cap) b /= 2;
@@ -1529,11 +1532,14 @@ __device__ __forceinline__ int find_problem(const int *__restrict__ woff, int np
 }
 
 // threads of the specialised strided-axis pass: 512 for the 2D FP64 pencils
-// of 2025 points (one pencil of both components per work-group) and for the
-// 3D tiles of 225 points (315 or 405 transforms of 15 points per stage), so
-// that every stage of the transform takes one round of the threads; else 256
+// of 2025 points (one pencil of both components per work-group), the 2D FP32
+// tiles of 729 points and the 3D tiles of 225 points (315 or 405 transforms of
+// 15 points per stage), so that every stage of the transform takes one round
+// of the threads; else 256
 constexpr int pencil_nt(int n, int es, int d) {
-    return ((es >= 16 && d == 2 && n >= 2025) || (d == 3 && n == 225)) ? 512 : kThreads;
+    return ((es >= 16 && d == 2 && n >= 2025) || (es < 16 && d == 2 && n == 729) || (d == 3 && n == 225))
+               ? 512
+               : kThreads;
 }
 
 template <typename T, int FI, int D>
@@ -3919,7 +3925,8 @@ hipError_t launch_convert_d2f(float *dst, const double *src, size_t n, hipStream
 }
 
 hipError_t launch_sum_partials(double *out, const double *part, int nparts, int nvals, hipStream_t s) {
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kThreads), 0, s, out, part, nparts, nvals);
+    if (nvals < 1) return hipSuccess;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(nvals), dim3(kThreads), 0, s, out, part, nparts, nvals);
     return hipGetLastError();
 }
 
