@@ -393,8 +393,8 @@ struct fftgal_plan {
     size_t so(size_t off) const { return off + (size_t)slot * Lo.slot_bytes; }
     std::vector<unsigned char> margs_host;  // staging of the multi-shift argument tables
     int ring = 0;
-    unsigned char ring_host[kRingSlots][kArgSlot];
-    unsigned char iter_host[kIterSlots][kArgSlot];
+    unsigned char ring_host[kRingSlots][kArgSlot] = {};
+    unsigned char iter_host[kIterSlots][kArgSlot] = {};  // host images of the iteration slots
     char *arg_slot(int i) { return ws + Lo.args + kArgSlot * (size_t)i; }  // 0: offsets {0}
     char *iter_slot(int i) { return arg_slot(2 + i); }
     char *ring_slot(int i) { return arg_slot(2 + kIterSlots + i); }
@@ -1174,19 +1174,23 @@ int upload_iteration(Plan *pl, const IterCfg &cfg) {
     if (mused > 0)
         HIPCHECK(pl, hipMemcpyAsync(pl->ws + pl->Lo.margs, pl->margs_host.data(), mused, hipMemcpyHostToDevice,
                                     pl->stream));
+    // every write to an iteration slot goes through its host image, so the
+    // slots of the passes go up in one copy (slots of passes that take their
+    // arguments elsewhere carry their previous, unread contents), and the
+    // update and CG item in a second
     for (size_t i = 0; i < cfg.passes.size(); ++i) {
         const PassRec &r = cfg.passes[i];
         const bool fast = r.type == 0 ? r.pa.fast : r.ra.fast;
         if (!fast || r.np > 1) continue;
         const size_t sz = r.type == 0 ? sizeof(PencilArgs) : sizeof(RowArgs);
         std::memcpy(pl->iter_host[i], r.type == 0 ? (const void *)&r.pa : (const void *)&r.ra, sz);
-        HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot((int)i), pl->iter_host[i], sz, hipMemcpyHostToDevice, pl->stream));
     }
+    if (!cfg.passes.empty())
+        HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(0), pl->iter_host[0], cfg.passes.size() * kArgSlot,
+                                    hipMemcpyHostToDevice, pl->stream));
     std::memcpy(pl->iter_host[kMaxPasses], &cfg.upd, sizeof(UpdArgs));
     std::memcpy(pl->iter_host[kMaxPasses + 1], &cfg.item, sizeof(CgItem));
-    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(kMaxPasses), pl->iter_host[kMaxPasses], sizeof(UpdArgs),
-                                hipMemcpyHostToDevice, pl->stream));
-    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(kMaxPasses + 1), pl->iter_host[kMaxPasses + 1], sizeof(CgItem),
+    HIPCHECK(pl, hipMemcpyAsync(pl->iter_slot(kMaxPasses), pl->iter_host[kMaxPasses], 2 * kArgSlot,
                                 hipMemcpyHostToDevice, pl->stream));
     return FFTGAL_OK;
 }
