@@ -33,6 +33,14 @@ CASES = [
     ("circles2d_N63_fp32", lambda: synth.random_circles(5), (63, 63), "fp32", 1e-7),
     ("aniso3d_N23_fp32", lambda: synth.cube_inclusion_aniso(0.45, 4), (23, 23, 23), "fp32", 5e-6),
     ("vox3d_N21_fp64", lambda: synth.grf_voxels(6, (41, 41, 41), d=3, corr_len=0.1), (21, 21, 21), "fp64", 1e-9),
+    # the 225-point tiles of both strided passes (7 FP64 / 9 FP32 pencils,
+    # ragged at these pencil counts) and the 729-point FP32 tiles, several
+    # problems per launch
+    ("vox3d_N113x113x5_fp64", lambda: synth.grf_voxels(8, (225, 225, 9), d=3, corr_len=0.1), (113, 113, 5),
+     "fp64", 1e-9),
+    ("vox3d_N113x113x5_fp32", lambda: synth.grf_voxels(8, (225, 225, 9), d=3, corr_len=0.1), (113, 113, 5),
+     "fp32", 5e-6),
+    ("circles2d_N365_fp32", lambda: synth.random_circles(9, contrast=30.0), (365, 365), "fp32", 5e-6),
 ]
 
 
