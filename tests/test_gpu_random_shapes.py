@@ -1,0 +1,108 @@
+"""First-order GPU parity on seeded random shapes: orders, materials and plan
+options drawn at random, compared entry by entry with the oracle.
+
+Each case draws d, an odd order per axis (small enough for the oracle), a
+material (isotropic square or disc inclusions, an anisotropic cube, a scalar
+voxel image at a voxel resolution P that may differ from the double grid and
+need not be 3,5,7-smooth, multi-phase anisotropic inclusions or a matrix
+voxel image) and the plan flags (concurrent solves, matrix fields, the
+per-pass kernels for small 2D grids).  Every primal and dual solve stops
+after K conjugate-gradient steps (rtol 0), so the bounds are first order in
+the operator (Remark CG: the iterate is a fixed Krylov polynomial), and each
+entry must match the oracle's bounds of the same iterates (Prop.
+struct_bounds) to 1e-11 of the reference norm.  The draws cover the generic
+transform kernels at many odd lengths, Bluestein lengths of the voxel setup
+and ragged batches of every pass.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ga, material
+
+K = 6
+N2 = (1, 3, 5, 7, 9, 11, 13, 15, 17, 19, 21, 25, 27, 31)
+N3 = (1, 3, 5, 7, 9, 11)
+KINDS2 = ("square", "disc", "aniso", "vox", "multi", "poly")
+KINDS3 = ("square", "aniso", "vox", "multi", "poly")
+
+
+def _draw(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = 2 if rng.random() < 0.55 else 3
+    N = tuple(int(rng.choice(N2 if d == 2 else N3)) for _ in range(d))
+    if max(N) < 3:  # at least one axis with a nonzero frequency
+        N = (3,) + N[1:]
+    kind = str(rng.choice(KINDS2 if d == 2 else KINDS3))
+    M = tuple(2 * n - 1 for n in N)
+    c = float(10.0 ** rng.uniform(0.5, 2.5))
+    if kind == "square":
+        micro = synth.square_inclusion(d, float(rng.uniform(0.2, 0.7)), 1.0, c,
+                                       center=rng.uniform(-0.2, 0.2, size=d))
+    elif kind == "disc":
+        micro = synth.circle_inclusion_vf(float(rng.uniform(0.1, 0.5)), 1.0, c,
+                                          center=rng.uniform(-0.2, 0.2, size=2))
+    elif kind == "aniso":
+        micro = synth.cube_inclusion_aniso(float(rng.uniform(0.3, 0.6)), int(rng.integers(1, 1000)), d=d)
+    elif kind == "vox":
+        P = tuple(int(m if rng.random() < 0.5 else 2 * rng.integers(2, m + 2) + 1) for m in M)
+        micro = synth.grf_voxels(int(rng.integers(1, 1000)), P, d=d, corr_len=0.15,
+                                 vf=float(rng.uniform(0.2, 0.6)), a_matrix=1.0, a_incl=c)
+    elif kind == "multi":
+        micro = synth.multiphase_aniso(int(rng.integers(1, 1000)), d=d, n=int(rng.integers(1, 4)))
+    else:
+        P = tuple(int(2 * rng.integers(2, m + 2) + 1) for m in M)
+        micro = synth.polycrystal(int(rng.integers(1, 1000)), P, d=d, n_grains=int(rng.integers(2, 7)))
+    opts = {"concurrent": bool(rng.random() < 0.4)}
+    if kind in ("multi", "poly"):
+        opts["tensor"] = True
+    if d == 2 and rng.random() < 0.3:
+        opts["separate_passes"] = True
+    return N, kind, micro, opts
+
+
+SEEDS = list(range(101, 131))
+
+
+@pytest.fixture(scope="module")
+def fg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_2033_amd import fftgal
+    fftgal.load_library()
+    return fftgal
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_shape_truncated_matches_oracle(fg, seed):
+    N, kind, micro, opts = _draw(seed)
+    print("random case seed=%d N=%s %s %s" % (seed, N, kind, opts), flush=True)
+    plan = fg.Plan(len(N), N, "fp64", P=micro.get("P"), **opts)
+    try:
+        res = plan.run(micro, rtol=0.0, maxit=K)
+    finally:
+        plan.close()
+    ref = ga.ga_bounds(material.make_material(micro), N, tol=0.0, maxit=K)
+    assert [i["iters"] for i in res["info_primal"]] == ref["iters_primal"]
+    assert [i["iters"] for i in res["info_dual"]] == ref["iters_dual"]
+    for key in ("upper", "lower"):
+        a = np.asarray(res[key])
+        b = np.asarray(ref[key])
+        err = np.max(np.abs(a - b)) / np.linalg.norm(b)
+        print("  %s: max entry error %.2e of |ref|" % (key, err))
+        assert err < 1e-11, (key, err, a, b)
+
+
+def test_draws_cover_the_options():
+    # the seeded draws exercise every material kind, both dimensions and every flag
+    draws = [_draw(s) for s in SEEDS]
+    kinds = {k for _, k, _, _ in draws}
+    assert kinds == set(KINDS2)
+    assert {len(N) for N, _, _, _ in draws} == {2, 3}
+    assert any(o["concurrent"] for _, _, _, o in draws)
+    assert any(o.get("separate_passes") for _, _, _, o in draws)
+    assert any(m.get("P") is not None and tuple(m["P"]) != tuple(2 * n - 1 for n in N)
+               for N, _, m, _ in draws)
