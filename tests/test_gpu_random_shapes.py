@@ -12,7 +12,10 @@ the operator (Remark CG: the iterate is a fixed Krylov polynomial), and each
 entry must match the oracle's bounds of the same iterates (Prop.
 struct_bounds) to 1e-11 of the reference norm.  The draws cover the generic
 transform kernels at many odd lengths, Bluestein lengths of the voxel setup
-and ragged batches of every pass.
+and ragged batches of every pass.  The FP32-iteration form runs the same
+draws at low contrast (at most 10, where FP32 rounding of two CG steps stays
+far below the tolerance) and after K32 steps must match the FP64 run of the
+same steps to 1e-7.
 """
 
 import numpy as np
@@ -22,13 +25,14 @@ import synth
 from oracle import ga, material
 
 K = 6
+K32 = 2
 N2 = (1, 3, 5, 7, 9, 11, 13, 15, 17, 19, 21, 25, 27, 31)
 N3 = (1, 3, 5, 7, 9, 11)
 KINDS2 = ("square", "disc", "aniso", "vox", "multi", "poly")
 KINDS3 = ("square", "aniso", "vox", "multi", "poly")
 
 
-def _draw(seed):
+def _draw(seed, low_contrast=False):
     rng = np.random.Generator(np.random.PCG64(seed))
     d = 2 if rng.random() < 0.55 else 3
     N = tuple(int(rng.choice(N2 if d == 2 else N3)) for _ in range(d))
@@ -37,6 +41,8 @@ def _draw(seed):
     kind = str(rng.choice(KINDS2 if d == 2 else KINDS3))
     M = tuple(2 * n - 1 for n in N)
     c = float(10.0 ** rng.uniform(0.5, 2.5))
+    if low_contrast:
+        c = 1.0 + c % 9.0
     if kind == "square":
         micro = synth.square_inclusion(d, float(rng.uniform(0.2, 0.7)), 1.0, c,
                                        center=rng.uniform(-0.2, 0.2, size=d))
@@ -44,16 +50,22 @@ def _draw(seed):
         micro = synth.circle_inclusion_vf(float(rng.uniform(0.1, 0.5)), 1.0, c,
                                           center=rng.uniform(-0.2, 0.2, size=2))
     elif kind == "aniso":
-        micro = synth.cube_inclusion_aniso(float(rng.uniform(0.3, 0.6)), int(rng.integers(1, 1000)), d=d)
+        sd = int(rng.integers(1, 1000))
+        micro = synth.cube_inclusion_aniso(float(rng.uniform(0.3, 0.6)), sd, d=d)
+        if low_contrast:
+            micro["A_in"] = synth.random_spd(sd, d, 0.0, 1.0).reshape(1, d, d)
     elif kind == "vox":
         P = tuple(int(m if rng.random() < 0.5 else 2 * rng.integers(2, m + 2) + 1) for m in M)
         micro = synth.grf_voxels(int(rng.integers(1, 1000)), P, d=d, corr_len=0.15,
                                  vf=float(rng.uniform(0.2, 0.6)), a_matrix=1.0, a_incl=c)
     elif kind == "multi":
-        micro = synth.multiphase_aniso(int(rng.integers(1, 1000)), d=d, n=int(rng.integers(1, 4)))
+        hi = 1.0 if low_contrast else 2.0
+        micro = synth.multiphase_aniso(int(rng.integers(1, 1000)), d=d, n=int(rng.integers(1, 4)), log10_hi=hi)
     else:
         P = tuple(int(2 * rng.integers(2, m + 2) + 1) for m in M)
-        micro = synth.polycrystal(int(rng.integers(1, 1000)), P, d=d, n_grains=int(rng.integers(2, 7)))
+        hi = 1.0 if low_contrast else 2.0
+        micro = synth.polycrystal(int(rng.integers(1, 1000)), P, d=d, n_grains=int(rng.integers(2, 7)),
+                                  log10_hi=hi)
     opts = {"concurrent": bool(rng.random() < 0.4)}
     if kind in ("multi", "poly"):
         opts["tensor"] = True
@@ -94,6 +106,31 @@ def test_random_shape_truncated_matches_oracle(fg, seed):
         err = np.max(np.abs(a - b)) / np.linalg.norm(b)
         print("  %s: max entry error %.2e of |ref|" % (key, err))
         assert err < 1e-11, (key, err, a, b)
+
+
+def _run(fg, micro, N, precision, k, opts):
+    plan = fg.Plan(len(N), N, precision, P=micro.get("P"), **opts)
+    try:
+        return plan.run(micro, rtol=0.0, maxit=k)
+    finally:
+        plan.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_shape_fp32_matches_fp64(fg, seed):
+    N, kind, micro, opts = _draw(seed, low_contrast=True)
+    print("random fp32 case seed=%d N=%s %s %s" % (seed, N, kind, opts), flush=True)
+    r64 = _run(fg, micro, N, "fp64", K32, opts)
+    r32 = _run(fg, micro, N, "fp32", K32, opts)
+    assert [i["iters"] for i in r32["info_primal"] + r32["info_dual"]] == \
+        [i["iters"] for i in r64["info_primal"] + r64["info_dual"]]
+    for key in ("upper", "lower"):
+        a = np.asarray(r32[key])
+        b = np.asarray(r64[key])
+        err = np.max(np.abs(a - b)) / np.linalg.norm(b)
+        print("  %s: max entry error %.2e of |fp64|" % (key, err))
+        assert err < 1e-7, (key, err, a, b)
 
 
 def test_draws_cover_the_options():
