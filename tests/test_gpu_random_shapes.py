@@ -15,14 +15,17 @@ transform kernels at many odd lengths, Bluestein lengths of the voxel setup
 and ragged batches of every pass.  The FP32-iteration form runs the same
 draws at low contrast (at most 10, where FP32 rounding of two CG steps stays
 far below the tolerance) and after K32 steps must match the FP64 run of the
-same steps to 1e-7.
+same steps to 1e-7.  Draws with scalar materials also run as reduced-Ga plans
+(Lemma reduce_grid; first order against the oracle's reduced Ga) and as GaNi
+plans (Def. GaNi; converged, against the oracle's GaNi, and lower = upper for
+odd N by Remark duality_gani).
 """
 
 import numpy as np
 import pytest
 
 import synth
-from oracle import ga, material
+from oracle import ga, gani, material, reduced
 
 K = 6
 K32 = 2
@@ -131,6 +134,60 @@ def test_random_shape_fp32_matches_fp64(fg, seed):
         err = np.max(np.abs(a - b)) / np.linalg.norm(b)
         print("  %s: max entry error %.2e of |fp64|" % (key, err))
         assert err < 1e-7, (key, err, a, b)
+
+
+def _draw_scalar(seed):
+    # the reduced Ga and GaNi plans: scalar materials (inclusions with one
+    # matrix each are reduced to the two-phase / isotropic classes by the
+    # draw), orders >= 3 on every axis, no matrix-field or concurrent flags
+    N, kind, micro, opts = _draw(seed)
+    N = tuple(max(n, 3) for n in N)
+    if kind in ("multi", "poly"):
+        M = tuple(2 * n - 1 for n in N)
+        micro = synth.grf_voxels(seed, M, d=len(N), corr_len=0.15, vf=0.4, a_matrix=1.0, a_incl=30.0)
+        kind = "vox"
+    return N, kind, micro
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", SEEDS[:15])
+def test_random_shape_reduced_truncated_matches_oracle(fg, seed):
+    # Lemma reduce_grid: the operator on the N-grid with 2^d shifted
+    # transforms (Bluestein at the orders that are not 3,5,7-smooth)
+    N, kind, micro = _draw_scalar(seed)
+    print("random reduced case seed=%d N=%s %s" % (seed, N, kind), flush=True)
+    plan = fg.Plan(len(N), N, "fp64", P=micro.get("P"), scheme="reduced")
+    try:
+        res = plan.run(micro, rtol=0.0, maxit=K)
+    finally:
+        plan.close()
+    ref = reduced.reduced_bounds(material.make_material(micro), N, tol=0.0, maxit=K)
+    for key in ("upper", "lower"):
+        b = np.asarray(ref[key])
+        err = np.max(np.abs(np.asarray(res[key]) - b)) / np.linalg.norm(b)
+        print("  %s: max entry error %.2e of |ref|" % (key, err))
+        assert err < 1e-11, (key, err)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", SEEDS[15:])
+def test_random_shape_gani_matches_oracle(fg, seed):
+    # Def. GaNi (material sampled on the grid of the order N), converged;
+    # duality of the two GaNi values for odd N (Remark duality_gani)
+    N, kind, micro = _draw_scalar(seed)
+    print("random gani case seed=%d N=%s %s" % (seed, N, kind), flush=True)
+    plan = fg.Plan(len(N), N, "fp64", P=micro.get("P"), scheme="gani")
+    try:
+        res = plan.run(micro, rtol=1e-11)
+    finally:
+        plan.close()
+    ref = gani.gani(micro, N, tol=1e-11)
+    up = np.asarray(res["upper"])
+    lo = np.asarray(res["lower"])
+    assert np.linalg.norm(up - ref["A_gani"]) <= 1e-10 * np.linalg.norm(ref["A_gani"])
+    Bi = np.linalg.inv(ref["B_gani"])
+    assert np.linalg.norm(lo - Bi) <= 1e-10 * np.linalg.norm(Bi)
+    assert np.linalg.norm(lo - up) <= 1e-9 * np.linalg.norm(up)
 
 
 def test_draws_cover_the_options():
