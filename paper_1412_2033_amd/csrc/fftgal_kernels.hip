@@ -296,7 +296,7 @@ __device__ __forceinline__ void stage(const Vt<T> *X, Vt<T> *Y, int n, int p, in
 // The stages of a transform of length f.L in LDS, ping-ponging between A and
 // Bf; returns the buffer holding the result.
 template <typename T, bool ROWL>
-__device__ Vt<T> *fft_stages(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
+__device__ __forceinline__ Vt<T> *fft_stages(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
     Vt<T> *X = A;
     Vt<T> *Y = Bf;
     int p = 1;
@@ -325,7 +325,7 @@ __device__ Vt<T> *fft_stages(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, cons
 // pos nb + b); returns the buffer holding the result.  Must be called by
 // every thread of the work-group.
 template <typename T, bool ROWL>
-__device__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
+__device__ __forceinline__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
     if (!f.blue) return fft_stages<T, ROWL>(A, Bf, f, nb, tw, sg);
     // Bluestein: u_j = x_j c_j zero-padded to L, H (.) DFT^- u, DFT^+, times c_k
     const int n = f.n, L = f.L;
@@ -469,8 +469,16 @@ __device__ __forceinline__ double sinc_pi(double x) {
 // ---------------------------------------------------------------------------
 // Pencil pass: batched DFT along a strided axis.
 // ---------------------------------------------------------------------------
+// t[al] for a runtime component al < 3 without indexing a private array
 template <typename T>
-__global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
+__device__ __forceinline__ T pick3(const T *t, int al) {
+    return al == 0 ? t[0] : (al == 1 ? t[1] : t[2]);
+}
+
+// two waves per SIMD: the radix-25 stage alone would take the register
+// file of one
+template <typename T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void pencil_kernel(PencilArgs a) {
     using V = Vt<T>;
     if (a.status != nullptr && a.status->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
@@ -538,10 +546,13 @@ __global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
                     T t[2][3];
                     const int nt = basis<T>(a.d, a.kind, k1, k2, k3, t);
                     T ex = T(0), ey = T(0);
-                    for (int c = 0; c < nt; ++c) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        if (c >= nt) break;
                         const V cv = acc[(c * a.L_in + l) * B + bb];
-                        ex -= t[c][al] * cv.y;  // i * t * c
-                        ey += t[c][al] * cv.x;
+                        const T tc = pick3<T>(t[c], al);
+                        ex -= tc * cv.y;  // i * t * c
+                        ey += tc * cv.x;
                     }
                     if (has_shift(a)) {
                         double pc, ps;
@@ -602,9 +613,11 @@ __global__ __launch_bounds__(kThreads) void pencil_kernel(PencilArgs a) {
                 T t[2][3];
                 const int nt = basis<T>(a.d, a.kind, k1, k2, k3, t);
                 const V y = res[posmod(k1, n) * B + bb];
-                for (int c = 0; c < nt; ++c) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (c >= nt) break;
                     V &q = acc[(c * a.L_out + l) * B + bb];
-                    const T tt = t[c][al] * scale;
+                    const T tt = pick3<T>(t[c], al) * scale;
                     q.x += tt * y.y;
                     q.y -= tt * y.x;
                 }
@@ -839,7 +852,7 @@ __device__ __forceinline__ void sym_load(const T *g, long stride, long pt, int d
 // ---------------------------------------------------------------------------
 // Row pass: real transforms along the last axis, two rows per complex DFT.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int DIM>
 __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     using V = Vt<T>;
     if (a.status != nullptr && a.status->done) return;
@@ -857,7 +870,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     const int npairs_total = (a.nrows + 1) / 2;
     const int nvp = min(RP, npairs_total - pair0);
     const V zero = mk<T>(T(0), T(0));
-    const int d = a.d;
+    constexpr int d = DIM;  // the material and field loops unroll (no private arrays)
     const int nzc = (a.mode == ROW_RHS || a.mode == ROW_R2C) ? (a.mode == ROW_RHS ? d : 1) : a.ncomp;
 
     auto zbuf = [&](int c) { return Z + (size_t)c * RP * ln; };
@@ -3659,10 +3672,17 @@ hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t
 hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s) {
     if (a.RP < 1 || a.fast) return hipErrorInvalidValue;
     const size_t lds = row_lds_bytes(a, fp64);
+    if (a.d != 2 && a.d != 3) return hipErrorInvalidValue;
     if (fp64) {
-        hipLaunchKernelGGL(row_kernel<double>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);
+        if (a.d == 3)
+            hipLaunchKernelGGL((row_kernel<double, 3>), dim3(row_grid(a)), dim3(kThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((row_kernel<double, 2>), dim3(row_grid(a)), dim3(kThreads), lds, s, a);
     } else {
-        hipLaunchKernelGGL(row_kernel<float>, dim3(row_grid(a)), dim3(kThreads), lds, s, a);
+        if (a.d == 3)
+            hipLaunchKernelGGL((row_kernel<float, 3>), dim3(row_grid(a)), dim3(kThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((row_kernel<float, 2>), dim3(row_grid(a)), dim3(kThreads), lds, s, a);
     }
     return hipGetLastError();
 }
