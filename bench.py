@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--reduced-prime", type=int, default=113,
                     help="N of the reduced-Ga section at an order that is not 3,5,7-smooth (Bluestein "
                          "transforms; default the benchmark order 113; 0: skip)")
+    ap.add_argument("--fast-grid", type=int, default=1,
+                    help="FFTGAL_FAST_GRID against the default grid at 3D N = 81 and 2D N = 201 (0: skip)")
     ap.add_argument("--envelope", type=int, default=1,
                     help="upper-upper / lower-lower bounds section on an anisotropic cube inclusion (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -220,6 +222,7 @@ def main():
     args = ap.parse_args()
     if args.main_only:
         args.serve = args.serve3d = args.gani = args.warm_coarse = args.reduced = args.reduced_prime = 0
+        args.fast_grid = 0
         args.equal_accuracy = 0
         args.envelope = args.aniso = args.sweep2d = 0
     if args.gpus != 1:
@@ -387,6 +390,8 @@ def main():
     if args.reduced_prime > 0:
         out["reduced_bluestein"] = reduced_bench(fftgal, micro_dev, d, M, args.reduced_prime, rtol64, dev,
                                                  variants=("reduced", "reduced_lean"))
+    if args.fast_grid:
+        out["fast_grid"] = fast_grid_bench(fftgal, micro_dev, d, M, dev)
     if args.envelope:
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.aniso:
@@ -564,6 +569,43 @@ def reduced_bench(fftgal, micro_dev, d, P, Nr, rtol, dev, variants=("reduced", "
     out["bound_rel_diff"] = max(
         float(np.linalg.norm(res[v][k] - res["ga"][k]) / np.linalg.norm(res["ga"][k]))
         for v in variants for k in ("upper", "lower"))
+    return out
+
+
+def fast_grid_bench(fftgal, micro_dev, d, P, dev, N3=81, N2=201):
+    """FFTGAL_FAST_GRID against the default grid: the benchmark image at 3D
+    order N3 (default double grid 175^3, generic kernels; fast 225^3) and the
+    2D disc at order N2 (405^2 against 729^2), FP64."""
+    import numpy as np
+    import synth
+    import torch
+    print("bench: fast grid 3D N=%d, 2D N=%d" % (N3, N2), file=sys.stderr, flush=True)
+    cases = (("3d", (N3,) * d, micro_dev, P, 1e-8),
+             ("2d", (N2, N2), synth.circle_inclusion_vf(0.3, 1.0, 100.0), None, 1e-10))
+    out = {}
+    for tag, Nt, micro, Pm, rtol in cases:
+        res = {}
+        sec = {"N": Nt[0], "rtol": rtol}
+        for fast in (False, True):
+            plan = fftgal.Plan(len(Nt), Nt, "fp64", device=dev, P=Pm, fast_grid=fast)
+            try:
+                plan.run(micro, rtol=rtol)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = plan.run(micro, rtol=rtol)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                grid = list(plan.M)
+            finally:
+                plan.close()
+            res[fast] = r
+            sec["fast_grid" if fast else "default"] = {
+                "time_to_bounds_s": round(el, 4), "grid": grid, "workspace_bytes": plan.nbytes,
+                "cg_iterations": sum(i["iters"] for i in r["info_primal"] + r["info_dual"])}
+        sec["speedup"] = round(sec["default"]["time_to_bounds_s"] / sec["fast_grid"]["time_to_bounds_s"], 2)
+        sec["bound_rel_diff"] = max(float(np.linalg.norm(res[True][k] - res[False][k]) / np.linalg.norm(res[False][k]))
+                                    for k in ("upper", "lower"))
+        out[tag] = sec
     return out
 
 

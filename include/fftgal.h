@@ -95,8 +95,9 @@ enum fftgal_precision {
 
 /* Flag or-ed into `precision` of fftgal_workspace_bytes* and the plan
  * constructors.  By default the CG iterations of 2D Ga plans whose double
- * grid is 81 x 81 (N = 41; FP32-iteration form also 81 or 125 on either axis,
- * N = 41 or 63) run entirely inside one work-group per solve: the CG vectors
+ * grid is 81 x 81 (N = 41, or smaller N with FFTGAL_FAST_GRID; FP32-iteration
+ * form also 81 or 125 on either axis) run entirely inside one work-group per
+ * solve: the CG vectors
  * in registers, the operator of Algorithm 2 on the M_1 x M_2 grid in LDS, the
  * update and the stopping test in the same kernel, many iterations per launch
  * (timing class FFTGAL_K_SOLO).  Solves of such plans in a batch run that way
@@ -105,6 +106,20 @@ enum fftgal_precision {
  * Both forms compute the same iterations; their results agree to rounding.
  * It changes no workspace size. */
 #define FFTGAL_SEPARATE_PASSES 0x800
+
+/* Flag or-ed into `precision` of fftgal_workspace_bytes* and fftgal_plan /
+ * fftgal_plan_static.  By default a Ga plan takes per axis the smallest
+ * 3,5,7-smooth double grid M >= 2N - 1.  With the flag it takes instead the
+ * smallest length with specialised kernels (81, 125, 225, 245, 729 or 2025
+ * points) at least 2N - 1 on each axis where that length is at most twice the
+ * default one, when the grid then holds at most four times the points of the
+ * default grid (else the default grid).  The double-grid
+ * quadrature is exact for every M >= 2N - 1 (Lemma integ_eval_VM, eq. MBA_GA),
+ * so the bounds are those of the default grid up to rounding.  The specialised
+ * transforms run several times faster per point than the generic ones, and the
+ * workspace grows with the grid.  fftgal_grid_size reports the grid taken.
+ * EINVAL with GaNi and reduced plans, whose grids the scheme fixes. */
+#define FFTGAL_FAST_GRID 0x1000
 
 enum fftgal_material_kind {
     FFTGAL_INCLUSIONS = 0, /* eq. inclcomp: matrix phase plus inclusions          */

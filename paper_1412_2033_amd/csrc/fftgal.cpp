@@ -97,18 +97,44 @@ enum Scheme { kSchemeGa = 0, kSchemeGani = 1, kSchemeReduced = 2 };
 // (Def. GaNi, Algorithm 1).  Reduced Ga: the material series keeps its support
 // Z_{2N-1}, the transforms run on the N-grid (2^d shifted copies).  Lengths
 // that are not 3,5,7-smooth are transformed by Bluestein's algorithm.
-bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = kSchemeGa, bool tensor = false) {
+// Smallest length with specialised kernels that is at least m, or 0.
+int fast_length_at_least(int m) {
+    int best = 0;
+    for (int i = 0; i < kNumFast; ++i)
+        if (kFastSched[i].n >= m && (best == 0 || kFastSched[i].n < best)) best = kFastSched[i].n;
+    return best;
+}
+
+bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = kSchemeGa, bool tensor = false,
+               bool fast_grid = false) {
     if ((d != 2 && d != 3) || N == nullptr) return false;
     const bool gani = scheme == kSchemeGani, red = scheme == kSchemeReduced;
     o->d = d;
     for (int a = 0; a < d; ++a) {
         if (N[a] < 1 || N[a] % 2 == 0 || N[a] > 100000) return false;
+        if (P && (P[a] < 1 || P[a] % 2 == 0 || P[a] > 100000)) return false;
         o->N[a] = N[a];
         o->L[a] = gani ? N[a] : 2 * N[a] - 1;
         o->M[a] = (gani || red) ? N[a] : smooth_odd(2 * N[a] - 1);
-        o->P[a] = P ? std::max<int>(P[a], o->M[a]) : o->M[a];
-        if (P && (P[a] < 1 || P[a] % 2 == 0 || P[a] > 100000)) return false;
     }
+    if (fast_grid && !gani && !red) {
+        // the specialised length at least 2N - 1 on every axis where it is at
+        // most twice the default length, if together they hold at most four
+        // times the points (every M >= 2N - 1 integrates exactly)
+        int Mf[3] = {0, 0, 0};
+        double ratio = 1.0;
+        for (int a = 0; a < d; ++a) {
+            const int f = fast_length_at_least(2 * N[a] - 1);
+            if (f > 0 && f <= 2 * o->M[a]) {
+                Mf[a] = f;
+                ratio *= (double)f / (double)o->M[a];
+            }
+        }
+        if (ratio <= 4.0)
+            for (int a = 0; a < d; ++a)
+                if (Mf[a] > 0) o->M[a] = Mf[a];
+    }
+    for (int a = 0; a < d; ++a) o->P[a] = P ? std::max<int>(P[a], o->M[a]) : o->M[a];
     o->Nh = (o->N[d - 1] + 1) / 2;
     o->Lh = gani ? o->Nh : o->N[d - 1];
     o->Ns = (d == 3 ? (long)o->N[0] * o->N[1] : (long)o->N[0]) * o->Nh;
@@ -1842,16 +1868,19 @@ size_t workspace_bytes(int d, const int32_t *N, int precision, const int32_t *P,
     const bool lean = (precision & FFTGAL_REDUCED_LEAN) != 0;
     const bool tensor = (precision & FFTGAL_TENSOR) != 0;
     const bool conc = (precision & FFTGAL_CONCURRENT) != 0;
-    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT | FFTGAL_SEPARATE_PASSES);
+    const bool fastg = (precision & FFTGAL_FAST_GRID) != 0;
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT | FFTGAL_SEPARATE_PASSES |
+                   FFTGAL_FAST_GRID);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER) return 0;
     if (lean && scheme != kSchemeReduced) return 0;
     if (tensor && scheme != kSchemeGa) return 0;
     if (conc && scheme == kSchemeReduced) return 0;
-    if (!make_dims(d, N, nullptr, &D, scheme, tensor)) return 0;
+    if (fastg && scheme != kSchemeGa) return 0;
+    if (!make_dims(d, N, nullptr, &D, scheme, tensor, fastg)) return 0;
     const size_t base = make_layout(D, precision, !lean, conc ? 2 * d : 1).total + (conc ? bws_bytes(d) : 0);
     if (P == nullptr) return base;
     Dims DP;
-    if (!make_dims(d, N, P, &DP, scheme, tensor)) return 0;
+    if (!make_dims(d, N, P, &DP, scheme, tensor, fastg)) return 0;
     // a plan lays out its regions without P: an image that does not fit them
     // uses a tail of twiddles, U and W regions after the layout
     int Pv[3] = {1, 1, 1};
@@ -1874,16 +1903,20 @@ int make_plan(struct fftgal_plan **out, int d, const int32_t *N, int precision, 
     const bool tensor = (precision & FFTGAL_TENSOR) != 0;
     const bool conc = (precision & FFTGAL_CONCURRENT) != 0;
     const bool sep = (precision & FFTGAL_SEPARATE_PASSES) != 0;
-    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT | FFTGAL_SEPARATE_PASSES);
+    const bool fastg = (precision & FFTGAL_FAST_GRID) != 0;
+    precision &= ~(FFTGAL_REDUCED_LEAN | FFTGAL_TENSOR | FFTGAL_CONCURRENT | FFTGAL_SEPARATE_PASSES |
+                   FFTGAL_FAST_GRID);
     if (precision != FFTGAL_FP64 && precision != FFTGAL_FP32_ITER)
         return fail(nullptr, FFTGAL_EINVAL, "unknown precision %d", precision);
+    if (fastg && scheme != kSchemeGa)
+        return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_FAST_GRID applies to Ga plans only");
     if (lean && scheme != kSchemeReduced)
         return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_REDUCED_LEAN applies to reduced plans only");
     if (tensor && scheme != kSchemeGa)
         return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_TENSOR applies to Ga plans only");
     if (conc && scheme == kSchemeReduced)
         return fail(nullptr, FFTGAL_EINVAL, "FFTGAL_CONCURRENT applies to Ga and GaNi plans");
-    if (!make_dims(d, N, nullptr, &D, scheme, tensor))
+    if (!make_dims(d, N, nullptr, &D, scheme, tensor, fastg))
         return fail(nullptr, FFTGAL_EINVAL,
                     "d must be 2 or 3 and every N odd and >= 1");
     if (dev_workspace == nullptr || (reinterpret_cast<uintptr_t>(dev_workspace) & 255u))

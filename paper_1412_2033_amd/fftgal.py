@@ -25,6 +25,7 @@ REDUCED_LEAN = 0x100  # reduced Ga laid out with one set of intermediates (shift
 TENSOR = 0x200  # d(d+1)/2 material fields per side (matrix images, anisotropic multi-phase inclusions)
 CONCURRENT = 0x400  # per-solve buffers for all 2d solves: they may run at once
 SEPARATE_PASSES = 0x800  # small 2D grids: per-pass kernels instead of one work-group per solve
+FAST_GRID = 0x1000  # Ga plans: the double grid with specialised kernels if it holds at most 4x the points
 PRECISIONS = {"fp64": FP64, "fp32": FP32_ITER, "fp32_iter": FP32_ITER}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTCONV", -5: "ESTATE", -6: "EBREAKDOWN"}
@@ -367,7 +368,7 @@ class Plan:
     """A plan plus the torch device workspace it runs in."""
 
     def __init__(self, d, N, precision="fp64", device="cuda", stream=None, P=None, scheme="ga", lean=False,
-                 tensor=False, concurrent=False, separate_passes=False):
+                 tensor=False, concurrent=False, separate_passes=False, fast_grid=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fftgal needs a HIP device")
@@ -376,7 +377,8 @@ class Plan:
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.scheme = scheme
         flags = self.precision | (REDUCED_LEAN if lean else 0) | (TENSOR if tensor else 0) | \
-            (CONCURRENT if concurrent else 0) | (SEPARATE_PASSES if separate_passes else 0)
+            (CONCURRENT if concurrent else 0) | (SEPARATE_PASSES if separate_passes else 0) | \
+            (FAST_GRID if fast_grid else 0)
         self.concurrent = bool(concurrent)
         self.nbytes = fftgal_workspace_bytes(self.d, self.N, flags, P, scheme)
         if self.nbytes == 0:
