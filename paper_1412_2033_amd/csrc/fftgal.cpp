@@ -550,8 +550,32 @@ void *ring_upload(Plan *pl, const A &a, hipError_t *err) {
     return pl->ring_slot(i);
 }
 
-int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int cls) {
+// The generic kernels on small grids: fewer pencils (row pairs) per
+// work-group while a launch has fewer than two work-groups per CU and the
+// halved batch still holds a point per thread of the work-group; a handful of
+// work-groups, each transforming many long pencils one stage and one barrier
+// at a time, otherwise sets the time of the pass (2D order 201: 114 -> 70 us
+// per iteration), while batches of short pencils shrunk to one per
+// work-group leave most threads idle (3D GaNi of order 41: 1.6x slower).
+constexpr long kGenericMinWorkGroups = 512;
+constexpr int kGenericMinPoints = 256;
+
+void configure_pencil_spread(PencilArgs &a, int nouter, bool fp64) {
     configure_pencil(a, fp64);
+    if (a.fast) return;
+    while (a.B > 1 && (long)pencil_grid_x(a) * nouter < kGenericMinWorkGroups &&
+           (a.B / 2) * a.f.L >= kGenericMinPoints)
+        a.B /= 2;
+}
+
+void configure_row_spread(RowArgs &r, bool fp64) {
+    configure_row(r, fp64);
+    if (r.fast) return;
+    while (r.RP > 1 && row_grid(r) < kGenericMinWorkGroups && (r.RP / 2) * r.f.L >= kGenericMinPoints) r.RP /= 2;
+}
+
+int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int cls) {
+    configure_pencil_spread(a, nouter, fp64);
     if (pencil_lds_bytes(a, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "transform length %d too large for one work-group", a.f.n);
     if (pl->capture) {
@@ -581,7 +605,7 @@ int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int cls) {
 }
 
 int run_row(Plan *pl, RowArgs &r, bool fp64, int cls) {
-    configure_row(r, fp64);
+    configure_row_spread(r, fp64);
     const int nz = r.mode == ROW_GRAM ? r.ncomp : r.d;
     if (row_lds_bytes(r, fp64) > 160 * 1024)
         return fail(pl, FFTGAL_EINVAL, "row length %d with %d components too large for one work-group", r.f.n, nz);
@@ -1344,7 +1368,7 @@ int start_solve(Plan *pl, int kind, int alpha, double rtol, int maxit) {
     for (int s = 0; s < D.nshift; ++s) {
         RowArgs r = base_row(pl, fp64, ROW_RHS, rows, kind, s);
         for (int a = 0; a < 3; ++a) r.E[a] = (a == alpha) ? 1.0 : 0.0;
-        configure_row(r, fp64);  // the work-group count fixes the partial offsets
+        configure_row_spread(r, fp64);  // the work-group count fixes the partial offsets
         nload = row_grid(r);
         if ((size_t)D.nshift * nload > pl->Lo.part_len) return fail(pl, FFTGAL_EINVAL, "partial buffers too small");
         r.partial = pl->at<double>(pl->so(pl->Lo.part_b)) + (size_t)s * nload;
