@@ -551,13 +551,15 @@ void *ring_upload(Plan *pl, const A &a, hipError_t *err) {
 }
 
 // The generic kernels on small grids: fewer pencils (row pairs) per
-// work-group while a launch has fewer than two work-groups per CU and the
-// halved batch still holds a point per thread of the work-group; a handful of
+// work-group while a launch has fewer work-groups than CUs and the halved
+// batch still holds a point per thread of the work-group; a handful of
 // work-groups, each transforming many long pencils one stage and one barrier
 // at a time, otherwise sets the time of the pass (2D order 201: 114 -> 70 us
 // per iteration), while batches of short pencils shrunk to one per
-// work-group leave most threads idle (3D GaNi of order 41: 1.6x slower).
-constexpr long kGenericMinWorkGroups = 512;
+// work-group leave most threads idle (3D GaNi of order 41: 1.6x slower), and
+// launches with a work-group per CU already lose by it (175^3: 5 % slower
+// when aiming at two per CU).
+constexpr long kGenericMinWorkGroups = 256;
 constexpr int kGenericMinPoints = 256;
 
 void configure_pencil_spread(PencilArgs &a, int nouter, bool fp64) {
