@@ -120,17 +120,19 @@ bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = 
     if (fast_grid && !gani && !red) {
         // the specialised length at least 2N - 1 on every axis where it is at
         // most twice the default length, if together they hold at most four
-        // times the points (every M >= 2N - 1 integrates exactly)
+        // times the points, or at most 2^21 points (small grids, where the
+        // memory does not matter; every M >= 2N - 1 integrates exactly)
         int Mf[3] = {0, 0, 0};
-        double ratio = 1.0;
+        double ratio = 1.0, pts = 1.0;
         for (int a = 0; a < d; ++a) {
             const int f = fast_length_at_least(2 * N[a] - 1);
             if (f > 0 && f <= 2 * o->M[a]) {
                 Mf[a] = f;
                 ratio *= (double)f / (double)o->M[a];
             }
+            pts *= (double)(Mf[a] > 0 ? Mf[a] : o->M[a]);
         }
-        if (ratio <= 4.0)
+        if (ratio <= 4.0 || pts <= (double)(1 << 21))
             for (int a = 0; a < d; ++a)
                 if (Mf[a] > 0) o->M[a] = Mf[a];
     }

@@ -8,7 +8,8 @@ after a fixed number of CG steps entry by entry against the oracle (which
 integrates on M = 2N - 1) to 1e-11, first order in the operator.  The grids
 taken are those the flag documents: 2D N = 21 on 81^2 (the single work-group
 solver), 2D N = 201 on 729^2, 3D (35, 5, 35) on 81 x 9 x 81 (the middle axis
-keeps its generic length) and 3D N = 81 on 225^3.
+keeps its generic length), 3D N = 81 on 225^3 and 3D N = 21 on 81^3 (a small
+grid).
 """
 
 import numpy as np
@@ -38,6 +39,9 @@ CASES = {
     "aniso3d_N35x5x35": (lambda: synth.cube_inclusion_aniso(0.45, 6), (35, 5, 35), (81, 9, 81)),
     "vox3d_N81": (lambda: synth.grf_voxels(5, (161, 161, 161), d=3, corr_len=0.05, vf=0.4, a_incl=100.0),
                   (81, 81, 81), (225, 225, 225)),
+    # 5.8 times the points of 45^3, taken because the grid is small
+    "vox3d_N21": (lambda: synth.grf_voxels(7, (41, 41, 41), d=3, corr_len=0.1, vf=0.4, a_incl=30.0),
+                  (21, 21, 21), (81, 81, 81)),
 }
 
 
