@@ -11,7 +11,9 @@ of the batch advances all active solves of all requests.  Larger grids, whose
 single solve already fills the GPU, keep one buffer set (a request's solves
 then run one after another), and so does every plan with concurrent=False.
 When a request's last solve retires, its bounds are evaluated (FP64
-quadrature) and its latency recorded.
+quadrature) and its latency recorded.  Plans are made with FFTGAL_FAST_GRID
+by default: orders whose smallest double grid has no specialised kernels run
+on a slightly larger grid that has them, with the same bounds.
 
 All scheduling is host logic; every step of the computation runs in the HIP
 library.
@@ -33,7 +35,7 @@ def percentile(xs, q):
 
 class Server:
     def __init__(self, precision="fp32", rtol=5e-6, maxit=20000, capacity=256, hbm_budget=64 << 30,
-                 iters_per_step=8, device="cuda:0", concurrent="auto"):
+                 iters_per_step=8, device="cuda:0", concurrent="auto", fast_grid=True):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -49,6 +51,7 @@ class Server:
         self.peak_bytes = 0
         self.plans_created = 0
         self.concurrent = concurrent
+        self.fast_grid = bool(fast_grid)
 
     def concurrent_for(self, d, N):
         """Whether plans of this shape hold one buffer set per solve."""
@@ -57,7 +60,8 @@ class Server:
         return bool(self.concurrent)
 
     def flags_for(self, d, N):
-        return fftgal.PRECISIONS[self.precision] | (fftgal.CONCURRENT if self.concurrent_for(d, N) else 0)
+        return fftgal.PRECISIONS[self.precision] | (fftgal.CONCURRENT if self.concurrent_for(d, N) else 0) | \
+            (fftgal.FAST_GRID if self.fast_grid else 0)
 
     def _plan(self, d, N):
         key = (d, N)
@@ -80,7 +84,7 @@ class Server:
         self.peak_bytes = max(self.peak_bytes, self.used_bytes)
         self.plans_created += 1
         return fftgal.Plan(d, N, self.precision, device=self.device, stream=self.batch.stream,
-                           concurrent=self.concurrent_for(d, N))
+                           concurrent=self.concurrent_for(d, N), fast_grid=self.fast_grid)
 
     def run(self, requests, realtime=True):
         """Serve `requests` (dicts with id, arrival_s, N, micro); returns per-request records."""

@@ -103,7 +103,8 @@ def test_server_3d_mix_under_hbm_budget(fg):
     # wait for memory; every result matches the plain FP64 path within 1e-6
     from paper_1412_2033_amd import serve
     reqs = [dict(r, arrival_s=0.0) for r in synth.serving_requests_3d(4, 10, rate_per_s=1.0, N_choices=(5, 13, 23))]
-    flags = fg.PRECISIONS["fp32"] | fg.CONCURRENT  # the server's plans (small grids: concurrent)
+    # the server's plans: small grids concurrent, specialised grids (N = 23: 81^3)
+    flags = fg.PRECISIONS["fp32"] | fg.CONCURRENT | fg.FAST_GRID
     need = {N: fg.fftgal_workspace_bytes(3, (N,) * 3, flags) for N in (5, 13, 23)}
     budget = sum(need.values()) + need[5] // 2
     # capacity for all 6 solves of four requests: memory, not slots, defers one
