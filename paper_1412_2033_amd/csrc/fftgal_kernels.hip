@@ -2827,18 +2827,55 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
     const int pair0 = lb * RP;
     const int nvp = min(RP, (a.nrows + 1) / 2 - pair0);
     const V zero = mk<T>(T(0), T(0));
-    for (int idx = threadIdx.x; idx < N * NB; idx += kThreads) X[idx] = zero;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NB * nh; idx += kThreads) {
+    // every global load of the work-group in flight at once: the half-spectrum
+    // rows (at most (N + 1) / 2 points each) and, for the scalar-field form,
+    // the material values of the accumulation below; the band of positions
+    // no load writes is zeroed by a loop of its own
+    constexpr int NHMAX = (N + 1) / 2;
+    constexpr int PE = (NB * NHMAX + kThreads - 1) / kThreads;
+    constexpr int GP = (RP * N + kThreads - 1) / kThreads;
+    V u1v[PE], u2v[PE];
+#pragma unroll
+    for (int t = 0; t < PE; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
         const int pc = idx / nh;
         const int kx = idx - pc * nh;
         const int c = pc / RP;
         const int j = pc - c * RP;
-        if (j >= nvp) continue;
-        const int r1 = 2 * (pair0 + j);
-        const int r2 = r1 + 1;
-        const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
-        const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+        const bool ok = idx < NB * nh && j < nvp;
+        const int r1 = 2 * (pair0 + (ok ? j : 0));
+        const bool two = ok && r1 + 1 < a.nrows;
+        const long o1 = ok ? (long)c * a.cs + (long)r1 * nh + kx : 0L;
+        const long o2 = two ? o1 + nh : 0L;  // in range even if the load is issued
+        u1v[t] = ok ? data[o1] : zero;
+        u2v[t] = two ? data[o2] : zero;
+    }
+    T gv1[GP], gv2[GP];
+    const bool gpre = a.nfield == 1;
+#pragma unroll
+    for (int t = 0; t < GP; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        const int j = idx / N;
+        const int x = idx - j * N;
+        const bool ok = gpre && idx < RP * N && j < nvp;
+        const bool two = ok && 2 * (pair0 + j) + 1 < a.nrows;
+        const long r1 = 2 * (pair0 + (ok ? j : 0));
+        const long i1 = ok ? r1 * N + x : 0L, i2 = two ? i1 + N : 0L;
+        gv1[t] = ok ? g[i1] : T(0);
+        gv2[t] = two ? g[i2] : T(0);
+    }
+    const int nzb = N - 2 * nh + 1;  // positions nh .. N - nh of every field
+    for (int idx = threadIdx.x; idx < NB * nzb; idx += kThreads) {
+        const int pc = idx / nzb;
+        X[pc * N + nh + (idx - pc * nzb)] = zero;
+    }
+#pragma unroll
+    for (int t = 0; t < PE; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        if (idx >= NB * nh) continue;
+        const int pc = idx / nh;
+        const int kx = idx - pc * nh;
+        const V u1 = u1v[t], u2 = u2v[t];  // zero for idle row pairs
         if (kx == 0) {
             X[pc * N] = mk<T>(u1.x, u2.x);
         } else {
@@ -2857,7 +2894,10 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
     double gs[D * D];
 #pragma unroll
     for (int i = 0; i < D * D; ++i) gs[i] = 0.0;
-    for (int idx = threadIdx.x; idx < RP * N; idx += kThreads) {
+#pragma unroll
+    for (int t = 0; t < GP; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        if (idx >= RP * N) continue;
         const int j = idx / N;
         const int x = idx - j * N;
         if (j >= nvp) continue;
@@ -2870,7 +2910,7 @@ __global__ __launch_bounds__(kThreads) void row_gram_fast(const RowArgs *__restr
             if (a.nfield > 1) {
                 sym_load<T>(g, a.gstride, (long)r * N + x, D, am);
             } else {
-                const T gg = g[(long)r * N + x];
+                const T gg = half ? gv2[t] : gv1[t];
 #pragma unroll
                 for (int i = 0; i < D * D; ++i) am[i] = A0[i] + gg * Dm[i];
             }
