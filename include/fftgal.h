@@ -111,9 +111,9 @@ enum fftgal_precision {
  * fftgal_plan_static.  By default a Ga plan takes per axis the smallest
  * 3,5,7-smooth double grid M >= 2N - 1.  With the flag it takes instead the
  * smallest length with specialised kernels (81, 125, 225, 245, 729 or 2025
- * points) at least 2N - 1 on each axis where that length is at most twice the
- * default one, when the grid then holds at most four times the points of the
- * default grid or at most 2^21 points (else the default grid).  The double-grid
+ * points) at least 2N - 1 on each axis whose default length is at least 9,
+ * when the grid then holds at most four times the points of the default grid
+ * or at most 2^21 points (else the default grid).  The double-grid
  * quadrature is exact for every M >= 2N - 1 (Lemma integ_eval_VM, eq. MBA_GA),
  * so the bounds are those of the default grid up to rounding.  The specialised
  * transforms run several times faster per point than the generic ones, and the

@@ -118,15 +118,16 @@ bool make_dims(int d, const int32_t *N, const int32_t *P, Dims *o, int scheme = 
         o->M[a] = (gani || red) ? N[a] : smooth_odd(2 * N[a] - 1);
     }
     if (fast_grid && !gani && !red) {
-        // the specialised length at least 2N - 1 on every axis where it is at
-        // most twice the default length, if together they hold at most four
-        // times the points, or at most 2^21 points (small grids, where the
-        // memory does not matter; every M >= 2N - 1 integrates exactly)
+        // the specialised length at least 2N - 1 on every axis whose default
+        // length is at least 9, if the grid then holds at most four times the
+        // points, or at most 2^21 points (small grids, where the memory does
+        // not matter and the generic kernels' launches set the time; every
+        // M >= 2N - 1 integrates exactly)
         int Mf[3] = {0, 0, 0};
         double ratio = 1.0, pts = 1.0;
         for (int a = 0; a < d; ++a) {
             const int f = fast_length_at_least(2 * N[a] - 1);
-            if (f > 0 && f <= 2 * o->M[a]) {
+            if (f > 0 && o->M[a] >= 9) {
                 Mf[a] = f;
                 ratio *= (double)f / (double)o->M[a];
             }

@@ -58,19 +58,19 @@ def test_workspace_bytes_validation(lib):
 
 
 def test_fast_grid_workspace(lib):
-    # FFTGAL_FAST_GRID: specialised lengths on the axes where they are at most
-    # twice the smallest 3,5,7-smooth one, when the grid then holds at most
+    # FFTGAL_FAST_GRID: specialised lengths on the axes whose smallest
+    # 3,5,7-smooth length is at least 9, when the grid then holds at most
     # four times its points or at most 2^21 points (3D N = 81: 225^3 against
-    # 175^3; 2D N = 21: 81^2 against 45^2; (35, 5, 35): 81 x 9 x 81 against
-    # 75 x 9 x 75; 3D N = 21: 81^3 against 45^3, 5.8x but small); unchanged
-    # where the smooth grid is already specialised (N = 41, 113) or the
-    # specialised one is too large (3D N = 201: 729^3 against 405^3, 5.8x);
-    # Ga plans only
+    # 175^3; 2D N = 21: 81^2 against 45^2; (35, 3, 151): 81 x 5 x 729 against
+    # 75 x 5 x 315; 3D N = 21: 81^3 against 45^3, 5.8x but small); unchanged
+    # where the smooth grid is already specialised (N = 41, 113), too short
+    # (N = 3: 5 points) or the specialised one too large (3D N = 201: 729^3
+    # against 405^3, 5.8x); Ga plans only
     from paper_1412_2033_amd import fftgal
     F = fftgal.FAST_GRID
-    for d, N in ((3, (81, 81, 81)), (2, (21, 21)), (2, (201, 201)), (3, (35, 5, 35)), (3, (21, 21, 21))):
+    for d, N in ((3, (81, 81, 81)), (2, (21, 21)), (2, (201, 201)), (3, (35, 3, 151)), (3, (21, 21, 21))):
         assert fftgal.fftgal_workspace_bytes(d, N, F) > fftgal.fftgal_workspace_bytes(d, N, 0), N
-    for d, N in ((2, (41, 41)), (3, (113, 113, 113)), (3, (201, 201, 201)), (2, (1013, 1013))):
+    for d, N in ((2, (41, 41)), (3, (113, 113, 113)), (3, (201, 201, 201)), (2, (1013, 1013)), (2, (3, 3))):
         assert fftgal.fftgal_workspace_bytes(d, N, F) == fftgal.fftgal_workspace_bytes(d, N, 0), N
     # the same 225^3 intermediates as N = 113, a smaller CG state on Z_81
     assert fftgal.fftgal_workspace_bytes(3, (81, 81, 81), F) < fftgal.fftgal_workspace_bytes(3, (113, 113, 113), 0)

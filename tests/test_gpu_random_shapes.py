@@ -6,7 +6,7 @@ material (isotropic square or disc inclusions, an anisotropic cube, a scalar
 voxel image at a voxel resolution P that may differ from the double grid and
 need not be 3,5,7-smooth, multi-phase anisotropic inclusions or a matrix
 voxel image) and the plan flags (concurrent solves, matrix fields, the
-per-pass kernels for small 2D grids).  Every primal and dual solve stops
+per-pass kernels for small 2D grids, the double grid of specialised lengths).  Every primal and dual solve stops
 after K conjugate-gradient steps (rtol 0), so the bounds are first order in
 the operator (Remark CG: the iterate is a fixed Krylov polynomial), and each
 entry must match the oracle's bounds of the same iterates (Prop.
@@ -74,6 +74,8 @@ def _draw(seed, low_contrast=False):
         opts["tensor"] = True
     if d == 2 and rng.random() < 0.3:
         opts["separate_passes"] = True
+    if rng.random() < 0.35:
+        opts["fast_grid"] = True  # the specialised double grid (same bounds)
     return N, kind, micro, opts
 
 
@@ -198,5 +200,6 @@ def test_draws_cover_the_options():
     assert {len(N) for N, _, _, _ in draws} == {2, 3}
     assert any(o["concurrent"] for _, _, _, o in draws)
     assert any(o.get("separate_passes") for _, _, _, o in draws)
+    assert sum(bool(o.get("fast_grid")) for _, _, _, o in draws) >= 5
     assert any(m.get("P") is not None and tuple(m["P"]) != tuple(2 * n - 1 for n in N)
                for N, _, m, _ in draws)
