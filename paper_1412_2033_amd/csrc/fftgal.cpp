@@ -1563,6 +1563,7 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
     int enq = 0;
     int it_prev = 0;
     double rr_prev = 0.0;
+    bool first = true;
     for (;;) {
         const int todo = std::min(chunk, std::max(0, maxit - enq));
         for (int i = 0; i < todo; ++i) {
@@ -1576,11 +1577,17 @@ int run_solve(Plan *pl, int kind, int alpha, double rtol, int maxit, fftgal_info
         if (h.done || enq >= maxit) break;
         const double target = std::max(h.tol2 * h.rr0, h.floor2);
         int next = 2 * chunk;
-        if (it_prev > 0 && h.iter > it_prev && h.rr < rr_prev && h.rr > 0.0 && target > 0.0) {
-            const double rate = std::log(h.rr / rr_prev) / (h.iter - it_prev);  // < 0
+        // the rate since the previous read (at the first read: since the start,
+        // from the initial residual); an iteration enqueued past convergence
+        // costs its seven no-op launches, one too few a read of the status
+        const int i0 = first ? 0 : it_prev;
+        const double r0v = first ? h.rr0 : rr_prev;
+        if (h.iter > i0 && h.rr < r0v && h.rr > 0.0 && target > 0.0) {
+            const double rate = std::log(h.rr / r0v) / (h.iter - i0);  // < 0
             const double remain = std::log(target / h.rr) / rate;
-            next = (int)std::ceil(1.1 * remain) + 1;
+            next = (int)std::ceil(remain) + 2;
         }
+        first = false;
         chunk = std::max(2, std::min(next, 64));
         it_prev = h.iter;
         rr_prev = h.rr;
