@@ -331,13 +331,20 @@ void build_fft(int n, size_t tw_base_entry, std::vector<double> &tab, FftDesc *f
         vr[idx] = cr[am];
         vi[idx] = -ci[am];
     }
+    // the angle of term (m, k) depends only on q = m k mod L: one cosine and
+    // sine per residue instead of per term
+    std::vector<long double> wc(L), ws(L);
+    for (int q = 0; q < L; ++q) {
+        const long double ang = -2.0L * kPiL * (long double)q / (long double)L;
+        wc[q] = cosl(ang);
+        ws[q] = sinl(ang);
+    }
     for (int k = 0; k < L; ++k) {
         long double hr = 0.0L, hi = 0.0L;
         for (int m = 0; m < L; ++m) {
             if (vr[m] == 0.0L && vi[m] == 0.0L) continue;
-            const long long q = ((long long)m * k) % L;
-            const long double ang = -2.0L * kPiL * (long double)q / (long double)L;
-            const long double c = cosl(ang), sn = sinl(ang);
+            const int q = (int)(((long long)m * k) % L);
+            const long double c = wc[q], sn = ws[q];
             hr += vr[m] * c - vi[m] * sn;
             hi += vr[m] * sn + vi[m] * c;
         }
