@@ -562,7 +562,8 @@ void *ring_upload(Plan *pl, const A &a, hipError_t *err) {
 
 // The generic kernels on small grids: fewer pencils (row pairs) per
 // work-group while a launch has fewer work-groups than CUs and the halved
-// batch still holds a point per thread of the work-group; a handful of
+// batch (pencils times the components transformed together) still holds a
+// point per thread of the work-group; a handful of
 // work-groups, each transforming many long pencils one stage and one barrier
 // at a time, otherwise sets the time of the pass (2D order 201: 114 -> 70 us
 // per iteration), while batches of short pencils shrunk to one per
@@ -576,8 +577,10 @@ void configure_pencil_spread(PencilArgs &a, int nouter, bool fp64) {
     configure_pencil(a, fp64);
     if (a.fast) return;
     while (a.B > 1 && (long)pencil_grid_x(a) * nouter < kGenericMinWorkGroups &&
-           (a.B / 2) * a.f.L >= kGenericMinPoints)
+           (a.B / 2) * a.f.L * a.cb >= kGenericMinPoints) {
         a.B /= 2;
+        fit_pencil_components(a, fp64);
+    }
 }
 
 void configure_row_spread(RowArgs &r, bool fp64) {

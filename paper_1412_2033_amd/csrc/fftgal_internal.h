@@ -106,6 +106,7 @@ struct PencilArgs {
     int nb;       // batch extent (contiguous)
     int B;        // pencils per work-group
     int ncomp;    // transformed components (per solution)
+    int cb;       // generic kernel: components transformed together (1 .. ncomp)
     int sgn;      // +1: inverse DFT (omega^{+mk}); -1: forward
     double scale; // applied to every output value
     FftDesc f;
@@ -257,6 +258,10 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64);
 // Choose pencils per work-group / row pairs per work-group (and whether the
 // specialised kernel runs) for a launch; sets a.B / r.RP.
 void configure_pencil(PencilArgs &a, bool fp64);
+// Generic pencil kernel: the most components per transform batch (a.cb) whose
+// buffers fit kGenericLds at the batch a.B.
+void fit_pencil_components(PencilArgs &a, bool fp64);
+constexpr size_t kGenericLds = 80 * 1024;
 void configure_row(RowArgs &r, bool fp64);
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s);
 hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s);

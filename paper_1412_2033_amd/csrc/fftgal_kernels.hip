@@ -476,7 +476,10 @@ __device__ __forceinline__ T pick3(const T *t, int al) {
 }
 
 // two waves per SIMD: the radix-25 stage alone would take the register
-// file of one
+// file of one.  The components of a pencil are transformed a.cb at a time in
+// one batch of cb * B sequences (layout: position * (cn B) + j B + b for
+// component al0 + j of the chunk), so that a small grid runs one chain of
+// stages and barriers per work-group instead of one per component.
 template <typename T>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void pencil_kernel(PencilArgs a) {
     using V = Vt<T>;
@@ -484,9 +487,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     extern __shared__ __align__(16) unsigned char smem_raw[];  // 16-byte complex doubles
     const int n = a.f.n;
     const int B = a.B;
+    const int cb = a.cb;
     V *bufA = reinterpret_cast<V *>(smem_raw);
-    V *bufB = bufA + (size_t)a.f.L * B;
-    V *acc = bufB + (size_t)a.f.L * B;
+    V *bufB = bufA + (size_t)a.f.L * cb * B;
+    V *acc = bufB + (size_t)a.f.L * cb * B;
     const int b0 = blockIdx.x * B;
     const int o = blockIdx.y;
     const int nbw = min(B, a.nb - b0);
@@ -534,8 +538,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                 acc[(c * a.L_in + l) * B + bb] = v;
             }
             __syncthreads();
-            for (int al = 0; al < a.ncomp; ++al) {
-                for (int idx = threadIdx.x; idx < n * B; idx += blockDim.x) bufA[idx] = zero;
+            for (int al0 = 0; al0 < a.ncomp; al0 += cb) {
+                const int cn = min(cb, a.ncomp - al0);
+                const int nbt = cn * B;
+                for (int idx = threadIdx.x; idx < n * nbt; idx += blockDim.x) bufA[idx] = zero;
                 __syncthreads();
                 for (int idx = threadIdx.x; idx < a.L_in * B; idx += blockDim.x) {
                     const int bb = idx % B;
@@ -545,35 +551,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                     freq(l, a.L_in, b0 + bb, &k1, &k2, &k3);
                     T t[2][3];
                     const int nt = basis<T>(a.d, a.kind, k1, k2, k3, t);
-                    T ex = T(0), ey = T(0);
+                    double pc = 1.0, ps = 0.0;
+                    if (has_shift(a)) shift_phase(a, k1, k2, k3, &pc, &ps);
+                    V *dst = bufA + posmod(k1, n) * nbt + bb;
+                    for (int j = 0; j < cn; ++j) {
+                        const int al = al0 + j;
+                        T ex = T(0), ey = T(0);
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        if (c >= nt) break;
-                        const V cv = acc[(c * a.L_in + l) * B + bb];
-                        const T tc = pick3<T>(t[c], al);
-                        ex -= tc * cv.y;  // i * t * c
-                        ey += tc * cv.x;
+                        for (int c = 0; c < 2; ++c) {
+                            if (c >= nt) break;
+                            const V cv = acc[(c * a.L_in + l) * B + bb];
+                            const T tc = pick3<T>(t[c], al);
+                            ex -= tc * cv.y;  // i * t * c
+                            ey += tc * cv.x;
+                        }
+                        if (has_shift(a)) {
+                            const T nx = ex * T(pc) - ey * T(ps);
+                            ey = ex * T(ps) + ey * T(pc);
+                            ex = nx;
+                        }
+                        dst[j * B] = mk<T>(ex, ey);
                     }
-                    if (has_shift(a)) {
-                        double pc, ps;
-                        shift_phase(a, k1, k2, k3, &pc, &ps);
-                        const T nx = ex * T(pc) - ey * T(ps);
-                        ey = ex * T(ps) + ey * T(pc);
-                        ex = nx;
-                    }
-                    bufA[posmod(k1, n) * B + bb] = mk<T>(ex, ey);
                 }
                 __syncthreads();
-                V *res = fft_lds<T, false>(bufA, bufB, a.f, B, tw, sg);
-                const long cbase = (long)(s * a.ncomp + al) * a.out_cs + (long)o * a.out_os + b0;
-                for (int idx = threadIdx.x; idx < a.L_out * B; idx += blockDim.x) {
-                    const int bb = idx % B;
-                    const int l = idx / B;
+                V *res = fft_lds<T, false>(bufA, bufB, a.f, nbt, tw, sg);
+                for (int idx = threadIdx.x; idx < a.L_out * nbt; idx += blockDim.x) {
+                    const int bt = idx % nbt;
+                    const int l = idx / nbt;
+                    const int j = bt / B;
+                    const int bb = bt - j * B;
                     if (bb >= nbw) continue;
                     const int pos = posmod(wrapi(l, a.L_out), n);
-                    V v = res[pos * B + bb];
+                    V v = res[pos * nbt + bt];
                     v.x *= scale;
                     v.y *= scale;
+                    const long cbase = (long)(s * a.ncomp + al0 + j) * a.out_cs + (long)o * a.out_os + b0;
                     out[cbase + (long)l * a.out_ls + bb] = v;
                 }
                 __syncthreads();
@@ -587,23 +599,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int idx = threadIdx.x; idx < a.nc * a.L_out * B; idx += blockDim.x) acc[idx] = zero;
     }
     double part = 0.0;
-    for (int al = 0; al < a.ncomp; ++al) {
+    for (int al0 = 0; al0 < a.ncomp; al0 += cb) {
+        const int cn = min(cb, a.ncomp - al0);
+        const int nbt = cn * B;
         if (a.L_in < n) {
-            for (int idx = threadIdx.x; idx < n * B; idx += blockDim.x) bufA[idx] = zero;
+            for (int idx = threadIdx.x; idx < n * nbt; idx += blockDim.x) bufA[idx] = zero;
             __syncthreads();
         }
-        const long ibase = (long)al * a.in_cs + (long)o * a.in_os + b0;
-        for (int idx = threadIdx.x; idx < a.L_in * B; idx += blockDim.x) {
-            const int bb = idx % B;
-            const int l = idx / B;
+        for (int idx = threadIdx.x; idx < a.L_in * nbt; idx += blockDim.x) {
+            const int bt = idx % nbt;
+            const int l = idx / nbt;
+            const int j = bt / B;
+            const int bb = bt - j * B;
             V v = zero;
-            if (bb < nbw) v = in[ibase + (long)l * a.in_ls + bb];
-            bufA[posmod(wrapi(l, a.L_in), n) * B + bb] = v;
+            if (bb < nbw) v = in[(long)(al0 + j) * a.in_cs + (long)o * a.in_os + b0 + (long)l * a.in_ls + bb];
+            bufA[posmod(wrapi(l, a.L_in), n) * nbt + bt] = v;
         }
         __syncthreads();
-        V *res = fft_lds<T, false>(bufA, bufB, a.f, B, tw, sg);
+        V *res = fft_lds<T, false>(bufA, bufB, a.f, nbt, tw, sg);
         if (a.epi == EPI_PROJECT) {
-            // q_a += -i t_a(k)_alpha yhat_alpha(k) on Z_N
+            // q_a += -i t_a(k)_alpha yhat_alpha(k) on Z_N, alpha in ascending order
             for (int idx = threadIdx.x; idx < a.L_out * B; idx += blockDim.x) {
                 const int bb = idx % B;
                 const int l = idx / B;
@@ -612,24 +627,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                 freq(l, a.L_out, b0 + bb, &k1, &k2, &k3);
                 T t[2][3];
                 const int nt = basis<T>(a.d, a.kind, k1, k2, k3, t);
-                const V y = res[posmod(k1, n) * B + bb];
+                const V *src = res + posmod(k1, n) * nbt + bb;
+                for (int j = 0; j < cn; ++j) {
+                    const V y = src[j * B];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    if (c >= nt) break;
-                    V &q = acc[(c * a.L_out + l) * B + bb];
-                    const T tt = pick3<T>(t[c], al) * scale;
-                    q.x += tt * y.y;
-                    q.y -= tt * y.x;
+                    for (int c = 0; c < 2; ++c) {
+                        if (c >= nt) break;
+                        V &q = acc[(c * a.L_out + l) * B + bb];
+                        const T tt = pick3<T>(t[c], al0 + j) * scale;
+                        q.x += tt * y.y;
+                        q.y -= tt * y.x;
+                    }
                 }
             }
         } else {
-            const long obase = (long)al * a.out_cs + (long)o * a.out_os + b0;
-            for (int idx = threadIdx.x; idx < a.L_out * B; idx += blockDim.x) {
-                const int bb = idx % B;
-                const int l = idx / B;
+            for (int idx = threadIdx.x; idx < a.L_out * nbt; idx += blockDim.x) {
+                const int bt = idx % nbt;
+                const int l = idx / nbt;
+                const int j = bt / B;
+                const int bb = bt - j * B;
                 if (bb >= nbw) continue;
                 const int kk = wrapi(l, a.L_out);
-                V v = res[posmod(kk, n) * B + bb];
+                V v = res[posmod(kk, n) * nbt + bt];
                 T sc = scale;
                 if (a.epi == EPI_WINDOW) {
                     int k1, k2, k3;
@@ -640,6 +659,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                 }
                 v.x *= sc;
                 v.y *= sc;
+                const long obase = (long)(al0 + j) * a.out_cs + (long)o * a.out_os + b0;
                 out[obase + (long)l * a.out_ls + bb] = v;
             }
         }
@@ -3593,7 +3613,7 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
     int lacc = 0;
     if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
     if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
-    return es * ((size_t)2 * a.f.L * a.B + (size_t)lacc * a.B);
+    return es * ((size_t)2 * a.f.L * std::max(a.cb, 1) * a.B + (size_t)lacc * a.B);
 }
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
@@ -3640,13 +3660,15 @@ void configure_pencil(PencilArgs &a, bool fp64) {
         return;
     }
     a.fast = 0;
-    int lacc = 0;
-    if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
-    if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
-    const size_t es = fp64 ? 16 : 8;
-    int B = fp64 ? 8 : 16;
-    while (B > 1 && es * ((size_t)2 * a.f.L * B + (size_t)lacc * B) > 80 * 1024) B /= 2;
-    a.B = B;
+    a.cb = 1;
+    a.B = fp64 ? 8 : 16;
+    while (a.B > 1 && pencil_lds_bytes(a, fp64) > kGenericLds) a.B /= 2;
+    fit_pencil_components(a, fp64);
+}
+
+void fit_pencil_components(PencilArgs &a, bool fp64) {
+    a.cb = std::max(a.ncomp, 1);
+    while (a.cb > 1 && pencil_lds_bytes(a, fp64) > kGenericLds) --a.cb;
 }
 
 void configure_row(RowArgs &r, bool fp64) {
