@@ -586,7 +586,10 @@ void configure_pencil_spread(PencilArgs &a, int nouter, bool fp64) {
 void configure_row_spread(RowArgs &r, bool fp64) {
     configure_row(r, fp64);
     if (r.fast) return;
-    while (r.RP > 1 && row_grid(r) < kGenericMinWorkGroups && (r.RP / 2) * r.f.L >= kGenericMinPoints) r.RP /= 2;
+    while (r.RP > 1 && row_grid(r) < kGenericMinWorkGroups && (r.RP / 2) * r.f.L >= kGenericMinPoints) {
+        r.RP /= 2;
+        fit_row_batch(r, fp64);
+    }
 }
 
 int run_pencil(Plan *pl, PencilArgs &a, int nouter, bool fp64, int cls) {

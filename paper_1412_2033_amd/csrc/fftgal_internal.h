@@ -167,6 +167,9 @@ struct RowArgs {
     // transform (RP rows per work-group) instead of two rows of one component
     // (RP row pairs), halving the transform buffers for long rows
     int gpack;
+    // generic kernel: the components' rows form one batch of transforms (LDS
+    // for two buffers of every component) instead of one batch per component
+    int zbatch;
     double E[3];      // load for ROW_RHS
     void *real_out;   // ROW_C2R output rows (length n)
     const void *real_in;  // ROW_R2C input rows (length n)
@@ -261,6 +264,8 @@ void configure_pencil(PencilArgs &a, bool fp64);
 // Generic pencil kernel: the most components per transform batch (a.cb) whose
 // buffers fit kGenericLds at the batch a.B.
 void fit_pencil_components(PencilArgs &a, bool fp64);
+// Generic row kernel: a.zbatch = 1 when the batched buffers fit kGenericLds at a.RP.
+void fit_row_batch(RowArgs &r, bool fp64);
 constexpr size_t kGenericLds = 80 * 1024;
 void configure_row(RowArgs &r, bool fp64);
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s);

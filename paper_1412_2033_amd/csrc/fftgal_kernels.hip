@@ -872,6 +872,14 @@ __device__ __forceinline__ void sym_load(const T *g, long stride, long pt, int d
 // ---------------------------------------------------------------------------
 // Row pass: real transforms along the last axis, two rows per complex DFT.
 // ---------------------------------------------------------------------------
+// Transform buffers (components) of the generic row kernel.
+__host__ __device__ inline int row_zbufs(const RowArgs &a) {
+    if (a.mode == ROW_RHS) return a.d;
+    if (a.mode == ROW_R2C || a.mode == ROW_C2R) return 1;
+    if (a.mode == ROW_GRAM && a.gpack) return (a.ncomp + 1) / 2;
+    return a.ncomp;
+}
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     using V = Vt<T>;
@@ -881,8 +889,13 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     const int ln = a.f.L;  // buffer length per transform (n unless Bluestein)
     const int RP = a.RP;
     const int nh = a.Nh_row;
-    V *S = reinterpret_cast<V *>(smem_raw);
-    V *Z = S + (size_t)RP * ln;  // Z[c] = Z + c * RP * ln
+    // one buffer per component (Z[c] = Z + c RP ln) and the transforms'
+    // scratch S: RP ln (a batch per component) or the size of Z (zbatch: the
+    // rows of all components form one batch, sequence c RP + j at (c RP + j) ln)
+    const bool zb = a.zbatch != 0;
+    const int nzb = row_zbufs(a);
+    V *const S = reinterpret_cast<V *>(smem_raw) + (zb ? (size_t)nzb * RP * ln : 0);
+    V *const Z = reinterpret_cast<V *>(smem_raw) + (zb ? 0 : (size_t)RP * ln);
     const V *tw = reinterpret_cast<const V *>(a.tw);
     V *data = reinterpret_cast<V *>(a.data);
     const T *g = reinterpret_cast<const T *>(a.g);
@@ -978,7 +991,35 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
     }
 
     // ---- spatial values ----
-    if (a.mode == ROW_OPER || a.mode == ROW_GRAM || a.mode == ROW_C2R) {
+    if (zb && (a.mode == ROW_OPER || a.mode == ROW_GRAM || a.mode == ROW_C2R)) {
+        const int nall = a.ncomp * RP;
+        for (int idx = threadIdx.x; idx < nall * ln; idx += blockDim.x) Z[idx] = zero;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nall * nh; idx += blockDim.x) {
+            const int cj = idx / nh;  // c RP + j
+            const int kx = idx - cj * nh;
+            const int c = cj / RP;
+            const int j = cj - c * RP;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
+            const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+            V *zr = Z + (size_t)cj * ln;
+            if (kx == 0) {
+                zr[0] = mk<T>(u1.x, u2.x);
+            } else {
+                zr[kx] = mk<T>(u1.x - u2.y, u1.y + u2.x);
+                zr[n - kx] = mk<T>(u1.x + u2.y, u2.x - u1.y);
+            }
+        }
+        __syncthreads();
+        const V *res = fft_lds<T, true>(Z, S, a.f, nall, tw, T(1));
+        if (res != Z) {
+            for (int idx = threadIdx.x; idx < nall * ln; idx += blockDim.x) Z[idx] = res[idx];
+            __syncthreads();
+        }
+    } else if (a.mode == ROW_OPER || a.mode == ROW_GRAM || a.mode == ROW_C2R) {
         for (int c = 0; c < a.ncomp; ++c) {
             V *zc = zbuf(c);
             for (int idx = threadIdx.x; idx < RP * ln; idx += blockDim.x) zc[idx] = zero;
@@ -1150,6 +1191,25 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
 
     // ---- forward transforms and Hermitian split ----
     const T half = T(a.scale) * T(0.5);
+    if (zb) {
+        const V *res = fft_lds<T, true>(Z, S, a.f, nzc * RP, tw, T(-1));
+        for (int idx = threadIdx.x; idx < nzc * RP * nh; idx += blockDim.x) {
+            const int cj = idx / nh;
+            const int kx = idx - cj * nh;
+            const int c = cj / RP;
+            const int j = cj - c * RP;
+            if (j >= nvp) continue;
+            const int r1 = 2 * (pair0 + j);
+            const int r2 = r1 + 1;
+            const V *zr = res + (size_t)cj * ln;
+            const V w = zr[posmod(kx, n)];
+            const V wm = zr[posmod(-kx, n)];
+            data[(long)c * a.cs + (long)r1 * nh + kx] = mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half);
+            if (r2 < a.nrows)
+                data[(long)c * a.cs + (long)r2 * nh + kx] = mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half);
+        }
+        return;
+    }
     for (int c = 0; c < nzc; ++c) {
         fft_into(c, T(-1));
         const V *zc = zbuf(c);
@@ -3631,11 +3691,8 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64) {
     if (a.fast)
         return es * ((size_t)a.f.n * (a.mode == ROW_GRAM ? a.d * a.d : a.d) * a.RP +
                      (a.mode == ROW_GRAM ? 0 : tw_lds_entries(a.f.n, (int)es)));
-    int nz = a.ncomp;
-    if (a.mode == ROW_RHS) nz = a.d;
-    if (a.mode == ROW_R2C || a.mode == ROW_C2R) nz = 1;
-    if (a.mode == ROW_GRAM && a.gpack) nz = (a.ncomp + 1) / 2;
-    return es * (size_t)(nz + 1) * a.RP * a.f.L;
+    const int nz = row_zbufs(a);
+    return es * (size_t)(a.zbatch ? 2 * nz : nz + 1) * a.RP * a.f.L;
 }
 
 int pencil_grid_x(const PencilArgs &a) { return a.B > 0 ? (a.nb + a.B - 1) / a.B : 0; }
@@ -3704,19 +3761,20 @@ void configure_row(RowArgs &r, bool fp64) {
         return;
     }
     r.fast = 0;
-    int nz = r.ncomp;
-    if (r.mode == ROW_RHS) nz = r.d;
-    if (r.mode == ROW_R2C || r.mode == ROW_C2R) nz = 1;
-    const size_t es = fp64 ? 16 : 8;
+    r.zbatch = 0;
     r.gpack = 0;
-    if (r.mode == ROW_GRAM && es * (size_t)(nz + 1) * r.f.L > 80 * 1024) {
-        // long rows: two components of one row per transform
-        r.gpack = 1;
-        nz = (r.ncomp + 1) / 2;
-    }
-    int RP = 8;
-    while (RP > 1 && es * (size_t)(nz + 1) * RP * r.f.L > 80 * 1024) RP /= 2;
-    r.RP = RP;
+    r.RP = 1;
+    if (r.mode == ROW_GRAM && row_lds_bytes(r, fp64) > kGenericLds) r.gpack = 1;  // long rows: two components of one row per transform
+    r.RP = 8;
+    while (r.RP > 1 && row_lds_bytes(r, fp64) > kGenericLds) r.RP /= 2;
+    fit_row_batch(r, fp64);
+}
+
+void fit_row_batch(RowArgs &r, bool fp64) {
+    r.zbatch = 0;
+    if (r.fast || r.gpack || row_zbufs(r) < 2) return;
+    r.zbatch = 1;
+    if (row_lds_bytes(r, fp64) > kGenericLds) r.zbatch = 0;
 }
 
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s) {
