@@ -932,7 +932,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                 if (j >= nvr) continue;
                 const long row = (long)(r0 + j) * nh + kx;
                 const V u1 = data[(long)(2 * c2) * a.cs + row];
-                const V u2 = two ? data[(long)(2 * c2 + 1) * a.cs + row] : zero;
+                const V u2 = two ? data[(long)(2 * c2 + 1) * a.cs + row] : mk<T>(T(0), T(0));
                 if (kx == 0) {
                     zc[j * ln] = mk<T>(u1.x, u2.x);
                 } else {
@@ -1004,7 +1004,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
             const int r1 = 2 * (pair0 + j);
             const int r2 = r1 + 1;
             const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
-            const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+            const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : mk<T>(T(0), T(0));
             V *zr = Z + (size_t)cj * ln;
             if (kx == 0) {
                 zr[0] = mk<T>(u1.x, u2.x);
@@ -1031,7 +1031,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs a) {
                 const int r1 = 2 * (pair0 + j);
                 const int r2 = r1 + 1;
                 const V u1 = data[(long)c * a.cs + (long)r1 * nh + kx];
-                const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : zero;
+                const V u2 = (r2 < a.nrows) ? data[(long)c * a.cs + (long)r2 * nh + kx] : mk<T>(T(0), T(0));
                 if (kx == 0) {
                     zc[j * ln] = mk<T>(u1.x, u2.x);
                 } else {
