@@ -1,0 +1,82 @@
+"""First-order GPU parity of the generic transform kernels' component batches.
+
+The generic pencil kernel transforms the d field components of its pencils in
+chunks of cb components (cb * B sequences per batch, cb the most components
+whose buffers fit the kernel's LDS cap at its batch B), and the generic row
+kernel transforms the rows of all components as one batch when two buffers per
+component fit.  Small grids take every component at once; the grid below,
+N = (45, 67, 33) with the double grid (105, 135, 75) (all generic, 3,5,7-smooth
+lengths), has the axis-2 pencils of length 135 at B = 8 with room for two of
+the three components, so each of those passes runs a chunk of two components
+and a chunk of one, and its rows of length 75 run as one batch.  As in the
+truncated-iteration tests of the specialised lengths (Remark CG: after k steps
+the iterate is a fixed polynomial in the operator), every solve stops after K
+steps and each entry of the bounds must match the oracle's bounds of the same
+iterates to 1e-11 of the reference norm; the FP32-iteration form must match the
+FP64 run of K32 steps at contrast 10 to 1e-7.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ga, material
+
+pytestmark = pytest.mark.gpu
+
+K = 3
+K32 = 2
+N = (45, 67, 33)
+
+
+@pytest.fixture(scope="module")
+def fg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_2033_amd import fftgal
+    fftgal.load_library()
+    return fftgal
+
+
+def _micro(contrast):
+    P = tuple(2 * n - 1 for n in N)
+    return synth.grf_voxels(17, P, d=3, corr_len=0.1, vf=0.4, a_matrix=1.0, a_incl=contrast)
+
+
+def _run(fg, micro, precision, k):
+    print("generic batches N=%s %s k=%d" % (N, precision, k), flush=True)
+    plan = fg.Plan(3, N, precision, P=micro.get("P"))
+    try:
+        assert tuple(plan.M) == (105, 135, 75)
+        return plan.run(micro, rtol=0.0, maxit=k)
+    finally:
+        plan.close()
+
+
+def _max_entry_err(res, ref):
+    out = []
+    for key in ("upper", "lower"):
+        b = np.asarray(ref[key])
+        out.append(np.max(np.abs(np.asarray(res[key]) - b)) / np.linalg.norm(b))
+    return max(out)
+
+
+def test_component_chunks_fp64_match_oracle(fg):
+    micro = _micro(30.0)
+    res = _run(fg, micro, "fp64", K)
+    ref = ga.ga_bounds(material.make_material(micro), N, tol=0.0, maxit=K)
+    assert [i["iters"] for i in res["info_primal"]] == ref["iters_primal"] == [K] * 3
+    assert [i["iters"] for i in res["info_dual"]] == ref["iters_dual"] == [K] * 3
+    err = _max_entry_err(res, ref)
+    print("max entry error %.2e of |ref|" % err)
+    assert err < 1e-11
+
+
+def test_component_chunks_fp32_match_fp64(fg):
+    micro = _micro(10.0)
+    r64 = _run(fg, micro, "fp64", K32)
+    r32 = _run(fg, micro, "fp32", K32)
+    err = _max_entry_err(r32, r64)
+    print("fp32 max entry error %.2e of |fp64|" % err)
+    assert err < 1e-7
