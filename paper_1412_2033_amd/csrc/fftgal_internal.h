@@ -261,13 +261,15 @@ size_t row_lds_bytes(const RowArgs &a, bool fp64);
 // Choose pencils per work-group / row pairs per work-group (and whether the
 // specialised kernel runs) for a launch; sets a.B / r.RP.
 void configure_pencil(PencilArgs &a, bool fp64);
+void configure_row(RowArgs &r, bool fp64);
+// LDS of a generic-kernel work-group (its transform buffers): at most 80 KB,
+// two work-groups per CU
+constexpr size_t kGenericLds = 80 * 1024;
 // Generic pencil kernel: the most components per transform batch (a.cb) whose
 // buffers fit kGenericLds at the batch a.B.
 void fit_pencil_components(PencilArgs &a, bool fp64);
 // Generic row kernel: a.zbatch = 1 when the batched buffers fit kGenericLds at a.RP.
 void fit_row_batch(RowArgs &r, bool fp64);
-constexpr size_t kGenericLds = 80 * 1024;
-void configure_row(RowArgs &r, bool fp64);
 hipError_t launch_pencil(const PencilArgs &a, int nouter, bool fp64, hipStream_t s);
 hipError_t launch_row(const RowArgs &a, bool fp64, hipStream_t s);
 int row_grid(const RowArgs &a);

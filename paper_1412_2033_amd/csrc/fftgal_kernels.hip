@@ -578,7 +578,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                 for (int idx = threadIdx.x; idx < a.L_out * nbt; idx += blockDim.x) {
                     const int bt = idx % nbt;
                     const int l = idx / nbt;
-                    const int j = bt / B;
+                    const int j = cn > 1 ? bt / B : 0;  // no division for one component
                     const int bb = bt - j * B;
                     if (bb >= nbw) continue;
                     const int pos = posmod(wrapi(l, a.L_out), n);
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int idx = threadIdx.x; idx < a.L_in * nbt; idx += blockDim.x) {
             const int bt = idx % nbt;
             const int l = idx / nbt;
-            const int j = bt / B;
+            const int j = cn > 1 ? bt / B : 0;
             const int bb = bt - j * B;
             V v = zero;
             if (bb < nbw) v = in[(long)(al0 + j) * a.in_cs + (long)o * a.in_os + b0 + (long)l * a.in_ls + bb];
@@ -644,7 +644,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             for (int idx = threadIdx.x; idx < a.L_out * nbt; idx += blockDim.x) {
                 const int bt = idx % nbt;
                 const int l = idx / nbt;
-                const int j = bt / B;
+                const int j = cn > 1 ? bt / B : 0;
                 const int bb = bt - j * B;
                 if (bb >= nbw) continue;
                 const int kk = wrapi(l, a.L_out);
