@@ -215,6 +215,8 @@ def main():
                          "transforms; default the benchmark order 113; 0: skip)")
     ap.add_argument("--fast-grid", type=int, default=1,
                     help="FFTGAL_FAST_GRID against the default grid at 3D N = 81 and 2D N = 201 (0: skip)")
+    ap.add_argument("--generic", type=int, default=1,
+                    help="plans on lengths without specialised kernels (3D 45^3, GaNi 41^3 and 201^2; 0: skip)")
     ap.add_argument("--envelope", type=int, default=1,
                     help="upper-upper / lower-lower bounds section on an anisotropic cube inclusion (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -222,7 +224,7 @@ def main():
     args = ap.parse_args()
     if args.main_only:
         args.serve = args.serve3d = args.gani = args.warm_coarse = args.reduced = args.reduced_prime = 0
-        args.fast_grid = 0
+        args.fast_grid = args.generic = 0
         args.equal_accuracy = 0
         args.envelope = args.aniso = args.sweep2d = 0
     if args.gpus != 1:
@@ -392,6 +394,8 @@ def main():
                                                  variants=("reduced", "reduced_lean"))
     if args.fast_grid:
         out["fast_grid"] = fast_grid_bench(fftgal, micro_dev, d, M, dev)
+    if args.generic:
+        out["generic"] = generic_bench(fftgal, dev)
     if args.envelope:
         out["envelope"] = envelope_bench(fftgal, d, N, M, rtol64, dev)
     if args.aniso:
@@ -605,6 +609,49 @@ def fast_grid_bench(fftgal, micro_dev, d, P, dev, N3=81, N2=201):
         sec["speedup"] = round(sec["default"]["time_to_bounds_s"] / sec["fast_grid"]["time_to_bounds_s"], 2)
         sec["bound_rel_diff"] = max(float(np.linalg.norm(res[True][k] - res[False][k]) / np.linalg.norm(res[False][k]))
                                     for k in ("upper", "lower"))
+        out[tag] = sec
+    return out
+
+
+def generic_bench(fftgal, dev):
+    """Plans on lengths without specialised kernels (the generic transform
+    kernels): the 3D double grid 45^3 (order 21, radices 9 5), 3D GaNi of order
+    41 (Bluestein, L = 81) and 2D GaNi of order 201 (Bluestein, L = 405 = 9 9 5),
+    FP64 and FP32 iterations; time to bounds (set_material, 2d solves, bounds;
+    best of two runs after a warm-up) and that time per CG iteration."""
+    import synth
+    import torch
+    print("bench: generic lengths", file=sys.stderr, flush=True)
+    cases = (("ga3d_N21", 3, 21, "ga", 1e-8),
+             ("gani3d_N41", 3, 41, "gani", 1e-8),
+             ("gani2d_N201", 2, 201, "gani", 1e-10))
+    out = {}
+    for tag, d, n, scheme, rtol in cases:
+        P = 2 * n - 1
+        if d == 3:
+            micro = synth.grf_voxels(5, (P,) * 3, d=3, corr_len=0.05, vf=0.4, a_matrix=1.0, a_incl=100.0)
+        else:
+            micro = synth.circle_inclusion_vf(0.3, 1.0, 100.0)
+        sec = {}
+        for prec in ("fp64", "fp32"):
+            rt = rtol if prec == "fp64" else 5e-6
+            plan = fftgal.Plan(d, (n,) * d, prec, device=dev, P=micro.get("P"), scheme=scheme)
+            try:
+                plan.run(micro, rtol=rt)  # warm-up
+                best = None
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r = plan.run(micro, rtol=rt)
+                    torch.cuda.synchronize()
+                    el = time.perf_counter() - t0
+                    best = el if best is None else min(best, el)
+                grid = list(plan.M)
+            finally:
+                plan.close()
+            its = sum(i["iters"] for i in r["info_primal"] + r["info_dual"])
+            sec[prec] = {"rtol": rt, "grid": grid, "time_to_bounds_s": round(best, 4), "cg_iterations": its,
+                         "us_per_cg_iteration": round(best / max(its, 1) * 1e6, 1)}
         out[tag] = sec
     return out
 
