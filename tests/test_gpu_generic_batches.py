@@ -13,14 +13,17 @@ truncated-iteration tests of the specialised lengths (Remark CG: after k steps
 the iterate is a fixed polynomial in the operator), every solve stops after K
 steps and each entry of the bounds must match the oracle's bounds of the same
 iterates to 1e-11 of the reference norm; the FP32-iteration form must match the
-FP64 run of K32 steps at contrast 10 to 1e-7.
+FP64 run of K32 steps at contrast 10 to 1e-7.  A GaNi plan of order 41 in 3D
+(Def. GaNi: transforms of 41 points, Bluestein with 81-point buffers) runs all
+three components of its pencils in one batch of Bluestein transforms; after K
+steps its two matrices match the oracle's GaNi matrices of the same iterates.
 """
 
 import numpy as np
 import pytest
 
 import synth
-from oracle import ga, material
+from oracle import ga, gani, material
 
 pytestmark = pytest.mark.gpu
 
@@ -80,3 +83,20 @@ def test_component_chunks_fp32_match_fp64(fg):
     err = _max_entry_err(r32, r64)
     print("fp32 max entry error %.2e of |fp64|" % err)
     assert err < 1e-7
+
+
+def test_gani_bluestein_batches_match_oracle(fg):
+    Ng = (41, 41, 41)
+    micro = synth.grf_voxels(19, Ng, d=3, corr_len=0.1, vf=0.4, a_matrix=1.0, a_incl=30.0)
+    print("generic batches GaNi N=%s k=%d" % (Ng, K), flush=True)
+    plan = fg.Plan(3, Ng, "fp64", P=micro.get("P"), scheme="gani")
+    try:
+        res = plan.run(micro, rtol=0.0, maxit=K)
+    finally:
+        plan.close()
+    ref = gani.gani(micro, Ng, tol=0.0, maxit=K)
+    assert [i["iters"] for i in res["info_primal"]] == ref["iters_primal"] == [K] * 3
+    assert [i["iters"] for i in res["info_dual"]] == ref["iters_dual"] == [K] * 3
+    err = _max_entry_err(res, {"upper": ref["A_gani"], "lower": np.linalg.inv(ref["B_gani"])})
+    print("GaNi max entry error %.2e of |ref|" % err)
+    assert err < 1e-11
