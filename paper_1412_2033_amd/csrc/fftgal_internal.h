@@ -107,6 +107,7 @@ struct PencilArgs {
     int B;        // pencils per work-group
     int ncomp;    // transformed components (per solution)
     int cb;       // generic kernel: components transformed together (1 .. ncomp)
+    int twl;      // generic kernel: table entries staged in LDS (0: read from the table)
     int sgn;      // +1: inverse DFT (omega^{+mk}); -1: forward
     double scale; // applied to every output value
     FftDesc f;
@@ -266,7 +267,8 @@ void configure_row(RowArgs &r, bool fp64);
 // two work-groups per CU
 constexpr size_t kGenericLds = 80 * 1024;
 // Generic pencil kernel: the most components per transform batch (a.cb) whose
-// buffers fit kGenericLds at the batch a.B.
+// buffers fit kGenericLds at the batch a.B, then a.twl > 0 when the
+// transform's table fits beside them too.
 void fit_pencil_components(PencilArgs &a, bool fp64);
 // Generic row kernel: a.zbatch = 1 when the batched buffers fit kGenericLds at a.RP.
 void fit_row_batch(RowArgs &r, bool fp64);

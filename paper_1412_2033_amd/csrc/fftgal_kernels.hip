@@ -296,13 +296,14 @@ __device__ __forceinline__ void stage(const Vt<T> *X, Vt<T> *Y, int n, int p, in
 // The stages of a transform of length f.L in LDS, ping-ponging between A and
 // Bf; returns the buffer holding the result.
 template <typename T, bool ROWL>
-__device__ __forceinline__ Vt<T> *fft_stages(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
+__device__ __forceinline__ Vt<T> *fft_stages(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg,
+                                              int tb = 0) {
     Vt<T> *X = A;
     Vt<T> *Y = Bf;
     int p = 1;
     for (int s = 0; s < f.nst; ++s) {
         const int r = f.radix[s];
-        const Vt<T> *t = tw + f.twoff[s];
+        const Vt<T> *t = tw + (f.twoff[s] - tb);
         switch (r) {
             case 3: stage<T, 3, ROWL>(X, Y, f.L, p, nb, t, sg); break;
             case 5: stage<T, 5, ROWL>(X, Y, f.L, p, nb, t, sg); break;
@@ -325,12 +326,13 @@ __device__ __forceinline__ Vt<T> *fft_stages(Vt<T> *A, Vt<T> *Bf, const FftDesc 
 // pos nb + b); returns the buffer holding the result.  Must be called by
 // every thread of the work-group.
 template <typename T, bool ROWL>
-__device__ __forceinline__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg) {
-    if (!f.blue) return fft_stages<T, ROWL>(A, Bf, f, nb, tw, sg);
+__device__ __forceinline__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f, int nb, const Vt<T> *tw, T sg,
+                                           int tb = 0) {
+    if (!f.blue) return fft_stages<T, ROWL>(A, Bf, f, nb, tw, sg, tb);
     // Bluestein: u_j = x_j c_j zero-padded to L, H (.) DFT^- u, DFT^+, times c_k
     const int n = f.n, L = f.L;
-    const Vt<T> *chirp = tw + f.choff;
-    const Vt<T> *H = tw + f.hoff;
+    const Vt<T> *chirp = tw + (f.choff - tb);
+    const Vt<T> *H = tw + (f.hoff - tb);
     auto at = [&](Vt<T> *buf, int pos, int b) -> Vt<T> & { return ROWL ? buf[b * L + pos] : buf[pos * nb + b]; };
     auto chirp_of = [&](int m) {  // c_m for the sign sg
         Vt<T> c = chirp[m];
@@ -343,7 +345,7 @@ __device__ __forceinline__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f,
         v = pos < n ? cmul(v, chirp_of(pos)) : mk<T>(T(0), T(0));
     }
     __syncthreads();
-    Vt<T> *X = fft_stages<T, ROWL>(A, Bf, f, nb, tw, T(-1));
+    Vt<T> *X = fft_stages<T, ROWL>(A, Bf, f, nb, tw, T(-1), tb);
     for (int idx = threadIdx.x; idx < L * nb; idx += blockDim.x) {
         const int b = idx / L, k = idx - b * L;
         // H for the sign sg: H_k (sg = +1) or conj(H_{-k}) (sg = -1)
@@ -353,7 +355,7 @@ __device__ __forceinline__ Vt<T> *fft_lds(Vt<T> *A, Vt<T> *Bf, const FftDesc &f,
         v = cmul(v, h);
     }
     __syncthreads();
-    Vt<T> *Y = fft_stages<T, ROWL>(X, X == A ? Bf : A, f, nb, tw, T(1));
+    Vt<T> *Y = fft_stages<T, ROWL>(X, X == A ? Bf : A, f, nb, tw, T(1), tb);
     for (int idx = threadIdx.x; idx < n * nb; idx += blockDim.x) {
         const int b = idx / n, pos = idx - b * n;
         Vt<T> &v = at(Y, pos, b);
@@ -495,6 +497,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int o = blockIdx.y;
     const int nbw = min(B, a.nb - b0);
     const V *tw = reinterpret_cast<const V *>(a.tw);
+    // the transform's table entries (stage twiddles; Bluestein chirp and
+    // filter) staged in LDS after the buffers when they fit (a.twl entries from
+    // entry twoff[0]); visible to the stages after the loads' barrier
+    int tb = 0;
+    if (a.twl > 0) {
+        int lacc = 0;
+        if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
+        if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
+        V *twl = acc + (size_t)lacc * B;
+        tb = a.f.twoff[0];
+        for (int i = threadIdx.x; i < a.twl; i += blockDim.x) twl[i] = tw[tb + i];
+        tw = twl;
+    }
     const T sg = T(a.sgn);
     const T scale = T(a.scale);
     const V *in = reinterpret_cast<const V *>(a.in);
@@ -574,7 +589,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                     }
                 }
                 __syncthreads();
-                V *res = fft_lds<T, false>(bufA, bufB, a.f, nbt, tw, sg);
+                V *res = fft_lds<T, false>(bufA, bufB, a.f, nbt, tw, sg, tb);
                 for (int idx = threadIdx.x; idx < a.L_out * nbt; idx += blockDim.x) {
                     const int bt = idx % nbt;
                     const int l = idx / nbt;
@@ -616,7 +631,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             bufA[posmod(wrapi(l, a.L_in), n) * nbt + bt] = v;
         }
         __syncthreads();
-        V *res = fft_lds<T, false>(bufA, bufB, a.f, nbt, tw, sg);
+        V *res = fft_lds<T, false>(bufA, bufB, a.f, nbt, tw, sg, tb);
         if (a.epi == EPI_PROJECT) {
             // q_a += -i t_a(k)_alpha yhat_alpha(k) on Z_N, alpha in ascending order
             for (int idx = threadIdx.x; idx < a.L_out * B; idx += blockDim.x) {
@@ -3673,7 +3688,7 @@ size_t pencil_lds_bytes(const PencilArgs &a, bool fp64) {
     int lacc = 0;
     if (a.pro == PRO_EXPAND) lacc = a.nc * a.L_in;
     if (a.epi == EPI_PROJECT) lacc = a.nc * a.L_out;
-    return es * ((size_t)2 * a.f.L * std::max(a.cb, 1) * a.B + (size_t)lacc * a.B);
+    return es * ((size_t)2 * a.f.L * std::max(a.cb, 1) * a.B + (size_t)lacc * a.B + (size_t)std::max(a.twl, 0));
 }
 
 size_t row_lds_bytes(const RowArgs &a, bool fp64) {
@@ -3718,14 +3733,21 @@ void configure_pencil(PencilArgs &a, bool fp64) {
     }
     a.fast = 0;
     a.cb = 1;
+    a.twl = 0;
     a.B = fp64 ? 8 : 16;
     while (a.B > 1 && pencil_lds_bytes(a, fp64) > kGenericLds) a.B /= 2;
     fit_pencil_components(a, fp64);
 }
 
 void fit_pencil_components(PencilArgs &a, bool fp64) {
+    a.twl = 0;
     a.cb = std::max(a.ncomp, 1);
     while (a.cb > 1 && pencil_lds_bytes(a, fp64) > kGenericLds) --a.cb;
+    // then the table in LDS, if it fits too: the stage twiddles (L - 1
+    // entries), for Bluestein followed by the chirp (n) and the filter (L)
+    if (a.f.nst < 1) return;
+    a.twl = a.f.blue ? a.f.hoff + a.f.L - a.f.twoff[0] : a.f.L - 1;
+    if (a.twl < 1 || pencil_lds_bytes(a, fp64) > kGenericLds) a.twl = 0;
 }
 
 void configure_row(RowArgs &r, bool fp64) {
